@@ -1,0 +1,458 @@
+/*
+ * Oracle (test infrastructure only): hybrid encoding, intersection MLP, first-hit query,
+ * multi-task loss with its analytic gradient, and Adam, in FP64.
+ *
+ * Passages followed:
+ *  - Encoding, Eq. (1) and "Combining Positional Encoding with the Grid Encoding":
+ *    gamma(x) = [x, sin(2^k x), cos(2^k x)] for k < F; the multi-level hash grid phi
+ *    interpolates features from the neighbouring vertices of each level and concatenates
+ *    the levels; the composite psi = phi(gamma(x)) runs phi on every PE sample separately.
+ *    Readings: x is clamped to [0,1]^3 and the sin/cos samples are mapped to [0,1] by
+ *    (v+1)/2 (the grid takes normalized points); one table set serves every sample; the
+ *    hash is the Instant-NGP spatial hash (the grid encoding LSNIF builds on), dense
+ *    indexing where (N_l+1)^3 fits the table.
+ *  - Network and heads, Methodology and "Uncertainty-Weighted Multi-Task Loss": the
+ *    encoded entry and exit points feed an MLP predicting occlusion, distance (ReLU),
+ *    normal, albedo (sigmoid) and material.
+ *  - Query, "Segmented Ray Distance Accumulation": segments are visited front to back and
+ *    the first voxel with a predicted hit ends the ray; D = sum(delta_j + l_j) + delta_k + t_k,
+ *    which for consecutive segments of one straight ray telescopes to t_in + local distance.
+ *  - Loss, "Uncertainty-Weighted Multi-Task Loss": regression 0.5 exp(-s) L + 0.5 s,
+ *    classification exp(-s) L + 0.5 s; log-space MSE for distance, cosine loss for normals,
+ *    L1 on sigmoid albedo, cross-entropy for material and occlusion.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+#define DIST_EPS 1e-4
+
+static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+static double sigmoid(double v) { return 1.0 / (1.0 + exp(-v)); }
+
+static int n_samples(const orc_model* m) { return 1 + 2 * m->pe_freqs; }
+static int point_width(const orc_model* m) { return n_samples(m) * m->levels * m->feat_dim; }
+
+/* Sample s of gamma(x) for one coordinate, and its derivative d sample / d x. */
+static double pe_sample(int s, double x, double* dsdx) {
+    if (s == 0) { *dsdx = 1.0; return x; }
+    int k = (s - 1) / 2;
+    double f = ldexp(1.0, k);
+    if ((s - 1) % 2 == 0) { *dsdx = 0.5 * f * cos(f * x); return 0.5 * (sin(f * x) + 1.0); }
+    *dsdx = -0.5 * f * sin(f * x);
+    return 0.5 * (cos(f * x) + 1.0);
+}
+
+static uint32_t grid_index(const orc_model* m, int l, const uint32_t v[3]) {
+    uint32_t n1 = (uint32_t)m->res[l] + 1u;
+    uint32_t T = 1u << m->log2_table;
+    if ((uint64_t)n1 * n1 * n1 <= T) return v[0] + n1 * (v[1] + n1 * v[2]);
+    uint32_t h = (v[0] * 1u) ^ (v[1] * 2654435761u) ^ (v[2] * 805459861u);
+    return h & (T - 1u);
+}
+
+/* Cell and weights of one sample at level l. */
+static void grid_cell(const orc_model* m, int l, const double S[3], uint32_t i0[3], double w[3]) {
+    int N = m->res[l];
+    for (int a = 0; a < 3; ++a) {
+        double pos = S[a] * N;
+        double f = floor(pos);
+        if (f > N - 1) f = N - 1;
+        i0[a] = (uint32_t)f;
+        w[a] = pos - f;
+    }
+}
+
+void orc_encode_point(const orc_model* m, const double* tables, const double xin[3], double* out) {
+    const int L = m->levels, Fd = m->feat_dim, S = n_samples(m);
+    const int64_t T = 1LL << m->log2_table;
+    double x[3] = {clamp01(xin[0]), clamp01(xin[1]), clamp01(xin[2])};
+    for (int s = 0; s < S; ++s) {
+        double smp[3], dd;
+        for (int a = 0; a < 3; ++a) smp[a] = pe_sample(s, x[a], &dd);
+        for (int l = 0; l < L; ++l) {
+            uint32_t i0[3];
+            double w[3];
+            grid_cell(m, l, smp, i0, w);
+            double* o = out + ((int64_t)s * L + l) * Fd;
+            for (int f = 0; f < Fd; ++f) o[f] = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                uint32_t v[3];
+                double wt = 1.0;
+                for (int a = 0; a < 3; ++a) {
+                    int bit = (c >> a) & 1;
+                    v[a] = i0[a] + bit;
+                    wt *= bit ? w[a] : 1.0 - w[a];
+                }
+                const double* e = tables + ((int64_t)l * T + grid_index(m, l, v)) * Fd;
+                for (int f = 0; f < Fd; ++f) o[f] += wt * e[f];
+            }
+        }
+    }
+}
+
+/* Backward of one point's encoding: accumulates d tables and (optionally) d x. */
+static void encode_point_backward(const orc_model* m, const double* tables, const double xin[3],
+                                  const double* dout, double* gtab, double* gx) {
+    const int L = m->levels, Fd = m->feat_dim, S = n_samples(m);
+    const int64_t T = 1LL << m->log2_table;
+    double x[3], inside[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = clamp01(xin[a]);
+        inside[a] = (xin[a] >= 0.0 && xin[a] <= 1.0) ? 1.0 : 0.0;
+    }
+    double gacc[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < S; ++s) {
+        double smp[3], dsdx[3];
+        for (int a = 0; a < 3; ++a) smp[a] = pe_sample(s, x[a], &dsdx[a]);
+        for (int l = 0; l < L; ++l) {
+            uint32_t i0[3];
+            double w[3];
+            grid_cell(m, l, smp, i0, w);
+            const double* g = dout + ((int64_t)s * L + l) * Fd;
+            double dw[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 8; ++c) {
+                uint32_t v[3];
+                double f1[3];
+                for (int a = 0; a < 3; ++a) {
+                    int bit = (c >> a) & 1;
+                    v[a] = i0[a] + bit;
+                    f1[a] = bit ? w[a] : 1.0 - w[a];
+                }
+                double wt = f1[0] * f1[1] * f1[2];
+                int64_t base = ((int64_t)l * T + grid_index(m, l, v)) * Fd;
+                double gdot = 0.0;
+                for (int f = 0; f < Fd; ++f) {
+                    if (gtab) gtab[base + f] += wt * g[f];
+                    gdot += g[f] * tables[base + f];
+                }
+                for (int a = 0; a < 3; ++a) {
+                    double sgn = ((c >> a) & 1) ? 1.0 : -1.0;
+                    dw[a] += gdot * sgn * f1[(a + 1) % 3] * f1[(a + 2) % 3];
+                }
+            }
+            for (int a = 0; a < 3; ++a) gacc[a] += dw[a] * m->res[l] * dsdx[a];
+        }
+    }
+    if (gx) for (int a = 0; a < 3; ++a) gx[a] += gacc[a] * inside[a];
+}
+
+/* Affine layers with ReLU between them (none after the last).  acts receives the input of
+   every layer (acts[0] = the encoding) when non-null; z the output of the last layer. */
+void orc_mlp_forward(const orc_model* m, const double* params, const double* in, double* z,
+                     double* acts) {
+    int maxw = 0;
+    for (int j = 0; j <= m->n_layers; ++j) if (m->dims[j] > maxw) maxw = m->dims[j];
+    double* cur = (double*)malloc(sizeof(double) * maxw);
+    double* nxt = (double*)malloc(sizeof(double) * maxw);
+    memcpy(cur, in, sizeof(double) * m->dims[0]);
+    const double* p = params;
+    int64_t aoff = 0;
+    for (int j = 0; j < m->n_layers; ++j) {
+        int ni = m->dims[j], no = m->dims[j + 1];
+        if (acts) { memcpy(acts + aoff, cur, sizeof(double) * ni); aoff += ni; }
+        const double* W = p;
+        const double* b = p + (int64_t)no * ni;
+        for (int r = 0; r < no; ++r) {
+            double acc = b[r];
+            for (int c = 0; c < ni; ++c) acc += W[(int64_t)r * ni + c] * cur[c];
+            nxt[r] = (j + 1 < m->n_layers && acc < 0.0) ? 0.0 : acc;
+        }
+        p += (int64_t)no * ni + no;
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    memcpy(z, cur, sizeof(double) * m->dims[m->n_layers]);
+    free(cur); free(nxt);
+}
+
+/* Conditioning of the hit logit: |b| + sum |w||h| of the last layer's row 0. */
+static double hit_logit_scale(const orc_model* m, const double* params, const double* acts) {
+    const double* p = params;
+    int64_t aoff = 0;
+    for (int j = 0; j + 1 < m->n_layers; ++j) {
+        p += (int64_t)m->dims[j + 1] * m->dims[j] + m->dims[j + 1];
+        aoff += m->dims[j];
+    }
+    int ni = m->dims[m->n_layers - 1], no = m->dims[m->n_layers];
+    double s = fabs(p[(int64_t)no * ni]);
+    for (int c = 0; c < ni; ++c) s += fabs(p[c] * acts[aoff + c]);
+    return s;
+}
+
+static int64_t acts_width(const orc_model* m) {
+    int64_t s = 0;
+    for (int j = 0; j < m->n_layers; ++j) s += m->dims[j];
+    return s;
+}
+
+static void features(const orc_model* m, const double* tables, const double x0[3],
+                     const double x1[3], double* enc) {
+    orc_encode_point(m, tables, x0, enc);
+    orc_encode_point(m, tables, x1, enc + point_width(m));
+}
+
+/* ------------------------------------------------------------------ batch entry points */
+
+void orc_deform_batch(int32_t kind, double s, int64_t n, const double* p, double* q, int32_t inverse) {
+    for (int64_t i = 0; i < n; ++i) {
+        if (inverse) orc_deform_inv(kind, s, p + 3 * i, q + 3 * i);
+        else orc_deform(kind, s, p + 3 * i, q + 3 * i);
+    }
+}
+
+void orc_jacdet_batch(int32_t kind, double s, int64_t n, const double* p, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_deform_jacdet(kind, s, p + 3 * i);
+}
+
+void orc_scene_f_batch(int32_t kind, const double* sp, int64_t n, const double* p, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_scene_f(kind, sp, p + 3 * i);
+}
+
+void orc_label_batch(int32_t kind, const double* sp, int32_t force_march, int64_t n,
+                     const double* x0, const double* x1, uint8_t* hit, double* t, double* nrm,
+                     double* alb, int32_t* mat) {
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i)
+        orc_label(kind, sp, force_march, x0 + 3 * i, x1 + 3 * i, hit + i, t + i, nrm + 3 * i,
+                  alb + 3 * i, mat + i);
+}
+
+/* Hit lists of n rays (o, d as n x 3): segments of ray i at [i*max_out, ...). */
+void orc_trace_batch(int32_t N, const uint8_t* occ, const double* V, int64_t n, const double* o,
+                     const double* d, int32_t brute, int32_t max_out, int32_t* cell, double* tin,
+                     double* tout, int32_t* count, int32_t* flags) {
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i)
+        count[i] = orc_hitlist(N, occ, V, o + 3 * i, d + 3 * i, brute, max_out, cell + i * max_out,
+                               tin + i * max_out, tout + i * max_out, flags ? flags + i : NULL);
+}
+
+void orc_encode_batch(const orc_model* m, const double* tables, int64_t n, const double* x,
+                      double* out) {
+    const int W = point_width(m);
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) orc_encode_point(m, tables, x + 3 * i, out + i * W);
+}
+
+/* Network on given rest-space point pairs: z[i] = MLP(psi(x0_i) ++ psi(x1_i)). */
+void orc_forward_batch(const orc_model* m, const double* tables, const double* params, int64_t n,
+                       const double* x0, const double* x1, double* z, double* zscale) {
+    const int E = m->dims[0], H = m->dims[m->n_layers];
+    #pragma omp parallel
+    {
+        double* enc = (double*)malloc(sizeof(double) * E);
+        double* acts = (double*)malloc(sizeof(double) * acts_width(m));
+        #pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            features(m, tables, x0 + 3 * i, x1 + 3 * i, enc);
+            orc_mlp_forward(m, params, enc, z + i * H, acts);
+            if (zscale) zscale[i] = hit_logit_scale(m, params, acts);
+        }
+        free(enc); free(acts);
+    }
+}
+
+/* First-hit query of n rays under one pose.  Per ray: hit, distance D along the ray,
+   rest-space hit point, normal, albedo, material, voxel, hit logit, segments evaluated,
+   and the smallest relative margin |z0| / scale among the evaluated segments. */
+void orc_query_batch(const orc_model* m, const double* tables, const double* params, int32_t N,
+                     const uint8_t* occ, int32_t kind, double s, int64_t n, const double* o,
+                     const double* d, uint8_t* hit, double* tout_ray, double* xrest, double* nrm,
+                     double* alb, int32_t* mat, int32_t* cell_out, double* logit, int32_t* nq,
+                     double* margin) {
+    const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials;
+    double* V = (double*)malloc(sizeof(double) * 3 * (size_t)(N + 1) * (N + 1) * (N + 1));
+    orc_lattice_vertices(kind, s, N, V);
+    const int cap = 16 * N + 64;
+    #pragma omp parallel
+    {
+        int32_t* cells = (int32_t*)malloc(sizeof(int32_t) * cap);
+        double* tin = (double*)malloc(sizeof(double) * cap);
+        double* tou = (double*)malloc(sizeof(double) * cap);
+        double* enc = (double*)malloc(sizeof(double) * E);
+        double* acts = (double*)malloc(sizeof(double) * acts_width(m));
+        double* z = (double*)malloc(sizeof(double) * H);
+        #pragma omp for schedule(dynamic, 8)
+        for (int64_t r = 0; r < n; ++r) {
+            const double* ro = o + 3 * r;
+            const double* rd = d + 3 * r;
+            int32_t ns = orc_hitlist(N, occ, V, ro, rd, 0, cap, cells, tin, tou, NULL);
+            if (ns > cap) ns = cap;
+            hit[r] = 0; tout_ray[r] = INFINITY; cell_out[r] = -1; mat[r] = -1;
+            logit[r] = -INFINITY; nq[r] = 0; margin[r] = INFINITY;
+            for (int a = 0; a < 3; ++a) { xrest[3 * r + a] = 0; nrm[3 * r + a] = 0; alb[3 * r + a] = 0; }
+            for (int k = 0; k < ns; ++k) {
+                double p0[3], p1[3], x0[3], x1[3];
+                for (int a = 0; a < 3; ++a) { p0[a] = ro[a] + tin[k] * rd[a]; p1[a] = ro[a] + tou[k] * rd[a]; }
+                orc_deform_inv(kind, s, p0, x0);
+                orc_deform_inv(kind, s, p1, x1);
+                features(m, tables, x0, x1, enc);
+                orc_mlp_forward(m, params, enc, z, acts);
+                nq[r] = k + 1;
+                logit[r] = z[0];
+                double sc = hit_logit_scale(m, params, acts);
+                double mg = sc > 0.0 ? fabs(z[0]) / sc : INFINITY;
+                if (mg < margin[r]) margin[r] = mg;
+                if (!(z[0] > 0.0)) continue;
+                double e[3] = {x1[0] - x0[0], x1[1] - x0[1], x1[2] - x0[2]};
+                double lr = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                double dh = z[1] > 0.0 ? z[1] : 0.0;
+                double f = lr > 0.0 ? clamp01(dh / lr) : 0.0;
+                hit[r] = 1;
+                tout_ray[r] = tin[k] + f * (tou[k] - tin[k]);
+                for (int a = 0; a < 3; ++a) xrest[3 * r + a] = x0[a] + f * e[a];
+                double nl = sqrt(z[2] * z[2] + z[3] * z[3] + z[4] * z[4]);
+                if (nl < 1e-12) nl = 1e-12;
+                for (int a = 0; a < 3; ++a) { nrm[3 * r + a] = z[2 + a] / nl; alb[3 * r + a] = sigmoid(z[5 + a]); }
+                if (M == 1) mat[r] = z[8] > 0.0 ? 1 : 0;
+                else {
+                    int best = 0;
+                    for (int c = 1; c < M; ++c) if (z[8 + c] > z[8 + best]) best = c;
+                    mat[r] = best;
+                }
+                cell_out[r] = cells[k];
+                break;
+            }
+        }
+        free(cells); free(tin); free(tou); free(enc); free(acts); free(z);
+    }
+    free(V);
+}
+
+/* Multi-task loss over a batch and its gradient with respect to every parameter.
+   Task order: hit, distance, normal, albedo, material; s holds log sigma^2 per task.
+   losses[0..4] = per-task batch losses, losses[5] = weighted total.  Gradients are added
+   to the g_* arrays (which the caller zeroes); g_x0 / g_x1 may be null. */
+void orc_loss_grad(const orc_model* m, const double* tables, const double* params, const double* s,
+                   int64_t B, const double* x0, const double* x1, const uint8_t* lhit,
+                   const double* lt, const double* ln, const double* la, const int32_t* lm,
+                   double* losses, double* g_tables, double* g_params, double* g_s, double* g_x0,
+                   double* g_x1) {
+    const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials, PW = point_width(m);
+    int64_t P = 0;
+    for (int64_t i = 0; i < B; ++i) P += lhit[i] ? 1 : 0;
+    double w[5];
+    w[0] = exp(-s[0]);              /* classification */
+    w[1] = 0.5 * exp(-s[1]);        /* regression */
+    w[2] = 0.5 * exp(-s[2]);
+    w[3] = 0.5 * exp(-s[3]);
+    w[4] = exp(-s[4]);              /* classification */
+    double sum[5] = {0, 0, 0, 0, 0};
+    double* enc = (double*)malloc(sizeof(double) * E);
+    double* acts = (double*)malloc(sizeof(double) * acts_width(m));
+    double* z = (double*)malloc(sizeof(double) * H);
+    double* dz = (double*)malloc(sizeof(double) * H);
+    int maxw = 0;
+    for (int j = 0; j <= m->n_layers; ++j) if (m->dims[j] > maxw) maxw = m->dims[j];
+    double* dcur = (double*)malloc(sizeof(double) * maxw);
+    double* dprev = (double*)malloc(sizeof(double) * maxw);
+    for (int64_t i = 0; i < B; ++i) {
+        features(m, tables, x0 + 3 * i, x1 + 3 * i, enc);
+        orc_mlp_forward(m, params, enc, z, acts);
+        for (int h = 0; h < H; ++h) dz[h] = 0.0;
+        /* occlusion: binary cross-entropy with logits over the whole batch */
+        double y = lhit[i] ? 1.0 : 0.0;
+        sum[0] += (z[0] > 0 ? z[0] : 0.0) - z[0] * y + log1p(exp(-fabs(z[0])));
+        dz[0] = w[0] * (sigmoid(z[0]) - y) / (double)B;
+        if (lhit[i] && P > 0) {
+            /* distance: MSE of logs, ReLU output */
+            double dh = z[1] > 0.0 ? z[1] : 0.0;
+            double r = log(dh + DIST_EPS) - log(lt[i] + DIST_EPS);
+            sum[1] += r * r;
+            if (z[1] > 0.0) dz[1] = w[1] * 2.0 * r / (dh + DIST_EPS) / (double)P;
+            /* normal: 1 - cosine */
+            const double* nt = ln + 3 * i;
+            double v[3] = {z[2], z[3], z[4]};
+            double vl = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            double den = vl > 1e-12 ? vl : 1e-12;
+            double nh[3] = {v[0] / den, v[1] / den, v[2] / den};
+            double c = nh[0] * nt[0] + nh[1] * nt[1] + nh[2] * nt[2];
+            sum[2] += 1.0 - c;
+            for (int a = 0; a < 3; ++a) {
+                double g = vl > 1e-12 ? -(nt[a] - nh[a] * c) / vl : -nt[a] / 1e-12;
+                dz[2 + a] = w[2] * g / (double)P;
+            }
+            /* albedo: L1 on sigmoid outputs, mean over the three channels */
+            for (int a = 0; a < 3; ++a) {
+                double ah = sigmoid(z[5 + a]);
+                double df = ah - la[3 * i + a];
+                sum[3] += fabs(df) / 3.0;
+                double sg = df > 0 ? 1.0 : (df < 0 ? -1.0 : 0.0);
+                dz[5 + a] = w[3] * sg * ah * (1.0 - ah) / (3.0 * (double)P);
+            }
+            /* material: softmax cross-entropy (binary for a single logit) */
+            if (M == 1) {
+                double ym = lm[i] ? 1.0 : 0.0;
+                sum[4] += (z[8] > 0 ? z[8] : 0.0) - z[8] * ym + log1p(exp(-fabs(z[8])));
+                dz[8] = w[4] * (sigmoid(z[8]) - ym) / (double)P;
+            } else {
+                double mx = z[8];
+                for (int c2 = 1; c2 < M; ++c2) if (z[8 + c2] > mx) mx = z[8 + c2];
+                double se = 0.0;
+                for (int c2 = 0; c2 < M; ++c2) se += exp(z[8 + c2] - mx);
+                double lse = mx + log(se);
+                sum[4] += lse - z[8 + lm[i]];
+                for (int c2 = 0; c2 < M; ++c2) {
+                    double pr = exp(z[8 + c2] - lse);
+                    dz[8 + c2] = w[4] * (pr - (c2 == lm[i] ? 1.0 : 0.0)) / (double)P;
+                }
+            }
+        }
+        /* backward through the MLP */
+        memcpy(dcur, dz, sizeof(double) * H);
+        int64_t poff = 0, aoff = 0;
+        int64_t* po = (int64_t*)malloc(sizeof(int64_t) * m->n_layers);
+        int64_t* ao = (int64_t*)malloc(sizeof(int64_t) * m->n_layers);
+        for (int j = 0; j < m->n_layers; ++j) {
+            po[j] = poff; ao[j] = aoff;
+            poff += (int64_t)m->dims[j + 1] * m->dims[j] + m->dims[j + 1];
+            aoff += m->dims[j];
+        }
+        for (int j = m->n_layers - 1; j >= 0; --j) {
+            int ni = m->dims[j], no = m->dims[j + 1];
+            const double* W = params + po[j];
+            double* gW = g_params + po[j];
+            double* gb = gW + (int64_t)no * ni;
+            const double* hin = acts + ao[j];
+            for (int r = 0; r < no; ++r) {
+                gb[r] += dcur[r];
+                for (int c = 0; c < ni; ++c) gW[(int64_t)r * ni + c] += dcur[r] * hin[c];
+            }
+            for (int c = 0; c < ni; ++c) {
+                double acc = 0.0;
+                for (int r = 0; r < no; ++r) acc += W[(int64_t)r * ni + c] * dcur[r];
+                /* the input of hidden layers went through ReLU: zero where it was clipped */
+                dprev[c] = (j > 0 && !(hin[c] > 0.0)) ? 0.0 : acc;
+            }
+            double* t = dcur; dcur = dprev; dprev = t;
+        }
+        free(po); free(ao);
+        /* dcur now holds d loss / d encoding */
+        encode_point_backward(m, tables, x0 + 3 * i, dcur, g_tables, g_x0 ? g_x0 + 3 * i : NULL);
+        encode_point_backward(m, tables, x1 + 3 * i, dcur + PW, g_tables, g_x1 ? g_x1 + 3 * i : NULL);
+    }
+    double Ls[5];
+    Ls[0] = sum[0] / (double)B;
+    for (int k = 1; k < 5; ++k) Ls[k] = P > 0 ? sum[k] / (double)P : 0.0;
+    double total = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        total += w[k] * Ls[k] + 0.5 * s[k];
+        g_s[k] += -w[k] * Ls[k] + 0.5;
+        losses[k] = Ls[k];
+    }
+    losses[5] = total;
+    free(enc); free(acts); free(z); free(dz); free(dcur); free(dprev);
+}
+
+/* One Adam step with bias correction (the torch.optim.Adam update, no weight decay). */
+void orc_adam(int64_t n, double* theta, const double* g, double* mo, double* ve, int32_t step,
+              double lr, double b1, double b2, double eps) {
+    double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+    for (int64_t i = 0; i < n; ++i) {
+        mo[i] = b1 * mo[i] + (1.0 - b1) * g[i];
+        ve[i] = b2 * ve[i] + (1.0 - b2) * g[i] * g[i];
+        double mh = mo[i] / c1, vh = ve[i] / c2;
+        theta[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
