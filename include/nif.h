@@ -1,0 +1,218 @@
+/*
+ * libnif -- deformation-aware neural intersection function on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of the method: per-ray neural intersection queries
+ * under a parameterized deformation, and the training step of the network.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status: NIF_OK (0) or an error code > 0.  On error the
+ *    call has enqueued nothing, and nif_last_error() returns a message for the calling
+ *    thread.  No C++ exception crosses this boundary.
+ *  - Pointers named *_dev are device pointers owned by the caller; pointers named *_host
+ *    are host pointers read during the call only.  Buffers are contiguous and FP32 unless
+ *    stated.  Rays and points are structure-of-arrays.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is enqueued on it
+ *    and the call returns without synchronising, except where stated.
+ *  - Opaque handles (nif_model, nif_grid) own their device memory, which is allocated at
+ *    create/build time only.  nif_query, nif_trace, nif_forward, nif_encode, nif_backward
+ *    and nif_train_step never allocate device memory.  A handle must not be used by two
+ *    streams at once.
+ *  - Device-side conditions (segment-list overflow, non-finite loss) are reported through
+ *    device buffers the caller reads after its own synchronisation.
+ */
+#ifndef NIF_H
+#define NIF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    NIF_OK = 0,
+    NIF_E_INVALID_ARG = 1,   /* null pointer, bad size, bad enum value */
+    NIF_E_UNSUPPORTED = 2,   /* valid but not implemented (e.g. a layer width that is not a multiple of 16) */
+    NIF_E_OOM = 3,           /* device allocation failed (create/build only) */
+    NIF_E_DEVICE = 4,        /* a HIP runtime call failed */
+    NIF_E_STATE = 5          /* handle not ready (e.g. parameters never set) */
+};
+const char* nif_status_string(int status);
+const char* nif_last_error(void);
+int nif_version(void);
+
+typedef struct nif_model nif_model;
+typedef struct nif_grid nif_grid;
+typedef void* nif_stream;
+
+/* ---------------------------------------------------------------- deformation
+ * A pose is one parameterized deformation D of the rest space (Methodology: the network
+ * lives in rest space; rays are traced in deformed space and mapped back through the
+ * inverse deformation).  Kinds and strength s in [0, 1]; pivot at the cube centre c:
+ *   TWIST: rotation about the z axis through c by 0.6 s z radians;
+ *   BEND : circular bend in the x-z plane with curvature s / 1.5;
+ *   TAPER: x, y scaled about c by 1 - 0.5 s z.
+ */
+enum { NIF_DEFORM_IDENTITY = 0, NIF_DEFORM_TWIST = 1, NIF_DEFORM_BEND = 2, NIF_DEFORM_TAPER = 3 };
+typedef struct { int32_t kind; float strength; } nif_pose;
+
+/* ---------------------------------------------------------------- model
+ * Hybrid encoding psi = phi(gamma(x)) of Eq. (1) (PE samples, each run through the
+ * multiresolution hash grid) on the rest-space entry and exit points of a voxel segment,
+ * followed by an MLP with ReLU hidden layers and 8 + n_materials outputs:
+ * [hit logit, distance, normal(3), albedo(3), material logits].
+ * Canonical FP32 parameter layouts (the ones nif_model_set_params takes):
+ *   tables: [levels][2^log2_table][feat_dim]
+ *   mlp   : per layer W[out][in] row-major then b[out]; layer widths
+ *           E = 2 (1 + 2 pe_freqs) levels feat_dim, hidden_width x hidden_layers, 8 + n_materials
+ *   s     : [5] log-variances of the tasks (hit, distance, normal, albedo, material)
+ */
+enum { NIF_TABLE_F32 = 0, NIF_TABLE_F16 = 1 };
+enum { NIF_PREC_FP32 = 0, NIF_PREC_BF16 = 1, NIF_PREC_FP16 = 2 };
+
+typedef struct {
+    int32_t levels;          /* L: 8 or 16 */
+    int32_t log2_table;      /* T = 2^log2_table entries per level, 4..24 */
+    int32_t feat_dim;        /* features per level; 2 */
+    int32_t table_dtype;     /* NIF_TABLE_F32 or NIF_TABLE_F16 (working copy; master is FP32) */
+    int32_t res[32];         /* per-level grid resolution N_l >= 1 */
+    int32_t pe_freqs;        /* F >= 0: PE samples per point = 1 + 2F */
+    int32_t hidden_width;    /* multiple of 16, <= 128 */
+    int32_t hidden_layers;   /* 1..8 */
+    int32_t n_materials;     /* 1..8 */
+} nif_model_desc;
+
+/* Allocates parameters (FP32 masters and working copies), gradients and Adam state. */
+int nif_model_create(const nif_model_desc* desc, nif_model** out);
+int nif_model_destroy(nif_model* model);
+/* Element counts of the canonical tables and MLP parameter vectors. */
+int nif_model_sizes(const nif_model_desc* desc, int64_t* n_table, int64_t* n_mlp);
+/* Copies canonical FP32 parameters in (device pointers; s_dev may be NULL = zeros) and
+   refreshes the working copies (FP16 tables, padded FP32/BF16/FP16 MLP) by
+   round-to-nearest-even.  Resets gradients, Adam moments and the step counter. */
+int nif_model_set_params(nif_model* model, const float* tables_dev, const float* mlp_dev,
+                         const float* s_dev, nif_stream stream);
+/* Copies the FP32 masters out (any pointer may be NULL). */
+int nif_model_get_params(const nif_model* model, float* tables_dev, float* mlp_dev, float* s_dev,
+                         nif_stream stream);
+/* Gradient accumulators (FP32, canonical layouts) filled by nif_backward / nif_train_step. */
+int nif_model_get_grads(const nif_model* model, float* g_tables_dev, float* g_mlp_dev, float* g_s_dev,
+                        nif_stream stream);
+int nif_model_zero_grads(nif_model* model, nif_stream stream);
+/* Allocates the training scratch for batches of up to max_batch samples (activations,
+   deltas); nif_backward and nif_train_step fail with NIF_E_STATE above it. */
+int nif_model_reserve(nif_model* model, int64_t max_batch);
+
+/* ---------------------------------------------------------------- scene preparation
+ * Rest-space voxelization (Methodology: the geometry is voxelized in rest space).  Cell
+ * (i,j,k) of the N^3 grid over [0,1]^3 is occupied iff the scene's implicit function,
+ * sampled on the 5^3 sub-lattice of the closed cell, takes both signs.
+ *   scene_kind 0 torus   params [cx,cy,cz,R,r]
+ *              1 spheres params [n, (cx,cy,cz,r, ar,ag,ab, material) x n]
+ *              2 blobs   params [n, (mx,my,mz,sigma, cr,cg,cb, material) x n]
+ * occ_dev: u8[N^3], index i + N (j + N k).  Evaluated in FP32. */
+int nif_voxelize(int32_t scene_kind, const double* params_host, int32_t n_params, int32_t N,
+                 uint8_t* occ_dev, nif_stream stream);
+
+/* ---------------------------------------------------------------- deformed grid
+ * Per pose: the deformed lattice vertices V_ijk = D(i/N, j/N, k/N) (faces split along their
+ * main diagonal), and an acceleration structure over the occupied deformed voxels
+ * (Methodology, "Voxel Traversal under Deformation": voxel sizes vary under deformation, so
+ * voxels are found by geometric tests rather than index arithmetic).  Here the structure is
+ * a uniform bin grid over each pose's deformed bounding box; bins_per_axis = 0 picks N/2.
+ * Synchronises `stream` (it sizes the bin lists on the host) and allocates.
+ * occ_dev: u8[N^3] as above; poses_host: [n_poses]. */
+int nif_build_grid(const uint8_t* occ_dev, int32_t N, const nif_pose* poses_host, int32_t n_poses,
+                   int32_t bins_per_axis, nif_grid** out, nif_stream stream);
+int nif_grid_destroy(nif_grid* grid);
+/* Number of occupied voxels; total bin-list entries of one pose. */
+int nif_grid_info(const nif_grid* grid, int32_t pose, int64_t* n_occupied, int64_t* n_refs);
+
+/* ---------------------------------------------------------------- rays
+ * Deformed-space rays o + t d, grouped by pose: rays [pose_offsets[p], pose_offsets[p+1])
+ * use pose p.  pose_offsets_dev: int64[n_poses + 1] on the device, pose_offsets[0] = 0 and
+ * pose_offsets[n_poses] = n_rays.  d need not be unit; t is in units of |d|. */
+typedef struct {
+    const float *ox, *oy, *oz, *dx, *dy, *dz;
+    const int64_t* pose_offsets;
+} nif_rays;
+
+/* Ordered occupied-voxel segments of each ray (Methodology, "Segmented Ray Distance
+ * Accumulation": entry/exit points of every occupied voxel the straight deformed ray
+ * crosses).  Segment k of ray i is stored at i*max_seg + k: voxel id, t_in (clipped to
+ * t >= 0), t_out, and the rest-space entry/exit points x0 = D^-1(o + t_in d),
+ * x1 = D^-1(o + t_out d) as SoA [3][n_rays*max_seg].  count[i] is the full number of
+ * segments (may exceed max_seg: only the first max_seg are stored).  Nullable: x0, x1. */
+typedef struct {
+    int32_t* count; int32_t* cell; float* t_in; float* t_out; float* x0; float* x1;
+} nif_segments;
+int nif_trace(const nif_grid* grid, const nif_rays* rays, int64_t n_rays, int32_t max_seg,
+              const nif_segments* out, nif_stream stream);
+
+/* ---------------------------------------------------------------- query
+ * First-hit neural intersection query (the hot path).  Per ray: walk its occupied voxels
+ * front to back; for each, map entry/exit to rest space, encode with psi, run the MLP;
+ * the first voxel whose hit logit is > 0 ends the ray.  Its distance is
+ * D = t_in + f (t_out - t_in), f = clamp(relu(z_dist) / |x1 - x0|, 0, 1) (the segmented
+ * accumulation of the paper, which telescopes for one straight ray), its rest-space hit
+ * point x0 + f (x1 - x0), normal z_n / |z_n|, albedo sigmoid(z_a), material argmax.
+ * Misses: hit 0, t +inf, cell -1, material -1, other fields 0.
+ * Every output pointer is nullable (not written).  Outputs are indexed by ray. */
+typedef struct {
+    uint8_t* hit; float* t; float *nx, *ny, *nz; float *ar, *ag, *ab; int32_t* material;
+    int32_t* cell; float* hit_logit; int32_t* n_queried; float *xr, *yr, *zr;
+} nif_hits;
+enum { NIF_Q_FIRST_HIT = 0, NIF_Q_NO_NETWORK = 8 };
+/* flags: NIF_Q_FIRST_HIT, or NIF_Q_NO_NETWORK (the voxel proxy: first occupied voxel is
+ * the hit, D = t_in, no network).  precision: NIF_PREC_*.  stats_dev: nullable int64[4]
+ * {rays done, network evaluations, cell-test overflows, reserved}, accumulated. */
+int nif_query(const nif_model* model, const nif_grid* grid, const nif_rays* rays, int64_t n_rays,
+              const nif_hits* out, uint32_t flags, int32_t precision, int64_t* stats_dev,
+              nif_stream stream);
+
+/* ---------------------------------------------------------------- network on points
+ * psi encoding of n rest-space points (SoA [3][n]) -> out[n][(1+2F) L feat_dim], FP32. */
+int nif_encode(const nif_model* model, const float* x_dev, int64_t n, float* out_dev, nif_stream stream);
+/* Heads of B point pairs: heads_dev[B][8 + n_materials] = MLP(psi(x0) ++ psi(x1)). */
+int nif_forward(const nif_model* model, const float* x0_dev, const float* x1_dev, int64_t B,
+                float* heads_dev, int32_t precision, nif_stream stream);
+/* Backward of nif_forward given d heads [B][8 + n_materials]: adds dL/dtables, dL/dmlp to
+ * the model's gradient accumulators (zeroed first unless accumulate != 0) and writes
+ * dL/dx0, dL/dx1 (SoA, nullable).  Hand-written: MLP backward, hash-grid scatter-add with
+ * the trilinear weights (FP32 atomics), PE chain rule; the encoding is recomputed. */
+int nif_backward(nif_model* model, const float* x0_dev, const float* x1_dev, int64_t B,
+                 const float* d_heads_dev, float* d_x0_dev, float* d_x1_dev, int32_t accumulate,
+                 int32_t precision, nif_stream stream);
+
+/* ---------------------------------------------------------------- training
+ * One step of training on a batch of B voxel segments with rest-space supervision
+ * (Methodology: a dataset of deformed-space ray queries with rest-space labels): forward,
+ * uncertainty-weighted multi-task loss ("Uncertainty-Weighted Multi-Task Loss": regression
+ * 0.5 e^-s L + 0.5 s for distance (log-space MSE, eps 1e-4), normal (1 - cos) and albedo
+ * (L1 of sigmoid); classification e^-s L + 0.5 s for occlusion (BCE) and material (CE);
+ * geometric and appearance terms averaged over the hit samples only), backward and Adam
+ * (bias-corrected; lr for tables, MLP and s).  BF16/FP16 use dynamic loss scaling: a
+ * non-finite gradient skips the update and halves the scale.
+ * losses_dev: float[16] = {L_hit, L_dist, L_nrm, L_alb, L_mat, total, s[5], loss scale,
+ * skipped (0/1), n_hit, 0, 0}. */
+typedef struct {
+    const float *x0, *x1;       /* SoA [3][B] rest-space entry / exit points */
+    const uint8_t* hit;         /* [B] occlusion label */
+    const float* t;             /* [B] rest-space distance from x0 along the segment */
+    const float* n;             /* SoA [3][B] unit normal */
+    const float* a;             /* SoA [3][B] albedo */
+    const int32_t* m;           /* [B] material id */
+} nif_batch;
+typedef struct {
+    float lr_table, lr_mlp, lr_s, beta1, beta2, eps;
+    int32_t precision;          /* NIF_PREC_* of the MLP */
+    float loss_scale_init;      /* 0 = 1 for FP32/BF16, 32768 for FP16 */
+} nif_train_cfg;
+int nif_train_step(nif_model* model, const nif_batch* batch, int64_t B, const nif_train_cfg* cfg,
+                   float* losses_dev, nif_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

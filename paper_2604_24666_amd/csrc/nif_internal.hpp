@@ -1,0 +1,95 @@
+// Host-side state behind the opaque libnif handles, and the launchers each translation unit
+// provides to the C ABI layer (nif_api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/nif.h"
+#include "nif_device.hpp"
+
+struct nif_grid {
+    int32_t N = 0, n_poses = 0;
+    std::vector<nif::PoseDev> poses_host;   // as last read back after the build
+    nif::PoseDev* poses = nullptr;          // device [n_poses]
+    float4* verts = nullptr;                // device [n_poses][(N+1)^3]
+    int32_t* bin_start = nullptr;           // device, per pose nbins + 1 (exclusive scan)
+    int32_t* bin_cells = nullptr;           // device, occupied voxel ids per bin
+    int64_t n_occupied = 0;
+    std::vector<int64_t> refs_per_pose;
+};
+
+struct nif_model {
+    nif_model_desc desc{};
+    int32_t S = 0;           // PE samples per point
+    int32_t E = 0;           // encoding width (both points)
+    int32_t H = 0;           // head count (8 + materials)
+    int64_t n_table = 0, n_mlp = 0;
+    int32_t n_layers = 0;    // affine layers
+    std::vector<int32_t> dims;          // [n_layers + 1], canonical (last = H)
+    std::vector<int32_t> dims_pad;      // last padded to 16
+    std::vector<int64_t> w_off, b_off;  // canonical offsets of each layer's W and b
+    std::vector<int64_t> wp_off, bp_off;// offsets in the padded working copies
+    int64_t n_mlp_pad = 0;
+    // parameters
+    float* tables = nullptr;            // FP32 master [L][T][Fd]
+    __half* tables_h = nullptr;         // FP16 working copy (table_dtype == F16)
+    float* mlp = nullptr;               // FP32 master, canonical
+    float* mlp_pad_f32 = nullptr;       // padded working copies
+    uint16_t* mlp_pad_bf16 = nullptr;
+    __half* mlp_pad_f16 = nullptr;
+    float* s = nullptr;                 // [5]
+    // gradients (FP32, canonical layout) and Adam moments
+    float *g_tables = nullptr, *g_mlp = nullptr, *g_s = nullptr;
+    float *m_tables = nullptr, *v_tables = nullptr, *m_mlp = nullptr, *v_mlp = nullptr;
+    float *m_s = nullptr, *v_s = nullptr;
+    float* g_mlp_pad = nullptr;         // backward accumulates here (padded), then unpadded
+    // training scratch (sized for max_batch samples; grown only by nif_model_reserve)
+    int64_t max_batch = 0;
+    float* dz = nullptr;                // [max_batch][16]
+    float* acts = nullptr;              // stored hidden activations
+    float* delta = nullptr;             // backward deltas of hidden layers
+    float* delta1 = nullptr;            // delta at the first hidden layer (FP32)
+    float* train_acc = nullptr;         // loss sums and flags [32]
+    int32_t step = 0;
+    float loss_scale = 1.f;
+    int32_t good_steps = 0;
+    bool params_set = false;
+    int64_t* counters = nullptr;        // [8] device work counters
+};
+
+namespace nif {
+
+// error reporting (thread-local message)
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+// nif_grid.hip
+int grid_build(nif_grid* g, const uint8_t* occ, int32_t N, const nif_pose* poses, int32_t n_poses,
+               int32_t bins_per_axis, hipStream_t st);
+void grid_free(nif_grid* g);
+int voxelize_launch(int32_t scene_kind, const float* params_dev, int32_t N, uint8_t* occ,
+                    hipStream_t st);
+
+// nif_query.hip
+int trace_launch(const nif_grid* g, const nif_rays* r, int64_t n, int32_t max_seg,
+                 const nif_segments* out, hipStream_t st);
+int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64_t n,
+                 const nif_hits* out, uint32_t flags, int32_t precision, int64_t* stats,
+                 hipStream_t st);
+int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st);
+int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads,
+                   int32_t precision, float* acts, hipStream_t st);
+
+// nif_train.hip
+int model_alloc(nif_model* m);
+void model_free(nif_model* m);
+int model_sync_working(nif_model* m, hipStream_t st);
+int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh,
+                    int32_t dh_stride, float* dx0, float* dx1, int32_t precision, hipStream_t st);
+int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg,
+                      float* losses, hipStream_t st);
+int model_reserve(nif_model* m, int64_t B);
+
+}  // namespace nif

@@ -1,0 +1,352 @@
+// Hybrid encoding psi = phi(gamma(x)) and the intersection MLP, for one wavefront.
+//
+// Eq. (1) and "Combining Positional Encoding with the Grid Encoding": each rest-space point
+// x (clamped to the unit cube) is expanded into S = 1 + 2F positional-encoding samples
+// [x, (sin 2^k x + 1)/2, (cos 2^k x + 1)/2]; every sample is looked up in the same
+// L-level grid (dense indexing where (N_l + 1)^3 fits the table, the Instant-NGP spatial
+// hash otherwise) with trilinear interpolation; the features of the entry and exit points
+// are concatenated (point, sample, level, feature) and fed to the MLP (Methodology: the
+// network predicts hit, distance, normal, albedo and material).
+//
+// Precision.  The sin/cos samples and the grid position S * N_l are formed in FP64 (one FP32
+// ulp of a sample moves a finest-level position by N_l / 2^24, which the interpolation turns
+// into a relative feature error of ~1e-4); interpolation weights, features and the MLP run in
+// FP32, or BF16/FP16 MFMA with FP32 accumulation.  sin/cos of 2^k x come from one FP64
+// sincos and the double-angle recurrence.
+//
+// MLP on MFMA (v_mfma_f32_16x16x{4f32,16bf16_1k,16f16}).  The wave evaluates 16*CB
+// segments at a time in transposed form: out^T[n_out x segs] = W[n_out x n_in] x in^T.
+// Weights are the A operand (rows = output neurons), activations the B operand (columns =
+// segments).  The 16x16 result tile of lane l holds neurons 4(l/16)+r, r < 4, of segment
+// l%16, which is exactly the B-operand layout of the next layer's K-block, so hidden layers
+// chain in registers.  For the first layer each lane computes the features the B operand
+// needs: lane quarter q = l/16 evaluates levels [q L/4, (q+1) L/4) of segment l%16.
+#pragma once
+#include "nif_device.hpp"
+
+namespace nif {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+
+enum { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
+constexpr int kMaxLayers = 10;
+constexpr int kSegStride = 8;    // LDS floats per segment: x0 (3), pad, x1 (3), pad
+constexpr int kZStride = 17;     // LDS floats per segment of head outputs (16 + pad)
+
+struct EncParams {
+    const void* tab;        // [L][T][2] FP32 or FP16
+    int32_t f16;
+    int32_t L, log2T, F;
+    int32_t res[16];
+    uint32_t dense_mask;    // bit l: level l indexed densely
+};
+
+struct NetParams {
+    EncParams enc;
+    const void* W[kMaxLayers];   // padded weights in the MLP precision, row-major [out][in]
+    const float* b[kMaxLayers];  // padded FP32 biases
+    int32_t n_hidden;            // hidden layers
+    int32_t E;                   // encoding width (both points)
+    int32_t H;                   // real head count
+};
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int PREC>
+__device__ __forceinline__ shortx4 pack4(float a, float b, float c, float d) {
+    shortx4 r;
+    if constexpr (PREC == P_BF16) {
+        r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
+    } else {
+        _Float16 h0 = (_Float16)a, h1 = (_Float16)b, h2 = (_Float16)c, h3 = (_Float16)d;
+        r[0] = __builtin_bit_cast(short, h0); r[1] = __builtin_bit_cast(short, h1);
+        r[2] = __builtin_bit_cast(short, h2); r[3] = __builtin_bit_cast(short, h3);
+    }
+    return r;
+}
+
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma16(shortx4 a, shortx4 b, floatx4 c) {
+    if constexpr (PREC == P_BF16) return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(halfx4, a), __builtin_bit_cast(halfx4, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 mfma32(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Grid cell and FP32 weights of one sample coordinate at resolution N.
+__device__ __forceinline__ void grid_axis(double s, int N, uint32_t& i0, float& w) {
+    double pos = s * (double)N;
+    double f = floor(pos);
+    f = fmin(fmax(f, 0.0), (double)(N - 1));   // samples can leave [0, 1] by an ulp
+    i0 = (uint32_t)f;
+    w = (float)(pos - f);
+}
+
+__device__ __forceinline__ uint32_t grid_index(uint32_t vx, uint32_t vy, uint32_t vz, uint32_t n1, bool dense,
+                                               uint32_t mask) {
+    uint32_t hd = vx + n1 * (vy + n1 * vz);
+    uint32_t hh = (vx ^ (vy * 2654435761u) ^ (vz * 805459861u)) & mask;
+    return dense ? hd : hh;
+}
+
+// Trilinearly interpolated 2-feature entry of level l at sample (sx, sy, sz).
+__device__ __forceinline__ float2 grid_lookup(const EncParams& ep, int l, double sx, double sy, double sz) {
+    const int N = ep.res[l];
+    const bool dense = (ep.dense_mask >> l) & 1u;
+    const uint32_t n1 = (uint32_t)N + 1u, mask = (1u << ep.log2T) - 1u;
+    uint32_t ix, iy, iz;
+    float wx, wy, wz;
+    grid_axis(sx, N, ix, wx);
+    grid_axis(sy, N, iy, wy);
+    grid_axis(sz, N, iz, wz);
+    const size_t base = (size_t)l << ep.log2T;
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+        const uint32_t idx = grid_index(ix + bx, iy + by, iz + bz, n1, dense, mask);
+        const float wt = (bx ? wx : 1.f - wx) * (by ? wy : 1.f - wy) * (bz ? wz : 1.f - wz);
+        float2 v;
+        if (ep.f16) {
+            const __half2 h = reinterpret_cast<const __half2*>(ep.tab)[base + idx];
+            v = __half22float2(h);
+        } else {
+            v = reinterpret_cast<const float2*>(ep.tab)[base + idx];
+        }
+        acc.x = fmaf(wt, v.x, acc.x);
+        acc.y = fmaf(wt, v.y, acc.y);
+    }
+    return acc;
+}
+
+// Positional-encoding state of one point coordinate triple across the samples.
+struct PEState {
+    double x[3], sn[3], cs[3];
+};
+
+__device__ __forceinline__ void pe_begin(PEState& st, float x, float y, float z) {
+    st.x[0] = fmin(fmax((double)x, 0.0), 1.0);
+    st.x[1] = fmin(fmax((double)y, 0.0), 1.0);
+    st.x[2] = fmin(fmax((double)z, 0.0), 1.0);
+}
+
+// Sample s (0..2F) of the point; must be called with s increasing from 0.
+__device__ __forceinline__ void pe_sample(PEState& st, int s, double out[3]) {
+    if (s == 0) {
+        out[0] = st.x[0]; out[1] = st.x[1]; out[2] = st.x[2];
+        return;
+    }
+    const int k = (s - 1) >> 1;
+    if ((s & 1) == 1) {             // sin sample of frequency 2^k: advance the recurrence
+        if (k == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sincos(st.x[a], &st.sn[a], &st.cs[a]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double s1 = st.sn[a], c1 = st.cs[a];
+                st.sn[a] = 2.0 * s1 * c1;
+                st.cs[a] = (c1 - s1) * (c1 + s1);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = 0.5 * (st.sn[a] + 1.0);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = 0.5 * (st.cs[a] + 1.0);
+    }
+}
+
+// ------------------------------------------------------------------ one MLP pass
+// Evaluates the network on segments [seg_base, seg_base + 16*CB) whose rest-space points sit
+// in s_seg (kSegStride floats each) and writes the 16 padded head outputs to s_z.
+// acts (nullable): hidden activations are also stored to acts[layer][seg_g0 + seg][HW].
+template <int HW, int CB, int PREC>
+__device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg, int seg_base, float* s_z,
+                                         float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid) {
+    constexpr int OB = HW / 16;
+    const int lane = lane_id();
+    const int q = lane >> 4, j = lane & 15;
+    const int L = np.enc.L, LQ = L >> 2, FQ = 2 * LQ;
+    const int S = 1 + 2 * np.enc.F;
+    const int E = np.E;
+
+    floatx4 acc[OB][CB];
+    {
+        const float* b1 = np.b[0];
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) {
+            const float4 bb = *reinterpret_cast<const float4*>(b1 + ob * 16 + 4 * q);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
+        }
+    }
+    // ---- layer 1: stream the encoding chunk by chunk (one chunk = one point and PE sample)
+    for (int p = 0; p < 2; ++p) {
+        PEState pe[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const float* sp = s_seg + (seg_base + cb * 16 + j) * kSegStride + 4 * p;
+            pe_begin(pe[cb], sp[0], sp[1], sp[2]);
+        }
+        for (int s = 0; s < S; ++s) {
+            float feat[CB][8];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                double smp[3];
+                pe_sample(pe[cb], s, smp);
+#pragma unroll
+                for (int li = 0; li < 4; ++li) {
+                    if (li < LQ) {
+                        const float2 f = grid_lookup(np.enc, q * LQ + li, smp[0], smp[1], smp[2]);
+                        feat[cb][2 * li] = f.x;
+                        feat[cb][2 * li + 1] = f.y;
+                    } else {
+                        feat[cb][2 * li] = 0.f;
+                        feat[cb][2 * li + 1] = 0.f;
+                    }
+                }
+            }
+            const int e0 = (p * S + s) * L * 2 + FQ * q;
+#pragma unroll
+            for (int ob = 0; ob < OB; ++ob) {
+                if constexpr (PREC == P_FP32) {
+                    const float* w = reinterpret_cast<const float*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0;
+                    float wf[8];
+                    const float4 w0 = *reinterpret_cast<const float4*>(w);
+                    wf[0] = w0.x; wf[1] = w0.y; wf[2] = w0.z; wf[3] = w0.w;
+                    if (FQ == 8) {
+                        const float4 w1 = *reinterpret_cast<const float4*>(w + 4);
+                        wf[4] = w1.x; wf[5] = w1.y; wf[6] = w1.z; wf[7] = w1.w;
+                    } else {
+                        wf[4] = wf[5] = wf[6] = wf[7] = 0.f;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        if (t < FQ) {
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(wf[t], feat[cb][t], acc[ob][cb]);
+                        }
+                    }
+                } else {
+                    const shortx4* w = reinterpret_cast<const shortx4*>(
+                        reinterpret_cast<const uint16_t*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        if (4 * t < FQ) {
+                            const shortx4 wa = w[t];
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) {
+                                const shortx4 fb = pack4<PREC>(feat[cb][4 * t], feat[cb][4 * t + 1], feat[cb][4 * t + 2],
+                                                               feat[cb][4 * t + 3]);
+                                acc[ob][cb] = mfma16<PREC>(wa, fb, acc[ob][cb]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // ---- hidden layers 2..n_hidden, output layer
+    for (int layer = 1; layer <= np.n_hidden; ++layer) {
+        // ReLU of the previous layer's outputs (and optional store)
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[ob][cb][r] = fmaxf(acc[ob][cb][r], 0.f);
+                if (acts) {
+                    const int64_t seg = seg_g0 + cb * 16 + j;
+                    if (seg < n_valid) {
+                        float* dst = acts + (int64_t)(layer - 1) * act_stride_layer + seg * HW + ob * 16 + 4 * q;
+                        *reinterpret_cast<float4*>(dst) = make_float4(acc[ob][cb][0], acc[ob][cb][1], acc[ob][cb][2], acc[ob][cb][3]);
+                    }
+                }
+            }
+        const bool is_out = layer == np.n_hidden;
+        if (!is_out) {
+            floatx4 nxt[OB][CB];
+            const float* bl = np.b[layer];
+#pragma unroll
+            for (int ob = 0; ob < OB; ++ob) {
+                const float4 bb = *reinterpret_cast<const float4*>(bl + ob * 16 + 4 * q);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) nxt[ob][cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
+            }
+#pragma unroll
+            for (int oo = 0; oo < OB; ++oo)
+#pragma unroll
+                for (int ob = 0; ob < OB; ++ob) {
+                    if constexpr (PREC == P_FP32) {
+                        const float4 wv = *reinterpret_cast<const float4*>(
+                            reinterpret_cast<const float*>(np.W[layer]) + (size_t)(oo * 16 + j) * HW + ob * 16 + 4 * q);
+                        const float wf[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) nxt[oo][cb] = mfma32(wf[r], acc[ob][cb][r], nxt[oo][cb]);
+                    } else {
+                        const shortx4 wa = *reinterpret_cast<const shortx4*>(
+                            reinterpret_cast<const uint16_t*>(np.W[layer]) + (size_t)(oo * 16 + j) * HW + ob * 16 + 4 * q);
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const shortx4 hb = pack4<PREC>(acc[ob][cb][0], acc[ob][cb][1], acc[ob][cb][2], acc[ob][cb][3]);
+                            nxt[oo][cb] = mfma16<PREC>(wa, hb, nxt[oo][cb]);
+                        }
+                    }
+                }
+#pragma unroll
+            for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = nxt[ob][cb];
+        } else {
+            floatx4 out[CB];
+            const float4 bb = *reinterpret_cast<const float4*>(np.b[layer] + 4 * q);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) out[cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+            for (int ob = 0; ob < OB; ++ob) {
+                if constexpr (PREC == P_FP32) {
+                    const float4 wv = *reinterpret_cast<const float4*>(
+                        reinterpret_cast<const float*>(np.W[layer]) + (size_t)j * HW + ob * 16 + 4 * q);
+                    const float wf[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) out[cb] = mfma32(wf[r], acc[ob][cb][r], out[cb]);
+                } else {
+                    const shortx4 wa = *reinterpret_cast<const shortx4*>(
+                        reinterpret_cast<const uint16_t*>(np.W[layer]) + (size_t)j * HW + ob * 16 + 4 * q);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const shortx4 hb = pack4<PREC>(acc[ob][cb][0], acc[ob][cb][1], acc[ob][cb][2], acc[ob][cb][3]);
+                        out[cb] = mfma16<PREC>(wa, hb, out[cb]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s_z[(seg_base + cb * 16 + j) * kZStride + 4 * q + r] = out[cb][r];
+        }
+    }
+}
+
+// Make this wave's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace nif

@@ -1,0 +1,484 @@
+// Query-side kernels: segment tracing, the fused first-hit query, the voxel proxy, and the
+// network on given rest-space points.
+//
+// The fused query (Methodology; "Segmented Ray Distance Accumulation") is one persistent
+// kernel.  Every lane owns a ray; a wave takes rays from a global counter (one atomic per
+// wave, rays of all poses in one index space).  Each round, every lane finds its ray's next
+// occupied deformed voxel, maps the voxel's entry/exit points to rest space, and the wave
+// evaluates encoding + MLP for all 64 segments together on MFMA.  A lane whose hit logit is
+// positive writes the ray's result and takes a new ray; the others continue front to back.
+// Lanes whose rays miss everything take new rays before the network round, so the MFMA
+// tiles stay full while rays last.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "nif_internal.hpp"
+#include "nif_net.hpp"
+#include "nif_trace.hpp"
+
+namespace nif {
+
+struct GridArgs {
+    const PoseDev* poses;
+    const float4* V;
+    const int32_t* bin_start;
+    const int32_t* bin_cells;
+    int32_t N;
+};
+
+struct RayArgs {
+    const float *ox, *oy, *oz, *dx, *dy, *dz;
+    const int64_t* off;
+    int32_t n_poses;
+    int64_t n;
+};
+
+__device__ __forceinline__ Ray load_ray(const RayArgs& R, int64_t r) {
+    Ray ray;
+    ray.o = make_float3(R.ox[r], R.oy[r], R.oz[r]);
+    ray.d = make_float3(R.dx[r], R.dy[r], R.dz[r]);
+    return ray;
+}
+
+__device__ __forceinline__ float3 ray_at(const Ray& R, float t) {
+    return make_float3(fmaf(t, R.d.x, R.o.x), fmaf(t, R.d.y, R.o.y), fmaf(t, R.d.z, R.o.z));
+}
+
+__global__ void k_reset(int64_t* counters, int n) {
+    if (threadIdx.x < n) counters[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------------ segments of every ray
+
+__global__ void __launch_bounds__(256) k_trace(GridArgs G, RayArgs R, int32_t max_seg, nif_segments out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R.n; r += (int64_t)gridDim.x * blockDim.x) {
+        const Ray ray = load_ray(R, r);
+        const PoseDev P = G.poses[find_pose(R.off, R.n_poses, r)];
+        Trav tv;
+        trav_init(P, ray, tv);
+        Segment sg;
+        int bad = 0, n = 0;
+        const int64_t total = R.n * (int64_t)max_seg;
+        while (next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad)) {
+            if (n < max_seg) {
+                const int64_t k = r * max_seg + n;
+                if (out.cell) out.cell[k] = sg.cell;
+                if (out.t_in) out.t_in[k] = sg.a;
+                if (out.t_out) out.t_out[k] = sg.b;
+                if (out.x0 || out.x1) {
+                    const float3 x0 = deform_inv(P, ray_at(ray, sg.a));
+                    const float3 x1 = deform_inv(P, ray_at(ray, sg.b));
+                    if (out.x0) { out.x0[k] = x0.x; out.x0[total + k] = x0.y; out.x0[2 * total + k] = x0.z; }
+                    if (out.x1) { out.x1[k] = x1.x; out.x1[total + k] = x1.y; out.x1[2 * total + k] = x1.z; }
+                }
+            }
+            ++n;
+        }
+        if (out.count) out.count[r] = n;
+    }
+}
+
+// ------------------------------------------------------------------ outputs of one ray
+
+__device__ __forceinline__ void write_miss(const nif_hits& o, int64_t r, int nq, float last_z0) {
+    if (o.hit) o.hit[r] = 0;
+    if (o.t) o.t[r] = INFINITY;
+    if (o.nx) o.nx[r] = 0.f;
+    if (o.ny) o.ny[r] = 0.f;
+    if (o.nz) o.nz[r] = 0.f;
+    if (o.ar) o.ar[r] = 0.f;
+    if (o.ag) o.ag[r] = 0.f;
+    if (o.ab) o.ab[r] = 0.f;
+    if (o.material) o.material[r] = -1;
+    if (o.cell) o.cell[r] = -1;
+    if (o.hit_logit) o.hit_logit[r] = last_z0;
+    if (o.n_queried) o.n_queried[r] = nq;
+    if (o.xr) o.xr[r] = 0.f;
+    if (o.yr) o.yr[r] = 0.f;
+    if (o.zr) o.zr[r] = 0.f;
+}
+
+__device__ __forceinline__ float sigmoidf_(float v) { return 1.f / (1.f + expf(-v)); }
+
+__device__ __forceinline__ void write_hit(const nif_hits& o, int64_t r, const Segment& sg, float3 x0, float3 x1,
+                                          const float* z, int nq, int n_mat) {
+    const float ex = x1.x - x0.x, ey = x1.y - x0.y, ez = x1.z - x0.z;
+    const float lr = sqrtf(ex * ex + ey * ey + ez * ez);
+    const float dh = fmaxf(z[1], 0.f);
+    const float f = lr > 0.f ? fminf(fmaxf(dh / lr, 0.f), 1.f) : 0.f;
+    if (o.hit) o.hit[r] = 1;
+    if (o.t) o.t[r] = fmaf(f, sg.b - sg.a, sg.a);
+    const float nl = fmaxf(sqrtf(z[2] * z[2] + z[3] * z[3] + z[4] * z[4]), 1e-12f);
+    if (o.nx) o.nx[r] = z[2] / nl;
+    if (o.ny) o.ny[r] = z[3] / nl;
+    if (o.nz) o.nz[r] = z[4] / nl;
+    if (o.ar) o.ar[r] = sigmoidf_(z[5]);
+    if (o.ag) o.ag[r] = sigmoidf_(z[6]);
+    if (o.ab) o.ab[r] = sigmoidf_(z[7]);
+    if (o.material) {
+        int best = 0;
+        if (n_mat == 1) best = z[8] > 0.f ? 1 : 0;
+        else
+            for (int c = 1; c < n_mat; ++c)
+                if (z[8 + c] > z[8 + best]) best = c;
+        o.material[r] = best;
+    }
+    if (o.cell) o.cell[r] = sg.cell;
+    if (o.hit_logit) o.hit_logit[r] = z[0];
+    if (o.n_queried) o.n_queried[r] = nq;
+    if (o.xr) o.xr[r] = fmaf(f, ex, x0.x);
+    if (o.yr) o.yr[r] = fmaf(f, ey, x0.y);
+    if (o.zr) o.zr[r] = fmaf(f, ez, x0.z);
+}
+
+__device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t a, int64_t b, int64_t c) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    if (lane_id() == 0) {
+        atomicAdd((unsigned long long*)&stats[0], (unsigned long long)a);
+        atomicAdd((unsigned long long*)&stats[1], (unsigned long long)b);
+        atomicAdd((unsigned long long*)&stats[2], (unsigned long long)c);
+    }
+}
+
+// ------------------------------------------------------------------ fused first-hit query
+
+template <int HW, int PREC>
+__global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
+                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats) {
+    constexpr int CB = HW >= 128 ? 2 : 4;
+    constexpr int PASSES = 4 / CB;
+    __shared__ float s_seg_all[4][64 * kSegStride];
+    __shared__ float s_z_all[4][64 * kZStride];
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    float* s_seg = s_seg_all[w];
+    float* s_z = s_z_all[w];
+    const int n_mat = np.H - 8;
+
+    int64_t r = -1;
+    bool exhausted = false, has = false;
+    Ray ray;
+    ray.o = ray.d = make_float3(0.f, 0.f, 0.f);
+    Trav tv;
+    tv.active = 0;
+    PoseDev P;
+    P.kind = 0;
+    Segment sg;
+    sg.cell = -1; sg.a = sg.b = 0.f; sg.face = -1;
+    int nq = 0, bad = 0;
+    float last_z0 = -INFINITY;
+    int64_t n_done = 0, n_eval = 0;
+
+    for (;;) {
+        // ---- give every lane a segment, taking new rays as old ones finish or miss
+        for (;;) {
+            const bool need = !exhausted && r < 0;
+            const uint64_t m = ballot(need);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd((unsigned long long*)&counters[0], (unsigned long long)popc64(m));
+                base = __shfl(base, leader);
+                if (need) {
+                    r = (int64_t)base + rank_below(m);
+                    if (r >= R.n) {
+                        r = -1;
+                        exhausted = true;
+                    } else {
+                        ray = load_ray(R, r);
+                        P = G.poses[find_pose(R.off, R.n_poses, r)];
+                        trav_init(P, ray, tv);
+                        nq = 0;
+                        last_z0 = -INFINITY;
+                    }
+                }
+            }
+            const bool search = r >= 0 && !has;
+            if (!ballot(search)) break;
+            if (search) {
+                has = next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad);
+                if (!has) {
+                    write_miss(out, r, nq, last_z0);
+                    r = -1;
+                    ++n_done;
+                }
+            }
+        }
+        if (!ballot(has)) break;
+        // ---- rest-space entry/exit points (local linearization inside the voxel)
+        float3 x0 = make_float3(0.5f, 0.5f, 0.5f), x1 = x0;
+        if (has) {
+            x0 = deform_inv(P, ray_at(ray, sg.a));
+            x1 = deform_inv(P, ray_at(ray, sg.b));
+        }
+        float* my = s_seg + lane * kSegStride;
+        my[0] = x0.x; my[1] = x0.y; my[2] = x0.z;
+        my[4] = x1.x; my[5] = x1.y; my[6] = x1.z;
+        wave_lds_sync();
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
+        wave_lds_sync();
+        if (has) {
+            ++nq;
+            ++n_eval;
+            const float* z = s_z + lane * kZStride;
+            last_z0 = z[0];
+            if (z[0] > 0.f) {
+                write_hit(out, r, sg, x0, x1, z, nq, n_mat);
+                r = -1;
+                ++n_done;
+            }
+            has = false;
+        }
+        wave_lds_sync();
+    }
+    if (stats) wave_add_stats(stats, n_done, n_eval, bad);
+}
+
+// ------------------------------------------------------------------ voxel proxy (no network)
+// The first occupied voxel is the hit: D = t_in, rest point D^-1(entry), normal = outward
+// rest-space normal of the entered face.
+
+__global__ void __launch_bounds__(256) k_proxy(GridArgs G, RayArgs R, nif_hits out, int64_t* __restrict__ stats) {
+    int64_t n_done = 0;
+    int bad = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R.n; r += (int64_t)gridDim.x * blockDim.x) {
+        const Ray ray = load_ray(R, r);
+        const PoseDev P = G.poses[find_pose(R.off, R.n_poses, r)];
+        Trav tv;
+        trav_init(P, ray, tv);
+        Segment sg;
+        if (next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad)) {
+            const float3 x0 = deform_inv(P, ray_at(ray, sg.a));
+            float z[16];
+            for (int i = 0; i < 16; ++i) z[i] = 0.f;
+            z[0] = 1.f;
+            // the face normal enters the outputs as z_n; the distance head is 0 so D = t_in
+            if (sg.face >= 0) z[2 + (sg.face >> 1)] = (sg.face & 1) ? 1.f : -1.f;
+            write_hit(out, r, sg, x0, x0, z, 1, 1);
+            if (out.ar) out.ar[r] = 0.f;
+            if (out.ag) out.ag[r] = 0.f;
+            if (out.ab) out.ab[r] = 0.f;
+            if (out.material) out.material[r] = 0;
+        } else {
+            write_miss(out, r, 0, -INFINITY);
+        }
+        ++n_done;
+    }
+    if (stats) {
+        int64_t a = n_done, c = bad;
+        for (int off = 32; off > 0; off >>= 1) { a += __shfl_xor(a, off); c += __shfl_xor(c, off); }
+        if (lane_id() == 0) {
+            atomicAdd((unsigned long long*)&stats[0], (unsigned long long)a);
+            atomicAdd((unsigned long long*)&stats[2], (unsigned long long)c);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ network on given points
+
+// Full encoding of n points (lane per point): out[i][(s L + l) 2 + f].
+__global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __restrict__ x, int64_t n,
+                                                float* __restrict__ out) {
+    const int S = 1 + 2 * ep.F;
+    const int W = S * ep.L * 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        PEState pe;
+        pe_begin(pe, x[i], x[n + i], x[2 * n + i]);
+        for (int s = 0; s < S; ++s) {
+            double smp[3];
+            pe_sample(pe, s, smp);
+            for (int l = 0; l < ep.L; ++l) {
+                const float2 f = grid_lookup(ep, l, smp[0], smp[1], smp[2]);
+                out[i * W + (s * ep.L + l) * 2] = f.x;
+                out[i * W + (s * ep.L + l) * 2 + 1] = f.y;
+            }
+        }
+    }
+}
+
+// Heads of point pairs.  Each wave evaluates tiles of 64 pairs; acts (nullable) receives the
+// hidden activations [layer][B][HW] for the training backward.
+template <int HW, int PREC>
+__global__ void __launch_bounds__(256) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
+                                                 int64_t B, float* __restrict__ heads, float* __restrict__ acts) {
+    constexpr int CB = HW >= 128 ? 2 : 4;
+    constexpr int PASSES = 4 / CB;
+    __shared__ float s_seg_all[4][64 * kSegStride];
+    __shared__ float s_z_all[4][64 * kZStride];
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    float* s_seg = s_seg_all[w];
+    float* s_z = s_z_all[w];
+    const int64_t n_tiles = (B + 63) / 64;
+    const int64_t wave_g = (int64_t)blockIdx.x * 4 + w, n_waves = (int64_t)gridDim.x * 4;
+    for (int64_t tile = wave_g; tile < n_tiles; tile += n_waves) {
+        const int64_t seg = tile * 64 + lane;
+        float* my = s_seg + lane * kSegStride;
+        if (seg < B) {
+            my[0] = x0[seg]; my[1] = x0[B + seg]; my[2] = x0[2 * B + seg];
+            my[4] = x1[seg]; my[5] = x1[B + seg]; my[6] = x1[2 * B + seg];
+        } else {
+            my[0] = my[1] = my[2] = my[4] = my[5] = my[6] = 0.5f;
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps)
+            net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * 64 + ps * 16 * CB, B);
+        wave_lds_sync();
+        if (seg < B)
+            for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
+        wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------------------ host launchers
+
+static int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+NetParams make_net_params(const nif_model* m, int32_t precision) {
+    NetParams np;
+    memset(&np, 0, sizeof(np));
+    const nif_model_desc& d = m->desc;
+    np.enc.tab = d.table_dtype == NIF_TABLE_F16 ? (const void*)m->tables_h : (const void*)m->tables;
+    np.enc.f16 = d.table_dtype == NIF_TABLE_F16;
+    np.enc.L = d.levels;
+    np.enc.log2T = d.log2_table;
+    np.enc.F = d.pe_freqs;
+    np.enc.dense_mask = 0;
+    for (int l = 0; l < d.levels; ++l) {
+        np.enc.res[l] = d.res[l];
+        const uint64_t n1 = (uint64_t)d.res[l] + 1;
+        if (n1 * n1 * n1 <= (1ull << d.log2_table)) np.enc.dense_mask |= 1u << l;
+    }
+    for (int i = 0; i < m->n_layers; ++i) {
+        if (precision == NIF_PREC_FP32) np.W[i] = m->mlp_pad_f32 + m->wp_off[i];
+        else if (precision == NIF_PREC_BF16) np.W[i] = m->mlp_pad_bf16 + m->wp_off[i];
+        else np.W[i] = m->mlp_pad_f16 + m->wp_off[i];
+        np.b[i] = m->mlp_pad_f32 + m->bp_off[i];
+    }
+    np.n_hidden = d.hidden_layers;
+    np.E = m->E;
+    np.H = m->H;
+    return np;
+}
+
+static GridArgs grid_args(const nif_grid* g) {
+    GridArgs G;
+    G.poses = g->poses; G.V = g->verts; G.bin_start = g->bin_start; G.bin_cells = g->bin_cells; G.N = g->N;
+    return G;
+}
+
+static RayArgs ray_args(const nif_grid* g, const nif_rays* r, int64_t n) {
+    RayArgs R;
+    R.ox = r->ox; R.oy = r->oy; R.oz = r->oz; R.dx = r->dx; R.dy = r->dy; R.dz = r->dz;
+    R.off = r->pose_offsets; R.n_poses = g->n_poses; R.n = n;
+    return R;
+}
+
+int trace_launch(const nif_grid* g, const nif_rays* r, int64_t n, int32_t max_seg, const nif_segments* out,
+                 hipStream_t st) {
+    if (n == 0) return NIF_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL(k_trace, dim3((unsigned)blocks), dim3(256), 0, st, grid_args(g), ray_args(g, r, n), max_seg, *out);
+    return check_hip(hipGetLastError(), "k_trace launch");
+}
+
+template <int HW, int PREC>
+static void launch_query(const NetParams& np, const GridArgs& G, const RayArgs& R, const nif_hits& out, int64_t* ctr,
+                         int64_t* stats, hipStream_t st) {
+    const int64_t waves = (R.n + 63) / 64;
+    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, (int64_t)device_cus() * 8);
+    hipLaunchKernelGGL((k_query<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, G, R, out, ctr, stats);
+}
+
+template <int PREC>
+static int dispatch_query(int hw, const NetParams& np, const GridArgs& G, const RayArgs& R, const nif_hits& out,
+                          int64_t* ctr, int64_t* stats, hipStream_t st) {
+    switch (hw) {
+        case 16: launch_query<16, PREC>(np, G, R, out, ctr, stats, st); break;
+        case 32: launch_query<32, PREC>(np, G, R, out, ctr, stats, st); break;
+        case 64: launch_query<64, PREC>(np, G, R, out, ctr, stats, st); break;
+        case 128: launch_query<128, PREC>(np, G, R, out, ctr, stats, st); break;
+        default: return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
+    }
+    return NIF_OK;
+}
+
+int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64_t n, const nif_hits* out,
+                 uint32_t flags, int32_t precision, int64_t* stats, hipStream_t st) {
+    if (n == 0) return NIF_OK;
+    const GridArgs G = grid_args(g);
+    const RayArgs R = ray_args(g, r, n);
+    if (flags & NIF_Q_NO_NETWORK) {
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)device_cus() * 16);
+        hipLaunchKernelGGL(k_proxy, dim3((unsigned)blocks), dim3(256), 0, st, G, R, *out, stats);
+        return check_hip(hipGetLastError(), "k_proxy launch");
+    }
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, m->counters, 4);
+    int rc;
+    const NetParams np = make_net_params(m, precision);
+    const int hw = m->desc.hidden_width;
+    if (precision == NIF_PREC_FP32) rc = dispatch_query<P_FP32>(hw, np, G, R, *out, m->counters, stats, st);
+    else if (precision == NIF_PREC_BF16) rc = dispatch_query<P_BF16>(hw, np, G, R, *out, m->counters, stats, st);
+    else rc = dispatch_query<P_FP16>(hw, np, G, R, *out, m->counters, stats, st);
+    if (rc) return rc;
+    return check_hip(hipGetLastError(), "k_query launch");
+}
+
+int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st) {
+    if (n == 0) return NIF_OK;
+    const NetParams np = make_net_params(m, NIF_PREC_FP32);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL(k_encode, dim3((unsigned)blocks), dim3(256), 0, st, np.enc, x, n, out);
+    return check_hip(hipGetLastError(), "k_encode launch");
+}
+
+template <int HW, int PREC>
+static void launch_forward(const NetParams& np, const float* x0, const float* x1, int64_t B, float* heads, float* acts,
+                           hipStream_t st) {
+    const int64_t tiles = (B + 63) / 64;
+    const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cus() * 8);
+    hipLaunchKernelGGL((k_forward<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts);
+}
+
+template <int PREC>
+static int dispatch_forward(int hw, const NetParams& np, const float* x0, const float* x1, int64_t B, float* heads,
+                            float* acts, hipStream_t st) {
+    switch (hw) {
+        case 16: launch_forward<16, PREC>(np, x0, x1, B, heads, acts, st); break;
+        case 32: launch_forward<32, PREC>(np, x0, x1, B, heads, acts, st); break;
+        case 64: launch_forward<64, PREC>(np, x0, x1, B, heads, acts, st); break;
+        case 128: launch_forward<128, PREC>(np, x0, x1, B, heads, acts, st); break;
+        default: return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
+    }
+    return NIF_OK;
+}
+
+int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads, int32_t precision,
+                   float* acts, hipStream_t st) {
+    if (B == 0) return NIF_OK;
+    const NetParams np = make_net_params(m, precision);
+    const int hw = m->desc.hidden_width;
+    int rc;
+    if (precision == NIF_PREC_FP32) rc = dispatch_forward<P_FP32>(hw, np, x0, x1, B, heads, acts, st);
+    else if (precision == NIF_PREC_BF16) rc = dispatch_forward<P_BF16>(hw, np, x0, x1, B, heads, acts, st);
+    else rc = dispatch_forward<P_FP16>(hw, np, x0, x1, B, heads, acts, st);
+    if (rc) return rc;
+    return check_hip(hipGetLastError(), "k_forward launch");
+}
+
+}  // namespace nif

@@ -1,0 +1,94 @@
+"""The C-ABI library loads and exports every symbol include/nif.h declares, and its host-side
+argument validation rejects bad input before touching the device (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nif.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nif_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2604_24666_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2604_24666_amd import build
+        build.build()
+    return P
+
+
+def test_every_declared_symbol_is_exported(P):
+    L = C.CDLL(P.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings(P):
+    L = P.lib()
+    assert L.nif_status_string(0) == b"ok"
+    assert L.nif_status_string(1) == b"invalid argument"
+    assert L.nif_version() >= 1
+
+
+def _desc(P, **kw):
+    a = dict(levels=8, log2_table=14, feat_dim=2, table_dtype=0, res=[16, 24, 35, 53, 78, 116, 172, 256],
+             pe_freqs=6, hidden_width=64, hidden_layers=2, n_materials=1)
+    a.update(kw)
+    return P.model_desc(**a)
+
+
+def test_model_sizes_match_the_canonical_layout(P):
+    nt, nm = P.nif_model_sizes(_desc(P))
+    assert nt == 8 * 2 ** 14 * 2
+    assert nm == (416 * 64 + 64) + (64 * 64 + 64) + (64 * 9 + 9)
+    nt, nm = P.nif_model_sizes(_desc(P, levels=16, log2_table=19, res=[16] * 16, hidden_width=128,
+                                     hidden_layers=4, n_materials=4))
+    assert nm == (832 * 128 + 128) + 3 * (128 * 128 + 128) + (128 * 12 + 12)
+
+
+@pytest.mark.parametrize("kw,code", [(dict(feat_dim=3), 1), (dict(levels=6), 1), (dict(log2_table=30), 1),
+                                     (dict(hidden_width=48), 2), (dict(hidden_layers=0), 1),
+                                     (dict(n_materials=0), 1), (dict(table_dtype=7), 1),
+                                     (dict(res=[0] * 8), 1), (dict(pe_freqs=-1), 1)])
+def test_bad_model_descriptions_are_rejected(P, kw, code):
+    L = P.lib()
+    d = _desc(P, **kw)
+    rc = L.nif_model_sizes(C.byref(d), None, None)
+    assert rc == code
+    assert L.nif_last_error()
+
+
+def test_bad_grid_arguments_are_rejected_on_the_host(P):
+    L = P.lib()
+    poses = (P.Pose * 1)(P.Pose(1, 0.5))
+    h = C.c_void_p()
+    assert L.nif_build_grid(None, 16, poses, 1, 0, C.byref(h), None) == 1           # null occupancy
+    dummy = C.c_void_p(1)
+    assert L.nif_build_grid(dummy, 0, poses, 1, 0, C.byref(h), None) == 1           # N = 0
+    bad = (P.Pose * 1)(P.Pose(9, 0.5))
+    assert L.nif_build_grid(dummy, 16, bad, 1, 0, C.byref(h), None) == 1            # unknown kind
+    bad = (P.Pose * 1)(P.Pose(3, 1.5))
+    assert L.nif_build_grid(dummy, 16, bad, 1, 0, C.byref(h), None) == 1            # strength > 1
+    assert L.nif_build_grid(dummy, 16, poses, 0, 0, C.byref(h), None) == 1          # no poses
+
+
+def test_bad_query_arguments_are_rejected_on_the_host(P):
+    L = P.lib()
+    hits = P.Hits()
+    rays = P.Rays()
+    g = C.c_void_p(1)
+    assert L.nif_query(None, None, C.byref(rays), 4, C.byref(hits), 0, 0, None, None) == 1   # null grid
+    assert L.nif_query(None, g, C.byref(rays), 4, C.byref(hits), 0, 0, None, None) == 1      # null ray arrays
+    assert L.nif_query(None, g, C.byref(rays), -1, C.byref(hits), 0, 0, None, None) == 1     # negative count
+    assert L.nif_query(None, g, C.byref(rays), 0, C.byref(hits), 0, 7, None, None) == 1      # bad precision
+    assert L.nif_query(None, g, C.byref(rays), 0, C.byref(hits), 0x40, 0, None, None) == 1   # unknown flag
+    assert L.nif_query(None, g, C.byref(rays), 0, C.byref(hits), 0, 0, None, None) == 1      # null model

@@ -1,0 +1,138 @@
+"""GPU parity of the geometry stage (voxelization, deformed lattice, bin-grid traversal,
+entry/exit points, inverse deformation) against the FP64 oracle on the same inputs.
+
+Bar: voxel hit lists bit-exact on every non-grazing ray; t_in/t_out within 1e-5; rest-space
+entry/exit points within 1e-6 (FP32 geometry vs FP64)."""
+import numpy as np
+import pytest
+
+import nif_synth as S
+from _helpers import dev_f32, offsets, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2604_24666_amd as P
+    return P
+
+
+def _compare_trace(orc, P, N, occ, kind, s, o, d, max_seg=96, brute=True):
+    import torch
+    grid = P.Grid(torch.as_tensor(occ).cuda(), N, [kind], [s])
+    out = grid.trace(dev_f32(o), dev_f32(d), offsets([o.shape[1]]), max_seg=max_seg)
+    torch.cuda.synchronize()
+    cnt = out["count"].cpu().numpy()
+    cell = out["cell"].cpu().numpy()
+    tin = out["t_in"].cpu().numpy().astype(np.float64)
+    tout = out["t_out"].cpu().numpy().astype(np.float64)
+    x0 = out["x0"].cpu().numpy().astype(np.float64)
+    x1 = out["x1"].cpu().numpy().astype(np.float64)
+    V = orc.lattice_vertices(kind, float(np.float32(s)), N)
+    rc, rtin, rtout, rcnt, fl = orc.trace(N, occ, V, o, d, brute=brute, max_out=max_seg)
+    ok = fl == 0
+    say(f"  rays {len(cnt)}  grazing {int((~ok).sum())}  with segments {int((rcnt > 0).sum())}")
+    assert np.array_equal(cnt[ok], rcnt[ok]), np.nonzero((cnt != rcnt) & ok)[0][:10]
+    assert cnt.max() <= max_seg
+    n_seg = 0
+    o64 = o.T.astype(np.float64)
+    d64 = d.T.astype(np.float64)
+    s64 = float(np.float32(s))
+    for r in np.nonzero(ok & (rcnt > 0))[0]:
+        k = rcnt[r]
+        assert np.array_equal(cell[r, :k], rc[r, :k]), (r, cell[r, :k], rc[r, :k])
+        assert np.abs(tin[r, :k] - rtin[r, :k]).max() <= 1e-5
+        assert np.abs(tout[r, :k] - rtout[r, :k]).max() <= 1e-5
+        ref0 = orc.deform_inv(kind, s64, o64[r] + rtin[r, :k, None] * d64[r])
+        ref1 = orc.deform_inv(kind, s64, o64[r] + rtout[r, :k, None] * d64[r])
+        assert np.abs(x0[:, r, :k].T - ref0).max() <= 1e-6
+        assert np.abs(x1[:, r, :k].T - ref1).max() <= 1e-6
+        n_seg += k
+    return n_seg
+
+
+@pytest.mark.parametrize("name,N", [("torus16", 16), ("spheres64", 64), ("blobs128", 40)])
+def test_voxelization_matches_oracle(orc, P, name, N):
+    import torch
+    w = S.workload(name)
+    sp = S.scene_params(w.scene_kind, w.seed)
+    say(f"voxelize {name} N={N}")
+    ref = orc.voxelize(w.scene_kind, sp, N)
+    occ = torch.zeros(N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, N, occ)
+    got = occ.cpu().numpy()
+    diff = np.nonzero(got != ref)[0]
+    # a mismatch is only allowed where the sign test is decided by a value within FP32
+    # rounding of zero on the 5^3 sub-lattice of the cell
+    g = np.stack(np.meshgrid(*[np.arange(5) / 4.0] * 3, indexing="ij"), -1).reshape(-1, 3)
+    for c in diff:
+        ijk = np.array([c % N, (c // N) % N, c // (N * N)])
+        f = orc.scene_f(w.scene_kind, sp, (ijk + g) / N)
+        assert min(abs(f.min()), abs(f.max())) < 1e-5, (name, c, f.min(), f.max())
+    assert ref.sum() > 0 and len(diff) <= max(2, 1e-4 * ref.sum())
+
+
+@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 1.0), (S.IDENTITY, 0.0),
+                                    (S.BEND, 0.05), (S.TWIST, 0.37)])
+def test_hit_lists_torus16(orc, P, kind, s):
+    w = S.workload("torus16")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    o, d = S.rays_random(4096, w.seed)
+    oi, di = S.rays_inside(1024, w.seed + 1)
+    o = np.concatenate([o, oi], axis=1)
+    d = np.concatenate([d, di], axis=1)
+    say(f"trace torus16 kind={kind} s={s}")
+    n_seg = _compare_trace(orc, P, w.N, occ, kind, s, o, d, brute=True)
+    assert n_seg > 2000
+
+
+@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 0.625), (S.TAPER, 1.0)])
+def test_hit_lists_spheres64_sampled(orc, P, kind, s):
+    w = S.workload("spheres64")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    o, d = S.rays_camera(1024, 45.0, sub=509)
+    oi, di = S.rays_inside(500, 77, lo=0.2, hi=0.8)
+    o = np.concatenate([o, oi], axis=1)
+    d = np.concatenate([d, di], axis=1)
+    say(f"trace spheres64 kind={kind} s={s} rays={o.shape[1]}")
+    n_seg = _compare_trace(orc, P, w.N, occ, kind, s, o, d, brute=False)
+    assert n_seg > 1000
+
+
+def test_multi_pose_grid_and_empty_and_degenerate_inputs(orc, P):
+    import torch
+    w = S.workload("torus16")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    kinds, strengths = [S.TWIST, S.BEND, S.TAPER], [1.0, 0.5, 0.75]
+    o, d = S.rays_random(999, 5)          # ragged split over three poses
+    counts = [400, 0, 599]
+    say("trace multi-pose torus16 with an empty pose range")
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    out = grid.trace(dev_f32(o), dev_f32(d), offsets(counts), max_seg=96)
+    cnt = out["count"].cpu().numpy()
+    cell = out["cell"].cpu().numpy()
+    start = 0
+    for p, c in enumerate(counts):
+        if c == 0:
+            continue
+        V = orc.lattice_vertices(kinds[p], float(np.float32(strengths[p])), w.N)
+        rc, _, _, rcnt, fl = orc.trace(w.N, occ, V, o[:, start:start + c], d[:, start:start + c])
+        ok = fl == 0
+        assert np.array_equal(cnt[start:start + c][ok], rcnt[ok])
+        for r in np.nonzero(ok)[0]:
+            assert np.array_equal(cell[start + r, :rcnt[r]], rc[r, :rcnt[r]])
+        start += c
+    # zero rays: a no-op
+    grid.trace(dev_f32(o[:, :0]), dev_f32(d[:, :0]), offsets([0, 0, 0]))
+    # an empty scene: every ray misses
+    empty = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    g2 = P.Grid(empty, w.N, [S.TWIST], [1.0])
+    out = g2.trace(dev_f32(o), dev_f32(d), offsets([o.shape[1]]))
+    assert int(out["count"].sum()) == 0
+    # max_seg smaller than the list: counts are still complete
+    out = grid.trace(dev_f32(o), dev_f32(d), offsets(counts), max_seg=1)
+    assert np.array_equal(out["count"].cpu().numpy(), cnt)

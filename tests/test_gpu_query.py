@@ -1,0 +1,142 @@
+"""End-to-end parity of the fused first-hit query against the oracle's query on the same
+rays, poses, tables and weights.
+
+Rays that are grazing (geometry may legitimately differ) or ambiguous (some evaluated
+segment has |hit logit| within 1e-4 of its scale |b| + sum|w||h|, far above the FP32
+error of ~1e-6 of that scale) are counted and excluded; on the rest, hit decisions,
+voxels and segment counts are exact and the continuous outputs agree within the bounds
+derived in the design doc."""
+import numpy as np
+import pytest
+
+import nif_synth as S
+from _helpers import dev_f32, model_params, offsets, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2604_24666_amd as P
+    return P
+
+
+def _grazing(orc, N, occ, kind, s, o, d):
+    V = orc.lattice_vertices(kind, s, N)
+    return orc.trace(N, occ, V, o, d, brute=N <= 16)[4] != 0
+
+
+def _compare(orc, P, m, tab_seen, prm, N, occ, kind, s, o, d, got, sl=slice(None)):
+    s64 = float(np.float32(s))
+    ref = orc.query(m, tab_seen, prm.astype(np.float64), N, occ, kind, s64, o, d)
+    graz = _grazing(orc, N, occ, kind, s64, o, d)
+    amb = ref["margin"] < 1e-4
+    ok = ~graz & ~amb
+    g = {k: v[sl] for k, v in got.items()}
+    say(f"  rays {len(ok)}  grazing {int(graz.sum())}  ambiguous {int((amb & ~graz).sum())}  "
+        f"hits {int(ref['hit'][ok].sum())}")
+    assert np.array_equal(g["hit"][ok], ref["hit"][ok])
+    assert np.array_equal(g["n_queried"][ok], ref["n_queried"][ok])
+    assert np.array_equal(g["cell"][ok], ref["cell"][ok])
+    h = ok & (ref["hit"] == 1)
+    assert np.abs(g["t"][h] - ref["t"][h]).max(initial=0) <= 1e-5 * (1 + np.abs(ref["t"][h])).max(initial=1)
+    xr = np.stack([g["xr"], g["yr"], g["zr"]], 1)
+    assert np.abs(xr[h] - ref["xrest"][h]).max(initial=0) <= 2e-6
+    nrm = np.stack([g["nx"], g["ny"], g["nz"]], 1)
+    assert np.abs(nrm[h] - ref["normal"][h]).max(initial=0) <= 1e-4
+    alb = np.stack([g["ar"], g["ag"], g["ab"]], 1)
+    assert np.abs(alb[h] - ref["albedo"][h]).max(initial=0) <= 1e-5
+    assert np.array_equal(g["material"][h], ref["material"][h])
+    miss = ok & (ref["hit"] == 0)
+    assert np.all(np.isinf(g["t"][miss])) and np.all(g["cell"][miss] == -1)
+    return int(ok.sum()), int(h.sum())
+
+
+def _np(out):
+    return {k: v.cpu().numpy().astype(np.float64) if v.dtype.is_floating_point else v.cpu().numpy()
+            for k, v in out.items()}
+
+
+@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 0.5)])
+def test_query_torus16_fp32(orc, P, kind, s):
+    import torch
+    w = S.workload("torus16")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, [kind], [s])
+    o, d = S.rays_random(4096, w.seed)
+    say(f"query torus16 kind={kind} s={s}")
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    got = _np(grid.query(model, dev_f32(o), dev_f32(d), offsets([4096]), stats=stats))
+    st = stats.cpu().numpy()
+    assert st[0] == 4096 and st[1] == got["n_queried"].sum()
+    n_ok, n_hit = _compare(orc, P, m, seen, prm, w.N, occ, kind, s, o, d, got)
+    assert n_ok > 3500 and n_hit > 200
+
+
+def test_query_voxel_proxy_is_the_first_segment(orc, P):
+    import torch
+    w = S.workload("torus16")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, [S.TWIST], [1.0])
+    o, d = S.rays_random(2048, 3)
+    say("query proxy torus16")
+    got = _np(grid.query(None, dev_f32(o), dev_f32(d), offsets([2048]), no_network=True))
+    tr = grid.trace(dev_f32(o), dev_f32(d), offsets([2048]), max_seg=4)
+    cnt = tr["count"].cpu().numpy()
+    assert np.array_equal(got["hit"], (cnt > 0).astype(np.uint8))
+    h = cnt > 0
+    assert np.array_equal(got["t"][h], tr["t_in"].cpu().numpy()[h, 0].astype(np.float64))
+    assert np.array_equal(got["cell"][h], tr["cell"].cpu().numpy()[h, 0])
+    nrm = np.stack([got["nx"], got["ny"], got["nz"]], 1)[h]
+    assert np.allclose(np.abs(nrm).sum(1), 1.0)               # an axis-aligned rest-space face normal
+
+
+def test_query_spheres64_full_workload_sampled(orc, P):
+    """The 24-pose, 24 x 1024^2-ray workload in one launch; sampled rays of several poses are
+    checked against the oracle one by one."""
+    import torch
+    w = S.workload("spheres64")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ_ref = orc.voxelize(w.scene_kind, sp, w.N)
+    occ = torch.as_tensor(occ_ref).cuda()
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    kinds, strengths = S.poses(w)
+    grid = P.Grid(occ, w.N, kinds, strengths)
+    n_pose = w.cam_res ** 2
+    say("query spheres64: 24 poses x 1024^2 rays")
+    o_all = torch.empty((3, 24 * n_pose), device="cuda")
+    d_all = torch.empty((3, 24 * n_pose), device="cuda")
+    for p in range(24):
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p])
+        o_all[:, p * n_pose:(p + 1) * n_pose] = dev_f32(o)
+        d_all[:, p * n_pose:(p + 1) * n_pose] = dev_f32(d)
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    out = grid.query(model, o_all, d_all, offsets([n_pose] * 24), stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    say(f"  rays done {st[0]}  network evaluations {st[1]}  degenerate voxel tests {st[2]}")
+    assert st[0] == 24 * n_pose
+    hit = out["hit"].cpu().numpy()
+    assert 0.01 < hit.mean() < 0.5
+    rng = np.random.default_rng(0)
+    total_ok = 0
+    for p in (0, 5, 11, 16, 23):
+        # mostly rays that touch the geometry, plus a few that do not
+        touch = np.nonzero(out["n_queried"][p * n_pose:(p + 1) * n_pose].cpu().numpy() > 0)[0]
+        idx = np.sort(np.concatenate([rng.choice(touch, 300, replace=False), rng.integers(0, n_pose, 50)]))
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p])
+        got = {k: v[p * n_pose:(p + 1) * n_pose][torch.as_tensor(idx).cuda()] for k, v in out.items()}
+        say(f"  pose {p} kind {kinds[p]} s {strengths[p]}")
+        n_ok, _ = _compare(orc, P, m, seen, prm, w.N, occ_ref, int(kinds[p]), float(strengths[p]),
+                           o[:, idx], d[:, idx], _np(got))
+        total_ok += n_ok
+    assert total_ok > 1500
