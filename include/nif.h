@@ -126,8 +126,16 @@ int nif_voxelize(int32_t scene_kind, const double* params_host, int32_t n_params
 int nif_build_grid(const uint8_t* occ_dev, int32_t N, const nif_pose* poses_host, int32_t n_poses,
                    int32_t bins_per_axis, nif_grid** out, nif_stream stream);
 int nif_grid_destroy(nif_grid* grid);
-/* Number of occupied voxels; total bin-list entries of one pose. */
-int nif_grid_info(const nif_grid* grid, int32_t pose, int64_t* n_occupied, int64_t* n_refs);
+/* Re-poses an existing grid (same occupancy, same pose count): new kinds/strengths, the
+ * lattice vertices, bounding boxes, bin sizes and bin lists are recomputed on the device.
+ * No allocation and no synchronisation.  The bin lists keep the capacity of the build plus
+ * 50%; a pose whose lists would not fit is emptied (its rays miss) and the overflow flag of
+ * nif_grid_info is set. */
+int nif_grid_update(nif_grid* grid, const nif_pose* poses_host, int32_t n_poses, nif_stream stream);
+/* Number of occupied voxels; bin-list entries of one pose at build time; overflow flag of the
+ * last build/update (reading it synchronises the null stream).  Any pointer may be NULL. */
+int nif_grid_info(const nif_grid* grid, int32_t pose, int64_t* n_occupied, int64_t* n_refs,
+                  int32_t* overflow);
 
 /* ---------------------------------------------------------------- rays
  * Deformed-space rays o + t d, grouped by pose: rays [pose_offsets[p], pose_offsets[p+1])

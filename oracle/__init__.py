@@ -143,18 +143,23 @@ def lattice_vertices(kind: int, s: float, N: int) -> np.ndarray:
 
 
 def trace(N: int, occ, V, o, d, brute: bool = False, max_out: int | None = None,
-          with_flags: bool = True):
-    """Ordered occupied hit lists.  Returns (cells[n][max_out], tin, tout, count[n], flags[n])."""
+          with_flags: bool = True, with_cos: bool = False):
+    """Ordered occupied hit lists.  Returns (cells[n][max_out], tin, tout, count[n], flags[n]),
+    plus (cos_in, cos_out) of each interval's bounding crossings when with_cos."""
     occ = np.ascontiguousarray(occ, dtype=np.uint8); V = _f64(V)
     o = _aos(o); d = _aos(d)
     n = len(o)
     mo = max_out or (4 * N + 16)
     cells = np.full((n, mo), -1, np.int32); tin = np.zeros((n, mo)); tout = np.zeros((n, mo))
     cnt = np.zeros(n, np.int32); fl = np.zeros(n, np.int32)
+    ci = np.ones((n, mo)); co = np.ones((n, mo))
     lib().orc_trace_batch(C.c_int32(N), _p(occ, C.c_uint8), _p(V, C.c_double), C.c_int64(n),
                           _p(o, C.c_double), _p(d, C.c_double), C.c_int32(int(brute)), C.c_int32(mo),
                           _p(cells, C.c_int32), _p(tin, C.c_double), _p(tout, C.c_double),
-                          _p(cnt, C.c_int32), _p(fl, C.c_int32) if with_flags else None)
+                          _p(cnt, C.c_int32), _p(fl, C.c_int32) if with_flags else None,
+                          _p(ci, C.c_double) if with_cos else None, _p(co, C.c_double) if with_cos else None)
+    if with_cos:
+        return cells, tin, tout, cnt, fl, ci, co
     return cells, tin, tout, cnt, fl
 
 
@@ -184,6 +189,8 @@ def forward(desc, tables, params, x0, x1, with_scale: bool = False):
 
 
 def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
+    """Per-ray first-hit outputs; for hits also zhit (raw heads of the hit segment) and
+    seginfo = (t_in, t_out, rest length, |cos| at entry, |cos| at exit) of that segment."""
     m = model_struct(desc)
     tab = _f64(tables).reshape(-1); prm = _f64(params)
     occ = np.ascontiguousarray(occ, dtype=np.uint8)
@@ -191,14 +198,16 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
     n = len(o)
     r = dict(hit=np.zeros(n, np.uint8), t=np.zeros(n), xrest=np.zeros((n, 3)), normal=np.zeros((n, 3)),
              albedo=np.zeros((n, 3)), material=np.zeros(n, np.int32), cell=np.zeros(n, np.int32),
-             logit=np.zeros(n), n_queried=np.zeros(n, np.int32), margin=np.zeros(n))
+             logit=np.zeros(n), n_queried=np.zeros(n, np.int32), margin=np.zeros(n),
+             zhit=np.zeros((n, desc.n_heads)), seginfo=np.zeros((n, 5)))
     lib().orc_query_batch(C.byref(m), _p(tab, C.c_double), _p(prm, C.c_double), C.c_int32(N),
                           _p(occ, C.c_uint8), C.c_int32(kind), C.c_double(s), C.c_int64(n),
                           _p(o, C.c_double), _p(d, C.c_double), _p(r["hit"], C.c_uint8),
                           _p(r["t"], C.c_double), _p(r["xrest"], C.c_double), _p(r["normal"], C.c_double),
                           _p(r["albedo"], C.c_double), _p(r["material"], C.c_int32),
                           _p(r["cell"], C.c_int32), _p(r["logit"], C.c_double),
-                          _p(r["n_queried"], C.c_int32), _p(r["margin"], C.c_double))
+                          _p(r["n_queried"], C.c_int32), _p(r["margin"], C.c_double),
+                          _p(r["zhit"], C.c_double), _p(r["seginfo"], C.c_double))
     return r
 
 

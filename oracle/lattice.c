@@ -310,14 +310,29 @@ static int walk_crossings(int32_t N, const double* V, const double* o, const dou
     return n;
 }
 
+/* |cos| of the angle between the line and the normal of the crossed triangle. */
+static double crossing_cos(int32_t N, const double* V, const xing* x, const double* d) {
+    int a, w, u, v;
+    face_decode(N, x->face, &a, &w, &u, &v);
+    const double* q[4];
+    face_quad(N, V, a, w, u, v, q);
+    const double* A = q[0];
+    const double* B = x->tri == 0 ? q[1] : q[2];
+    const double* C = x->tri == 0 ? q[2] : q[3];
+    double e1[3], e2[3], n[3];
+    sub3(B, A, e1); sub3(C, A, e2); cross3(e1, e2, n);
+    double den = sqrt(dot3(n, n) * dot3(d, d));
+    return den > 0.0 ? fabs(dot3(n, d)) / den : 0.0;
+}
+
 int32_t orc_hitlist(int32_t N, const uint8_t* occ, const double* V, const double o[3], const double d[3],
                     int32_t brute, int32_t max_out, int32_t* cell, double* tin, double* tout,
-                    int32_t* flags) {
+                    int32_t* flags, double* cin, double* cout) {
     xing* xs = NULL;
     int32_t fl = 0;
     int n = brute ? brute_crossings(N, V, o, d, &xs) : walk_crossings(N, V, o, d, &xs, &fl);
     int32_t cur = -1, start_cell = -1, count = 0;
-    double tprev = -INFINITY;
+    double tprev = -INFINITY, cprev = 1.0;
     for (int i = 0; i < n; ++i) {
         const xing* x = &xs[i];
         if (flags) fl |= crossing_flags(N, occ, V, x, o, d);
@@ -329,12 +344,17 @@ int32_t orc_hitlist(int32_t N, const uint8_t* occ, const double* V, const double
             double a = tprev > 0.0 ? tprev : 0.0, b = x->t;
             if (tprev <= 0.0 && b > 0.0) start_cell = cur;
             if (b > a && occ[cur]) {
-                if (count < max_out) { cell[count] = cur; tin[count] = a; tout[count] = b; }
+                if (count < max_out) {
+                    cell[count] = cur; tin[count] = a; tout[count] = b;
+                    if (cin) cin[count] = tprev > 0.0 ? cprev : 1.0;   /* clipped start: no crossing */
+                    if (cout) cout[count] = crossing_cos(N, V, x, d);
+                }
                 ++count;
             }
         }
         cur = next;
         tprev = x->t;
+        if (cin) cprev = crossing_cos(N, V, x, d);
     }
     if (cur != -1) fl |= 16;
     free(xs);

@@ -221,11 +221,12 @@ void orc_label_batch(int32_t kind, const double* sp, int32_t force_march, int64_
 /* Hit lists of n rays (o, d as n x 3): segments of ray i at [i*max_out, ...). */
 void orc_trace_batch(int32_t N, const uint8_t* occ, const double* V, int64_t n, const double* o,
                      const double* d, int32_t brute, int32_t max_out, int32_t* cell, double* tin,
-                     double* tout, int32_t* count, int32_t* flags) {
+                     double* tout, int32_t* count, int32_t* flags, double* cin, double* cout) {
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i)
         count[i] = orc_hitlist(N, occ, V, o + 3 * i, d + 3 * i, brute, max_out, cell + i * max_out,
-                               tin + i * max_out, tout + i * max_out, flags ? flags + i : NULL);
+                               tin + i * max_out, tout + i * max_out, flags ? flags + i : NULL,
+                               cin ? cin + i * max_out : NULL, cout ? cout + i * max_out : NULL);
 }
 
 void orc_encode_batch(const orc_model* m, const double* tables, int64_t n, const double* x,
@@ -260,7 +261,7 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
                      const uint8_t* occ, int32_t kind, double s, int64_t n, const double* o,
                      const double* d, uint8_t* hit, double* tout_ray, double* xrest, double* nrm,
                      double* alb, int32_t* mat, int32_t* cell_out, double* logit, int32_t* nq,
-                     double* margin) {
+                     double* margin, double* zhit, double* seginfo) {
     const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials;
     double* V = (double*)malloc(sizeof(double) * 3 * (size_t)(N + 1) * (N + 1) * (N + 1));
     orc_lattice_vertices(kind, s, N, V);
@@ -270,6 +271,8 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
         int32_t* cells = (int32_t*)malloc(sizeof(int32_t) * cap);
         double* tin = (double*)malloc(sizeof(double) * cap);
         double* tou = (double*)malloc(sizeof(double) * cap);
+        double* cin = (double*)malloc(sizeof(double) * cap);
+        double* cou = (double*)malloc(sizeof(double) * cap);
         double* enc = (double*)malloc(sizeof(double) * E);
         double* acts = (double*)malloc(sizeof(double) * acts_width(m));
         double* z = (double*)malloc(sizeof(double) * H);
@@ -277,7 +280,7 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
         for (int64_t r = 0; r < n; ++r) {
             const double* ro = o + 3 * r;
             const double* rd = d + 3 * r;
-            int32_t ns = orc_hitlist(N, occ, V, ro, rd, 0, cap, cells, tin, tou, NULL);
+            int32_t ns = orc_hitlist(N, occ, V, ro, rd, 0, cap, cells, tin, tou, NULL, cin, cou);
             if (ns > cap) ns = cap;
             hit[r] = 0; tout_ray[r] = INFINITY; cell_out[r] = -1; mat[r] = -1;
             logit[r] = -INFINITY; nq[r] = 0; margin[r] = INFINITY;
@@ -312,10 +315,15 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
                     mat[r] = best;
                 }
                 cell_out[r] = cells[k];
+                if (zhit) for (int h = 0; h < H; ++h) zhit[r * H + h] = z[h];
+                if (seginfo) {
+                    double* si = seginfo + 5 * r;
+                    si[0] = tin[k]; si[1] = tou[k]; si[2] = lr; si[3] = cin[k]; si[4] = cou[k];
+                }
                 break;
             }
         }
-        free(cells); free(tin); free(tou); free(enc); free(acts); free(z);
+        free(cells); free(tin); free(tou); free(cin); free(cou); free(enc); free(acts); free(z);
     }
     free(V);
 }

@@ -47,7 +47,7 @@ void orc_label(int kind, const double* sp, int force_march, const double x0[3], 
 void orc_lattice_vertices(int kind, double s, int32_t N, double* V);
 int32_t orc_hitlist(int32_t N, const uint8_t* occ, const double* V, const double o[3], const double d[3],
                     int32_t brute, int32_t max_out, int32_t* cell, double* tin, double* tout,
-                    int32_t* flags);
+                    int32_t* flags, double* cin, double* cout);
 
 /* network.c */
 void orc_encode_point(const orc_model* m, const double* tables, const double x[3], double* out);

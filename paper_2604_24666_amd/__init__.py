@@ -18,7 +18,7 @@ import torch
 __all__ = ["NifError", "lib", "ModelDesc", "Pose", "Rays", "Hits", "Segments", "Batch", "TrainCfg",
            "nif_model_create", "nif_model_destroy", "nif_model_sizes", "nif_model_set_params",
            "nif_model_get_params", "nif_model_get_grads", "nif_model_zero_grads", "nif_model_reserve",
-           "nif_voxelize", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_trace", "nif_query",
+           "nif_voxelize", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_update", "nif_trace", "nif_query",
            "nif_encode", "nif_forward", "nif_backward", "nif_train_step",
            "Model", "Grid", "NifField"]
 
@@ -94,7 +94,7 @@ def lib():
             "nif_model_zero_grads": ([P, P], C.c_int), "nif_model_reserve": ([P, I64], C.c_int),
             "nif_voxelize": ([I32, P, I32, I32, P, P], C.c_int),
             "nif_build_grid": ([P, I32, P, I32, I32, P, P], C.c_int), "nif_grid_destroy": ([P], C.c_int),
-            "nif_grid_info": ([P, I32, P, P], C.c_int),
+            "nif_grid_info": ([P, I32, P, P, P], C.c_int), "nif_grid_update": ([P, P, I32, P], C.c_int),
             "nif_trace": ([P, P, I64, I32, P, P], C.c_int),
             "nif_query": ([P, P, P, I64, P, U32, I32, P, P], C.c_int),
             "nif_encode": ([P, P, I64, P, P], C.c_int),
@@ -189,9 +189,16 @@ def nif_grid_destroy(h):
 
 
 def nif_grid_info(h, pose: int = 0):
-    a, b = C.c_int64(), C.c_int64()
-    _check(lib().nif_grid_info(h, pose, C.byref(a), C.byref(b)))
-    return a.value, b.value
+    """(occupied voxels, bin-list entries of the pose at build, overflow flag of the last update)."""
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int32()
+    _check(lib().nif_grid_info(h, pose, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def nif_grid_update(h, kinds, strengths, stream=None):
+    n = len(kinds)
+    poses = (Pose * n)(*[Pose(int(k), float(s)) for k, s in zip(kinds, strengths)])
+    _check(lib().nif_grid_update(h, poses, n, _stream(stream)))
 
 
 def make_rays(o, d, pose_offsets) -> Rays:
@@ -307,6 +314,9 @@ class Grid:
 
     def info(self, pose=0):
         return nif_grid_info(self.h, pose)
+
+    def update(self, kinds, strengths):
+        nif_grid_update(self.h, kinds, strengths)
 
     def trace(self, o, d, pose_offsets, max_seg=64, with_points=True):
         n = o.shape[1]

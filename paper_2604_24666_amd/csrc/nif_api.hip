@@ -209,11 +209,22 @@ int nif_grid_destroy(nif_grid* g) {
     return NIF_OK;
 }
 
-int nif_grid_info(const nif_grid* g, int32_t pose, int64_t* n_occupied, int64_t* n_refs) {
+int nif_grid_update(nif_grid* g, const nif_pose* poses, int32_t n_poses, nif_stream stream) {
+    REQUIRE(g, "grid is null");
+    REQUIRE(poses && n_poses == g->n_poses, "n_poses must equal the grid's pose count");
+    for (int p = 0; p < n_poses; ++p) {
+        REQUIRE(poses[p].kind >= 0 && poses[p].kind <= 3, "unknown deformation kind");
+        REQUIRE(poses[p].strength >= 0.f && poses[p].strength <= 1.f, "pose strength must be in [0, 1]");
+    }
+    return nif::grid_update(g, poses, S(stream));
+}
+
+int nif_grid_info(const nif_grid* g, int32_t pose, int64_t* n_occupied, int64_t* n_refs, int32_t* overflow) {
     REQUIRE(g, "grid is null");
     REQUIRE(pose >= 0 && pose < g->n_poses, "pose out of range");
     if (n_occupied) *n_occupied = g->n_occupied;
     if (n_refs) *n_refs = g->refs_per_pose[pose];
+    if (overflow) return nif::grid_overflow(const_cast<nif_grid*>(g), nullptr, overflow);
     return NIF_OK;
 }
 
@@ -230,7 +241,7 @@ int nif_trace(const nif_grid* g, const nif_rays* rays, int64_t n, int32_t max_se
     if (rc) return rc;
     REQUIRE(out, "out is null");
     REQUIRE(max_seg >= 0, "max_seg must be >= 0");
-    REQUIRE(out->count, "out->count must not be null");
+    if (n > 0) REQUIRE(out->count, "out->count must not be null");
     return nif::trace_launch(g, rays, n, max_seg, out, S(stream));
 }
 

@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_scan(const PoseDev* __restrict__ poses
     __shared__ int32_t part[1024];
     const int T = blockDim.x;
     const int64_t per = (n + T - 1) / T;
-    const int64_t a = threadIdx.x * per, b = min(n, a + per);
+    const int64_t a = min(n, (int64_t)threadIdx.x * per), b = min(n, a + per);
     int32_t sum = 0;
     for (int64_t i = a; i < b; ++i) sum += c[i];
     part[threadIdx.x] = sum;
@@ -175,6 +175,48 @@ __global__ void __launch_bounds__(1024) k_scan(const PoseDev* __restrict__ poses
     int32_t run = part[threadIdx.x] - sum;   // exclusive prefix of this thread's range
     for (int64_t i = a; i < b; ++i) { s[i] = run; run += c[i]; }
     if (threadIdx.x == T - 1) { s[n] = part[T - 1]; totals[p] = part[T - 1]; }
+}
+
+// Per-pose offsets into the shared reference list (one thread).  A pose whose references do
+// not fit the allocated capacity is marked empty (its rays then miss) and flagged.
+__global__ void k_ref_offsets(PoseDev* __restrict__ poses, int n_poses, const int32_t* __restrict__ totals,
+                              int64_t capacity, int32_t* __restrict__ overflow) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t off = 0;
+    int32_t ov = 0;
+    for (int p = 0; p < n_poses; ++p) {
+        poses[p].ref_off = off;
+        if (off + totals[p] > capacity) { poses[p].empty = 1; ov = 1; }
+        else off += totals[p];
+    }
+    *overflow = ov;
+}
+
+// Bin-grid origin and bin size of every pose from its bounding box (bins per axis fixed).
+__global__ void k_pose_bins(PoseDev* __restrict__ poses, int n_poses, const int32_t* __restrict__ bbox, int32_t n_occ) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_poses) return;
+    PoseDev& q = poses[p];
+    q.empty = n_occ == 0;
+    for (int c = 0; c < 3; ++c) {
+        const int32_t ilo = bbox[6 * p + c], ihi = bbox[6 * p + 3 + c];
+        float lo = __int_as_float(ilo >= 0 ? ilo : (ilo ^ 0x7fffffff));
+        float hi = __int_as_float(ihi >= 0 ? ihi : (ihi ^ 0x7fffffff));
+        if (q.empty) { lo = 0.f; hi = 1.f; }
+        q.lo[c] = lo;
+        q.bs[c] = fmaxf((hi - lo) / q.nb[c], 1e-6f);
+        q.inv_bs[c] = 1.f / q.bs[c];
+    }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+__global__ void k_bbox_init(int32_t* __restrict__ bbox, int n_poses) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 6 * n_poses) return;
+    bbox[i] = (i % 6) < 3 ? 0x7f800000 : (int32_t)(0xff800000u ^ 0x7fffffffu);
 }
 
 __global__ void k_bin_fill(const PoseDev* __restrict__ poses, const float4* __restrict__ V, int32_t N,
@@ -221,11 +263,55 @@ __global__ void k_bin_sort(const PoseDev* __restrict__ poses, const int32_t* __r
 // ------------------------------------------------------------------ host orchestration
 
 void grid_free(nif_grid* g) {
-    if (g->poses) (void)hipFree(g->poses);
-    if (g->verts) (void)hipFree(g->verts);
-    if (g->bin_start) (void)hipFree(g->bin_start);
-    if (g->bin_cells) (void)hipFree(g->bin_cells);
+    void* ps[] = {g->poses, g->verts, g->bin_start, g->bin_cells, g->list, g->counts, g->scratch};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
     g->poses = nullptr; g->verts = nullptr; g->bin_start = nullptr; g->bin_cells = nullptr;
+    g->list = nullptr; g->counts = nullptr; g->scratch = nullptr;
+}
+
+// scratch layout: bbox [6 P] | totals [P] | overflow [1] | n_occ [1]
+static int32_t* sc_bbox(nif_grid* g) { return g->scratch; }
+static int32_t* sc_totals(nif_grid* g) { return g->scratch + 6 * g->n_poses; }
+static int32_t* sc_overflow(nif_grid* g) { return g->scratch + 7 * g->n_poses; }
+static int32_t* sc_nocc(nif_grid* g) { return g->scratch + 7 * g->n_poses + 1; }
+
+// Vertices, boxes, bin sizes, counts, scan and per-pose offsets; fills the reference lists
+// when `fill`.  Device work only: no allocation, no synchronisation.
+static int grid_rebin(nif_grid* g, bool fill, hipStream_t st) {
+    const int P = g->n_poses, N = g->N;
+    const int64_t nv = (int64_t)(N + 1) * (N + 1) * (N + 1);
+    const int32_t n_occ = (int32_t)g->n_occupied;
+    hipLaunchKernelGGL(k_vertices, dim3((unsigned)((nv + 255) / 256), P), dim3(256), 0, st, g->poses, N, g->verts);
+    hipLaunchKernelGGL(k_bbox_init, dim3((6 * P + 255) / 256), dim3(256), 0, st, sc_bbox(g), P);
+    if (n_occ > 0) {
+        unsigned nblk = (unsigned)std::min<int64_t>((n_occ + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_pose_bbox, dim3(nblk, P), dim3(256), 0, st, g->poses, g->verts, N, g->list, n_occ, sc_bbox(g));
+    }
+    hipLaunchKernelGGL(k_pose_bins, dim3((P + 63) / 64), dim3(64), 0, st, g->poses, P, sc_bbox(g), n_occ);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, st, g->counts, g->bin_total, 0);
+    const unsigned occ_blk = (unsigned)std::max<int64_t>(1, (n_occ + 255) / 256);
+    if (n_occ > 0)
+        hipLaunchKernelGGL(k_bin_count, dim3(occ_blk, P), dim3(256), 0, st, g->poses, g->verts, N, g->list, n_occ, g->counts);
+    hipLaunchKernelGGL(k_scan, dim3(P), dim3(1024), 0, st, g->poses, g->counts, g->bin_start, sc_totals(g));
+    hipLaunchKernelGGL(k_ref_offsets, dim3(1), dim3(64), 0, st, g->poses, P, sc_totals(g), fill ? g->ref_capacity : (int64_t)0,
+                       sc_overflow(g));
+    if (fill && n_occ > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, st, g->counts, g->bin_total, 0);
+        hipLaunchKernelGGL(k_bin_fill, dim3(occ_blk, P), dim3(256), 0, st, g->poses, g->verts, N, g->list, n_occ,
+                           g->bin_start, g->counts, g->bin_cells);
+        hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((g->max_bins + 255) / 256), P), dim3(256), 0, st, g->poses,
+                           g->bin_start, g->bin_cells);
+    }
+    return check_hip(hipGetLastError(), "grid rebin launch");
+}
+
+static void set_pose_params(std::vector<PoseDev>& P, const nif_pose* poses) {
+    for (size_t p = 0; p < P.size(); ++p) {
+        P[p].kind = poses[p].kind;
+        P[p].s = poses[p].strength;
+        pose_constants(P[p].kind, P[p].s, &P[p].k0, &P[p].k1);
+    }
 }
 
 int grid_build(nif_grid* g, const uint8_t* occ, int32_t N, const nif_pose* poses, int32_t n_poses,
@@ -237,115 +323,89 @@ int grid_build(nif_grid* g, const uint8_t* occ, int32_t N, const nif_pose* poses
     const int nbin_axis = bins_per_axis > 0 ? bins_per_axis : (N / 2 > 0 ? N / 2 : 1);
     std::vector<PoseDev> P(n_poses);
     for (int p = 0; p < n_poses; ++p) {
-        PoseDev& q = P[p];
-        memset(&q, 0, sizeof(q));
-        q.kind = poses[p].kind;
-        q.s = poses[p].strength;
-        pose_constants(q.kind, q.s, &q.k0, &q.k1);
-        q.vert_off = nv * p;
+        memset(&P[p], 0, sizeof(PoseDev));
+        P[p].vert_off = nv * p;
+        P[p].nb[0] = P[p].nb[1] = P[p].nb[2] = 1;
     }
+    set_pose_params(P, poses);
     int rc;
-    int32_t *list = nullptr, *tmp = nullptr, *counts = nullptr;
-    auto cleanup = [&]() {
-        if (list) (void)hipFree(list);
-        if (tmp) (void)hipFree(tmp);
-        if (counts) (void)hipFree(counts);
-    };
-#define NIF_TRY(expr, what)                                 \
-    do {                                                    \
-        if ((rc = check_hip((expr), what)) != NIF_OK) {     \
-            cleanup();                                      \
-            return rc;                                      \
-        }                                                   \
+#define NIF_TRY(expr, what)                                      \
+    do {                                                         \
+        if ((rc = check_hip((expr), what)) != NIF_OK) return rc; \
     } while (0)
     NIF_TRY(hipMalloc(&g->poses, sizeof(PoseDev) * n_poses), "hipMalloc poses");
     NIF_TRY(hipMalloc(&g->verts, sizeof(float4) * nv * n_poses), "hipMalloc vertices");
-    NIF_TRY(hipMalloc(&list, sizeof(int32_t) * (ncell + 1)), "hipMalloc occupied list");
-    NIF_TRY(hipMalloc(&tmp, sizeof(int32_t) * (6 * n_poses + 2 * n_poses + 1)), "hipMalloc build scratch");
-    NIF_TRY(hipMemcpyAsync(g->poses, P.data(), sizeof(PoseDev) * n_poses, hipMemcpyHostToDevice, st), "copy poses");
-    // 1 vertices
-    hipLaunchKernelGGL(k_vertices, dim3((unsigned)((nv + 255) / 256), n_poses), dim3(256), 0, st, g->poses, N, g->verts);
-    NIF_TRY(hipGetLastError(), "k_vertices");
-    // 2 occupied list
-    int32_t* d_count = tmp + 8 * n_poses;
-    NIF_TRY(hipMemsetAsync(d_count, 0, sizeof(int32_t), st), "memset");
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, occ, ncell, list, d_count);
+    NIF_TRY(hipMalloc(&g->scratch, sizeof(int32_t) * (7 * n_poses + 8)), "hipMalloc grid scratch");
+    NIF_TRY(hipMalloc(&g->list, sizeof(int32_t) * (ncell + 1)), "hipMalloc occupied list");
+    // occupied voxels, compacted once
+    NIF_TRY(hipMemsetAsync(sc_nocc(g), 0, sizeof(int32_t), st), "memset");
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, occ, ncell, g->list, sc_nocc(g));
     NIF_TRY(hipGetLastError(), "k_compact");
     int32_t n_occ = 0;
-    NIF_TRY(hipMemcpyAsync(&n_occ, d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read count");
+    NIF_TRY(hipMemcpyAsync(&n_occ, sc_nocc(g), sizeof(int32_t), hipMemcpyDeviceToHost, st), "read count");
     NIF_TRY(hipStreamSynchronize(st), "sync");
     g->n_occupied = n_occ;
-    // 3 bounding boxes
-    std::vector<int32_t> bb(6 * n_poses);
-    for (int p = 0; p < n_poses; ++p)
-        for (int c = 0; c < 3; ++c) { bb[6 * p + c] = 0x7f800000; bb[6 * p + 3 + c] = (int32_t)(0xff800000 ^ 0x7fffffff); }
-    NIF_TRY(hipMemcpyAsync(tmp, bb.data(), sizeof(int32_t) * 6 * n_poses, hipMemcpyHostToDevice, st), "copy bbox init");
+    // the first poses' bounding boxes fix the bins per axis (by aspect ratio)
+    NIF_TRY(hipMemcpyAsync(g->poses, P.data(), sizeof(PoseDev) * n_poses, hipMemcpyHostToDevice, st), "copy poses");
+    hipLaunchKernelGGL(k_vertices, dim3((unsigned)((nv + 255) / 256), n_poses), dim3(256), 0, st, g->poses, N, g->verts);
+    hipLaunchKernelGGL(k_bbox_init, dim3((6 * n_poses + 255) / 256), dim3(256), 0, st, sc_bbox(g), n_poses);
     if (n_occ > 0) {
         unsigned nblk = (unsigned)std::min<int64_t>((n_occ + 255) / 256, 1024);
-        hipLaunchKernelGGL(k_pose_bbox, dim3(nblk, n_poses), dim3(256), 0, st, g->poses, g->verts, N, list, n_occ, tmp);
-        NIF_TRY(hipGetLastError(), "k_pose_bbox");
+        hipLaunchKernelGGL(k_pose_bbox, dim3(nblk, n_poses), dim3(256), 0, st, g->poses, g->verts, N, g->list, n_occ, sc_bbox(g));
     }
-    NIF_TRY(hipMemcpyAsync(bb.data(), tmp, sizeof(int32_t) * 6 * n_poses, hipMemcpyDeviceToHost, st), "read bbox");
+    NIF_TRY(hipGetLastError(), "bbox");
+    std::vector<int32_t> bb(6 * n_poses);
+    NIF_TRY(hipMemcpyAsync(bb.data(), sc_bbox(g), sizeof(int32_t) * 6 * n_poses, hipMemcpyDeviceToHost, st), "read bbox");
     NIF_TRY(hipStreamSynchronize(st), "sync");
-    int64_t bin_total = 0;
+    int64_t bin_total = 0, max_bins = 1;
     for (int p = 0; p < n_poses; ++p) {
-        PoseDev& q = P[p];
-        float lo[3], hi[3];
-        for (int c = 0; c < 3; ++c) { lo[c] = ord2f_host(bb[6 * p + c]); hi[c] = ord2f_host(bb[6 * p + 3 + c]); }
-        q.empty = n_occ == 0;
-        float ext = 0.f;
-        for (int c = 0; c < 3; ++c) ext = std::max(ext, q.empty ? 1.f : hi[c] - lo[c]);
+        float e[3], ext = 0.f;
         for (int c = 0; c < 3; ++c) {
-            float e = q.empty ? 1.f : hi[c] - lo[c];
-            int nb = (int)std::ceil(nbin_axis * e / ext - 1e-3f);
-            q.nb[c] = std::max(1, std::min(nb, 4096));
-            q.lo[c] = q.empty ? 0.f : lo[c];
-            q.bs[c] = std::max(e / q.nb[c], 1e-6f);
-            q.inv_bs[c] = 1.f / q.bs[c];
+            e[c] = n_occ == 0 ? 1.f : ord2f_host(bb[6 * p + 3 + c]) - ord2f_host(bb[6 * p + c]);
+            ext = std::max(ext, e[c]);
         }
-        q.bin_off = bin_total;
-        bin_total += (int64_t)q.nb[0] * q.nb[1] * q.nb[2] + 1;
+        for (int c = 0; c < 3; ++c) P[p].nb[c] = std::max(1, std::min((int)std::ceil(nbin_axis * e[c] / ext - 1e-3f), 4096));
+        P[p].bin_off = bin_total;
+        const int64_t nb = (int64_t)P[p].nb[0] * P[p].nb[1] * P[p].nb[2];
+        bin_total += nb + 1;
+        max_bins = std::max(max_bins, nb);
     }
+    g->bin_total = bin_total;
+    g->max_bins = max_bins;
     NIF_TRY(hipMalloc(&g->bin_start, sizeof(int32_t) * bin_total), "hipMalloc bin_start");
-    NIF_TRY(hipMalloc(&counts, sizeof(int32_t) * bin_total), "hipMalloc bin counts");
-    NIF_TRY(hipMemsetAsync(counts, 0, sizeof(int32_t) * bin_total, st), "memset counts");
+    NIF_TRY(hipMalloc(&g->counts, sizeof(int32_t) * bin_total), "hipMalloc bin counts");
     NIF_TRY(hipMemcpyAsync(g->poses, P.data(), sizeof(PoseDev) * n_poses, hipMemcpyHostToDevice, st), "copy poses");
-    unsigned occ_blk = (unsigned)std::max<int64_t>(1, (n_occ + 255) / 256);
-    if (n_occ > 0) {
-        hipLaunchKernelGGL(k_bin_count, dim3(occ_blk, n_poses), dim3(256), 0, st, g->poses, g->verts, N, list, n_occ, counts);
-        NIF_TRY(hipGetLastError(), "k_bin_count");
-    }
-    int32_t* totals = tmp;   // reuse
-    hipLaunchKernelGGL(k_scan, dim3(n_poses), dim3(1024), 0, st, g->poses, counts, g->bin_start, totals);
-    NIF_TRY(hipGetLastError(), "k_scan");
+    // count pass, then size the reference lists with headroom for later re-poses
+    g->ref_capacity = 0;
+    if ((rc = grid_rebin(g, false, st))) return rc;
     std::vector<int32_t> tot(n_poses);
-    NIF_TRY(hipMemcpyAsync(tot.data(), totals, sizeof(int32_t) * n_poses, hipMemcpyDeviceToHost, st), "read totals");
+    NIF_TRY(hipMemcpyAsync(tot.data(), sc_totals(g), sizeof(int32_t) * n_poses, hipMemcpyDeviceToHost, st), "read totals");
     NIF_TRY(hipStreamSynchronize(st), "sync");
-    int64_t ref_total = 0;
-    g->refs_per_pose.assign(n_poses, 0);
-    for (int p = 0; p < n_poses; ++p) {
-        P[p].ref_off = ref_total;
-        g->refs_per_pose[p] = tot[p];
-        ref_total += tot[p];
-    }
-    NIF_TRY(hipMalloc(&g->bin_cells, sizeof(int32_t) * std::max<int64_t>(ref_total, 1)), "hipMalloc bin_cells");
-    NIF_TRY(hipMemcpyAsync(g->poses, P.data(), sizeof(PoseDev) * n_poses, hipMemcpyHostToDevice, st), "copy poses");
-    NIF_TRY(hipMemsetAsync(counts, 0, sizeof(int32_t) * bin_total, st), "memset cursors");
-    if (n_occ > 0) {
-        hipLaunchKernelGGL(k_bin_fill, dim3(occ_blk, n_poses), dim3(256), 0, st, g->poses, g->verts, N, list, n_occ,
-                           g->bin_start, counts, g->bin_cells);
-        NIF_TRY(hipGetLastError(), "k_bin_fill");
-        int64_t maxbins = 0;
-        for (int p = 0; p < n_poses; ++p) maxbins = std::max<int64_t>(maxbins, (int64_t)P[p].nb[0] * P[p].nb[1] * P[p].nb[2]);
-        hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((maxbins + 255) / 256), n_poses), dim3(256), 0, st, g->poses,
-                           g->bin_start, g->bin_cells);
-        NIF_TRY(hipGetLastError(), "k_bin_sort");
-    }
+    int64_t refs = 0;
+    for (int p = 0; p < n_poses; ++p) refs += tot[p];
+    g->ref_capacity = refs + refs / 2 + 4096;
+    NIF_TRY(hipMalloc(&g->bin_cells, sizeof(int32_t) * g->ref_capacity), "hipMalloc bin_cells");
+    if ((rc = grid_rebin(g, true, st))) return rc;
     NIF_TRY(hipStreamSynchronize(st), "sync");
     g->poses_host = P;
-    cleanup();
+    g->refs_per_pose.assign(tot.begin(), tot.end());
 #undef NIF_TRY
     return NIF_OK;
+}
+
+int grid_update(nif_grid* g, const nif_pose* poses, hipStream_t st) {
+    set_pose_params(g->poses_host, poses);
+    // kind, strength and constants change; boxes, bin sizes and offsets are recomputed on the device
+    int rc = check_hip(hipMemcpyAsync(g->poses, g->poses_host.data(), sizeof(PoseDev) * g->n_poses,
+                                      hipMemcpyHostToDevice, st), "copy poses");
+    if (rc) return rc;
+    return grid_rebin(g, true, st);
+}
+
+int grid_overflow(nif_grid* g, hipStream_t st, int32_t* overflow) {
+    int rc = check_hip(hipMemcpyAsync(overflow, sc_overflow(g), sizeof(int32_t), hipMemcpyDeviceToHost, st), "read overflow");
+    if (rc) return rc;
+    return check_hip(hipStreamSynchronize(st), "sync");
 }
 
 }  // namespace nif

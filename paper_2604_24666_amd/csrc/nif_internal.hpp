@@ -16,6 +16,10 @@ struct nif_grid {
     float4* verts = nullptr;                // device [n_poses][(N+1)^3]
     int32_t* bin_start = nullptr;           // device, per pose nbins + 1 (exclusive scan)
     int32_t* bin_cells = nullptr;           // device, occupied voxel ids per bin
+    int32_t* list = nullptr;                // device, occupied voxel ids (shared by all poses)
+    int32_t* counts = nullptr;              // device, per-bin counters (build scratch)
+    int32_t* scratch = nullptr;             // device, boxes / totals / flags
+    int64_t bin_total = 0, max_bins = 0, ref_capacity = 0;
     int64_t n_occupied = 0;
     std::vector<int64_t> refs_per_pose;
 };
@@ -69,6 +73,8 @@ int check_hip(hipError_t e, const char* what);
 int grid_build(nif_grid* g, const uint8_t* occ, int32_t N, const nif_pose* poses, int32_t n_poses,
                int32_t bins_per_axis, hipStream_t st);
 void grid_free(nif_grid* g);
+int grid_update(nif_grid* g, const nif_pose* poses, hipStream_t st);
+int grid_overflow(nif_grid* g, hipStream_t st, int32_t* overflow);
 int voxelize_launch(int32_t scene_kind, const float* params_dev, int32_t N, uint8_t* occ,
                     hipStream_t st);
 

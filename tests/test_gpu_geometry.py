@@ -1,8 +1,12 @@
 """GPU parity of the geometry stage (voxelization, deformed lattice, bin-grid traversal,
 entry/exit points, inverse deformation) against the FP64 oracle on the same inputs.
 
-Bar: voxel hit lists bit-exact on every non-grazing ray; t_in/t_out within 1e-5; rest-space
-entry/exit points within 1e-6 (FP32 geometry vs FP64)."""
+Bar: voxel hit lists bit-exact on every non-grazing ray.  t_in / t_out and the rest-space
+entry/exit points within the FP32 bound of the crossing (derivation in the design doc): an FP32
+vertex error delta_V moves a crossing along the ray by delta_V / |cos| (cos between the ray
+and the crossed face's normal), so
+    tol_t = 4 ulp(t) + 3e-7 / max(|cos|, 1e-3),   tol_x = 2 (tol_t + 2 ulp(1)) + 3e-7,
+(2 bounds the stretch of the inverse deformations on the domain)."""
 import numpy as np
 import pytest
 
@@ -18,6 +22,14 @@ def P():
     return P
 
 
+def _ulp(x):
+    return np.spacing(np.abs(x).astype(np.float32)).astype(np.float64)
+
+
+def _tol_t(t, c):
+    return 4 * _ulp(t) + 3e-7 / np.maximum(np.abs(c), 1e-3)
+
+
 def _compare_trace(orc, P, N, occ, kind, s, o, d, max_seg=96, brute=True):
     import torch
     grid = P.Grid(torch.as_tensor(occ).cuda(), N, [kind], [s])
@@ -30,25 +42,32 @@ def _compare_trace(orc, P, N, occ, kind, s, o, d, max_seg=96, brute=True):
     x0 = out["x0"].cpu().numpy().astype(np.float64)
     x1 = out["x1"].cpu().numpy().astype(np.float64)
     V = orc.lattice_vertices(kind, float(np.float32(s)), N)
-    rc, rtin, rtout, rcnt, fl = orc.trace(N, occ, V, o, d, brute=brute, max_out=max_seg)
+    rc, rtin, rtout, rcnt, fl, cin, cout = orc.trace(N, occ, V, o, d, brute=brute, max_out=max_seg,
+                                                     with_cos=True)
     ok = fl == 0
     say(f"  rays {len(cnt)}  grazing {int((~ok).sum())}  with segments {int((rcnt > 0).sum())}")
     assert np.array_equal(cnt[ok], rcnt[ok]), np.nonzero((cnt != rcnt) & ok)[0][:10]
     assert cnt.max() <= max_seg
     n_seg = 0
+    worst = 0.0
     o64 = o.T.astype(np.float64)
     d64 = d.T.astype(np.float64)
     s64 = float(np.float32(s))
     for r in np.nonzero(ok & (rcnt > 0))[0]:
         k = rcnt[r]
         assert np.array_equal(cell[r, :k], rc[r, :k]), (r, cell[r, :k], rc[r, :k])
-        assert np.abs(tin[r, :k] - rtin[r, :k]).max() <= 1e-5
-        assert np.abs(tout[r, :k] - rtout[r, :k]).max() <= 1e-5
+        ti, to = _tol_t(rtin[r, :k], cin[r, :k]), _tol_t(rtout[r, :k], cout[r, :k])
+        assert np.all(np.abs(tin[r, :k] - rtin[r, :k]) <= ti), (r, tin[r, :k] - rtin[r, :k], cin[r, :k])
+        assert np.all(np.abs(tout[r, :k] - rtout[r, :k]) <= to), (r, tout[r, :k] - rtout[r, :k], cout[r, :k])
         ref0 = orc.deform_inv(kind, s64, o64[r] + rtin[r, :k, None] * d64[r])
         ref1 = orc.deform_inv(kind, s64, o64[r] + rtout[r, :k, None] * d64[r])
-        assert np.abs(x0[:, r, :k].T - ref0).max() <= 1e-6
-        assert np.abs(x1[:, r, :k].T - ref1).max() <= 1e-6
+        e0 = np.abs(x0[:, r, :k].T - ref0).max(1)
+        e1 = np.abs(x1[:, r, :k].T - ref1).max(1)
+        assert np.all(e0 <= 2 * (ti + 2 * _ulp(1.0)) + 3e-7), (r, e0, cin[r, :k])
+        assert np.all(e1 <= 2 * (to + 2 * _ulp(1.0)) + 3e-7), (r, e1, cout[r, :k])
+        worst = max(worst, e0.max(), e1.max())
         n_seg += k
+    say(f"  segments {n_seg}  max rest-point error {worst:.2e}")
     return n_seg
 
 
@@ -136,3 +155,25 @@ def test_multi_pose_grid_and_empty_and_degenerate_inputs(orc, P):
     # max_seg smaller than the list: counts are still complete
     out = grid.trace(dev_f32(o), dev_f32(d), offsets(counts), max_seg=1)
     assert np.array_equal(out["count"].cpu().numpy(), cnt)
+
+
+def test_grid_update_equals_a_fresh_build(orc, P):
+    """Re-posing a grid on the device gives the same hit lists as building it for the new poses."""
+    import torch
+    w = S.workload("spheres64")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = torch.as_tensor(orc.voxelize(w.scene_kind, sp, w.N)).cuda()
+    o, d = S.rays_camera(256, 30.0)
+    k0, s0 = [S.TWIST, S.BEND], [0.25, 0.5]
+    k1, s1 = [S.TAPER, S.TWIST], [1.0, 0.9]
+    say("grid update vs fresh build, spheres64")
+    g = P.Grid(occ, w.N, k0, s0)
+    g.update(k1, s1)
+    fresh = P.Grid(occ, w.N, k1, s1)
+    off = offsets([o.shape[1] // 2, o.shape[1] - o.shape[1] // 2])
+    a = g.trace(dev_f32(o), dev_f32(d), off, max_seg=64, with_points=False)
+    b = fresh.trace(dev_f32(o), dev_f32(d), off, max_seg=64, with_points=False)
+    assert np.array_equal(a["count"].cpu().numpy(), b["count"].cpu().numpy())
+    assert np.array_equal(a["cell"].cpu().numpy(), b["cell"].cpu().numpy())
+    assert np.array_equal(a["t_in"].cpu().numpy(), b["t_in"].cpu().numpy())
+    assert g.info(0)[2] == 0 and int(a["count"].sum()) > 1000
