@@ -211,8 +211,9 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
     return r
 
 
-def loss_grad(desc, tables, params, s, x0, x1, hit, t, nrm, alb, mat, want_x: bool = False):
-    """Returns (losses[6], g_tables, g_params, g_s, g_x0, g_x1)."""
+def loss_grad(desc, tables, params, s, x0, x1, hit, t, nrm, alb, mat, want_x: bool = False,
+              want_dz: bool = False):
+    """Returns (losses[6], g_tables, g_params, g_s, g_x0, g_x1), plus dL/dz[B][H] if want_dz."""
     m = model_struct(desc)
     tab = _f64(tables).reshape(-1); prm = _f64(params); s = _f64(s)
     x0 = _aos(x0); x1 = _aos(x1)
@@ -222,11 +223,15 @@ def loss_grad(desc, tables, params, s, x0, x1, hit, t, nrm, alb, mat, want_x: bo
     losses = np.zeros(6); gt = np.zeros_like(tab); gp = np.zeros_like(prm); gs = np.zeros(5)
     gx0 = np.zeros_like(x0) if want_x else None
     gx1 = np.zeros_like(x1) if want_x else None
+    dz = np.zeros((B, desc.n_heads)) if want_dz else None
     lib().orc_loss_grad(C.byref(m), _p(tab, C.c_double), _p(prm, C.c_double), _p(s, C.c_double),
                         C.c_int64(B), _p(x0, C.c_double), _p(x1, C.c_double), _p(hit, C.c_uint8),
                         _p(t, C.c_double), _p(nrm, C.c_double), _p(alb, C.c_double), _p(mat, C.c_int32),
                         _p(losses, C.c_double), _p(gt, C.c_double), _p(gp, C.c_double), _p(gs, C.c_double),
-                        _p(gx0, C.c_double) if want_x else None, _p(gx1, C.c_double) if want_x else None)
+                        _p(gx0, C.c_double) if want_x else None, _p(gx1, C.c_double) if want_x else None,
+                        _p(dz, C.c_double) if want_dz else None)
+    if want_dz:
+        return losses, gt.reshape(np.shape(tables)), gp, gs, gx0, gx1, dz
     return losses, gt.reshape(np.shape(tables)), gp, gs, gx0, gx1
 
 

@@ -336,7 +336,7 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
                    int64_t B, const double* x0, const double* x1, const uint8_t* lhit,
                    const double* lt, const double* ln, const double* la, const int32_t* lm,
                    double* losses, double* g_tables, double* g_params, double* g_s, double* g_x0,
-                   double* g_x1) {
+                   double* g_x1, double* dz_out) {
     const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials, PW = point_width(m);
     int64_t P = 0;
     for (int64_t i = 0; i < B; ++i) P += lhit[i] ? 1 : 0;
@@ -407,6 +407,7 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
                 }
             }
         }
+        if (dz_out) memcpy(dz_out + i * H, dz, sizeof(double) * H);
         /* backward through the MLP */
         memcpy(dcur, dz, sizeof(double) * H);
         int64_t poff = 0, aoff = 0;

@@ -112,15 +112,15 @@ int nif_model_set_params(nif_model* m, const float* tables, const float* mlp, co
     } else if ((rc = nif::check_hip(hipMemsetAsync(m->s, 0, sizeof(float) * 8, st), "zero s"))) {
         return rc;
     }
-    const struct { void* p; int64_t n; } zs[] = {{m->g_tables, m->n_table}, {m->g_mlp, m->n_mlp}, {m->g_mlp_pad, m->n_mlp_pad},
+    const struct { void* p; int64_t n; } zs[] = {{m->g_tables, m->n_table}, {m->g_mlp, m->n_mlp},
                                                  {m->g_s, 8}, {m->m_tables, m->n_table}, {m->v_tables, m->n_table},
                                                  {m->m_mlp, m->n_mlp}, {m->v_mlp, m->n_mlp}, {m->m_s, 8}, {m->v_s, 8}};
     for (auto& z : zs)
         if ((rc = nif::check_hip(hipMemsetAsync(z.p, 0, sizeof(float) * z.n, st), "zero state"))) return rc;
     if ((rc = nif::model_sync_working(m, st))) return rc;
+    if ((rc = nif::check_hip(hipMemsetAsync(m->dacc, 0, sizeof(double) * 16, st), "zero train state"))) return rc;
+    if ((rc = nif::check_hip(hipMemsetAsync(m->tcount, 0, sizeof(int64_t) * 16, st), "zero train state"))) return rc;
     m->step = 0;
-    m->good_steps = 0;
-    m->loss_scale = 0.f;
     m->params_set = true;
     return NIF_OK;
 }
@@ -151,7 +151,6 @@ int nif_model_zero_grads(nif_model* m, nif_stream stream) {
     int rc;
     if ((rc = nif::check_hip(hipMemsetAsync(m->g_tables, 0, sizeof(float) * m->n_table, st), "zero grads"))) return rc;
     if ((rc = nif::check_hip(hipMemsetAsync(m->g_mlp, 0, sizeof(float) * m->n_mlp, st), "zero grads"))) return rc;
-    if ((rc = nif::check_hip(hipMemsetAsync(m->g_mlp_pad, 0, sizeof(float) * m->n_mlp_pad, st), "zero grads"))) return rc;
     return nif::check_hip(hipMemsetAsync(m->g_s, 0, sizeof(float) * 8, st), "zero grads");
 }
 

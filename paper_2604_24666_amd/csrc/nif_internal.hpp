@@ -35,6 +35,7 @@ struct nif_model {
     std::vector<int32_t> dims_pad;      // last padded to 16
     std::vector<int64_t> w_off, b_off;  // canonical offsets of each layer's W and b
     std::vector<int64_t> wp_off, bp_off;// offsets in the padded working copies
+    std::vector<int64_t> wt_off;        // transposed padded copy of layer i >= 1: [in][out_pad]
     int64_t n_mlp_pad = 0;
     // parameters
     float* tables = nullptr;            // FP32 master [L][T][Fd]
@@ -48,19 +49,17 @@ struct nif_model {
     float *g_tables = nullptr, *g_mlp = nullptr, *g_s = nullptr;
     float *m_tables = nullptr, *v_tables = nullptr, *m_mlp = nullptr, *v_mlp = nullptr;
     float *m_s = nullptr, *v_s = nullptr;
-    float* g_mlp_pad = nullptr;         // backward accumulates here (padded), then unpadded
     // training scratch (sized for max_batch samples; grown only by nif_model_reserve)
     int64_t max_batch = 0;
-    float* dz = nullptr;                // [max_batch][16]
-    float* acts = nullptr;              // stored hidden activations
-    float* delta = nullptr;             // backward deltas of hidden layers
-    float* delta1 = nullptr;            // delta at the first hidden layer (FP32)
-    float* train_acc = nullptr;         // loss sums and flags [32]
+    float* zbuf = nullptr;              // [max_batch][H] heads of the training forward
+    float* dz = nullptr;                // [max_batch][16] d loss / d heads (loss-scaled, padded)
+    float* acts = nullptr;              // [hidden_layers][max_batch][hidden_width] post-ReLU
+    float* delta = nullptr;             // [hidden_layers][max_batch][hidden_width] d loss / d pre-activation
+    double* dacc = nullptr;             // [16] loss sums, loss scale, Adam bias corrections
+    int64_t* tcount = nullptr;          // [16] positives, step, clean steps, flags
     int32_t step = 0;
-    float loss_scale = 1.f;
-    int32_t good_steps = 0;
     bool params_set = false;
-    int64_t* counters = nullptr;        // [8] device work counters
+    int64_t* counters = nullptr;        // [8] query work counters
 };
 
 namespace nif {
@@ -92,6 +91,7 @@ int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t
 int model_alloc(nif_model* m);
 void model_free(nif_model* m);
 int model_sync_working(nif_model* m, hipStream_t st);
+int model_sync_mlp(nif_model* m, hipStream_t st);
 int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh,
                     int32_t dh_stride, float* dx0, float* dx1, int32_t precision, hipStream_t st);
 int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg,

@@ -15,7 +15,7 @@ __global__ void k_sync_tables(const float* __restrict__ src, __half* __restrict_
 }
 
 struct LayerMap {
-    int64_t w_off[kMaxLayers], b_off[kMaxLayers], wp_off[kMaxLayers], bp_off[kMaxLayers];
+    int64_t w_off[kMaxLayers], b_off[kMaxLayers], wp_off[kMaxLayers], bp_off[kMaxLayers], wt_off[kMaxLayers];
     int32_t in[kMaxLayers], out[kMaxLayers], out_pad[kMaxLayers];
     int32_t n_layers;
 };
@@ -41,6 +41,13 @@ __global__ void k_sync_mlp(LayerMap lm, const float* __restrict__ src, float* __
         f32[dst] = v;
         bf16[dst] = f2bf(v);
         f16[dst] = __float2half_rn(v);
+        if (i < nw && layer > 0) {      // transposed copy [in][out_pad] for the backward
+            const int64_t row = i / nin, col = i % nin;
+            const int64_t t = lm.wt_off[layer] + col * npad + row;
+            f32[t] = v;
+            bf16[t] = f2bf(v);
+            f16[t] = __float2half_rn(v);
+        }
     }
 }
 
@@ -50,10 +57,16 @@ static LayerMap layer_map(const nif_model* m) {
     lm.n_layers = m->n_layers;
     for (int i = 0; i < m->n_layers; ++i) {
         lm.w_off[i] = m->w_off[i]; lm.b_off[i] = m->b_off[i];
-        lm.wp_off[i] = m->wp_off[i]; lm.bp_off[i] = m->bp_off[i];
+        lm.wp_off[i] = m->wp_off[i]; lm.bp_off[i] = m->bp_off[i]; lm.wt_off[i] = m->wt_off[i];
         lm.in[i] = m->dims[i]; lm.out[i] = m->dims[i + 1]; lm.out_pad[i] = m->dims_pad[i + 1];
     }
     return lm;
+}
+
+int model_sync_mlp(nif_model* m, hipStream_t st) {
+    hipLaunchKernelGGL(k_sync_mlp, dim3(64, m->n_layers), dim3(256), 0, st, layer_map(m), m->mlp, m->mlp_pad_f32,
+                       m->mlp_pad_bf16, m->mlp_pad_f16);
+    return check_hip(hipGetLastError(), "k_sync_mlp");
 }
 
 int model_sync_working(nif_model* m, hipStream_t st) {
@@ -91,13 +104,16 @@ int model_alloc(nif_model* m) {
     m->dims_pad = m->dims;
     m->dims_pad.back() = 16;
     m->w_off.assign(m->n_layers, 0); m->b_off.assign(m->n_layers, 0);
-    m->wp_off.assign(m->n_layers, 0); m->bp_off.assign(m->n_layers, 0);
+    m->wp_off.assign(m->n_layers, 0); m->bp_off.assign(m->n_layers, 0); m->wt_off.assign(m->n_layers, 0);
     int64_t off = 0, offp = 0;
     for (int i = 0; i < m->n_layers; ++i) {
         m->w_off[i] = off; off += (int64_t)m->dims[i + 1] * m->dims[i];
         m->b_off[i] = off; off += m->dims[i + 1];
         m->wp_off[i] = offp; offp += (int64_t)m->dims_pad[i + 1] * m->dims_pad[i];
         m->bp_off[i] = offp; offp += m->dims_pad[i + 1];
+    }
+    for (int i = 1; i < m->n_layers; ++i) {
+        m->wt_off[i] = offp; offp += (int64_t)m->dims_pad[i + 1] * m->dims_pad[i];
     }
     m->n_mlp = off;
     m->n_mlp_pad = offp;
@@ -111,7 +127,6 @@ int model_alloc(nif_model* m) {
     if ((rc = dalloc(&m->s, 8, "s"))) return rc;
     if ((rc = dalloc(&m->g_tables, m->n_table, "table grads"))) return rc;
     if ((rc = dalloc(&m->g_mlp, m->n_mlp, "mlp grads"))) return rc;
-    if ((rc = dalloc(&m->g_mlp_pad, m->n_mlp_pad, "padded mlp grads"))) return rc;
     if ((rc = dalloc(&m->g_s, 8, "s grads"))) return rc;
     if ((rc = dalloc(&m->m_tables, m->n_table, "adam m"))) return rc;
     if ((rc = dalloc(&m->v_tables, m->n_table, "adam v"))) return rc;
@@ -120,14 +135,15 @@ int model_alloc(nif_model* m) {
     if ((rc = dalloc(&m->m_s, 8, "adam m"))) return rc;
     if ((rc = dalloc(&m->v_s, 8, "adam v"))) return rc;
     if ((rc = dalloc(&m->counters, 8, "counters"))) return rc;
-    if ((rc = dalloc(&m->train_acc, 64, "train accumulators"))) return rc;
+    if ((rc = dalloc(&m->dacc, 16, "train accumulators"))) return rc;
+    if ((rc = dalloc(&m->tcount, 16, "train counters"))) return rc;
     return NIF_OK;
 }
 
 void model_free(nif_model* m) {
     void* ps[] = {m->tables, m->tables_h, m->mlp, m->mlp_pad_f32, m->mlp_pad_bf16, m->mlp_pad_f16, m->s,
-                  m->g_tables, m->g_mlp, m->g_mlp_pad, m->g_s, m->m_tables, m->v_tables, m->m_mlp, m->v_mlp,
-                  m->m_s, m->v_s, m->counters, m->train_acc, m->dz, m->acts, m->delta, m->delta1};
+                  m->g_tables, m->g_mlp, m->g_s, m->m_tables, m->v_tables, m->m_mlp, m->v_mlp,
+                  m->m_s, m->v_s, m->counters, m->dacc, m->tcount, m->zbuf, m->dz, m->acts, m->delta};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }

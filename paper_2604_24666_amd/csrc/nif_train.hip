@@ -1,4 +1,21 @@
-// Training: multi-task loss, hand-written backward and Adam.
+// Training step: uncertainty-weighted multi-task loss, hand-written backward and Adam.
+//
+// "Uncertainty-Weighted Multi-Task Loss": each task i has a learnable s_i = log sigma_i^2;
+// regression tasks (distance as MSE of logs with a ReLU output, normal as 1 - cosine,
+// albedo as L1 of sigmoid outputs) weigh 0.5 exp(-s) L + 0.5 s, classification tasks
+// (occlusion, material; cross-entropy) exp(-s) L + 0.5 s.  Reading used here: occlusion is
+// averaged over the whole batch, the geometric and appearance terms over the samples whose
+// label is a hit; the distance epsilon is 1e-4.  The optimizer (Adam with bias correction)
+// is not named by the paper.
+//
+// Launch sequence of one step (all on the caller's stream, no host synchronisation):
+//   begin / count positives -> zero gradients -> forward (stores hidden activations) ->
+//   loss and d loss / d heads (loss-scaled) -> MLP backward on MFMA (transposed weights,
+//   deltas chained in registers) -> split-K dW GEMMs on MFMA -> encoding backward (the
+//   encoding is recomputed chunk by chunk, d enc = W0^T delta, FP32 atomic scatter-add into
+//   the table gradients with the trilinear weights, dW0) -> non-finite check -> finalize
+//   (losses, d/ds, dynamic loss scale) -> Adam on all parameters (FP16 table copy refreshed
+//   in place) -> refresh of the MLP working copies.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -8,13 +25,21 @@
 
 namespace nif {
 
+NetParams make_net_params(const nif_model* m, int32_t precision);
+
+enum { TC_NPOS = 0, TC_STEP = 1, TC_GOOD = 2, TC_NONFINITE = 3, TC_SKIP = 4 };
+enum { DA_SUM = 0, DA_SCALE = 5, DA_SCALE_USED = 6, DA_C1 = 7, DA_C2 = 8 };
+constexpr float kDistEps = 1e-4f;
+constexpr int kGrowInterval = 1000;
+
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
-    for (float** p : {&m->dz, &m->acts, &m->delta, &m->delta1})
+    for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
     m->max_batch = 0;
     const int64_t hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
-    const struct { float** p; int64_t n; } a[] = {{&m->dz, B * 16}, {&m->acts, B * hw * nh}, {&m->delta, B * hw * nh}, {&m->delta1, B * hw}};
+    const struct { float** p; int64_t n; } a[] = {{&m->zbuf, B * m->H}, {&m->dz, B * 16}, {&m->acts, B * hw * nh},
+                                                  {&m->delta, B * hw * nh}};
     for (auto& x : a)
         if (hipMalloc((void**)x.p, sizeof(float) * (size_t)std::max<int64_t>(x.n, 1)) != hipSuccess) {
             (void)hipGetLastError();
@@ -24,13 +49,649 @@ int model_reserve(nif_model* m, int64_t B) {
     return NIF_OK;
 }
 
-int backward_launch(nif_model*, const float*, const float*, int64_t, const float*, int32_t, float*, float*, int32_t,
-                    hipStream_t) {
-    return fail(NIF_E_UNSUPPORTED, "backward not built yet");
+// ------------------------------------------------------------------ small kernels
+
+__global__ void k_zero_f32(float* __restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = 0.f;
 }
 
-int train_step_launch(nif_model*, const nif_batch*, int64_t, const nif_train_cfg*, float*, hipStream_t) {
-    return fail(NIF_E_UNSUPPORTED, "train step not built yet");
+__global__ void k_train_begin(double* dacc, int64_t* tcount, float scale_init) {
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 5; ++k) dacc[DA_SUM + k] = 0.0;
+    tcount[TC_NPOS] = 0;
+    tcount[TC_NONFINITE] = 0;
+    if (!(dacc[DA_SCALE] > 0.0)) dacc[DA_SCALE] = scale_init;
+    dacc[DA_SCALE_USED] = dacc[DA_SCALE];
+}
+
+__global__ void k_count_pos(const uint8_t* __restrict__ hit, int64_t B, int64_t* tcount) {
+    int64_t c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += (int64_t)gridDim.x * blockDim.x) c += hit[i] ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&tcount[TC_NPOS], (unsigned long long)c);
+}
+
+__global__ void k_pad_dz(const float* __restrict__ dh, int H, int64_t B, float* __restrict__ dz) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B * 16; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / 16;
+        const int h = (int)(i % 16);
+        dz[i] = h < H ? dh[r * H + h] : 0.f;
+    }
+}
+
+__device__ __forceinline__ float sigm(float v) { return 1.f / (1.f + expf(-v)); }
+
+// Per-sample loss terms and d loss / d heads (times the loss scale), padded to 16 columns.
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H, int64_t B,
+                                              const uint8_t* __restrict__ lhit, const float* __restrict__ lt,
+                                              const float* __restrict__ ln, const float* __restrict__ la,
+                                              const int32_t* __restrict__ lm, const float* __restrict__ s,
+                                              const int64_t* __restrict__ tcount, double* __restrict__ dacc,
+                                              float* __restrict__ dz) {
+    const int M = H - 8;
+    const double P = (double)tcount[TC_NPOS];
+    const float scale = (float)dacc[DA_SCALE_USED];
+    const float w0 = expf(-s[0]), w1 = 0.5f * expf(-s[1]), w2 = 0.5f * expf(-s[2]), w3 = 0.5f * expf(-s[3]),
+                w4 = expf(-s[4]);
+    const float invB = (float)(1.0 / (double)B), invP = P > 0 ? (float)(1.0 / P) : 0.f;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += (int64_t)gridDim.x * blockDim.x) {
+        const float* zi = z + i * H;
+        float g[16];
+#pragma unroll
+        for (int h = 0; h < 16; ++h) g[h] = 0.f;
+        const float y = lhit[i] ? 1.f : 0.f;
+        const float z0 = zi[0];
+        acc[0] += fmaxf(z0, 0.f) - z0 * y + log1pf(expf(-fabsf(z0)));
+        g[0] = w0 * (sigm(z0) - y) * invB;
+        if (lhit[i] && P > 0) {
+            const float dh = fmaxf(zi[1], 0.f);
+            const float r = logf(dh + kDistEps) - logf(lt[i] + kDistEps);
+            acc[1] += (double)r * r;
+            if (zi[1] > 0.f) g[1] = w1 * 2.f * r / (dh + kDistEps) * invP;
+            const float nt[3] = {ln[i], ln[B + i], ln[2 * B + i]};
+            const float v[3] = {zi[2], zi[3], zi[4]};
+            const float vl = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const float den = fmaxf(vl, 1e-12f);
+            const float nh[3] = {v[0] / den, v[1] / den, v[2] / den};
+            const float c = nh[0] * nt[0] + nh[1] * nt[1] + nh[2] * nt[2];
+            acc[2] += 1.0 - c;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[2 + a] = w2 * (vl > 1e-12f ? -(nt[a] - nh[a] * c) / vl : -nt[a] / 1e-12f) * invP;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float ah = sigm(zi[5 + a]);
+                const float df = ah - la[a * B + i];
+                acc[3] += fabsf(df) / 3.0;
+                const float sg = df > 0.f ? 1.f : (df < 0.f ? -1.f : 0.f);
+                g[5 + a] = w3 * sg * ah * (1.f - ah) * invP / 3.f;
+            }
+            if (M == 1) {
+                const float ym = lm[i] ? 1.f : 0.f;
+                acc[4] += fmaxf(zi[8], 0.f) - zi[8] * ym + log1pf(expf(-fabsf(zi[8])));
+                g[8] = w4 * (sigm(zi[8]) - ym) * invP;
+            } else {
+                const int mi = min(max(lm[i], 0), M - 1);   // ids outside [0, M) are clamped
+                float mx = zi[8];
+                for (int c2 = 1; c2 < M; ++c2) mx = fmaxf(mx, zi[8 + c2]);
+                float se = 0.f;
+                for (int c2 = 0; c2 < M; ++c2) se += expf(zi[8 + c2] - mx);
+                const float lse = mx + logf(se);
+                acc[4] += lse - zi[8 + mi];
+#pragma unroll
+                for (int c2 = 0; c2 < 8; ++c2)
+                    if (c2 < M) g[8 + c2] = w4 * (expf(zi[8 + c2] - lse) - (c2 == mi ? 1.f : 0.f)) * invP;
+            }
+        }
+        float4* dst = reinterpret_cast<float4*>(dz + i * 16);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) dst[h] = make_float4(scale * g[4 * h], scale * g[4 * h + 1], scale * g[4 * h + 2], scale * g[4 * h + 3]);
+    }
+    __shared__ double red[4][5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        for (int k = 0; k < 5; ++k) red[w][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i][threadIdx.x];
+        atomicAdd(&dacc[DA_SUM + threadIdx.x], t);
+    }
+}
+
+// ------------------------------------------------------------------ MLP backward (MFMA)
+
+struct BwdParams {
+    const void* Wt[kMaxLayers];   // transposed padded weights of layers >= 1, [in][out_pad]
+    int32_t n_hidden;
+};
+
+// delta[k][seg][HW] = d loss / d pre-activation of hidden layer k, chained from dz through the
+// transposed weights: d in^T = W^T x d out^T, then masked by ReLU'(stored activation).
+template <int HW, int PREC>
+__global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __restrict__ dz,
+                                                 const float* __restrict__ acts, float* __restrict__ delta,
+                                                 int64_t B) {
+    constexpr int CB = HW >= 128 ? 2 : 4;
+    constexpr int OB = HW / 16;
+    const int lane = lane_id(), q = lane >> 4, j = lane & 15;
+    const int64_t per_tile = 16 * CB;
+    const int64_t n_tiles = (B + per_tile - 1) / per_tile;
+    const int64_t wave_g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t tile = wave_g; tile < n_tiles; tile += n_waves) {
+        const int64_t seg0 = tile * per_tile;
+        floatx4 dh[OB][CB];
+        // output layer: d out from dz (16 padded outputs)
+        {
+            floatx4 dout[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int64_t seg = seg0 + cb * 16 + j;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (seg < B) v = *reinterpret_cast<const float4*>(dz + seg * 16 + 4 * q);
+                dout[cb] = floatx4{v.x, v.y, v.z, v.w};
+            }
+#pragma unroll
+            for (int ib = 0; ib < OB; ++ib)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                    if constexpr (PREC == P_FP32) {
+                        const float4 wv = *reinterpret_cast<const float4*>(
+                            reinterpret_cast<const float*>(bp.Wt[bp.n_hidden]) + (size_t)(ib * 16 + j) * 16 + 4 * q);
+                        const float wf[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc = mfma32(wf[r], dout[cb][r], acc);
+                    } else {
+                        const shortx4 wa = *reinterpret_cast<const shortx4*>(
+                            reinterpret_cast<const uint16_t*>(bp.Wt[bp.n_hidden]) + (size_t)(ib * 16 + j) * 16 + 4 * q);
+                        acc = mfma16<PREC>(wa, pack4<PREC>(dout[cb][0], dout[cb][1], dout[cb][2], dout[cb][3]), acc);
+                    }
+                    dh[ib][cb] = acc;
+                }
+        }
+        for (int k = bp.n_hidden - 1;; --k) {
+            // mask with ReLU'(h_k) and store delta_k
+#pragma unroll
+            for (int ib = 0; ib < OB; ++ib)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int64_t seg = seg0 + cb * 16 + j;
+                    if (seg < B) {
+                        const size_t o = ((size_t)k * B + seg) * HW + ib * 16 + 4 * q;
+                        const float4 a = *reinterpret_cast<const float4*>(acts + o);
+                        dh[ib][cb][0] = a.x > 0.f ? dh[ib][cb][0] : 0.f;
+                        dh[ib][cb][1] = a.y > 0.f ? dh[ib][cb][1] : 0.f;
+                        dh[ib][cb][2] = a.z > 0.f ? dh[ib][cb][2] : 0.f;
+                        dh[ib][cb][3] = a.w > 0.f ? dh[ib][cb][3] : 0.f;
+                        *reinterpret_cast<float4*>(delta + o) = make_float4(dh[ib][cb][0], dh[ib][cb][1], dh[ib][cb][2], dh[ib][cb][3]);
+                    } else {
+                        dh[ib][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    }
+                }
+            if (k == 0) break;
+            // through hidden layer k (affine layer k: hidden k-1 -> hidden k)
+            floatx4 dn[OB][CB];
+#pragma unroll
+            for (int ib = 0; ib < OB; ++ib)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) dn[ib][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ib = 0; ib < OB; ++ib)
+#pragma unroll
+                for (int ob = 0; ob < OB; ++ob) {
+                    if constexpr (PREC == P_FP32) {
+                        const float4 wv = *reinterpret_cast<const float4*>(
+                            reinterpret_cast<const float*>(bp.Wt[k]) + (size_t)(ib * 16 + j) * HW + ob * 16 + 4 * q);
+                        const float wf[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb) dn[ib][cb] = mfma32(wf[r], dh[ob][cb][r], dn[ib][cb]);
+                    } else {
+                        const shortx4 wa = *reinterpret_cast<const shortx4*>(
+                            reinterpret_cast<const uint16_t*>(bp.Wt[k]) + (size_t)(ib * 16 + j) * HW + ob * 16 + 4 * q);
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            dn[ib][cb] = mfma16<PREC>(wa, pack4<PREC>(dh[ob][cb][0], dh[ob][cb][1], dh[ob][cb][2], dh[ob][cb][3]), dn[ib][cb]);
+                    }
+                }
+#pragma unroll
+            for (int ib = 0; ib < OB; ++ib)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) dh[ib][cb] = dn[ib][cb];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ dW of layers >= 1 (MFMA)
+// gW[M_real][N] += sum over samples of d_out[s][m] * h_in[s][n]; gb[m] += sum d_out[s][m].
+// Split-K over samples; each block accumulates its chunk in registers (v_mfma_f32_16x16x4f32
+// from LDS-staged 32-sample tiles) and adds it to the FP32 gradient with atomics.
+__global__ void __launch_bounds__(256) k_dw(const float* __restrict__ dsrc, int dstride, int M_pad, int M_real,
+                                            const float* __restrict__ hin, int N, int64_t B, int64_t Kc,
+                                            float* __restrict__ gW, float* __restrict__ gb) {
+    __shared__ float sd[32][129];
+    __shared__ float sh[32][129];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
+    const int Tn = N / 16, T = (M_pad / 16) * Tn;
+    const int64_t k0 = (int64_t)blockIdx.x * Kc, k1 = std::min<int64_t>(B, k0 + Kc);
+    floatx4 acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int64_t kb = k0; kb < k1; kb += 32) {
+        for (int i = tid; i < 32 * M_pad; i += 256) {
+            const int sm = i / M_pad, mm = i % M_pad;
+            sd[sm][mm] = kb + sm < k1 ? dsrc[(kb + sm) * dstride + mm] : 0.f;
+        }
+        for (int i = tid; i < 32 * N; i += 256) {
+            const int sm = i / N, nn = i % N;
+            sh[sm][nn] = kb + sm < k1 ? hin[(kb + sm) * N + nn] : 0.f;
+        }
+        __syncthreads();
+        if (tid < M_pad)
+            for (int sm = 0; sm < 32; ++sm) bsum += sd[sm][tid];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = w + 4 * u;
+            if (t < T) {
+                const int mt = t / Tn, nt = t % Tn;
+#pragma unroll
+                for (int st = 0; st < 8; ++st)
+                    acc[u] = mfma32(sd[st * 4 + q][mt * 16 + j], sh[st * 4 + q][nt * 16 + j], acc[u]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int t = w + 4 * u;
+        if (t < T) {
+            const int mt = t / Tn, nt = t % Tn;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = mt * 16 + 4 * q + r;
+                if (row < M_real) unsafeAtomicAdd(&gW[(size_t)row * N + nt * 16 + j], acc[u][r]);
+            }
+        }
+    }
+    if (tid < M_real) unsafeAtomicAdd(&gb[tid], bsum);
+}
+
+// ------------------------------------------------------------------ encoding backward
+// Grid (sample splits, 2 S chunks).  Chunk c = (point p, PE sample s) owns encoding features
+// [c FW, (c+1) FW), FW = 2 L.  Per tile of 64 samples: recompute the chunk's features
+// (thread <-> one sample, levels w, w+4, ...), d enc = delta_0 . W0[:, chunk] (LDS), scatter
+// d enc times the trilinear weights into the FP32 table gradient (atomics), accumulate
+// dW0[:, chunk] += delta_0^T enc and, for chunk 0, db0.  Optional d x through phi and gamma.
+struct EncBwdParams {
+    EncParams enc;
+    const float* W0;     // FP32 [HW][E]
+    int32_t HW, E, S;
+    float* g_tables;
+    float* gW0;
+    float* gb0;
+    float* dx0;          // nullable SoA [3][B]
+    float* dx1;
+};
+
+__device__ __forceinline__ double pe_direct(int s, double x, double* dsdx) {
+    if (s == 0) { *dsdx = 1.0; return x; }
+    const int k = (s - 1) >> 1;
+    const double f = ldexp(1.0, k);
+    double sn, cs;
+    sincos(f * x, &sn, &cs);
+    if ((s & 1) == 1) { *dsdx = 0.5 * f * cs; return 0.5 * (sn + 1.0); }
+    *dsdx = -0.5 * f * sn;
+    return 0.5 * (cs + 1.0);
+}
+
+__global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __restrict__ x0,
+                                                 const float* __restrict__ x1, const float* __restrict__ delta0,
+                                                 int64_t B, int64_t Kc) {
+    const int L = P.enc.L, FW = 2 * L, HW = P.HW, E = P.E;
+    const int c = blockIdx.y, p = c / P.S, s = c % P.S;
+    const int tid = threadIdx.x, seg_l = tid & 63, lw = tid >> 6;   // levels lw, lw+4, lw+8, lw+12
+    __shared__ float sW[128][33];   // W0[:, chunk]
+    __shared__ float sD[64][129];   // delta_0 tile
+    __shared__ float sE[64][33];    // recomputed encoding
+    __shared__ float sG[64][33];    // d encoding
+    for (int i = tid; i < HW * FW; i += 256) {
+        const int o = i / FW, f = i % FW;
+        sW[o][f] = P.W0[(size_t)o * E + c * FW + f];
+    }
+    const int n_items = HW * FW / 256;   // dW0 items per thread (<= 16)
+    float accW[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) accW[u] = 0.f;
+    float bsum = 0.f;
+    const float* xs = p == 0 ? x0 : x1;
+    float* dxs = p == 0 ? P.dx0 : P.dx1;
+    const int64_t k0 = (int64_t)blockIdx.x * Kc, k1 = std::min<int64_t>(B, k0 + Kc);
+    const uint32_t mask = (1u << P.enc.log2T) - 1u;
+    __syncthreads();
+    for (int64_t seg0 = k0; seg0 < k1; seg0 += 64) {
+        const int64_t seg = seg0 + seg_l;
+        const bool valid = seg < k1;
+        for (int i = tid; i < 64 * HW; i += 256) {
+            const int sm = i / HW, o = i % HW;
+            sD[sm][o] = seg0 + sm < k1 ? delta0[(seg0 + sm) * HW + o] : 0.f;
+        }
+        // (a) features of this thread's sample and levels
+        double smp[3], dsdx[3];
+        float inside[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float xv = valid ? xs[a * B + seg] : 0.5f;
+            inside[a] = (xv >= 0.f && xv <= 1.f) ? 1.f : 0.f;
+            smp[a] = pe_direct(s, fmin(fmax((double)xv, 0.0), 1.0), &dsdx[a]);
+        }
+        uint32_t ci[4][3];
+        float cw[4][3];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int l = lw + 4 * v;
+            if (l < L) {
+                const int N = P.enc.res[l];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) grid_axis(smp[a], N, ci[v][a], cw[v][a]);
+                const float2 f = grid_lookup(P.enc, l, smp[0], smp[1], smp[2]);
+                sE[seg_l][2 * l] = f.x;
+                sE[seg_l][2 * l + 1] = f.y;
+            }
+        }
+        __syncthreads();
+        // (b) d enc = delta_0 . W0[:, chunk]
+        for (int f = lw; f < FW; f += 4) {
+            float sacc = 0.f;
+            for (int o = 0; o < HW; ++o) sacc = fmaf(sD[seg_l][o], sW[o][f], sacc);
+            sG[seg_l][f] = sacc;
+        }
+        __syncthreads();
+        // (c) scatter into the table gradient (and d x)
+        if (valid) {
+            float dpos[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int l = lw + 4 * v;
+                if (l >= L) continue;
+                const int N = P.enc.res[l];
+                const bool dense = (P.enc.dense_mask >> l) & 1u;
+                const uint32_t n1 = (uint32_t)N + 1u;
+                const float g0 = sG[seg_l][2 * l], g1 = sG[seg_l][2 * l + 1];
+                float* gt = P.g_tables + ((size_t)l << P.enc.log2T) * 2;
+                float dl[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc) {
+                    const uint32_t bx = cc & 1, by = (cc >> 1) & 1, bz = (cc >> 2) & 1;
+                    const uint32_t idx = grid_index(ci[v][0] + bx, ci[v][1] + by, ci[v][2] + bz, n1, dense, mask);
+                    const float fx = bx ? cw[v][0] : 1.f - cw[v][0];
+                    const float fy = by ? cw[v][1] : 1.f - cw[v][1];
+                    const float fz = bz ? cw[v][2] : 1.f - cw[v][2];
+                    const float wt = fx * fy * fz;
+                    unsafeAtomicAdd(&gt[2 * idx], wt * g0);
+                    unsafeAtomicAdd(&gt[2 * idx + 1], wt * g1);
+                    if (dxs) {
+                        float2 tv;
+                        const size_t e = ((size_t)l << P.enc.log2T) + idx;
+                        if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[e]);
+                        else tv = reinterpret_cast<const float2*>(P.enc.tab)[e];
+                        const float gd = g0 * tv.x + g1 * tv.y;
+                        dl[0] += gd * (bx ? 1.f : -1.f) * fy * fz;
+                        dl[1] += gd * (by ? 1.f : -1.f) * fx * fz;
+                        dl[2] += gd * (bz ? 1.f : -1.f) * fx * fy;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dpos[a] += dl[a] * (float)N;
+            }
+            if (dxs)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) unsafeAtomicAdd(&dxs[a * B + seg], dpos[a] * (float)dsdx[a] * inside[a]);
+        }
+        // (d) dW0[:, chunk] and db0
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (u < n_items) {
+                const int it = tid + 256 * u, o = it % HW, f = it / HW;
+                float sacc = 0.f;
+                for (int sm = 0; sm < 64; ++sm) sacc = fmaf(sD[sm][o], sE[sm][f], sacc);
+                accW[u] += sacc;
+            }
+        }
+        if (c == 0 && tid < HW)
+            for (int sm = 0; sm < 64; ++sm) bsum += sD[sm][tid];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        if (u < n_items) {
+            const int it = tid + 256 * u, o = it % HW, f = it / HW;
+            unsafeAtomicAdd(&P.gW0[(size_t)o * E + c * FW + f], accW[u]);
+        }
+    }
+    if (c == 0 && tid < HW) unsafeAtomicAdd(&P.gb0[tid], bsum);
+}
+
+// ------------------------------------------------------------------ step bookkeeping
+
+__global__ void k_check_finite(const float* __restrict__ a, int64_t n, int64_t* tcount) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(a[i]);
+    if (__ballot(bad) && lane_id() == 0) tcount[TC_NONFINITE] = 1;
+}
+
+// Losses, d total / d s, dynamic loss scale, skip decision, Adam bias corrections (one thread).
+__global__ void k_finalize(double* dacc, int64_t* tcount, const float* s, float* g_s, float* losses, int64_t B,
+                           int dynamic, float beta1, float beta2) {
+    if (threadIdx.x != 0) return;
+    const double P = (double)tcount[TC_NPOS];
+    double Ls[5], w[5];
+    Ls[0] = dacc[DA_SUM] / (double)B;
+    for (int k = 1; k < 5; ++k) Ls[k] = P > 0 ? dacc[DA_SUM + k] / P : 0.0;
+    w[0] = exp(-(double)s[0]); w[1] = 0.5 * exp(-(double)s[1]); w[2] = 0.5 * exp(-(double)s[2]);
+    w[3] = 0.5 * exp(-(double)s[3]); w[4] = exp(-(double)s[4]);
+    double total = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        total += w[k] * Ls[k] + 0.5 * s[k];
+        g_s[k] = (float)(-w[k] * Ls[k] + 0.5);
+        losses[k] = (float)Ls[k];
+        losses[6 + k] = s[k];
+    }
+    losses[5] = (float)total;
+    const bool bad = tcount[TC_NONFINITE] != 0 || !isfinite(total);
+    double scale = dacc[DA_SCALE];
+    losses[11] = (float)dacc[DA_SCALE_USED];
+    if (bad) {
+        tcount[TC_SKIP] = 1;
+        tcount[TC_GOOD] = 0;
+        if (dynamic) scale = fmax(scale * 0.5, 1.0 / 65536.0);
+    } else {
+        tcount[TC_SKIP] = 0;
+        tcount[TC_STEP] += 1;
+        tcount[TC_GOOD] += 1;
+        if (dynamic && tcount[TC_GOOD] >= kGrowInterval) { scale *= 2.0; tcount[TC_GOOD] = 0; }
+    }
+    dacc[DA_SCALE] = scale;
+    const double t = (double)tcount[TC_STEP];
+    dacc[DA_C1] = 1.0 - pow((double)beta1, t);
+    dacc[DA_C2] = 1.0 - pow((double)beta2, t);
+    losses[12] = bad ? 1.f : 0.f;
+    losses[13] = (float)P;
+    losses[14] = 0.f;
+    losses[15] = 0.f;
+}
+
+struct AdamParams {
+    float *tables, *g_tables, *m_tables, *v_tables;
+    __half* tables_h;
+    float *mlp, *g_mlp, *m_mlp, *v_mlp;
+    float *s, *g_s, *m_s, *v_s;
+    int64_t n_table, n_mlp;
+    float lr_table, lr_mlp, lr_s, beta1, beta2, eps;
+};
+
+__device__ __forceinline__ float adam_one(float& th, float g, float& m, float& v, float lr, float b1, float b2,
+                                          float eps, float c1, float c2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    const float mh = m / c1, vh = v / c2;
+    th -= lr * mh / (sqrtf(vh) + eps);
+    return th;
+}
+
+__global__ void k_adam(AdamParams A, const double* __restrict__ dacc, const int64_t* __restrict__ tcount) {
+    if (tcount[TC_SKIP]) return;
+    const float inv = (float)(1.0 / dacc[DA_SCALE_USED]);
+    const float c1 = (float)dacc[DA_C1], c2 = (float)dacc[DA_C2];
+    const int64_t n = A.n_table + A.n_mlp + 5;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < A.n_table) {
+            float th = A.tables[i], m = A.m_tables[i], v = A.v_tables[i];
+            adam_one(th, A.g_tables[i] * inv, m, v, A.lr_table, A.beta1, A.beta2, A.eps, c1, c2);
+            A.tables[i] = th; A.m_tables[i] = m; A.v_tables[i] = v;
+            if (A.tables_h) A.tables_h[i] = __float2half_rn(th);
+        } else if (i < A.n_table + A.n_mlp) {
+            const int64_t k = i - A.n_table;
+            float th = A.mlp[k], m = A.m_mlp[k], v = A.v_mlp[k];
+            adam_one(th, A.g_mlp[k] * inv, m, v, A.lr_mlp, A.beta1, A.beta2, A.eps, c1, c2);
+            A.mlp[k] = th; A.m_mlp[k] = m; A.v_mlp[k] = v;
+        } else {
+            const int64_t k = i - A.n_table - A.n_mlp;
+            float th = A.s[k], m = A.m_s[k], v = A.v_s[k];
+            adam_one(th, A.g_s[k], m, v, A.lr_s, A.beta1, A.beta2, A.eps, c1, c2);
+            A.s[k] = th; A.m_s[k] = m; A.v_s[k] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host launchers
+
+static int cus() {
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+
+static unsigned grid_for(int64_t n, int per = 256, int64_t cap_per_cu = 8) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, cus() * cap_per_cu));
+}
+
+template <int HW, int PREC>
+static void launch_mlp_bwd(const BwdParams& bp, const float* dz, const float* acts, float* delta, int64_t B, hipStream_t st) {
+    constexpr int CB = HW >= 128 ? 2 : 4;
+    const int64_t tiles = (B + 16 * CB - 1) / (16 * CB);
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, cus() * 8));
+    hipLaunchKernelGGL((k_mlp_bwd<HW, PREC>), dim3(blocks), dim3(256), 0, st, bp, dz, acts, delta, B);
+}
+
+template <int PREC>
+static int dispatch_mlp_bwd(int hw, const BwdParams& bp, const float* dz, const float* acts, float* delta, int64_t B,
+                            hipStream_t st) {
+    switch (hw) {
+        case 16: launch_mlp_bwd<16, PREC>(bp, dz, acts, delta, B, st); break;
+        case 32: launch_mlp_bwd<32, PREC>(bp, dz, acts, delta, B, st); break;
+        case 64: launch_mlp_bwd<64, PREC>(bp, dz, acts, delta, B, st); break;
+        case 128: launch_mlp_bwd<128, PREC>(bp, dz, acts, delta, B, st); break;
+        default: return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
+    }
+    return NIF_OK;
+}
+
+// Backward from dz (already in m->dz) to the gradient accumulators; activations in m->acts.
+static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t B, float* dx0, float* dx1,
+                         int32_t precision, hipStream_t st) {
+    const int hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
+    BwdParams bp;
+    memset(&bp, 0, sizeof(bp));
+    bp.n_hidden = nh;
+    for (int i = 1; i < m->n_layers; ++i) {
+        if (precision == NIF_PREC_FP32) bp.Wt[i] = m->mlp_pad_f32 + m->wt_off[i];
+        else if (precision == NIF_PREC_BF16) bp.Wt[i] = m->mlp_pad_bf16 + m->wt_off[i];
+        else bp.Wt[i] = m->mlp_pad_f16 + m->wt_off[i];
+    }
+    int rc;
+    if (precision == NIF_PREC_FP32) rc = dispatch_mlp_bwd<P_FP32>(hw, bp, m->dz, m->acts, m->delta, B, st);
+    else if (precision == NIF_PREC_BF16) rc = dispatch_mlp_bwd<P_BF16>(hw, bp, m->dz, m->acts, m->delta, B, st);
+    else rc = dispatch_mlp_bwd<P_FP16>(hw, bp, m->dz, m->acts, m->delta, B, st);
+    if (rc) return rc;
+    // dW of layers >= 1
+    const int64_t Kc = 2048;
+    const unsigned ksplit = (unsigned)((B + Kc - 1) / Kc);
+    for (int i = 1; i < m->n_layers; ++i) {
+        const bool out = i == m->n_layers - 1;
+        const float* dsrc = out ? m->dz : m->delta + (size_t)i * B * hw;
+        const int dstride = out ? 16 : hw;
+        const int M_pad = out ? 16 : hw, M_real = m->dims[i + 1];
+        const float* hin = m->acts + (size_t)(i - 1) * B * hw;
+        hipLaunchKernelGGL(k_dw, dim3(ksplit), dim3(256), 0, st, dsrc, dstride, M_pad, M_real, hin, hw, B, Kc,
+                           m->g_mlp + m->w_off[i], m->g_mlp + m->b_off[i]);
+    }
+    // encoding backward (layer 0)
+    EncBwdParams ep;
+    memset(&ep, 0, sizeof(ep));
+    ep.enc = make_net_params(m, NIF_PREC_FP32).enc;
+    ep.W0 = m->mlp_pad_f32 + m->wp_off[0];
+    ep.HW = hw; ep.E = m->E; ep.S = m->S;
+    ep.g_tables = m->g_tables; ep.gW0 = m->g_mlp + m->w_off[0]; ep.gb0 = m->g_mlp + m->b_off[0];
+    ep.dx0 = dx0; ep.dx1 = dx1;
+    const int64_t Kc0 = 2048;
+    hipLaunchKernelGGL(k_enc_bwd, dim3((unsigned)((B + Kc0 - 1) / Kc0), 2 * m->S), dim3(256), 0, st, ep, x0, x1,
+                       m->delta, B, Kc0);
+    return check_hip(hipGetLastError(), "backward launch");
+}
+
+int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh, int32_t, float* dx0,
+                    float* dx1, int32_t precision, hipStream_t st) {
+    if (B == 0) return NIF_OK;
+    int rc = forward_launch(m, x0, x1, B, m->zbuf, precision, m->acts, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_pad_dz, dim3(grid_for(B * 16)), dim3(256), 0, st, dh, m->H, B, m->dz);
+    if (dx0) hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * B)), dim3(256), 0, st, dx0, 3 * B);
+    if (dx1) hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * B)), dim3(256), 0, st, dx1, 3 * B);
+    return backward_core(m, x0, x1, B, dx0, dx1, precision, st);
+}
+
+int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg, float* losses,
+                      hipStream_t st) {
+    const int prec = cfg->precision;
+    const float scale_init = cfg->loss_scale_init > 0.f ? cfg->loss_scale_init : (prec == NIF_PREC_FP16 ? 32768.f : 1.f);
+    hipLaunchKernelGGL(k_train_begin, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, scale_init);
+    hipLaunchKernelGGL(k_count_pos, dim3(grid_for(B)), dim3(256), 0, st, b->hit, B, m->tcount);
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table);
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp);
+    int rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, m->zbuf, m->H, B, b->hit, b->t, b->n, b->a, b->m,
+                       m->s, m->tcount, m->dacc, m->dz);
+    if ((rc = backward_core(m, b->x0, b->x1, B, nullptr, nullptr, prec, st))) return rc;
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table, m->tcount);
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp, m->tcount);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, m->s, m->g_s, losses, B,
+                       prec != NIF_PREC_FP32 ? 1 : 0, cfg->beta1, cfg->beta2);
+    AdamParams A;
+    A.tables = m->tables; A.g_tables = m->g_tables; A.m_tables = m->m_tables; A.v_tables = m->v_tables;
+    A.tables_h = m->desc.table_dtype == NIF_TABLE_F16 ? m->tables_h : nullptr;
+    A.mlp = m->mlp; A.g_mlp = m->g_mlp; A.m_mlp = m->m_mlp; A.v_mlp = m->v_mlp;
+    A.s = m->s; A.g_s = m->g_s; A.m_s = m->m_s; A.v_s = m->v_s;
+    A.n_table = m->n_table; A.n_mlp = m->n_mlp;
+    A.lr_table = cfg->lr_table; A.lr_mlp = cfg->lr_mlp; A.lr_s = cfg->lr_s;
+    A.beta1 = cfg->beta1; A.beta2 = cfg->beta2; A.eps = cfg->eps;
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(m->n_table + m->n_mlp + 5)), dim3(256), 0, st, A, m->dacc, m->tcount);
+    if ((rc = check_hip(hipGetLastError(), "train step launch"))) return rc;
+    if ((rc = model_sync_mlp(m, st))) return rc;
+    ++m->step;
+    return NIF_OK;
 }
 
 }  // namespace nif

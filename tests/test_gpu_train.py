@@ -1,0 +1,153 @@
+"""GPU parity of the hand-written backward and of the training step against the FP64 oracle.
+
+Bar: gradients within 1e-4 relative, norm-wise per tensor and element-wise wherever
+|g| > 1e-3 max|g| (atomic accumulation order and FP32 arithmetic); losses within 1e-5
+relative; the first Adam update equals -lr g / (|g| + eps) element-wise."""
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import pytest
+
+import nif_synth as S
+from _helpers import dev_f32, model_params, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2604_24666_amd as P
+    return P
+
+
+def _batch(m, B, seed):
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(0.02, 0.98, (3, B)).astype(np.float32)
+    x1 = (x0 + rng.normal(scale=0.03, size=(3, B))).astype(np.float32)
+    hit = (rng.uniform(size=B) < 0.55).astype(np.uint8)
+    t = rng.uniform(0.001, 0.04, B).astype(np.float32)
+    nr = rng.normal(size=(3, B))
+    nr = (nr / np.linalg.norm(nr, axis=0)).astype(np.float32)
+    al = rng.uniform(0.1, 0.9, (3, B)).astype(np.float32)
+    mt = rng.integers(0, max(2, m.n_materials), B).astype(np.int32)
+    if m.n_materials == 1:
+        mt = np.minimum(mt, 1).astype(np.int32)
+    return x0, x1, hit, t, nr, al, mt
+
+
+def _grad_close(got, ref, name):
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    nrm = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    big = np.abs(ref) > 1e-3 * np.abs(ref).max()
+    el = (np.abs(got - ref)[big] / np.abs(ref)[big]).max(initial=0)
+    say(f"  {name:8s} norm-wise {nrm:.2e}  element-wise (|g| > 1e-3 max) {el:.2e}  n={int(big.sum())}")
+    assert nrm <= 1e-4 and el <= 1e-4, name
+
+
+MODELS = {
+    "torus16": dataclasses.replace(S.workload("torus16").model, hidden_width=32),
+    "spheres64": S.workload("spheres64").model,
+    "blobs128": S.workload("blobs128").model,
+}
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_backward_matches_oracle_gradient(orc, P, name):
+    import torch
+    m = MODELS[name]
+    say(f"backward {name}")
+    tab, prm, seen = model_params(m, 5, scale_tables=300.0)
+    B = 1500 + 37
+    x0, x1, hit, t, nr, al, mt = _batch(m, B, 6)
+    s = np.array([0.2, -0.1, 0.3, 0.1, -0.2])
+    L, gt, gp, gs, gx0, gx1, dz = orc.loss_grad(m, seen, prm.astype(np.float64), s, x0.T, x1.T, hit, t, nr.T, al.T, mt,
+                                                want_x=True, want_dz=True)
+    model = P.Model(m)
+    model.set_params(tab, prm, s.astype(np.float32))
+    P.nif_model_reserve(model.h, B)
+    dx0 = torch.empty((3, B), device="cuda")
+    dx1 = torch.empty((3, B), device="cuda")
+    P.nif_backward(model.h, dev_f32(x0), dev_f32(x1), B, dev_f32(dz), dx0, dx1, False, P.PREC_FP32)
+    g_t, g_p, _ = model.get_grads()
+    torch.cuda.synchronize()
+    _grad_close(g_t.cpu().numpy(), gt, "tables")
+    _grad_close(g_p.cpu().numpy(), gp, "mlp")
+    _grad_close(dx0.cpu().numpy().T, gx0, "d x0")
+    _grad_close(dx1.cpu().numpy().T, gx1, "d x1")
+
+
+def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3)):
+    import torch
+    x0, x1, hit, t, nr, al, mt = batch
+    keep = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
+            torch.as_tensor(mt).cuda()]
+    b = P.Batch(*[k.data_ptr() for k in keep])
+    cfg = P.TrainCfg(lr[0], lr[1], lr[2], 0.9, 0.999, 1e-8, prec, 0.0)
+    losses = torch.zeros(16, device="cuda")
+    P.nif_train_step(model.h, b, B, cfg, losses)
+    torch.cuda.synchronize()
+    return losses.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["torus16", "blobs128"])
+def test_train_step_matches_oracle(orc, P, name):
+    m = MODELS[name]
+    say(f"train step fp32 {name}")
+    tab, prm, seen = model_params(m, 7, scale_tables=300.0)
+    B = 2048 + 11
+    batch = _batch(m, B, 8)
+    x0, x1, hit, t, nr, al, mt = batch
+    s0 = np.zeros(5)
+    L, gt, gp, gs, _, _ = orc.loss_grad(m, seen, prm.astype(np.float64), s0, x0.T, x1.T, hit, t, nr.T, al.T, mt)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    P.nif_model_reserve(model.h, B)
+    losses = _train_step(P, model, batch, B)
+    say(f"  losses gpu {np.round(losses[:6], 6)}  oracle {np.round(L, 6)}")
+    assert np.all(np.abs(losses[:6] - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
+    assert losses[12] == 0 and losses[13] == hit.sum()
+    g_t, g_p, g_s = model.get_grads()
+    _grad_close(g_t.cpu().numpy(), gt, "tables")
+    _grad_close(g_p.cpu().numpy(), gp, "mlp")
+    assert np.abs(g_s.cpu().numpy() - gs).max() <= 1e-5 * np.abs(gs).max()
+    # first Adam step: theta - lr g / (|g| + eps), element-wise where the gradient is not tiny
+    t1, p1, s1 = [v.cpu().numpy().astype(np.float64) for v in model.get_params()]
+    for got, th0, g, lr in ((t1, tab.reshape(-1).astype(np.float64), gt.reshape(-1), 1e-2),
+                            (p1, prm.astype(np.float64), gp, 1e-3)):
+        ref = th0 - lr * g / (np.abs(g) + 1e-8)
+        big = np.abs(g) > 1e-3 * np.abs(g).max()
+        assert np.abs(got - ref)[big].max() <= 1e-6 * max(1.0, np.abs(th0).max()) + 1e-7
+    assert np.abs(s1 - (s0 - 1e-3 * gs / (np.abs(gs) + 1e-8))).max() <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_training_reduces_the_loss(orc, P, prec):
+    m = MODELS["blobs128"]
+    say(f"training loop prec={prec}")
+    tab, prm, _ = model_params(m, 9)
+    B = 8192
+    batch = _batch(m, B, 10)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    P.nif_model_reserve(model.h, B)
+    first = last = None
+    for it in range(30):
+        losses = _train_step(P, model, batch, B, prec)
+        assert np.all(np.isfinite(losses[:6]))
+        if first is None:
+            first = losses[5]
+        last = losses[5]
+    say(f"  total loss {first:.4f} -> {last:.4f}  loss scale {losses[11]}")
+    assert last < first
+
+
+def test_train_step_rejects_oversized_batches(P):
+    m = MODELS["torus16"]
+    model = P.Model(m)
+    tab, prm, _ = model_params(m, 3)
+    model.set_params(tab, prm)
+    P.nif_model_reserve(model.h, 64)
+    with pytest.raises(P.NifError):
+        _train_step(P, model, _batch(m, 65, 1), 65)
