@@ -34,6 +34,7 @@ enum { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
 constexpr int kMaxLayers = 10;
 constexpr int kSegStride = 8;    // LDS floats per segment: x0 (3), pad, x1 (3), pad
 constexpr int kZStride = 17;     // LDS floats per segment of head outputs (16 + pad)
+constexpr int kQueryCB = 2;      // 16-segment column blocks per MLP pass in the fused query
 
 struct EncParams {
     const void* tab;        // [L][T][2] FP32 or FP16

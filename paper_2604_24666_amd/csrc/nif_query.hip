@@ -150,7 +150,7 @@ __device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t a, int64_
 template <int HW, int PREC>
 __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
                                                int64_t* __restrict__ counters, int64_t* __restrict__ stats) {
-    constexpr int CB = HW >= 128 ? 2 : 4;
+    constexpr int CB = kQueryCB;
     constexpr int PASSES = 4 / CB;
     __shared__ float s_seg_all[4][64 * kSegStride];
     __shared__ float s_z_all[4][64 * kZStride];

@@ -32,6 +32,9 @@ struct Ray {
 struct Trav {
     int32_t ix, iy, iz;
     float tmx, tmy, tmz;
+    float tdx, tdy, tdz;  // t advance per bin along each axis
+    int32_t ex, ey, ez;   // bin index at which the walk leaves the grid along each axis
+    int32_t sx, sy, sz;   // step (+1 / -1)
     float t_lo;          // start of the current bin's t-range (-inf for the first bin)
     float last_a;        // key of the last returned segment
     int32_t last_cell;
@@ -44,19 +47,10 @@ __device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
-// Canonical edges (lower local vertex first); local vertex m = bx + 2 by + 4 bz.
-__device__ constexpr int kEdgeA[18] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3, 0, 1, 0, 2, 0, 4};
-__device__ constexpr int kEdgeB[18] = {1, 3, 5, 7, 2, 3, 6, 7, 4, 5, 6, 7, 6, 7, 5, 7, 3, 7};
-// 12 triangles, two per face, faces ordered x-low, x-high, y-low, y-high, z-low, z-high;
-// each face (p00, p10, p11, p01) splits into (p00, p10, p11) and (p00, p11, p01).
-__device__ constexpr int kTriV[12][3] = {{0, 2, 6}, {0, 6, 4}, {1, 3, 7}, {1, 7, 5}, {0, 1, 5}, {0, 5, 4},
-                                         {2, 3, 7}, {2, 7, 6}, {0, 1, 3}, {0, 3, 2}, {4, 5, 7}, {4, 7, 6}};
-// edge index and orientation (1 = reversed) of the triangle edges A->B, B->C, C->A
-__device__ constexpr int kTriE[12][3] = {{4, 10, 12}, {12, 6, 8}, {5, 11, 13}, {13, 7, 9}, {0, 9, 14}, {14, 2, 8},
-                                         {1, 11, 15}, {15, 3, 10}, {0, 5, 16}, {16, 1, 4}, {2, 7, 17}, {17, 3, 6}};
-__device__ constexpr int kTriR[12][3] = {{0, 0, 1}, {0, 1, 1}, {0, 0, 1}, {0, 1, 1}, {0, 0, 1}, {0, 1, 1},
-                                         {0, 0, 1}, {0, 1, 1}, {0, 0, 1}, {0, 1, 1}, {0, 0, 1}, {0, 1, 1}};
-
+// Local vertex m = bx + 2 by + 4 bz.  Canonical edges (lower local vertex first): 12 outer
+// edges and the 6 face diagonals.  The 12 triangles, two per face, faces ordered x-low,
+// x-high, y-low, y-high, z-low, z-high; a face (p00, p10, p11, p01) splits into
+// (p00, p10, p11) and (p00, p11, p01).  Written out so every index is a compile-time constant.
 struct CellHit {
     int n;               // intervals: 0, 1 or 2
     float a0, b0, a1, b1;
@@ -79,32 +73,39 @@ __device__ __forceinline__ CellHit cell_intervals(const float4* __restrict__ V, 
     float3 p[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) p[m] = f3sub(v[m], oc);
-    bool s[18];
-#pragma unroll
-    for (int e = 0; e < 18; ++e) s[e] = f3dot(R.d, f3cross(p[kEdgeA[e]], p[kEdgeB[e]])) >= 0.f;
+    // edge signs for the canonical orientation; an exact zero counts as positive
+#define NIF_E(a, b) (f3dot(R.d, f3cross(p[a], p[b])) >= 0.f)
+    const bool e01 = NIF_E(0, 1), e23 = NIF_E(2, 3), e45 = NIF_E(4, 5), e67 = NIF_E(6, 7);
+    const bool e02 = NIF_E(0, 2), e13 = NIF_E(1, 3), e46 = NIF_E(4, 6), e57 = NIF_E(5, 7);
+    const bool e04 = NIF_E(0, 4), e15 = NIF_E(1, 5), e26 = NIF_E(2, 6), e37 = NIF_E(3, 7);
+    const bool e06 = NIF_E(0, 6), e17 = NIF_E(1, 7), e05 = NIF_E(0, 5), e27 = NIF_E(2, 7);
+    const bool e03 = NIF_E(0, 3), e47 = NIF_E(4, 7);
+#undef NIF_E
     float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f, tmax = -INFINITY;
     int cnt = 0, face0 = -1;
-#pragma unroll
-    for (int tr = 0; tr < 12; ++tr) {
-        bool s0 = s[kTriE[tr][0]] != (bool)kTriR[tr][0];
-        bool s1 = s[kTriE[tr][1]] != (bool)kTriR[tr][1];
-        bool s2 = s[kTriE[tr][2]] != (bool)kTriR[tr][2];
-        if (s0 == s1 && s1 == s2) {
-            const float3 A = p[kTriV[tr][0]], B = p[kTriV[tr][1]], C = p[kTriV[tr][2]];
-            const float3 n = f3cross(f3sub(B, A), f3sub(C, A));
-            const float den = f3dot(n, R.d);
-            float t = tc + (den != 0.f ? f3dot(n, A) / den : 0.f);
-            // insertion into the sorted prefix t0..t3 (later crossings beyond 4 only move tmax)
-            if (cnt == 0 || t < t0) face0 = tr >> 1;
-            if (cnt >= 1 && t < t0) { float x = t0; t0 = t; t = x; }
-            if (cnt >= 2 && t < t1) { float x = t1; t1 = t; t = x; }
-            if (cnt >= 3 && t < t2) { float x = t2; t2 = t; t = x; }
-            if (cnt >= 4 && t < t3) { float x = t3; t3 = t; t = x; }
-            if (cnt == 0) t0 = t; else if (cnt == 1) t1 = t; else if (cnt == 2) t2 = t; else if (cnt == 3) t3 = t;
-            tmax = fmaxf(tmax, t);
-            ++cnt;
-        }
+    // triangle (A, B, C) is crossed iff its three oriented edge signs agree
+#define NIF_TRI(face, sab, sbc, sca, A, B, C)                                                   \
+    if ((sab) == (sbc) && (sbc) == (sca)) {                                                     \
+        const float3 n = f3cross(f3sub(p[B], p[A]), f3sub(p[C], p[A]));                         \
+        const float den = f3dot(n, R.d);                                                        \
+        float t = tc + (den != 0.f ? f3dot(n, p[A]) / den : 0.f);                               \
+        /* insertion into the sorted prefix t0..t3 (more crossings only move tmax) */           \
+        if (cnt == 0 || t < t0) face0 = (face);                                                 \
+        if (cnt >= 1 && t < t0) { float x = t0; t0 = t; t = x; }                                \
+        if (cnt >= 2 && t < t1) { float x = t1; t1 = t; t = x; }                                \
+        if (cnt >= 3 && t < t2) { float x = t2; t2 = t; t = x; }                                \
+        if (cnt >= 4 && t < t3) { float x = t3; t3 = t; t = x; }                                \
+        if (cnt == 0) t0 = t; else if (cnt == 1) t1 = t; else if (cnt == 2) t2 = t; else if (cnt == 3) t3 = t; \
+        tmax = fmaxf(tmax, t);                                                                  \
+        ++cnt;                                                                                  \
     }
+    NIF_TRI(0, e02, e26, !e06, 0, 2, 6) NIF_TRI(0, e06, !e46, !e04, 0, 6, 4)   // x-low
+    NIF_TRI(1, e13, e37, !e17, 1, 3, 7) NIF_TRI(1, e17, !e57, !e15, 1, 7, 5)   // x-high
+    NIF_TRI(2, e01, e15, !e05, 0, 1, 5) NIF_TRI(2, e05, !e45, !e04, 0, 5, 4)   // y-low
+    NIF_TRI(3, e23, e37, !e27, 2, 3, 7) NIF_TRI(3, e27, !e67, !e26, 2, 7, 6)   // y-high
+    NIF_TRI(4, e01, e13, !e03, 0, 1, 3) NIF_TRI(4, e03, !e23, !e02, 0, 3, 2)   // z-low
+    NIF_TRI(5, e45, e57, !e47, 4, 5, 7) NIF_TRI(5, e47, !e67, !e46, 4, 7, 6)   // z-high
+#undef NIF_TRI
     CellHit h;
     h.entry_face = face0;
     h.bad = 0;
@@ -124,32 +125,41 @@ __device__ __forceinline__ void trav_init(const PoseDev& P, const Ray& R, Trav& 
     T.t_lo = -INFINITY;
     if (P.empty) return;
     float t0 = 0.f, t1 = INFINITY;
+    bool miss = false;
     const float o[3] = {R.o.x, R.o.y, R.o.z}, d[3] = {R.d.x, R.d.y, R.d.z};
+    const float plo[3] = {P.lo[0], P.lo[1], P.lo[2]}, pbs[3] = {P.bs[0], P.bs[1], P.bs[2]};
+    const float pib[3] = {P.inv_bs[0], P.inv_bs[1], P.inv_bs[2]};
+    const int pnb[3] = {P.nb[0], P.nb[1], P.nb[2]};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float lo = P.lo[a], hi = P.lo[a] + P.nb[a] * P.bs[a];
+        const float lo = plo[a], hi = plo[a] + pnb[a] * pbs[a];
         if (d[a] == 0.f) {
-            if (o[a] < lo || o[a] > hi) return;
+            miss |= o[a] < lo || o[a] > hi;
         } else {
-            float ta = (lo - o[a]) / d[a], tb = (hi - o[a]) / d[a];
+            const float ta = (lo - o[a]) / d[a], tb = (hi - o[a]) / d[a];
             t0 = fmaxf(t0, fminf(ta, tb));
             t1 = fminf(t1, fmaxf(ta, tb));
         }
     }
-    if (t0 > t1) return;
+    if (miss || t0 > t1) return;
     int idx[3];
     float tm[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float x = fmaf(t0, d[a], o[a]);
-        int c = (int)floorf((x - P.lo[a]) * P.inv_bs[a]);
-        idx[a] = min(max(c, 0), P.nb[a] - 1);
-        if (d[a] > 0.f) tm[a] = (P.lo[a] + (idx[a] + 1) * P.bs[a] - o[a]) / d[a];
-        else if (d[a] < 0.f) tm[a] = (P.lo[a] + idx[a] * P.bs[a] - o[a]) / d[a];
+        const float x = fmaf(t0, d[a], o[a]);
+        const int c = (int)floorf((x - plo[a]) * pib[a]);
+        idx[a] = min(max(c, 0), pnb[a] - 1);
+        if (d[a] > 0.f) tm[a] = (plo[a] + (idx[a] + 1) * pbs[a] - o[a]) / d[a];
+        else if (d[a] < 0.f) tm[a] = (plo[a] + idx[a] * pbs[a] - o[a]) / d[a];
         else tm[a] = INFINITY;
     }
     T.ix = idx[0]; T.iy = idx[1]; T.iz = idx[2];
     T.tmx = tm[0]; T.tmy = tm[1]; T.tmz = tm[2];
+    T.tdx = d[0] != 0.f ? pbs[0] / fabsf(d[0]) : INFINITY;
+    T.tdy = d[1] != 0.f ? pbs[1] / fabsf(d[1]) : INFINITY;
+    T.tdz = d[2] != 0.f ? pbs[2] / fabsf(d[2]) : INFINITY;
+    T.sx = d[0] > 0.f ? 1 : -1; T.sy = d[1] > 0.f ? 1 : -1; T.sz = d[2] > 0.f ? 1 : -1;
+    T.ex = d[0] > 0.f ? pnb[0] : -1; T.ey = d[1] > 0.f ? pnb[1] : -1; T.ez = d[2] > 0.f ? pnb[2] : -1;
     T.active = 1;
 }
 
@@ -165,16 +175,17 @@ __device__ __forceinline__ bool next_segment(const PoseDev& P, const float4* __r
                                              const int32_t* __restrict__ bin_start,
                                              const int32_t* __restrict__ bin_cells, int N, const Ray& R,
                                              Trav& T, Segment& out, int* bad) {
-    const float d[3] = {R.d.x, R.d.y, R.d.z};
     while (T.active) {
         // which face of the current bin the ray leaves through
         int ax = 0;
         float th = T.tmx;
         if (T.tmy < th) { ax = 1; th = T.tmy; }
         if (T.tmz < th) { ax = 2; th = T.tmz; }
-        const int cur = ax == 0 ? T.ix : (ax == 1 ? T.iy : T.iz);
-        const int stp = d[ax] > 0.f ? 1 : -1;
-        const bool last = (cur + stp < 0) || (cur + stp >= P.nb[ax]) || !(th < INFINITY);
+        bool last;
+        if (ax == 0) last = T.ix + T.sx == T.ex;
+        else if (ax == 1) last = T.iy + T.sy == T.ey;
+        else last = T.iz + T.sz == T.ez;
+        last = last || !(th < INFINITY);
         const float t_hi = last ? INFINITY : th;
         const int64_t bin = (int64_t)T.ix + (int64_t)P.nb[0] * (T.iy + (int64_t)P.nb[1] * T.iz);
         const int32_t s0 = bin_start[P.bin_off + bin], s1 = bin_start[P.bin_off + bin + 1];
@@ -203,10 +214,9 @@ __device__ __forceinline__ bool next_segment(const PoseDev& P, const float4* __r
         }
         if (last) { T.active = 0; return false; }
         T.t_lo = t_hi;
-        const float bsd = P.bs[ax] / fabsf(d[ax]);
-        if (ax == 0) { T.ix += stp; T.tmx += bsd; }
-        else if (ax == 1) { T.iy += stp; T.tmy += bsd; }
-        else { T.iz += stp; T.tmz += bsd; }
+        if (ax == 0) { T.ix += T.sx; T.tmx += T.tdx; }
+        else if (ax == 1) { T.iy += T.sy; T.tmy += T.tdy; }
+        else { T.iz += T.sz; T.tmz += T.tdz; }
     }
     return false;
 }
