@@ -4,8 +4,10 @@ occupied deformed voxel is the hit, D = t_in, normal = the entered rest-space fa
 
 Data (all from the oracle, never from the GPU path): the 32-Gaussian blob scene voxelized at
 32^3 (reduced from 128^3 so the FP64 oracle traces and labels it in seconds); training rays
-through 48 random twist/bend poses of strength <= 0.75; every occupied segment becomes a
-training sample with the oracle's rest-space label.  Evaluation on 6 held-out poses of
+through 128 random twist/bend poses of strength <= 0.75; the samples are the segments a
+front-to-back first-hit query visits (each ray's occupied segments up to and including its
+first labelled hit), with the oracle's rest-space labels.  The distance head's bias starts at half
+a voxel so that its ReLU output is live for the log-space regression from the first step.  Evaluation on 6 held-out poses of
 strength in (0.75, 1]: ground truth per ray is the first segment whose label is a hit, at
 D = t_in + (t* / l_rest)(t_out - t_in).  Pass: distance MAE and mean normal angle of the
 trained network are each <= 0.5x the proxy's (on rays where both it and the truth hit)."""
@@ -44,6 +46,20 @@ def _segments(orc, occ, sp, kinds, strengths, n_rays, seed):
     return a, x0, x1, hit, t, nrm, alb, mat
 
 
+def _visited(a, hit):
+    """Mask of the segments a first-hit query visits: up to each ray's first labelled hit."""
+    keep = np.zeros(len(a), bool)
+    done = set()
+    for i in range(len(a)):
+        key = (int(a[i, 0]), int(a[i, 1]))
+        if key in done:
+            continue
+        keep[i] = True
+        if hit[i]:
+            done.add(key)
+    return keep
+
+
 def test_trained_network_beats_the_voxel_proxy(orc):
     import torch
 
@@ -54,13 +70,17 @@ def test_trained_network_beats_the_voxel_proxy(orc):
     sp = S.scene_params(w.scene_kind, w.seed)
     occ = orc.voxelize(w.scene_kind, sp, N)
     say("gain: oracle training data")
-    kt, st = S.random_poses(48, 1234, kinds=(S.TWIST, S.BEND), s_lo=0.0, s_hi=0.75)
-    _, x0, x1, hit, t, nrm, alb, mat = _segments(orc, occ, sp, kt, st, 384, 500)
+    kt, st = S.random_poses(128, 1234, kinds=(S.TWIST, S.BEND), s_lo=0.0, s_hi=0.75)
+    a, x0, x1, hit, t, nrm, alb, mat = _segments(orc, occ, sp, kt, st, 768, 500)
+    keep = _visited(a, hit)
+    x0, x1, hit, t, nrm, alb, mat = x0[keep], x1[keep], hit[keep], t[keep], nrm[keep], alb[keep], mat[keep]
     n = len(hit)
     say(f"  {n} training segments, hit ratio {hit.mean():.3f}")
-    assert n > 20000 and 0.05 < hit.mean() < 0.95
+    assert n > 50000 and 0.05 < hit.mean() < 0.95
     model = P.Model(m)
-    model.set_params(S.init_tables(m, 77), S.init_mlp(m, 77))
+    prm = S.init_mlp(m, 77)
+    prm[-m.n_heads + 1] = 0.5 / N          # distance-head bias
+    model.set_params(S.init_tables(m, 77), prm)
     B = 8192
     P.nif_model_reserve(model.h, B)
     data = [dev_f32(x0.T), dev_f32(x1.T), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nrm.T), dev_f32(alb.T),
@@ -70,13 +90,13 @@ def test_trained_network_beats_the_voxel_proxy(orc):
     gen = torch.Generator(device="cuda").manual_seed(0)
     say("gain: training")
     hist = []
-    for it in range(1500):
+    for it in range(1200):
         idx = torch.randint(0, n, (B,), device="cuda", generator=gen)
         bt = [data[0][:, idx].contiguous(), data[1][:, idx].contiguous(), data[2][idx].contiguous(),
               data[3][idx].contiguous(), data[4][:, idx].contiguous(), data[5][:, idx].contiguous(),
               data[6][idx].contiguous()]
         P.nif_train_step(model.h, P.Batch(*[b.data_ptr() for b in bt]), B, cfg, losses)
-        if it % 300 == 0 or it == 1499:
+        if it % 300 == 0 or it == 1199:
             lv = losses.cpu().numpy()
             hist.append(lv[5])
             say(f"  step {it}: total {lv[5]:.4f}  hit {lv[0]:.4f} dist {lv[1]:.4f} nrm {lv[2]:.4f} alb {lv[3]:.4f} "
