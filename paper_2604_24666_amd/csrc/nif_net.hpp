@@ -99,34 +99,83 @@ __device__ __forceinline__ uint32_t grid_index(uint32_t vx, uint32_t vy, uint32_
     return dense ? hd : hh;
 }
 
-// Trilinearly interpolated 2-feature entry of level l at sample (sx, sy, sz).
-__device__ __forceinline__ float2 grid_lookup(const EncParams& ep, int l, double sx, double sy, double sz) {
-    const int N = ep.res[l];
-    const bool dense = (ep.dense_mask >> l) & 1u;
-    const uint32_t n1 = (uint32_t)N + 1u, mask = (1u << ep.log2T) - 1u;
-    uint32_t ix, iy, iz;
-    float wx, wy, wz;
-    grid_axis(sx, N, ix, wx);
-    grid_axis(sy, N, iy, wy);
-    grid_axis(sz, N, iz, wz);
-    const size_t base = (size_t)l << ep.log2T;
-    float2 acc = make_float2(0.f, 0.f);
+template <bool F16>
+__device__ __forceinline__ float2 table_entry(const void* tab, size_t e) {
+    if constexpr (F16) return __half22float2(reinterpret_cast<const __half2*>(tab)[e]);
+    else return reinterpret_cast<const float2*>(tab)[e];
+}
+
+// Trilinearly interpolated 2-feature entries of NL levels (l0, l0 + dl, ...) at one sample.
+// All 8 NL corner gathers are issued before any is used, so they are in flight together.
+template <int NL, bool F16>
+__device__ __forceinline__ void grid_lookup_n(const EncParams& ep, int l0, int dl, double sx, double sy, double sz,
+                                              float2 out[NL]) {
+    const uint32_t mask = (1u << ep.log2T) - 1u;
+    uint32_t idx[NL][8];
+    float wx[NL], wy[NL], wz[NL];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const uint32_t bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
-        const uint32_t idx = grid_index(ix + bx, iy + by, iz + bz, n1, dense, mask);
-        const float wt = (bx ? wx : 1.f - wx) * (by ? wy : 1.f - wy) * (bz ? wz : 1.f - wz);
-        float2 v;
-        if (ep.f16) {
-            const __half2 h = reinterpret_cast<const __half2*>(ep.tab)[base + idx];
-            v = __half22float2(h);
-        } else {
-            v = reinterpret_cast<const float2*>(ep.tab)[base + idx];
-        }
-        acc.x = fmaf(wt, v.x, acc.x);
-        acc.y = fmaf(wt, v.y, acc.y);
+    for (int k = 0; k < NL; ++k) {
+        const int l = l0 + k * dl;
+        const int N = ep.res[l];
+        const bool dense = (ep.dense_mask >> l) & 1u;
+        const uint32_t n1 = (uint32_t)N + 1u;
+        uint32_t ix, iy, iz;
+        grid_axis(sx, N, ix, wx[k]);
+        grid_axis(sy, N, iy, wy[k]);
+        grid_axis(sz, N, iz, wz[k]);
+        const uint32_t base = (uint32_t)l << ep.log2T;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            idx[k][c] = base + grid_index(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1), n1, dense, mask);
     }
-    return acc;
+    float2 v[NL][8];
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[k][c] = table_entry<F16>(ep.tab, idx[k][c]);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float wt = ((c & 1) ? wx[k] : 1.f - wx[k]) * (((c >> 1) & 1) ? wy[k] : 1.f - wy[k]) *
+                             (((c >> 2) & 1) ? wz[k] : 1.f - wz[k]);
+            acc.x = fmaf(wt, v[k][c].x, acc.x);
+            acc.y = fmaf(wt, v[k][c].y, acc.y);
+        }
+        out[k] = acc;
+    }
+}
+
+// One level (used where a single lookup is wanted).
+__device__ __forceinline__ float2 grid_lookup(const EncParams& ep, int l, double sx, double sy, double sz) {
+    float2 r[1];
+    if (ep.f16) grid_lookup_n<1, true>(ep, l, 1, sx, sy, sz, r);
+    else grid_lookup_n<1, false>(ep, l, 1, sx, sy, sz, r);
+    return r[0];
+}
+
+// Features of lane quarter q for one sample: levels [q LQ, (q+1) LQ), 2 features each.
+template <int LQ, bool F16>
+__device__ __forceinline__ void quarter_features(const EncParams& ep, int q, const double smp[3], float feat[8]) {
+    float2 r[LQ];
+    grid_lookup_n<LQ, F16>(ep, q * LQ, 1, smp[0], smp[1], smp[2], r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        feat[2 * k] = k < LQ ? r[k < LQ ? k : 0].x : 0.f;
+        feat[2 * k + 1] = k < LQ ? r[k < LQ ? k : 0].y : 0.f;
+    }
+}
+
+__device__ __forceinline__ void lane_features(const EncParams& ep, int q, const double smp[3], float feat[8]) {
+    // uniform branches: one straight-line gather sequence per (levels, table type)
+    if (ep.L == 16) {
+        if (ep.f16) quarter_features<4, true>(ep, q, smp, feat);
+        else quarter_features<4, false>(ep, q, smp, feat);
+    } else {
+        if (ep.f16) quarter_features<2, true>(ep, q, smp, feat);
+        else quarter_features<2, false>(ep, q, smp, feat);
+    }
 }
 
 // Positional-encoding state of one point coordinate triple across the samples.
@@ -205,17 +254,7 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
             for (int cb = 0; cb < CB; ++cb) {
                 double smp[3];
                 pe_sample(pe[cb], s, smp);
-#pragma unroll
-                for (int li = 0; li < 4; ++li) {
-                    if (li < LQ) {
-                        const float2 f = grid_lookup(np.enc, q * LQ + li, smp[0], smp[1], smp[2]);
-                        feat[cb][2 * li] = f.x;
-                        feat[cb][2 * li + 1] = f.y;
-                    } else {
-                        feat[cb][2 * li] = 0.f;
-                        feat[cb][2 * li + 1] = 0.f;
-                    }
-                }
+                lane_features(np.enc, q, smp, feat[cb]);
             }
             const int e0 = (p * S + s) * L * 2 + FQ * q;
 #pragma unroll

@@ -293,10 +293,15 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
         for (int s = 0; s < S; ++s) {
             double smp[3];
             pe_sample(pe, s, smp);
-            for (int l = 0; l < ep.L; ++l) {
-                const float2 f = grid_lookup(ep, l, smp[0], smp[1], smp[2]);
-                out[i * W + (s * ep.L + l) * 2] = f.x;
-                out[i * W + (s * ep.L + l) * 2 + 1] = f.y;
+            for (int l0 = 0; l0 < ep.L; l0 += 4) {
+                float2 f[4];
+                if (ep.f16) grid_lookup_n<4, true>(ep, l0, 1, smp[0], smp[1], smp[2], f);
+                else grid_lookup_n<4, false>(ep, l0, 1, smp[0], smp[1], smp[2], f);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    out[i * W + (s * ep.L + l0 + k) * 2] = f[k].x;
+                    out[i * W + (s * ep.L + l0 + k) * 2 + 1] = f[k].y;
+                }
             }
         }
     }

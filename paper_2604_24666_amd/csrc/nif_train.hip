@@ -400,9 +400,25 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
                 const int N = P.enc.res[l];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) grid_axis(smp[a], N, ci[v][a], cw[v][a]);
-                const float2 f = grid_lookup(P.enc, l, smp[0], smp[1], smp[2]);
-                sE[seg_l][2 * l] = f.x;
-                sE[seg_l][2 * l + 1] = f.y;
+            }
+        }
+        {
+            // levels lw, lw + 4, ...: all corner gathers in flight together
+            float2 r[4];
+            if (L == 16) {
+                if (P.enc.f16) grid_lookup_n<4, true>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
+                else grid_lookup_n<4, false>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
+            } else {
+                if (P.enc.f16) grid_lookup_n<2, true>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
+                else grid_lookup_n<2, false>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int l = lw + 4 * v;
+                if (l < L) {
+                    sE[seg_l][2 * l] = r[v].x;
+                    sE[seg_l][2 * l + 1] = r[v].y;
+                }
             }
         }
         __syncthreads();
