@@ -136,6 +136,10 @@ int nif_grid_update(nif_grid* grid, const nif_pose* poses_host, int32_t n_poses,
  * last build/update (reading it synchronises the null stream).  Any pointer may be NULL. */
 int nif_grid_info(const nif_grid* grid, int32_t pose, int64_t* n_occupied, int64_t* n_refs,
                   int32_t* overflow);
+/* Deformed-space box of pose `pose`'s bin grid as of the last build/update: it holds every
+ * occupied deformed voxel (FP32 lattice, padded by 1e-5 on each side).  lo[3], hi[3] are host arrays; a
+ * pose with no occupied voxel gives lo = hi = 0.  Synchronises the null stream. */
+int nif_grid_bounds(const nif_grid* grid, int32_t pose, float* lo, float* hi);
 
 /* ---------------------------------------------------------------- rays
  * Deformed-space rays o + t d, grouped by pose: rays [pose_offsets[p], pose_offsets[p+1])
@@ -171,13 +175,22 @@ typedef struct {
     uint8_t* hit; float* t; float *nx, *ny, *nz; float *ar, *ag, *ab; int32_t* material;
     int32_t* cell; float* hit_logit; int32_t* n_queried; float *xr, *yr, *zr;
 } nif_hits;
-enum { NIF_Q_FIRST_HIT = 0, NIF_Q_NO_NETWORK = 8 };
+enum { NIF_Q_FIRST_HIT = 0, NIF_Q_NO_NETWORK = 8, NIF_Q_POSE_TIMES = 16 };
 /* flags: NIF_Q_FIRST_HIT, or NIF_Q_NO_NETWORK (the voxel proxy: first occupied voxel is
- * the hit, D = t_in, no network).  precision: NIF_PREC_*.  stats_dev: nullable int64[4]
- * {rays done, network evaluations, cell-test overflows, reserved}, accumulated. */
+ * the hit, D = t_in, no network); NIF_Q_POSE_TIMES adds per-pose completion times.
+ * precision: NIF_PREC_*.  stats_dev: nullable int64[4] {rays done, network evaluations,
+ * degenerate voxel tests, reserved}, accumulated; with NIF_Q_POSE_TIMES it must hold
+ * 5 + 2 n_poses entries: [4] the kernel's start and [5 + p] the completion of pose p, in
+ * device wall-clock ticks (hipDeviceAttributeWallClockRate kHz), [5 + n_poses + p] rays of
+ * pose p finished; these are reset by the call. */
 int nif_query(const nif_model* model, const nif_grid* grid, const nif_rays* rays, int64_t n_rays,
               const nif_hits* out, uint32_t flags, int32_t precision, int64_t* stats_dev,
               nif_stream stream);
+/* Frequency of the current device's wall clock (the ticks of NIF_Q_POSE_TIMES), in kHz. */
+int nif_wall_clock_khz(int32_t* khz);
+/* Launch shape of the fused query: persistent workgroups (4 waves each) per compute unit,
+ * 1..32 (default 8).  Process-wide; chosen by the autotuner. */
+int nif_set_query_blocks_per_cu(int32_t blocks_per_cu);
 
 /* ---------------------------------------------------------------- network on points
  * psi encoding of n rest-space points (SoA [3][n]) -> out[n][(1+2F) L feat_dim], FP32. */

@@ -13,12 +13,14 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 import torch
 
 __all__ = ["NifError", "lib", "ModelDesc", "Pose", "Rays", "Hits", "Segments", "Batch", "TrainCfg",
            "nif_model_create", "nif_model_destroy", "nif_model_sizes", "nif_model_set_params",
            "nif_model_get_params", "nif_model_get_grads", "nif_model_zero_grads", "nif_model_reserve",
-           "nif_voxelize", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_update", "nif_trace", "nif_query",
+           "nif_voxelize", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
            "nif_encode", "nif_forward", "nif_backward", "nif_train_step",
            "Model", "Grid", "NifField"]
 
@@ -27,7 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libnif.so")
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 TABLE_F32, TABLE_F16 = 0, 1
-Q_FIRST_HIT, Q_NO_NETWORK = 0, 8
+Q_FIRST_HIT, Q_NO_NETWORK, Q_POSE_TIMES = 0, 8, 16
 
 
 class NifError(RuntimeError):
@@ -94,9 +96,11 @@ def lib():
             "nif_model_zero_grads": ([P, P], C.c_int), "nif_model_reserve": ([P, I64], C.c_int),
             "nif_voxelize": ([I32, P, I32, I32, P, P], C.c_int),
             "nif_build_grid": ([P, I32, P, I32, I32, P, P], C.c_int), "nif_grid_destroy": ([P], C.c_int),
-            "nif_grid_info": ([P, I32, P, P, P], C.c_int), "nif_grid_update": ([P, P, I32, P], C.c_int),
+            "nif_grid_info": ([P, I32, P, P, P], C.c_int), "nif_grid_bounds": ([P, I32, P, P], C.c_int), "nif_grid_update": ([P, P, I32, P], C.c_int),
             "nif_trace": ([P, P, I64, I32, P, P], C.c_int),
             "nif_query": ([P, P, P, I64, P, U32, I32, P, P], C.c_int),
+            "nif_set_query_blocks_per_cu": ([I32], C.c_int),
+            "nif_wall_clock_khz": ([C.POINTER(C.c_int32)], C.c_int),
             "nif_encode": ([P, P, I64, P, P], C.c_int),
             "nif_forward": ([P, P, P, I64, P, I32, P], C.c_int),
             "nif_backward": ([P, P, P, I64, P, P, P, I32, I32, P], C.c_int),
@@ -195,6 +199,13 @@ def nif_grid_info(h, pose: int = 0):
     return a.value, b.value, c.value
 
 
+def nif_grid_bounds(h, pose: int = 0):
+    """Deformed-space box (lo[3], hi[3]) of a pose's occupied voxels."""
+    lo, hi = (C.c_float * 3)(), (C.c_float * 3)()
+    _check(lib().nif_grid_bounds(h, pose, lo, hi))
+    return np.array(lo[:]), np.array(hi[:])
+
+
 def nif_grid_update(h, kinds, strengths, stream=None):
     n = len(kinds)
     poses = (Pose * n)(*[Pose(int(k), float(s)) for k, s in zip(kinds, strengths)])
@@ -215,6 +226,16 @@ def nif_query(model, grid, rays: Rays, n: int, hits: Hits, flags: int = 0, preci
               stream=None):
     _check(lib().nif_query(model, grid, C.byref(rays), n, C.byref(hits), flags, precision, _ptr(stats),
                            _stream(stream)))
+
+
+def nif_wall_clock_khz() -> int:
+    v = C.c_int32(0)
+    _check(lib().nif_wall_clock_khz(C.byref(v)))
+    return int(v.value)
+
+
+def nif_set_query_blocks_per_cu(v: int):
+    _check(lib().nif_set_query_blocks_per_cu(int(v)))
 
 
 def nif_encode(model, x, n: int, out, stream=None):
@@ -314,6 +335,9 @@ class Grid:
 
     def info(self, pose=0):
         return nif_grid_info(self.h, pose)
+
+    def bounds(self, pose=0):
+        return nif_grid_bounds(self.h, pose)
 
     def update(self, kinds, strengths):
         nif_grid_update(self.h, kinds, strengths)

@@ -227,6 +227,13 @@ int nif_grid_info(const nif_grid* g, int32_t pose, int64_t* n_occupied, int64_t*
     return NIF_OK;
 }
 
+int nif_grid_bounds(const nif_grid* g, int32_t pose, float* lo, float* hi) {
+    REQUIRE(g, "grid is null");
+    REQUIRE(pose >= 0 && pose < g->n_poses, "pose out of range");
+    REQUIRE(lo && hi, "lo and hi must not be null");
+    return nif::grid_bounds(g, pose, lo, hi);
+}
+
 static int validate_rays(const nif_rays* r, int64_t n) {
     REQUIRE(r, "rays is null");
     REQUIRE(n >= 0, "n_rays must be >= 0");
@@ -250,13 +257,28 @@ int nif_query(const nif_model* m, const nif_grid* g, const nif_rays* rays, int64
     int rc = validate_rays(rays, n);
     if (rc) return rc;
     REQUIRE(out, "out is null");
-    REQUIRE((flags & ~(uint32_t)NIF_Q_NO_NETWORK) == 0, "unknown query flags");
+    REQUIRE((flags & ~(uint32_t)(NIF_Q_NO_NETWORK | NIF_Q_POSE_TIMES)) == 0, "unknown query flags");
     REQUIRE(precision >= 0 && precision <= 2, "precision must be NIF_PREC_FP32, _BF16 or _FP16");
     if (!(flags & NIF_Q_NO_NETWORK)) {
         REQUIRE(m, "model is null");
         if (!m->params_set) return fail(NIF_E_STATE, "model parameters were never set");
     }
     return nif::query_launch(m, g, rays, n, out, flags, precision, stats, S(stream));
+}
+
+int nif_wall_clock_khz(int32_t* khz) {
+    REQUIRE(khz, "khz is null");
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) != hipSuccess || v <= 0)
+        return fail(NIF_E_DEVICE, "wall clock rate not available");
+    *khz = v;
+    return NIF_OK;
+}
+
+int nif_set_query_blocks_per_cu(int32_t v) {
+    REQUIRE(v >= 1 && v <= 32, "blocks_per_cu must be in [1, 32]");
+    return nif::set_query_blocks_per_cu(v);
 }
 
 int nif_encode(const nif_model* m, const float* x, int64_t n, float* out, nif_stream stream) {

@@ -402,6 +402,17 @@ int grid_update(nif_grid* g, const nif_pose* poses, hipStream_t st) {
     return grid_rebin(g, true, st);
 }
 
+int grid_bounds(const nif_grid* g, int pose, float* lo, float* hi) {
+    PoseDev pd;
+    int rc = check_hip(hipMemcpy(&pd, g->poses + pose, sizeof(PoseDev), hipMemcpyDeviceToHost), "read pose");
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = pd.empty ? 0.f : pd.lo[a];
+        hi[a] = pd.empty ? 0.f : pd.lo[a] + pd.bs[a] * (float)pd.nb[a];
+    }
+    return NIF_OK;
+}
+
 int grid_overflow(nif_grid* g, hipStream_t st, int32_t* overflow) {
     int rc = check_hip(hipMemcpyAsync(overflow, sc_overflow(g), sizeof(int32_t), hipMemcpyDeviceToHost, st), "read overflow");
     if (rc) return rc;

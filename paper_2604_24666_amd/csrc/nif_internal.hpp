@@ -73,6 +73,7 @@ int grid_build(nif_grid* g, const uint8_t* occ, int32_t N, const nif_pose* poses
                int32_t bins_per_axis, hipStream_t st);
 void grid_free(nif_grid* g);
 int grid_update(nif_grid* g, const nif_pose* poses, hipStream_t st);
+int grid_bounds(const nif_grid* g, int pose, float* lo, float* hi);
 int grid_overflow(nif_grid* g, hipStream_t st, int32_t* overflow);
 int voxelize_launch(int32_t scene_kind, const float* params_dev, int32_t N, uint8_t* occ,
                     hipStream_t st);
@@ -83,6 +84,7 @@ int trace_launch(const nif_grid* g, const nif_rays* r, int64_t n, int32_t max_se
 int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64_t n,
                  const nif_hits* out, uint32_t flags, int32_t precision, int64_t* stats,
                  hipStream_t st);
+int set_query_blocks_per_cu(int v);
 int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st);
 int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads,
                    int32_t precision, float* acts, hipStream_t st);

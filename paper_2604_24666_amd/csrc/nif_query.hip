@@ -49,6 +49,35 @@ __global__ void k_reset(int64_t* counters, int n) {
     if (threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
+// Per-pose timing slots of the stats buffer: [4] start (min over waves), [5, 5+P) completion
+// time of each pose, [5+P, 5+2P) rays finished per pose.
+__global__ void k_reset_pose_times(int64_t* stats, int n_poses) {
+    for (int i = threadIdx.x; i < 1 + 2 * n_poses; i += blockDim.x) stats[4 + i] = i == 0 ? INT64_MAX : 0;
+}
+
+// Counts finished rays per pose (one atomic per wave when the finishing lanes share a pose)
+// and stamps a pose's completion time when its last ray is done.  Called by the whole wave.
+__device__ __forceinline__ void note_finished(int64_t* stats, const int64_t* off, int n_poses, bool fin, int pose) {
+    const uint64_t m = ballot(fin);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int p0 = __shfl(pose, leader);
+    const bool uniform = ballot(fin && pose != p0) == 0;
+    int64_t* done = stats + 5 + n_poses;
+    if (uniform) {
+        if (lane_id() == leader) {
+            const int64_t total = off[p0 + 1] - off[p0];
+            const int64_t c = (int64_t)popc64(m);
+            const int64_t old = (int64_t)atomicAdd((unsigned long long*)&done[p0], (unsigned long long)c);
+            if (old + c == total) atomicMax((unsigned long long*)&stats[5 + p0], (unsigned long long)wall_clock64());
+        }
+    } else if (fin) {
+        const int64_t total = off[pose + 1] - off[pose];
+        const int64_t old = (int64_t)atomicAdd((unsigned long long*)&done[pose], 1ull);
+        if (old + 1 == total) atomicMax((unsigned long long*)&stats[5 + pose], (unsigned long long)wall_clock64());
+    }
+}
+
 // ------------------------------------------------------------------ segments of every ray
 
 __global__ void __launch_bounds__(256) k_trace(GridArgs G, RayArgs R, int32_t max_seg, nif_segments out) {
@@ -149,7 +178,8 @@ __device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t a, int64_
 
 template <int HW, int PREC>
 __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
-                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats) {
+                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats,
+                                               int pose_times) {
     constexpr int CB = kQueryCB;
     constexpr int PASSES = 4 / CB;
     __shared__ float s_seg_all[4][64 * kSegStride];
@@ -170,9 +200,10 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
     P.kind = 0;
     Segment sg;
     sg.cell = -1; sg.a = sg.b = 0.f; sg.face = -1;
-    int nq = 0, bad = 0;
+    int nq = 0, bad = 0, pose = 0;
     float last_z0 = -INFINITY;
     int64_t n_done = 0, n_eval = 0;
+    if (pose_times && lane == 0) atomicMin((unsigned long long*)&stats[4], (unsigned long long)wall_clock64());
 
     for (;;) {
         // ---- give every lane a segment, taking new rays as old ones finish or miss
@@ -191,7 +222,8 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
                         exhausted = true;
                     } else {
                         ray = load_ray(R, r);
-                        P = G.poses[find_pose(R.off, R.n_poses, r)];
+                        pose = find_pose(R.off, R.n_poses, r);
+                        P = G.poses[pose];
                         trav_init(P, ray, tv);
                         nq = 0;
                         last_z0 = -INFINITY;
@@ -200,14 +232,17 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
             }
             const bool search = r >= 0 && !has;
             if (!ballot(search)) break;
+            bool missed = false;
             if (search) {
                 has = next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad);
                 if (!has) {
                     write_miss(out, r, nq, last_z0);
                     r = -1;
                     ++n_done;
+                    missed = true;
                 }
             }
+            if (pose_times) note_finished(stats, R.off, R.n_poses, missed, pose);
         }
         if (!ballot(has)) break;
         // ---- rest-space entry/exit points (local linearization inside the voxel)
@@ -223,6 +258,7 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
         wave_lds_sync();
+        bool hitnow = false;
         if (has) {
             ++nq;
             ++n_eval;
@@ -232,9 +268,11 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
                 write_hit(out, r, sg, x0, x1, z, nq, n_mat);
                 r = -1;
                 ++n_done;
+                hitnow = true;
             }
             has = false;
         }
+        if (pose_times) note_finished(stats, R.off, R.n_poses, hitnow, pose);
         wave_lds_sync();
     }
     if (stats) wave_add_stats(stats, n_done, n_eval, bad);
@@ -402,22 +440,26 @@ int trace_launch(const nif_grid* g, const nif_rays* r, int64_t n, int32_t max_se
     return check_hip(hipGetLastError(), "k_trace launch");
 }
 
+// Persistent grid size of the fused query: blocks of 4 waves per compute unit (tunable).
+static int g_query_blocks_per_cu = 8;
+
 template <int HW, int PREC>
 static void launch_query(const NetParams& np, const GridArgs& G, const RayArgs& R, const nif_hits& out, int64_t* ctr,
-                         int64_t* stats, hipStream_t st) {
+                         int64_t* stats, int pt, hipStream_t st) {
     const int64_t waves = (R.n + 63) / 64;
-    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, (int64_t)device_cus() * 8);
-    hipLaunchKernelGGL((k_query<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, G, R, out, ctr, stats);
+    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, (int64_t)device_cus() * g_query_blocks_per_cu);
+    hipLaunchKernelGGL((k_query<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, G, R, out, ctr,
+                       stats, pt);
 }
 
 template <int PREC>
 static int dispatch_query(int hw, const NetParams& np, const GridArgs& G, const RayArgs& R, const nif_hits& out,
-                          int64_t* ctr, int64_t* stats, hipStream_t st) {
+                          int64_t* ctr, int64_t* stats, int pt, hipStream_t st) {
     switch (hw) {
-        case 16: launch_query<16, PREC>(np, G, R, out, ctr, stats, st); break;
-        case 32: launch_query<32, PREC>(np, G, R, out, ctr, stats, st); break;
-        case 64: launch_query<64, PREC>(np, G, R, out, ctr, stats, st); break;
-        case 128: launch_query<128, PREC>(np, G, R, out, ctr, stats, st); break;
+        case 16: launch_query<16, PREC>(np, G, R, out, ctr, stats, pt, st); break;
+        case 32: launch_query<32, PREC>(np, G, R, out, ctr, stats, pt, st); break;
+        case 64: launch_query<64, PREC>(np, G, R, out, ctr, stats, pt, st); break;
+        case 128: launch_query<128, PREC>(np, G, R, out, ctr, stats, pt, st); break;
         default: return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
     }
     return NIF_OK;
@@ -434,14 +476,21 @@ int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64
         return check_hip(hipGetLastError(), "k_proxy launch");
     }
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, m->counters, 4);
+    const int pt = (flags & NIF_Q_POSE_TIMES) && stats ? 1 : 0;
+    if (pt) hipLaunchKernelGGL(k_reset_pose_times, dim3(1), dim3(256), 0, st, stats, g->n_poses);
     int rc;
     const NetParams np = make_net_params(m, precision);
     const int hw = m->desc.hidden_width;
-    if (precision == NIF_PREC_FP32) rc = dispatch_query<P_FP32>(hw, np, G, R, *out, m->counters, stats, st);
-    else if (precision == NIF_PREC_BF16) rc = dispatch_query<P_BF16>(hw, np, G, R, *out, m->counters, stats, st);
-    else rc = dispatch_query<P_FP16>(hw, np, G, R, *out, m->counters, stats, st);
+    if (precision == NIF_PREC_FP32) rc = dispatch_query<P_FP32>(hw, np, G, R, *out, m->counters, stats, pt, st);
+    else if (precision == NIF_PREC_BF16) rc = dispatch_query<P_BF16>(hw, np, G, R, *out, m->counters, stats, pt, st);
+    else rc = dispatch_query<P_FP16>(hw, np, G, R, *out, m->counters, stats, pt, st);
     if (rc) return rc;
     return check_hip(hipGetLastError(), "k_query launch");
+}
+
+int set_query_blocks_per_cu(int v) {
+    g_query_blocks_per_cu = v;
+    return NIF_OK;
 }
 
 int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st) {

@@ -149,3 +149,76 @@ def test_query_spheres64_full_workload_sampled(orc, P):
                            o[:, idx], d[:, idx], _np(got))
         total_ok += n_ok
     assert total_ok > 1500
+
+
+def test_query_pose_times_and_graph_replays(orc, P):
+    """Several poses of uneven ray counts in one launch: per-pose finished counts and completion
+    stamps; the same launch captured in a graph and replayed (with other GPU work between the
+    replays) gives the eager launch's outputs bit for bit on every replay."""
+    import torch
+    w = S.workload("torus16")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab, prm, _ = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    kinds, strengths = [S.TWIST, S.BEND, S.TAPER], [1.0, 0.5, 0.75]
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    counts = [3000, 77, 5000]
+    n = sum(counts)
+    o, d = S.rays_random(n, 21)
+    o, d = dev_f32(o), dev_f32(d)
+    off = offsets(counts)
+    rays = P.make_rays(o, d, off)
+    say("query pose times + graph replays, torus16, 3 poses")
+    ref = P.alloc_hits(n, "cuda")
+    stats = torch.zeros(5 + 2 * 3, dtype=torch.int64, device="cuda")
+    P.nif_query(model.h, grid.h, rays, n, P.hits_struct(ref), P.Q_POSE_TIMES, P.PREC_FP32, stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    assert st[0] == n and list(st[8:11]) == counts
+    assert np.all(st[5:8] >= st[4]) and P.nif_wall_clock_khz() > 0
+    out = P.alloc_hits(n, "cuda")
+    s_cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s_cap):
+        P.nif_query(model.h, grid.h, rays, n, P.hits_struct(out), P.Q_POSE_TIMES, P.PREC_FP32, stats,
+                    stream=s_cap)
+    other = P.alloc_hits(n, "cuda")
+    for rep in range(3):
+        for v in out.values():
+            v.zero_()
+        stats.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(out[k], ref[k]) or (out[k].dtype.is_floating_point and
+                                                   torch.equal(torch.nan_to_num(out[k]), torch.nan_to_num(ref[k]))), k
+        st = stats.cpu().numpy()
+        assert st[0] == n and list(st[8:11]) == counts and np.all(st[5:8] >= st[4])
+        # eager work between the replays
+        grid.query(model, o, d, off, out=other)
+        torch.cuda.synchronize()
+    del g
+
+
+def test_grid_bounds_hold_the_deformed_occupied_voxels(orc, P):
+    import torch
+    w = S.workload("torus16")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    kinds, strengths = [S.TWIST, S.BEND, S.TAPER], [1.0, 1.0, 1.0]
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    N = w.N
+    cells = np.nonzero(occ)[0]
+    for p, (k, s) in enumerate(zip(kinds, strengths)):
+        V = orc.lattice_vertices(k, s, N).reshape(N + 1, N + 1, N + 1, 3)
+        i, j, kk = cells % N, (cells // N) % N, cells // (N * N)
+        corners = np.concatenate([V[kk + c, j + b, i + a] for a in (0, 1) for b in (0, 1) for c in (0, 1)])
+        lo, hi = grid.bounds(p)
+        ext = corners.max(0) - corners.min(0)
+        say(f"  pose {p}: box {np.round(lo, 4)} .. {np.round(hi, 4)}")
+        assert np.all(lo <= corners.min(0) + 1e-6) and np.all(hi >= corners.max(0) - 1e-6)
+        # padded by 1e-5 on each side; FP32 lattice vs the FP64 one differ by ~1e-7
+        assert np.all(lo >= corners.min(0) - 2e-5) and np.all(hi <= corners.max(0) + 2e-5 + 1e-6 * ext)
