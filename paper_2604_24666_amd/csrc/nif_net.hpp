@@ -34,7 +34,10 @@ enum { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
 constexpr int kMaxLayers = 10;
 constexpr int kSegStride = 8;    // LDS floats per segment: x0 (3), pad, x1 (3), pad
 constexpr int kZStride = 17;     // LDS floats per segment of head outputs (16 + pad)
-constexpr int kQueryCB = 2;      // 16-segment column blocks per MLP pass in the fused query
+#ifndef NIF_QUERY_CB
+#define NIF_QUERY_CB 1
+#endif
+constexpr int kQueryCB = NIF_QUERY_CB;      // 16-segment column blocks per MLP pass in the fused query
 
 struct EncParams {
     const void* tab;        // [L][T][2] FP32 or FP16
@@ -155,6 +158,121 @@ __device__ __forceinline__ float2 grid_lookup(const EncParams& ep, int l, double
     return r[0];
 }
 
+// ------------------------------------------------------------------ wave-uniform level lookups
+// The first layer of the fused network assigns lanes as (PE combination, segment): every
+// lane of the wave looks up the same level at the same time, so the level's resolution,
+// table offset and dense/hash choice are wave-uniform.  The two x-neighbouring corners of
+// each (y, z) corner pair are fetched with one paired load: in a dense level they are
+// adjacent entries; in a hashed level (x prime 1) the entries of x and x+1 are the two
+// halves of one aligned pair when x is even, and a second single-entry load is issued
+// only by lanes whose x is odd.
+
+template <bool F16> struct TabTypes;
+template <> struct TabTypes<true> { using E = uint32_t; using Pr = uint2; };   // half2 entries
+template <> struct TabTypes<false> { using E = uint2; using Pr = uint4; };     // float2 entries
+
+__device__ __forceinline__ float2 entry_f2(uint32_t e) {
+    return __half22float2(__builtin_bit_cast(__half2, e));
+}
+__device__ __forceinline__ float2 entry_f2(uint2 e) {
+    return make_float2(__uint_as_float(e.x), __uint_as_float(e.y));
+}
+__device__ __forceinline__ void pair_split(uint2 p, uint32_t& lo, uint32_t& hi) { lo = p.x; hi = p.y; }
+__device__ __forceinline__ void pair_split(uint4 p, uint2& lo, uint2& hi) { lo = make_uint2(p.x, p.y); hi = make_uint2(p.z, p.w); }
+__device__ __forceinline__ uint32_t sel(bool c, uint32_t a, uint32_t b) { return c ? a : b; }
+__device__ __forceinline__ uint2 sel(bool c, uint2 a, uint2 b) { return make_uint2(c ? a.x : b.x, c ? a.y : b.y); }
+
+// Sample position of PE combination c = point * S + sample of a segment whose rest-space
+// points sit at sp[0..2] (entry) and sp[4..6] (exit): x, (sin 2^k x + 1)/2 or
+// (cos 2^k x + 1)/2 per axis, in FP64, x clamped to [0, 1].
+__device__ __forceinline__ void pe_combo(const float* sp, int c, int S, double out[3]) {
+    const int p = c >= S ? 1 : 0;
+    const int s = c - p * S;
+    const int k = s > 0 ? (s - 1) >> 1 : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double v = fmin(fmax((double)sp[4 * p + a], 0.0), 1.0);
+        double sn, cs;
+        sincos(ldexp(v, k), &sn, &cs);
+        out[a] = s == 0 ? v : 0.5 * (((s & 1) ? sn : cs) + 1.0);
+    }
+}
+
+// Interpolated features of levels l0 .. l0+LB-1 (wave-uniform) at one sample position:
+// feat[2k + f] = feature f of level l0 + k.
+template <int LB, bool F16>
+__device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const double smp[3], float feat[2 * LB]) {
+    using E = typename TabTypes<F16>::E;
+    using Pr = typename TabTypes<F16>::Pr;
+    const E* tab = reinterpret_cast<const E*>(ep.tab);
+    const uint32_t mask = (1u << ep.log2T) - 1u;
+    Pr A[LB][4];
+    E B[LB][4];
+    uint32_t swp[LB];       // bit pp: the pair's halves are swapped (hashed level, odd first index)
+    uint32_t ixs[LB];
+    float wx[LB], wy[LB], wz[LB];
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+        const int l = l0 + k;
+        const int N = ep.res[l];
+        uint32_t ix, iy, iz;
+        grid_axis(smp[0], N, ix, wx[k]);
+        grid_axis(smp[1], N, iy, wy[k]);
+        grid_axis(smp[2], N, iz, wz[k]);
+        ixs[k] = ix;
+        swp[k] = 0u;
+        const E* tl = tab + ((size_t)l << ep.log2T);
+        if ((ep.dense_mask >> l) & 1u) {
+            const uint32_t n1 = (uint32_t)N + 1u;
+#pragma unroll
+            for (int pp = 0; pp < 4; ++pp) {
+                const uint32_t e = ix + n1 * ((iy + (pp & 1)) + n1 * (iz + (pp >> 1)));
+                __builtin_memcpy(&A[k][pp], tl + e, sizeof(Pr));
+            }
+        } else {
+#pragma unroll
+            for (int pp = 0; pp < 4; ++pp) {
+                const uint32_t hyz = ((iy + (pp & 1)) * 2654435761u) ^ ((iz + (pp >> 1)) * 805459861u);
+                const uint32_t h0 = (ix ^ hyz) & mask;
+                swp[k] |= (h0 & 1u) << pp;
+                __builtin_memcpy(&A[k][pp], tl + (h0 & ~1u), sizeof(Pr));
+            }
+            if (ix & 1u) {
+#pragma unroll
+                for (int pp = 0; pp < 4; ++pp) {
+                    const uint32_t hyz = ((iy + (pp & 1)) * 2654435761u) ^ ((iz + (pp >> 1)) * 805459861u);
+                    B[k][pp] = tl[((ix + 1u) ^ hyz) & mask];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+        const bool dense = (ep.dense_mask >> (l0 + k)) & 1u;
+        const bool odd = !dense && (ixs[k] & 1u);
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) {
+            E lo, hi;
+            pair_split(A[k][pp], lo, hi);
+            const bool swap = (swp[k] >> pp) & 1u;
+            const E e0 = sel(swap, hi, lo);
+            const E e1 = odd ? B[k][pp] : sel(swap, lo, hi);
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int c = 2 * pp + cx;
+                const float wt = (cx ? wx[k] : 1.f - wx[k]) * (((c >> 1) & 1) ? wy[k] : 1.f - wy[k]) *
+                                 (((c >> 2) & 1) ? wz[k] : 1.f - wz[k]);
+                const float2 v = entry_f2(cx ? e1 : e0);
+                acc.x = fmaf(wt, v.x, acc.x);
+                acc.y = fmaf(wt, v.y, acc.y);
+            }
+        }
+        feat[2 * k] = acc.x;
+        feat[2 * k + 1] = acc.y;
+    }
+}
+
 // Features of lane quarter q for one sample: levels [q LQ, (q+1) LQ), 2 features each.
 template <int LQ, bool F16>
 __device__ __forceinline__ void quarter_features(const EncParams& ep, int q, const double smp[3], float feat[8]) {
@@ -226,7 +344,7 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
     constexpr int OB = HW / 16;
     const int lane = lane_id();
     const int q = lane >> 4, j = lane & 15;
-    const int L = np.enc.L, LQ = L >> 2, FQ = 2 * LQ;
+    const int L = np.enc.L;
     const int S = 1 + 2 * np.enc.F;
     const int E = np.E;
 
@@ -240,56 +358,56 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
             for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
         }
     }
-    // ---- layer 1: stream the encoding chunk by chunk (one chunk = one point and PE sample)
-    for (int p = 0; p < 2; ++p) {
-        PEState pe[CB];
+    // ---- layer 1: lane (q, j) takes PE combination c = 4u + q (point-major, 2S in all) of
+    // segment j; the wave walks the levels in batches of 4, all lanes on the same level.
+    // MFMA k-index = (combination of the lane's quarter, level, feature), so each lane loads
+    // the matching weights W0[row][c 2L + 2l + f].
+    const int n_comb = 2 * S;
+    for (int u = 0; 4 * u < n_comb; ++u) {
+        const int c_raw = 4 * u + q;
+        const bool live = c_raw < n_comb;
+        const int c = live ? c_raw : 0;
+        double smp[CB][3];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const float* sp = s_seg + (seg_base + cb * 16 + j) * kSegStride + 4 * p;
-            pe_begin(pe[cb], sp[0], sp[1], sp[2]);
-        }
-        for (int s = 0; s < S; ++s) {
+        for (int cb = 0; cb < CB; ++cb) pe_combo(s_seg + (seg_base + cb * 16 + j) * kSegStride, c, S, smp[cb]);
+        for (int l0 = 0; l0 < L; l0 += 4) {
             float feat[CB][8];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                double smp[3];
-                pe_sample(pe[cb], s, smp);
-                lane_features(np.enc, q, smp, feat[cb]);
+                if (np.enc.f16) {
+                    lookup_levels<4, true>(np.enc, l0, smp[cb], feat[cb]);
+                } else {     // FP32 entries are twice the size: two levels per batch
+                    lookup_levels<2, false>(np.enc, l0, smp[cb], feat[cb]);
+                    lookup_levels<2, false>(np.enc, l0 + 2, smp[cb], feat[cb] + 4);
+                }
+                if (!live) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) feat[cb][t] = 0.f;
+                }
             }
-            const int e0 = (p * S + s) * L * 2 + FQ * q;
+            const int e0 = c * 2 * L + 2 * l0;
 #pragma unroll
             for (int ob = 0; ob < OB; ++ob) {
                 if constexpr (PREC == P_FP32) {
                     const float* w = reinterpret_cast<const float*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0;
-                    float wf[8];
                     const float4 w0 = *reinterpret_cast<const float4*>(w);
-                    wf[0] = w0.x; wf[1] = w0.y; wf[2] = w0.z; wf[3] = w0.w;
-                    if (FQ == 8) {
-                        const float4 w1 = *reinterpret_cast<const float4*>(w + 4);
-                        wf[4] = w1.x; wf[5] = w1.y; wf[6] = w1.z; wf[7] = w1.w;
-                    } else {
-                        wf[4] = wf[5] = wf[6] = wf[7] = 0.f;
-                    }
+                    const float4 w1 = *reinterpret_cast<const float4*>(w + 4);
+                    const float wf[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        if (t < FQ) {
+                    for (int t = 0; t < 8; ++t)
 #pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(wf[t], feat[cb][t], acc[ob][cb]);
-                        }
-                    }
+                        for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(wf[t], feat[cb][t], acc[ob][cb]);
                 } else {
                     const shortx4* w = reinterpret_cast<const shortx4*>(
                         reinterpret_cast<const uint16_t*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0);
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
-                        if (4 * t < FQ) {
-                            const shortx4 wa = w[t];
+                        const shortx4 wa = w[t];
 #pragma unroll
-                            for (int cb = 0; cb < CB; ++cb) {
-                                const shortx4 fb = pack4<PREC>(feat[cb][4 * t], feat[cb][4 * t + 1], feat[cb][4 * t + 2],
-                                                               feat[cb][4 * t + 3]);
-                                acc[ob][cb] = mfma16<PREC>(wa, fb, acc[ob][cb]);
-                            }
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const shortx4 fb = pack4<PREC>(feat[cb][4 * t], feat[cb][4 * t + 1], feat[cb][4 * t + 2],
+                                                           feat[cb][4 * t + 3]);
+                            acc[ob][cb] = mfma16<PREC>(wa, fb, acc[ob][cb]);
                         }
                     }
                 }

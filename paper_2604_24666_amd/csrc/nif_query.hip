@@ -175,37 +175,111 @@ __device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t a, int64_
 }
 
 // ------------------------------------------------------------------ fused first-hit query
+//
+// Register budget.  The traversal state of a lane (ray index, pose, DDA state, current
+// segment) is parked in LDS while the wave runs the network, so the encoding + MLP phase
+// holds only its own values and the kernel fits more waves per SIMD; the ray and the pose
+// constants are re-read (L1/L2 resident) when the lane resumes.  One wave per workgroup.
+
+// Parked words per lane, stored [word][64] (lane-consecutive, no bank conflicts).
+enum {
+    QW_R_LO, QW_R_HI, QW_POSE, QW_NQ, QW_LASTZ, QW_HAS,
+    QW_IX, QW_IY, QW_IZ, QW_TMX, QW_TMY, QW_TMZ, QW_TDX, QW_TDY, QW_TDZ, QW_EX, QW_EY, QW_EZ,
+    QW_SX, QW_SY, QW_SZ, QW_TLO, QW_LASTA, QW_LASTC, QW_ACTIVE,
+    QW_CELL, QW_A, QW_B,
+    QW_WORDS
+};
+
+struct Parked {
+    int32_t* w;
+    int lane;
+    __device__ __forceinline__ void put(int k, int32_t v) const { w[k * 64 + lane] = v; }
+    __device__ __forceinline__ void putf(int k, float v) const { w[k * 64 + lane] = __float_as_int(v); }
+    __device__ __forceinline__ int32_t get(int k) const { return w[k * 64 + lane]; }
+    __device__ __forceinline__ float getf(int k) const { return __int_as_float(w[k * 64 + lane]); }
+};
+
+__device__ __forceinline__ void park_trav(const Parked& pk, const Trav& T) {
+    pk.put(QW_IX, T.ix); pk.put(QW_IY, T.iy); pk.put(QW_IZ, T.iz);
+    pk.putf(QW_TMX, T.tmx); pk.putf(QW_TMY, T.tmy); pk.putf(QW_TMZ, T.tmz);
+    pk.putf(QW_TDX, T.tdx); pk.putf(QW_TDY, T.tdy); pk.putf(QW_TDZ, T.tdz);
+    pk.put(QW_EX, T.ex); pk.put(QW_EY, T.ey); pk.put(QW_EZ, T.ez);
+    pk.put(QW_SX, T.sx); pk.put(QW_SY, T.sy); pk.put(QW_SZ, T.sz);
+    pk.putf(QW_TLO, T.t_lo); pk.putf(QW_LASTA, T.last_a); pk.put(QW_LASTC, T.last_cell); pk.put(QW_ACTIVE, T.active);
+}
+
+__device__ __forceinline__ void unpark_trav(const Parked& pk, Trav& T) {
+    T.ix = pk.get(QW_IX); T.iy = pk.get(QW_IY); T.iz = pk.get(QW_IZ);
+    T.tmx = pk.getf(QW_TMX); T.tmy = pk.getf(QW_TMY); T.tmz = pk.getf(QW_TMZ);
+    T.tdx = pk.getf(QW_TDX); T.tdy = pk.getf(QW_TDY); T.tdz = pk.getf(QW_TDZ);
+    T.ex = pk.get(QW_EX); T.ey = pk.get(QW_EY); T.ez = pk.get(QW_EZ);
+    T.sx = pk.get(QW_SX); T.sy = pk.get(QW_SY); T.sz = pk.get(QW_SZ);
+    T.t_lo = pk.getf(QW_TLO); T.last_a = pk.getf(QW_LASTA); T.last_cell = pk.get(QW_LASTC); T.active = pk.get(QW_ACTIVE);
+}
+
+#ifndef NIF_QUERY_MIN_WAVES
+#define NIF_QUERY_MIN_WAVES 2
+#endif
 
 template <int HW, int PREC>
-__global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
-                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats,
-                                               int pose_times) {
+__global__ void __launch_bounds__(64, HW >= 128 ? 1 : NIF_QUERY_MIN_WAVES) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
+                                              int64_t* __restrict__ counters, int64_t* __restrict__ stats,
+                                              int pose_times) {
     constexpr int CB = kQueryCB;
     constexpr int PASSES = 4 / CB;
-    __shared__ float s_seg_all[4][64 * kSegStride];
-    __shared__ float s_z_all[4][64 * kZStride];
-    const int w = threadIdx.x >> 6;
+    __shared__ int32_t s_park[QW_WORDS * 64];
+    __shared__ float s_seg[64 * kSegStride];
+    __shared__ float s_z[64 * kZStride];
     const int lane = lane_id();
-    float* s_seg = s_seg_all[w];
-    float* s_z = s_z_all[w];
+    const Parked pk{s_park, lane};
     const int n_mat = np.H - 8;
 
-    int64_t r = -1;
-    bool exhausted = false, has = false;
-    Ray ray;
-    ray.o = ray.d = make_float3(0.f, 0.f, 0.f);
-    Trav tv;
-    tv.active = 0;
-    PoseDev P;
-    P.kind = 0;
-    Segment sg;
-    sg.cell = -1; sg.a = sg.b = 0.f; sg.face = -1;
-    int nq = 0, bad = 0, pose = 0;
-    float last_z0 = -INFINITY;
+    bool exhausted = false;
+    int bad = 0;
     int64_t n_done = 0, n_eval = 0;
     if (pose_times && lane == 0) atomicMin((unsigned long long*)&stats[4], (unsigned long long)wall_clock64());
+    pk.put(QW_R_LO, -1); pk.put(QW_R_HI, -1); pk.put(QW_HAS, 0); pk.put(QW_POSE, 0);
 
     for (;;) {
+        // ---- resume the lane: ray, pose, and the result of the last network round
+        int64_t r = (int64_t)(((uint64_t)(uint32_t)pk.get(QW_R_HI) << 32) | (uint32_t)pk.get(QW_R_LO));
+        int pose = pk.get(QW_POSE);
+        bool has = pk.get(QW_HAS) != 0;
+        int nq = 0;
+        float last_z0 = -INFINITY;
+        Ray ray;
+        ray.o = ray.d = make_float3(0.f, 0.f, 0.f);
+        Trav tv;
+        tv.active = 0;
+        PoseDev P;
+        P.kind = 0;
+        Segment sg;
+        sg.cell = -1; sg.a = sg.b = 0.f; sg.face = -1;
+        if (r >= 0) {
+            nq = pk.get(QW_NQ);
+            last_z0 = pk.getf(QW_LASTZ);
+            unpark_trav(pk, tv);
+            ray = load_ray(R, r);
+            P = G.poses[pose];
+        }
+        bool hitnow = false;
+        if (has) {
+            ++nq;
+            ++n_eval;
+            const float* z = s_z + lane * kZStride;
+            last_z0 = z[0];
+            if (z[0] > 0.f) {
+                sg.cell = pk.get(QW_CELL); sg.a = pk.getf(QW_A); sg.b = pk.getf(QW_B);
+                const float* my = s_seg + lane * kSegStride;
+                write_hit(out, r, sg, make_float3(my[0], my[1], my[2]), make_float3(my[4], my[5], my[6]), z, nq, n_mat);
+                r = -1;
+                ++n_done;
+                hitnow = true;
+            }
+            has = false;
+        }
+        if (pose_times) note_finished(stats, R.off, R.n_poses, hitnow, pose);
+
         // ---- give every lane a segment, taking new rays as old ones finish or miss
         for (;;) {
             const bool need = !exhausted && r < 0;
@@ -245,7 +319,8 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
             if (pose_times) note_finished(stats, R.off, R.n_poses, missed, pose);
         }
         if (!ballot(has)) break;
-        // ---- rest-space entry/exit points (local linearization inside the voxel)
+
+        // ---- rest-space entry/exit points (local linearization inside the voxel), park, network
         float3 x0 = make_float3(0.5f, 0.5f, 0.5f), x1 = x0;
         if (has) {
             x0 = deform_inv(P, ray_at(ray, sg.a));
@@ -254,25 +329,16 @@ __global__ void __launch_bounds__(256) k_query(NetParams np, GridArgs G, RayArgs
         float* my = s_seg + lane * kSegStride;
         my[0] = x0.x; my[1] = x0.y; my[2] = x0.z;
         my[4] = x1.x; my[5] = x1.y; my[6] = x1.z;
+        pk.put(QW_R_LO, (int32_t)(uint32_t)(uint64_t)r); pk.put(QW_R_HI, (int32_t)(uint32_t)((uint64_t)r >> 32));
+        pk.put(QW_POSE, pose); pk.put(QW_HAS, has ? 1 : 0);
+        if (r >= 0) {
+            pk.put(QW_NQ, nq); pk.putf(QW_LASTZ, last_z0);
+            park_trav(pk, tv);
+            pk.put(QW_CELL, sg.cell); pk.putf(QW_A, sg.a); pk.putf(QW_B, sg.b);
+        }
         wave_lds_sync();
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
-        wave_lds_sync();
-        bool hitnow = false;
-        if (has) {
-            ++nq;
-            ++n_eval;
-            const float* z = s_z + lane * kZStride;
-            last_z0 = z[0];
-            if (z[0] > 0.f) {
-                write_hit(out, r, sg, x0, x1, z, nq, n_mat);
-                r = -1;
-                ++n_done;
-                hitnow = true;
-            }
-            has = false;
-        }
-        if (pose_times) note_finished(stats, R.off, R.n_poses, hitnow, pose);
         wave_lds_sync();
     }
     if (stats) wave_add_stats(stats, n_done, n_eval, bad);
@@ -440,15 +506,15 @@ int trace_launch(const nif_grid* g, const nif_rays* r, int64_t n, int32_t max_se
     return check_hip(hipGetLastError(), "k_trace launch");
 }
 
-// Persistent grid size of the fused query: blocks of 4 waves per compute unit (tunable).
-static int g_query_blocks_per_cu = 8;
+// Persistent grid size of the fused query: one-wave workgroups per compute unit (tunable).
+static int g_query_blocks_per_cu = 12;
 
 template <int HW, int PREC>
 static void launch_query(const NetParams& np, const GridArgs& G, const RayArgs& R, const nif_hits& out, int64_t* ctr,
                          int64_t* stats, int pt, hipStream_t st) {
     const int64_t waves = (R.n + 63) / 64;
-    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, (int64_t)device_cus() * g_query_blocks_per_cu);
-    hipLaunchKernelGGL((k_query<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, G, R, out, ctr,
+    const int64_t blocks = std::min<int64_t>(waves, (int64_t)device_cus() * g_query_blocks_per_cu);
+    hipLaunchKernelGGL((k_query<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(64), 0, st, np, G, R, out, ctr,
                        stats, pt);
 }
 
