@@ -33,7 +33,11 @@ HBM_PEAK_GBS = 8000.0
 # were taken on (SHA-256 of KQUERY_SOURCES); otherwise the traffic is reported as null.
 KQUERY_SOURCES = ["csrc/nif_query.hip", "csrc/nif_net.hpp", "csrc/nif_trace.hpp", "csrc/nif_device.hpp",
                   "csrc/nif_internal.hpp", "build.py"]
-KQUERY_TRAFFIC = None   # {"sources_sha256": ..., "fetch_kib": ..., "write_kib": ..., "fetch_scale": ..., "write_scale": ...}
+KQUERY_TRAFFIC = {
+    "sources_sha256": "c5f0f4f9805672524aeb19b56ed1c7513b4479fc1f8b99f3df8310e2d0bee4d3",
+    "fetch_kib": 1.18827e8, "write_kib": 1.73186e6,          # per k_query<64, FP32> launch, default workload
+    "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
+}
 
 
 def kquery_sources_sha() -> str:
