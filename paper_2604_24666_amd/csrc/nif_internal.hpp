@@ -55,6 +55,11 @@ struct nif_model {
     float* dz = nullptr;                // [max_batch][16] d loss / d heads (loss-scaled, padded)
     float* acts = nullptr;              // [hidden_layers][max_batch][hidden_width] post-ReLU
     float* delta = nullptr;             // [hidden_layers][max_batch][hidden_width] d loss / d pre-activation
+    int64_t bwd_chunk = 0;              // samples per encoding-backward round
+    int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
+    int32_t* bwd_scan = nullptr;        // scan partial sums + total
+    uint16_t* bwd_key = nullptr;        // table-gradient additions: entry within the bucket
+    float2* bwd_val = nullptr;          //                            value per feature
     double* dacc = nullptr;             // [16] loss sums, loss scale, Adam bias corrections
     int64_t* tcount = nullptr;          // [16] positives, step, clean steps, flags
     int32_t step = 0;

@@ -12,8 +12,9 @@
 //   begin / count positives -> zero gradients -> forward (stores hidden activations) ->
 //   loss and d loss / d heads (loss-scaled) -> MLP backward on MFMA (transposed weights,
 //   deltas chained in registers) -> split-K dW GEMMs on MFMA -> encoding backward (the
-//   encoding is recomputed chunk by chunk, d enc = W0^T delta, FP32 atomic scatter-add into
-//   the table gradients with the trilinear weights, dW0) -> non-finite check -> finalize
+//   encoding is recomputed chunk by chunk, d enc = W0^T delta, the table-gradient additions
+//   with the trilinear weights grouped by table slice and summed in LDS, dW0) -> non-finite
+//   check -> finalize
 //   (losses, d/ds, dynamic loss scale) -> Adam on all parameters (FP16 table copy refreshed
 //   in place) -> refresh of the MLP working copies.
 #include <algorithm>
@@ -31,12 +32,36 @@ enum { TC_NPOS = 0, TC_STEP = 1, TC_GOOD = 2, TC_NONFINITE = 3, TC_SKIP = 4 };
 enum { DA_SUM = 0, DA_SCALE = 5, DA_SCALE_USED = 6, DA_C1 = 7, DA_C2 = 8 };
 constexpr float kDistEps = 1e-4f;
 constexpr int kGrowInterval = 1000;
+constexpr int64_t kEncBwdKc = 2048;        // samples per encoding-backward block
+constexpr int64_t kEncBwdChunk = 1 << 16;  // samples per count/fill/reduce round
 
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
     for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
+    for (void** p : {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val})
+        if (*p) { (void)hipFree(*p); *p = nullptr; }
     m->max_batch = 0;
+    {
+        // encoding-backward additions: per chunk of samples, one per (sample, PE chunk, level, corner)
+        const int log2T = m->desc.log2_table, L = m->desc.levels;
+        const int SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
+        const int64_t n_buckets = (int64_t)L * (1 << (log2T - SB));
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(B, kEncBwdChunk));
+        const int64_t n_blk = ((chunk + kEncBwdKc - 1) / kEncBwdKc) * 2 * m->S;
+        const int64_t n_add = chunk * 2 * m->S * L * 8;
+        const int64_t n_cnt = n_buckets * n_blk;
+        const size_t sz[4] = {sizeof(int32_t) * (size_t)n_cnt,
+                              sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 2 + n_buckets),
+                              sizeof(uint16_t) * (size_t)n_add, sizeof(float2) * (size_t)n_add};
+        void** ptr[4] = {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val};
+        for (int i = 0; i < 4; ++i)
+            if (hipMalloc(ptr[i], sz[i]) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(NIF_E_OOM, "encoding-backward buffer allocation failed");
+            }
+        m->bwd_chunk = chunk;
+    }
     const int64_t hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
     const struct { float** p; int64_t n; } a[] = {{&m->zbuf, B * m->H}, {&m->dz, B * 16}, {&m->acts, B * hw * nh},
                                                   {&m->delta, B * hw * nh}};
@@ -324,11 +349,22 @@ __global__ void __launch_bounds__(256) k_dw(const float* __restrict__ dsrc, int 
 }
 
 // ------------------------------------------------------------------ encoding backward
-// Grid (sample splits, 2 S chunks).  Chunk c = (point p, PE sample s) owns encoding features
-// [c FW, (c+1) FW), FW = 2 L.  Per tile of 64 samples: recompute the chunk's features
-// (thread <-> one sample, levels w, w+4, ...), d enc = delta_0 . W0[:, chunk] (LDS), scatter
-// d enc times the trilinear weights into the FP32 table gradient (atomics), accumulate
-// dW0[:, chunk] += delta_0^T enc and, for chunk 0, db0.  Optional d x through phi and gamma.
+// The table gradient is a scatter-add: every (sample, PE chunk, level, corner) adds
+// w_corner * d enc to one table entry, about 2e9 additions per 2^18-sample step.  Device-
+// scope float atomics on this part are executed past the per-XCD L2s and would bound the
+// step, so the additions are grouped instead:
+//   count  - each block histograms the table slices ("buckets", at most 4096 entries of one
+//            level each) its additions fall into (LDS atomics) and stores the counts;
+//   scan   - an exclusive scan over (bucket, block) gives every block a private output range
+//            per bucket;
+//   fill   - the same block decomposition recomputes the additions and writes (entry within
+//            the slice, value pair) into its ranges (LDS cursors, no global atomics);
+//   reduce - one block per slice window sums its additions in LDS and adds the window to
+//            the FP32 table gradient.
+// Samples are processed in chunks so the addition buffer stays bounded.  Blocks are (sample
+// split, PE chunk c = point * S + sample); per tile of 64 samples a thread owns one sample
+// and levels w, w + 4, ...
+
 struct EncBwdParams {
     EncParams enc;
     const float* W0;     // FP32 [HW][E]
@@ -338,6 +374,17 @@ struct EncBwdParams {
     float* gb0;
     float* dx0;          // nullable SoA [3][B]
     float* dx1;
+    int64_t B;           // stride of the SoA point arrays and sample count of the whole batch
+    int64_t c0;          // first sample of this chunk
+    int64_t n;           // samples in this chunk
+    int64_t Kc;          // samples per block
+    int32_t SB;          // log2 entries per bucket
+    int32_t NBL;         // buckets per level
+    int32_t n_buckets;   // L * NBL
+    int32_t n_blk;       // blocks of the chunk grid
+    int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
+    uint16_t* key;       // additions: entry within the bucket
+    float2* val;         // additions: value per feature
 };
 
 __device__ __forceinline__ double pe_direct(int s, double x, double* dsdx) {
@@ -351,9 +398,135 @@ __device__ __forceinline__ double pe_direct(int s, double x, double* dsdx) {
     return 0.5 * (cs + 1.0);
 }
 
+// Sample position of this thread's sample in PE chunk (p, s), its d x factors and cells.
+struct EncPoint {
+    double smp[3], dsdx[3];
+    float inside[3];
+    uint32_t ci[4][3];
+    float cw[4][3];
+};
+
+__device__ __forceinline__ void enc_point(const EncBwdParams& P, const float* xs, int64_t seg, bool valid, int s,
+                                          int lw, EncPoint& e) {
+    const int L = P.enc.L;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float xv = valid ? xs[a * P.B + seg] : 0.5f;
+        e.inside[a] = (xv >= 0.f && xv <= 1.f) ? 1.f : 0.f;
+        e.smp[a] = pe_direct(s, fmin(fmax((double)xv, 0.0), 1.0), &e.dsdx[a]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int l = lw + 4 * v;
+        if (l < L) {
+            const int N = P.enc.res[l];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) grid_axis(e.smp[a], N, e.ci[v][a], e.cw[v][a]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P, const float* __restrict__ x0,
+                                                       const float* __restrict__ x1) {
+    extern __shared__ int32_t s_h[];    // [n_buckets]
+    const int c = blockIdx.y, p = c / P.S, s = c % P.S;
+    const int tid = threadIdx.x, seg_l = tid & 63, lw = tid >> 6;
+    const int L = P.enc.L;
+    const uint32_t mask = (1u << P.enc.log2T) - 1u;
+    for (int i = tid; i < P.n_buckets; i += 256) s_h[i] = 0;
+    __syncthreads();
+    const float* xs = p == 0 ? x0 : x1;
+    const int64_t k0 = P.c0 + (int64_t)blockIdx.x * P.Kc, k1 = std::min<int64_t>(P.c0 + P.n, k0 + P.Kc);
+    for (int64_t seg0 = k0; seg0 < k1; seg0 += 64) {
+        const int64_t seg = seg0 + seg_l;
+        if (seg >= k1) continue;
+        EncPoint e;
+        enc_point(P, xs, seg, true, s, lw, e);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int l = lw + 4 * v;
+            if (l >= L) continue;
+            const bool dense = (P.enc.dense_mask >> l) & 1u;
+            const uint32_t n1 = (uint32_t)P.enc.res[l] + 1u;
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const uint32_t idx = grid_index(e.ci[v][0] + (cc & 1), e.ci[v][1] + ((cc >> 1) & 1),
+                                                e.ci[v][2] + ((cc >> 2) & 1), n1, dense, mask);
+                atomicAdd(&s_h[l * P.NBL + (int)(idx >> P.SB)], 1);
+            }
+        }
+    }
+    __syncthreads();
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    for (int i = tid; i < P.n_buckets; i += 256) P.cnt[(int64_t)i * P.n_blk + blk] = s_h[i];
+}
+
+// Exclusive scan of n int32 in place, in chunks of 4096: per-chunk sums, a one-block scan of
+// the sums (total to *total), then per-chunk scans.
+__global__ void __launch_bounds__(256) k_scan_sums(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ sums) {
+    __shared__ int32_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * 4096;
+    int32_t acc = 0;
+    for (int i = threadIdx.x; i < 4096; i += 256)
+        if (base + i < n) acc += a[base + i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(int32_t* __restrict__ sums, int n_chunks, int32_t* __restrict__ total) {
+    __shared__ int32_t sh[1024];
+    int32_t carry = 0;
+    for (int base = 0; base < n_chunks; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int32_t v = i < n_chunks ? sums[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n_chunks) sums[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(int32_t* __restrict__ a, int64_t n, const int32_t* __restrict__ sums) {
+    __shared__ int32_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * 4096 + (int64_t)threadIdx.x * 16;
+    int32_t v[16];
+    int32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = base + k < n ? a[base + k] : 0;
+        acc += v[k];
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int32_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = sums[blockIdx.x] + sh[threadIdx.x] - acc;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __restrict__ x0,
-                                                 const float* __restrict__ x1, const float* __restrict__ delta0,
-                                                 int64_t B, int64_t Kc) {
+                                                 const float* __restrict__ x1, const float* __restrict__ delta0) {
     const int L = P.enc.L, FW = 2 * L, HW = P.HW, E = P.E;
     const int c = blockIdx.y, p = c / P.S, s = c % P.S;
     const int tid = threadIdx.x, seg_l = tid & 63, lw = tid >> 6;   // levels lw, lw+4, lw+8, lw+12
@@ -361,6 +534,9 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
     __shared__ float sD[64][129];   // delta_0 tile
     __shared__ float sE[64][33];    // recomputed encoding
     __shared__ float sG[64][33];    // d encoding
+    extern __shared__ int32_t s_cur[];   // [n_buckets]: this block's next output slot per bucket
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    for (int i = tid; i < P.n_buckets; i += 256) s_cur[i] = P.cnt[(int64_t)i * P.n_blk + blk];
     for (int i = tid; i < HW * FW; i += 256) {
         const int o = i / FW, f = i % FW;
         sW[o][f] = P.W0[(size_t)o * E + c * FW + f];
@@ -372,8 +548,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
     float bsum = 0.f;
     const float* xs = p == 0 ? x0 : x1;
     float* dxs = p == 0 ? P.dx0 : P.dx1;
-    const int64_t k0 = (int64_t)blockIdx.x * Kc, k1 = std::min<int64_t>(B, k0 + Kc);
-    const uint32_t mask = (1u << P.enc.log2T) - 1u;
+    const int64_t k0 = P.c0 + (int64_t)blockIdx.x * P.Kc, k1 = std::min<int64_t>(P.c0 + P.n, k0 + P.Kc);
+    const uint32_t mask = (1u << P.enc.log2T) - 1u, kmask = (1u << P.SB) - 1u;
     __syncthreads();
     for (int64_t seg0 = k0; seg0 < k1; seg0 += 64) {
         const int64_t seg = seg0 + seg_l;
@@ -383,34 +559,17 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
             sD[sm][o] = seg0 + sm < k1 ? delta0[(seg0 + sm) * HW + o] : 0.f;
         }
         // (a) features of this thread's sample and levels
-        double smp[3], dsdx[3];
-        float inside[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float xv = valid ? xs[a * B + seg] : 0.5f;
-            inside[a] = (xv >= 0.f && xv <= 1.f) ? 1.f : 0.f;
-            smp[a] = pe_direct(s, fmin(fmax((double)xv, 0.0), 1.0), &dsdx[a]);
-        }
-        uint32_t ci[4][3];
-        float cw[4][3];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int l = lw + 4 * v;
-            if (l < L) {
-                const int N = P.enc.res[l];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) grid_axis(smp[a], N, ci[v][a], cw[v][a]);
-            }
-        }
+        EncPoint e;
+        enc_point(P, xs, seg, valid, s, lw, e);
         {
             // levels lw, lw + 4, ...: all corner gathers in flight together
             float2 r[4];
             if (L == 16) {
-                if (P.enc.f16) grid_lookup_n<4, true>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
-                else grid_lookup_n<4, false>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
+                if (P.enc.f16) grid_lookup_n<4, true>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
+                else grid_lookup_n<4, false>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
             } else {
-                if (P.enc.f16) grid_lookup_n<2, true>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
-                else grid_lookup_n<2, false>(P.enc, lw, 4, smp[0], smp[1], smp[2], r);
+                if (P.enc.f16) grid_lookup_n<2, true>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
+                else grid_lookup_n<2, false>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -429,7 +588,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
             sG[seg_l][f] = sacc;
         }
         __syncthreads();
-        // (c) scatter into the table gradient (and d x)
+        // (c) the table-gradient additions of this sample (and d x)
         if (valid) {
             float dpos[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -440,23 +599,23 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
                 const bool dense = (P.enc.dense_mask >> l) & 1u;
                 const uint32_t n1 = (uint32_t)N + 1u;
                 const float g0 = sG[seg_l][2 * l], g1 = sG[seg_l][2 * l + 1];
-                float* gt = P.g_tables + ((size_t)l << P.enc.log2T) * 2;
                 float dl[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                 for (int cc = 0; cc < 8; ++cc) {
                     const uint32_t bx = cc & 1, by = (cc >> 1) & 1, bz = (cc >> 2) & 1;
-                    const uint32_t idx = grid_index(ci[v][0] + bx, ci[v][1] + by, ci[v][2] + bz, n1, dense, mask);
-                    const float fx = bx ? cw[v][0] : 1.f - cw[v][0];
-                    const float fy = by ? cw[v][1] : 1.f - cw[v][1];
-                    const float fz = bz ? cw[v][2] : 1.f - cw[v][2];
+                    const uint32_t idx = grid_index(e.ci[v][0] + bx, e.ci[v][1] + by, e.ci[v][2] + bz, n1, dense, mask);
+                    const float fx = bx ? e.cw[v][0] : 1.f - e.cw[v][0];
+                    const float fy = by ? e.cw[v][1] : 1.f - e.cw[v][1];
+                    const float fz = bz ? e.cw[v][2] : 1.f - e.cw[v][2];
                     const float wt = fx * fy * fz;
-                    unsafeAtomicAdd(&gt[2 * idx], wt * g0);
-                    unsafeAtomicAdd(&gt[2 * idx + 1], wt * g1);
+                    const int32_t slot = atomicAdd(&s_cur[l * P.NBL + (int)(idx >> P.SB)], 1);
+                    P.key[slot] = (uint16_t)(idx & kmask);
+                    P.val[slot] = make_float2(wt * g0, wt * g1);
                     if (dxs) {
                         float2 tv;
-                        const size_t e = ((size_t)l << P.enc.log2T) + idx;
-                        if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[e]);
-                        else tv = reinterpret_cast<const float2*>(P.enc.tab)[e];
+                        const size_t te = ((size_t)l << P.enc.log2T) + idx;
+                        if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[te]);
+                        else tv = reinterpret_cast<const float2*>(P.enc.tab)[te];
                         const float gd = g0 * tv.x + g1 * tv.y;
                         dl[0] += gd * (bx ? 1.f : -1.f) * fy * fz;
                         dl[1] += gd * (by ? 1.f : -1.f) * fx * fz;
@@ -468,7 +627,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
             }
             if (dxs)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) unsafeAtomicAdd(&dxs[a * B + seg], dpos[a] * (float)dsdx[a] * inside[a]);
+                for (int a = 0; a < 3; ++a) unsafeAtomicAdd(&dxs[a * P.B + seg], dpos[a] * (float)e.dsdx[a] * e.inside[a]);
         }
         // (d) dW0[:, chunk] and db0
 #pragma unroll
@@ -492,6 +651,78 @@ __global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __
         }
     }
     if (c == 0 && tid < HW) unsafeAtomicAdd(&P.gb0[tid], bsum);
+}
+
+// Work list of the reduction: bucket b is cut into parts of at most kReducePart additions;
+// parts[b] = exclusive prefix of the part counts (parts[n_buckets] = total parts).
+constexpr int64_t kReducePart = 1 << 17;
+
+__global__ void __launch_bounds__(1024) k_enc_bwd_parts(EncBwdParams P, const int32_t* __restrict__ total,
+                                                        int32_t* __restrict__ parts) {
+    __shared__ int32_t sh[1024];
+    int32_t carry = 0;
+    for (int base = 0; base < P.n_buckets; base += 1024) {
+        const int b = base + (int)threadIdx.x;
+        int32_t v = 0;
+        if (b < P.n_buckets) {
+            const int64_t start = P.cnt[(int64_t)b * P.n_blk];
+            const int64_t end = b + 1 < P.n_buckets ? (int64_t)P.cnt[(int64_t)(b + 1) * P.n_blk] : (int64_t)*total;
+            v = (int32_t)std::max<int64_t>(1, (end - start + kReducePart - 1) / kReducePart);
+        }
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (b < P.n_buckets) parts[b] = carry + sh[threadIdx.x] - v;
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[P.n_buckets] = carry;
+}
+
+// Block (i, w): part i of the work list, window w (4096 entries) of its bucket.  A bucket cut
+// into one part is added to the table gradient directly; parts of a bucket cut into several
+// add their nonzero window entries with atomics.
+__global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const int32_t* __restrict__ total,
+                                                        const int32_t* __restrict__ parts) {
+    __shared__ float s_acc[2 * 4096];
+    const int i = blockIdx.x, w = blockIdx.y;
+    if (i >= parts[P.n_buckets]) return;
+    int lo = 0, hi = P.n_buckets - 1;                    // bucket b: parts[b] <= i < parts[b + 1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (parts[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int b = lo;
+    const int n_parts = parts[b + 1] - parts[b], part = i - parts[b];
+    const int wn = P.SB < 12 ? (1 << P.SB) : 4096;   // entries per window
+    for (int k = threadIdx.x; k < 2 * wn; k += 256) s_acc[k] = 0.f;
+    __syncthreads();
+    const int64_t b_start = P.cnt[(int64_t)b * P.n_blk];
+    const int64_t b_end = b + 1 < P.n_buckets ? (int64_t)P.cnt[(int64_t)(b + 1) * P.n_blk] : (int64_t)*total;
+    const int64_t start = b_start + (int64_t)part * kReducePart;
+    const int64_t end = std::min<int64_t>(b_end, start + kReducePart);
+    for (int64_t k = start + threadIdx.x; k < end; k += 256) {
+        const uint32_t key = P.key[k];
+        if ((int)(key >> 12) != w) continue;
+        const float2 v = P.val[k];
+        const int e = (int)(key & 4095u);
+        atomicAdd(&s_acc[2 * e], v.x);
+        atomicAdd(&s_acc[2 * e + 1], v.y);
+    }
+    __syncthreads();
+    const int l = b / P.NBL, slice = b % P.NBL;
+    float* g = P.g_tables + (((size_t)l << P.enc.log2T) + ((size_t)slice << P.SB) + (size_t)w * 4096) * 2;
+    if (n_parts == 1) {
+        for (int k = threadIdx.x; k < 2 * wn; k += 256) g[k] += s_acc[k];
+    } else {
+        for (int k = threadIdx.x; k < 2 * wn; k += 256)
+            if (s_acc[k] != 0.f) unsafeAtomicAdd(&g[k], s_acc[k]);
+    }
 }
 
 // ------------------------------------------------------------------ step bookkeeping
@@ -653,7 +884,7 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         hipLaunchKernelGGL(k_dw, dim3(ksplit), dim3(256), 0, st, dsrc, dstride, M_pad, M_real, hin, hw, B, Kc,
                            m->g_mlp + m->w_off[i], m->g_mlp + m->b_off[i]);
     }
-    // encoding backward (layer 0)
+    // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
     EncBwdParams ep;
     memset(&ep, 0, sizeof(ep));
     ep.enc = make_net_params(m, NIF_PREC_FP32).enc;
@@ -661,9 +892,35 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     ep.HW = hw; ep.E = m->E; ep.S = m->S;
     ep.g_tables = m->g_tables; ep.gW0 = m->g_mlp + m->w_off[0]; ep.gb0 = m->g_mlp + m->b_off[0];
     ep.dx0 = dx0; ep.dx1 = dx1;
-    const int64_t Kc0 = 2048;
-    hipLaunchKernelGGL(k_enc_bwd, dim3((unsigned)((B + Kc0 - 1) / Kc0), 2 * m->S), dim3(256), 0, st, ep, x0, x1,
-                       m->delta, B, Kc0);
+    ep.B = B;
+    ep.Kc = kEncBwdKc;
+    const int log2T = m->desc.log2_table;
+    ep.SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
+    ep.NBL = 1 << (log2T - ep.SB);
+    ep.n_buckets = m->desc.levels * ep.NBL;
+    ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
+    const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
+    for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
+        ep.c0 = c0;
+        ep.n = std::min<int64_t>(m->bwd_chunk, B - c0);
+        const unsigned nbx = (unsigned)((ep.n + ep.Kc - 1) / ep.Kc);
+        ep.n_blk = (int32_t)(nbx * 2 * m->S);
+        const dim3 grid(nbx, 2 * m->S);
+        const size_t lds = sizeof(int32_t) * (size_t)ep.n_buckets;
+        hipLaunchKernelGGL(k_enc_bwd_count, grid, dim3(256), lds, st, ep, x0, x1);
+        const int64_t n_cnt = (int64_t)ep.n_buckets * ep.n_blk;
+        const int n_chunks = (int)((n_cnt + 4095) / 4096);
+        int32_t* sums = m->bwd_scan;
+        int32_t* total = m->bwd_scan + n_chunks;
+        hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, n_chunks, total);
+        hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
+        hipLaunchKernelGGL(k_enc_bwd, grid, dim3(256), lds, st, ep, x0, x1, m->delta);
+        int32_t* parts = total + 1;
+        hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, st, ep, total, parts);
+        const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
+        hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, st, ep, total, parts);
+    }
     return check_hip(hipGetLastError(), "backward launch");
 }
 
