@@ -296,7 +296,7 @@ int nif_forward(const nif_model* m, const float* x0, const float* x1, int64_t B,
     if (B > 0) REQUIRE(x0 && x1 && heads, "x0, x1 and heads must not be null");
     REQUIRE(precision >= 0 && precision <= 2, "precision must be NIF_PREC_FP32, _BF16 or _FP16");
     if (!m->params_set) return fail(NIF_E_STATE, "model parameters were never set");
-    return nif::forward_launch(m, x0, x1, B, heads, precision, nullptr, S(stream));
+    return nif::forward_launch(m, x0, x1, B, heads, precision, nullptr, nullptr, S(stream));
 }
 
 int nif_backward(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh, float* dx0, float* dx1,

@@ -35,7 +35,7 @@ struct nif_model {
     std::vector<int32_t> dims_pad;      // last padded to 16
     std::vector<int64_t> w_off, b_off;  // canonical offsets of each layer's W and b
     std::vector<int64_t> wp_off, bp_off;// offsets in the padded working copies
-    std::vector<int64_t> wt_off;        // transposed padded copy of layer i >= 1: [in][out_pad]
+    std::vector<int64_t> wt_off;        // transposed padded copy of layer i: [in][out_pad]
     int64_t n_mlp_pad = 0;
     // parameters
     float* tables = nullptr;            // FP32 master [L][T][Fd]
@@ -55,6 +55,7 @@ struct nif_model {
     float* dz = nullptr;                // [max_batch][16] d loss / d heads (loss-scaled, padded)
     float* acts = nullptr;              // [hidden_layers][max_batch][hidden_width] post-ReLU
     float* delta = nullptr;             // [hidden_layers][max_batch][hidden_width] d loss / d pre-activation
+    float* enc = nullptr;               // [max_batch][E] encoding of the training forward
     int64_t bwd_chunk = 0;              // samples per encoding-backward round
     int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
@@ -92,7 +93,7 @@ int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64
 int set_query_blocks_per_cu(int v);
 int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st);
 int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads,
-                   int32_t precision, float* acts, hipStream_t st);
+                   int32_t precision, float* acts, float* enc, hipStream_t st);
 
 // nif_train.hip
 int model_alloc(nif_model* m);

@@ -41,7 +41,7 @@ __global__ void k_sync_mlp(LayerMap lm, const float* __restrict__ src, float* __
         f32[dst] = v;
         bf16[dst] = f2bf(v);
         f16[dst] = __float2half_rn(v);
-        if (i < nw && layer > 0) {      // transposed copy [in][out_pad] for the backward
+        if (i < nw) {                   // transposed copy [in][out_pad] for the backward
             const int64_t row = i / nin, col = i % nin;
             const int64_t t = lm.wt_off[layer] + col * npad + row;
             f32[t] = v;
@@ -112,7 +112,7 @@ int model_alloc(nif_model* m) {
         m->wp_off[i] = offp; offp += (int64_t)m->dims_pad[i + 1] * m->dims_pad[i];
         m->bp_off[i] = offp; offp += m->dims_pad[i + 1];
     }
-    for (int i = 1; i < m->n_layers; ++i) {
+    for (int i = 0; i < m->n_layers; ++i) {
         m->wt_off[i] = offp; offp += (int64_t)m->dims_pad[i + 1] * m->dims_pad[i];
     }
     m->n_mlp = off;
@@ -144,7 +144,7 @@ void model_free(nif_model* m) {
     void* ps[] = {m->tables, m->tables_h, m->mlp, m->mlp_pad_f32, m->mlp_pad_bf16, m->mlp_pad_f16, m->s,
                   m->g_tables, m->g_mlp, m->g_s, m->m_tables, m->v_tables, m->m_mlp, m->v_mlp,
                   m->m_s, m->v_s, m->counters, m->dacc, m->tcount, m->zbuf, m->dz, m->acts, m->delta,
-                  m->bwd_cnt, m->bwd_scan, m->bwd_key, m->bwd_val};
+                  m->enc, m->bwd_cnt, m->bwd_scan, m->bwd_key, m->bwd_val};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }

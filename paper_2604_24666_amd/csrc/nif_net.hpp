@@ -337,10 +337,12 @@ __device__ __forceinline__ void pe_sample(PEState& st, int s, double out[3]) {
 // ------------------------------------------------------------------ one MLP pass
 // Evaluates the network on segments [seg_base, seg_base + 16*CB) whose rest-space points sit
 // in s_seg (kSegStride floats each) and writes the 16 padded head outputs to s_z.
-// acts (nullable): hidden activations are also stored to acts[layer][seg_g0 + seg][HW].
+// acts (nullable): hidden activations are also stored to acts[layer][seg_g0 + seg][HW];
+// enc_out (nullable): the first layer's input, enc_out[seg_g0 + seg][E].
 template <int HW, int CB, int PREC>
 __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg, int seg_base, float* s_z,
-                                         float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid) {
+                                         float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid,
+                                         float* enc_out = nullptr) {
     constexpr int OB = HW / 16;
     const int lane = lane_id();
     const int q = lane >> 4, j = lane & 15;
@@ -386,6 +388,17 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
                 }
             }
             const int e0 = c * 2 * L + 2 * l0;
+            if (enc_out) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int64_t seg = seg_g0 + cb * 16 + j;
+                    if (live && seg < n_valid) {
+                        float4* dst = reinterpret_cast<float4*>(enc_out + seg * E + e0);
+                        dst[0] = make_float4(feat[cb][0], feat[cb][1], feat[cb][2], feat[cb][3]);
+                        dst[1] = make_float4(feat[cb][4], feat[cb][5], feat[cb][6], feat[cb][7]);
+                    }
+                }
+            }
 #pragma unroll
             for (int ob = 0; ob < OB; ++ob) {
                 if constexpr (PREC == P_FP32) {

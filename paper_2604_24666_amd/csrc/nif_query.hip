@@ -412,10 +412,12 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
 }
 
 // Heads of point pairs.  Each wave evaluates tiles of 64 pairs; acts (nullable) receives the
-// hidden activations [layer][B][HW] for the training backward.
+// hidden activations [layer][B][HW] and enc (nullable) the encoding [B][E], for the training
+// backward.
 template <int HW, int PREC>
 __global__ void __launch_bounds__(256) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
-                                                 int64_t B, float* __restrict__ heads, float* __restrict__ acts) {
+                                                 int64_t B, float* __restrict__ heads, float* __restrict__ acts,
+                                                 float* __restrict__ enc) {
     constexpr int CB = HW >= 128 ? 2 : 4;
     constexpr int PASSES = 4 / CB;
     __shared__ float s_seg_all[4][64 * kSegStride];
@@ -438,7 +440,7 @@ __global__ void __launch_bounds__(256) k_forward(NetParams np, const float* __re
         wave_lds_sync();
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps)
-            net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * 64 + ps * 16 * CB, B);
+            net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * 64 + ps * 16 * CB, B, enc);
         wave_lds_sync();
         if (seg < B)
             for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
@@ -569,34 +571,34 @@ int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hip
 
 template <int HW, int PREC>
 static void launch_forward(const NetParams& np, const float* x0, const float* x1, int64_t B, float* heads, float* acts,
-                           hipStream_t st) {
+                           float* enc, hipStream_t st) {
     const int64_t tiles = (B + 63) / 64;
     const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cus() * 8);
-    hipLaunchKernelGGL((k_forward<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts);
+    hipLaunchKernelGGL((k_forward<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts, enc);
 }
 
 template <int PREC>
 static int dispatch_forward(int hw, const NetParams& np, const float* x0, const float* x1, int64_t B, float* heads,
-                            float* acts, hipStream_t st) {
+                            float* acts, float* enc, hipStream_t st) {
     switch (hw) {
-        case 16: launch_forward<16, PREC>(np, x0, x1, B, heads, acts, st); break;
-        case 32: launch_forward<32, PREC>(np, x0, x1, B, heads, acts, st); break;
-        case 64: launch_forward<64, PREC>(np, x0, x1, B, heads, acts, st); break;
-        case 128: launch_forward<128, PREC>(np, x0, x1, B, heads, acts, st); break;
+        case 16: launch_forward<16, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
+        case 32: launch_forward<32, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
+        case 64: launch_forward<64, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
+        case 128: launch_forward<128, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
         default: return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
     }
     return NIF_OK;
 }
 
 int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads, int32_t precision,
-                   float* acts, hipStream_t st) {
+                   float* acts, float* enc, hipStream_t st) {
     if (B == 0) return NIF_OK;
     const NetParams np = make_net_params(m, precision);
     const int hw = m->desc.hidden_width;
     int rc;
-    if (precision == NIF_PREC_FP32) rc = dispatch_forward<P_FP32>(hw, np, x0, x1, B, heads, acts, st);
-    else if (precision == NIF_PREC_BF16) rc = dispatch_forward<P_BF16>(hw, np, x0, x1, B, heads, acts, st);
-    else rc = dispatch_forward<P_FP16>(hw, np, x0, x1, B, heads, acts, st);
+    if (precision == NIF_PREC_FP32) rc = dispatch_forward<P_FP32>(hw, np, x0, x1, B, heads, acts, enc, st);
+    else if (precision == NIF_PREC_BF16) rc = dispatch_forward<P_BF16>(hw, np, x0, x1, B, heads, acts, enc, st);
+    else rc = dispatch_forward<P_FP16>(hw, np, x0, x1, B, heads, acts, enc, st);
     if (rc) return rc;
     return check_hip(hipGetLastError(), "k_forward launch");
 }

@@ -32,12 +32,12 @@ enum { TC_NPOS = 0, TC_STEP = 1, TC_GOOD = 2, TC_NONFINITE = 3, TC_SKIP = 4 };
 enum { DA_SUM = 0, DA_SCALE = 5, DA_SCALE_USED = 6, DA_C1 = 7, DA_C2 = 8 };
 constexpr float kDistEps = 1e-4f;
 constexpr int kGrowInterval = 1000;
-constexpr int64_t kEncBwdKc = 2048;        // samples per encoding-backward block
 constexpr int64_t kEncBwdChunk = 1 << 16;  // samples per count/fill/reduce round
+constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
 
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
-    for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta})
+    for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta, &m->enc})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
     for (void** p : {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
@@ -48,7 +48,7 @@ int model_reserve(nif_model* m, int64_t B) {
         const int SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
         const int64_t n_buckets = (int64_t)L * (1 << (log2T - SB));
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(B, kEncBwdChunk));
-        const int64_t n_blk = ((chunk + kEncBwdKc - 1) / kEncBwdKc) * 2 * m->S;
+        const int64_t n_blk = ((chunk + 15) / 16 + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock;
         const int64_t n_add = chunk * 2 * m->S * L * 8;
         const int64_t n_cnt = n_buckets * n_blk;
         const size_t sz[4] = {sizeof(int32_t) * (size_t)n_cnt,
@@ -64,7 +64,7 @@ int model_reserve(nif_model* m, int64_t B) {
     }
     const int64_t hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
     const struct { float** p; int64_t n; } a[] = {{&m->zbuf, B * m->H}, {&m->dz, B * 16}, {&m->acts, B * hw * nh},
-                                                  {&m->delta, B * hw * nh}};
+                                                  {&m->delta, B * hw * nh}, {&m->enc, B * m->E}};
     for (auto& x : a)
         if (hipMalloc((void**)x.p, sizeof(float) * (size_t)std::max<int64_t>(x.n, 1)) != hipSuccess) {
             (void)hipGetLastError();
@@ -293,63 +293,83 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
     }
 }
 
-// ------------------------------------------------------------------ dW of layers >= 1 (MFMA)
-// gW[M_real][N] += sum over samples of d_out[s][m] * h_in[s][n]; gb[m] += sum d_out[s][m].
-// Split-K over samples; each block accumulates its chunk in registers (v_mfma_f32_16x16x4f32
-// from LDS-staged 32-sample tiles) and adds it to the FP32 gradient with atomics.
-__global__ void __launch_bounds__(256) k_dw(const float* __restrict__ dsrc, int dstride, int M_pad, int M_real,
-                                            const float* __restrict__ hin, int N, int64_t B, int64_t Kc,
-                                            float* __restrict__ gW, float* __restrict__ gb) {
-    __shared__ float sd[32][129];
-    __shared__ float sh[32][129];
+// ------------------------------------------------------------------ weight gradients (MFMA)
+// gW[m][n] += sum over samples b of d[b][m] * h[b][n] (gW row stride ldw), gb[m] += sum d[b][m].
+// Block (sample split, 64-column tile): 32-sample K tiles of d and h are staged in LDS
+// transposed ([row][sample], sample contiguous) so that each lane reads its operand runs
+// with 128-bit LDS loads; the k index of v_mfma_f32_16x16x4f32 is permuted so that lane
+// quarter q covers samples [8q, 8q+8) of the tile.  Wave w owns row tiles 2w, 2w+1 (rows
+// < 128) and the four 16-column tiles; the block's sums are added with atomics.
+constexpr int kDwKt = 32;
+
+__global__ void __launch_bounds__(256) k_dw_gemm(const float* __restrict__ d, int dstride, int M_pad, int M_real,
+                                                 const float* __restrict__ h, int hstride, int N, int64_t B,
+                                                 int64_t Kc, float* __restrict__ gW, int ldw, float* __restrict__ gb) {
+    __shared__ float sA[128][kDwKt + 4];
+    __shared__ float sB[64][kDwKt + 4];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
-    const int Tn = N / 16, T = (M_pad / 16) * Tn;
+    const int n0 = blockIdx.y * 64;
     const int64_t k0 = (int64_t)blockIdx.x * Kc, k1 = std::min<int64_t>(B, k0 + Kc);
-    floatx4 acc[16];
+    floatx4 acc[2][4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (int64_t kb = k0; kb < k1; kb += 32) {
-        for (int i = tid; i < 32 * M_pad; i += 256) {
+    for (int64_t kb = k0; kb < k1; kb += kDwKt) {
+        for (int i = tid; i < kDwKt * M_pad; i += 256) {
             const int sm = i / M_pad, mm = i % M_pad;
-            sd[sm][mm] = kb + sm < k1 ? dsrc[(kb + sm) * dstride + mm] : 0.f;
+            sA[mm][sm] = kb + sm < k1 ? d[(kb + sm) * dstride + mm] : 0.f;
         }
-        for (int i = tid; i < 32 * N; i += 256) {
-            const int sm = i / N, nn = i % N;
-            sh[sm][nn] = kb + sm < k1 ? hin[(kb + sm) * N + nn] : 0.f;
+        for (int i = tid; i < kDwKt * 64; i += 256) {
+            const int sm = i >> 6, nn = i & 63;
+            sB[nn][sm] = (kb + sm < k1 && n0 + nn < N) ? h[(kb + sm) * hstride + n0 + nn] : 0.f;
         }
         __syncthreads();
-        if (tid < M_pad)
-            for (int sm = 0; sm < 32; ++sm) bsum += sd[sm][tid];
+        if (blockIdx.y == 0 && tid < M_pad)
+            for (int sm = 0; sm < kDwKt; ++sm) bsum += sA[tid][sm];
+        float bf[4][8];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int t = w + 4 * u;
-            if (t < T) {
-                const int mt = t / Tn, nt = t % Tn;
+        for (int c = 0; c < 4; ++c) {
+            const float4 u0 = *reinterpret_cast<const float4*>(&sB[c * 16 + j][8 * q]);
+            const float4 u1 = *reinterpret_cast<const float4*>(&sB[c * 16 + j][8 * q + 4]);
+            bf[c][0] = u0.x; bf[c][1] = u0.y; bf[c][2] = u0.z; bf[c][3] = u0.w;
+            bf[c][4] = u1.x; bf[c][5] = u1.y; bf[c][6] = u1.z; bf[c][7] = u1.w;
+        }
 #pragma unroll
-                for (int st = 0; st < 8; ++st)
-                    acc[u] = mfma32(sd[st * 4 + q][mt * 16 + j], sh[st * 4 + q][nt * 16 + j], acc[u]);
-            }
+        for (int a = 0; a < 2; ++a) {
+            const int mt = 2 * w + a;
+            if (mt * 16 >= M_pad) continue;
+            const float4 v0 = *reinterpret_cast<const float4*>(&sA[mt * 16 + j][8 * q]);
+            const float4 v1 = *reinterpret_cast<const float4*>(&sA[mt * 16 + j][8 * q + 4]);
+            const float af[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(af[t], bf[c][t], acc[a][c]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int t = w + 4 * u;
-        if (t < T) {
-            const int mt = t / Tn, nt = t % Tn;
+    for (int a = 0; a < 2; ++a) {
+        const int mt = 2 * w + a;
+        if (mt * 16 >= M_pad) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = n0 + c * 16 + j;
+            if (col >= N) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = mt * 16 + 4 * q + r;
-                if (row < M_real) unsafeAtomicAdd(&gW[(size_t)row * N + nt * 16 + j], acc[u][r]);
+                if (row < M_real) unsafeAtomicAdd(&gW[(size_t)row * ldw + col], acc[a][c][r]);
             }
         }
     }
-    if (tid < M_real) unsafeAtomicAdd(&gb[tid], bsum);
+    if (blockIdx.y == 0 && tid < M_real) unsafeAtomicAdd(&gb[tid], bsum);
 }
 
 // ------------------------------------------------------------------ encoding backward
-// The table gradient is a scatter-add: every (sample, PE chunk, level, corner) adds
+// The table gradient is a scatter-add: every (sample, PE combination, level, corner) adds
 // w_corner * d enc to one table entry, about 2e9 additions per 2^18-sample step.  Device-
 // scope float atomics on this part are executed past the per-XCD L2s and would bound the
 // step, so the additions are grouped instead:
@@ -359,25 +379,29 @@ __global__ void __launch_bounds__(256) k_dw(const float* __restrict__ dsrc, int 
 //            per bucket;
 //   fill   - the same block decomposition recomputes the additions and writes (entry within
 //            the slice, value pair) into its ranges (LDS cursors, no global atomics);
-//   reduce - one block per slice window sums its additions in LDS and adds the window to
-//            the FP32 table gradient.
-// Samples are processed in chunks so the addition buffer stays bounded.  Blocks are (sample
-// split, PE chunk c = point * S + sample); per tile of 64 samples a thread owns one sample
-// and levels w, w + 4, ...
+//   reduce - one block per part of a slice sums its additions in LDS and adds them to the
+//            FP32 table gradient.
+// Lanes are assigned as in the forward's first layer: lane (q, j) takes sample j of a
+// 16-sample tile and PE combination c = 4u + q; the wave walks the levels in pairs, all
+// lanes on the same level.  d enc = W0^T delta_0 is formed on MFMA in the same layout: the
+// 16 output rows of one step are (combination 4u + r/4, features of the level pair), so
+// lane (q, j) receives exactly the four d enc values of its own combination and sample.
+// dW0 comes from the stored encoding (k_dw_gemm).  Samples are processed in chunks so the
+// addition buffer stays bounded.
 
 struct EncBwdParams {
     EncParams enc;
-    const float* W0;     // FP32 [HW][E]
+    const float* W0t;    // FP32 [E][HW]: W0 transposed
+    const float* delta0; // [B][HW]
+    const float* x0;     // SoA [3][B]
+    const float* x1;
     int32_t HW, E, S;
     float* g_tables;
-    float* gW0;
-    float* gb0;
     float* dx0;          // nullable SoA [3][B]
     float* dx1;
-    int64_t B;           // stride of the SoA point arrays and sample count of the whole batch
+    int64_t B;           // stride of the SoA point arrays
     int64_t c0;          // first sample of this chunk
     int64_t n;           // samples in this chunk
-    int64_t Kc;          // samples per block
     int32_t SB;          // log2 entries per bucket
     int32_t NBL;         // buckets per level
     int32_t n_buckets;   // L * NBL
@@ -385,80 +409,192 @@ struct EncBwdParams {
     int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
     uint16_t* key;       // additions: entry within the bucket
     float2* val;         // additions: value per feature
+    int64_t cap;         // capacity of key / val
 };
 
-__device__ __forceinline__ double pe_direct(int s, double x, double* dsdx) {
-    if (s == 0) { *dsdx = 1.0; return x; }
-    const int k = (s - 1) >> 1;
+
+// Sample position, d position / d x and the in-range mask of PE combination c (point-major).
+__device__ __forceinline__ void pe_combo_grad(const float xs[6], int c, int S, double smp[3], float dsdx[3],
+                                              float inside[3]) {
+    const int p = c >= S ? 1 : 0;
+    const int s = c - p * S;
+    const int k = s > 0 ? (s - 1) >> 1 : 0;
     const double f = ldexp(1.0, k);
-    double sn, cs;
-    sincos(f * x, &sn, &cs);
-    if ((s & 1) == 1) { *dsdx = 0.5 * f * cs; return 0.5 * (sn + 1.0); }
-    *dsdx = -0.5 * f * sn;
-    return 0.5 * (cs + 1.0);
-}
-
-// Sample position of this thread's sample in PE chunk (p, s), its d x factors and cells.
-struct EncPoint {
-    double smp[3], dsdx[3];
-    float inside[3];
-    uint32_t ci[4][3];
-    float cw[4][3];
-};
-
-__device__ __forceinline__ void enc_point(const EncBwdParams& P, const float* xs, int64_t seg, bool valid, int s,
-                                          int lw, EncPoint& e) {
-    const int L = P.enc.L;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float xv = valid ? xs[a * P.B + seg] : 0.5f;
-        e.inside[a] = (xv >= 0.f && xv <= 1.f) ? 1.f : 0.f;
-        e.smp[a] = pe_direct(s, fmin(fmax((double)xv, 0.0), 1.0), &e.dsdx[a]);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int l = lw + 4 * v;
-        if (l < L) {
-            const int N = P.enc.res[l];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) grid_axis(e.smp[a], N, e.ci[v][a], e.cw[v][a]);
-        }
+        const float xv = xs[3 * p + a];
+        inside[a] = (xv >= 0.f && xv <= 1.f) ? 1.f : 0.f;
+        const double v = fmin(fmax((double)xv, 0.0), 1.0);
+        double sn, cs;
+        sincos(f * v, &sn, &cs);
+        if (s == 0) { smp[a] = v; dsdx[a] = 1.f; }
+        else if (s & 1) { smp[a] = 0.5 * (sn + 1.0); dsdx[a] = (float)(0.5 * f * cs); }
+        else { smp[a] = 0.5 * (cs + 1.0); dsdx[a] = (float)(-0.5 * f * sn); }
     }
 }
 
-__global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P, const float* __restrict__ x0,
-                                                       const float* __restrict__ x1) {
+// The 8 corner entries (within the level) and trilinear weights of one level at smp.
+__device__ __forceinline__ void level_corners(const EncParams& ep, int l, const double smp[3], uint32_t idx[8],
+                                              float wx[3]) {
+    const int N = ep.res[l];
+    const uint32_t mask = (1u << ep.log2T) - 1u;
+    uint32_t ix, iy, iz;
+    grid_axis(smp[0], N, ix, wx[0]);
+    grid_axis(smp[1], N, iy, wx[1]);
+    grid_axis(smp[2], N, iz, wx[2]);
+    const bool dense = (ep.dense_mask >> l) & 1u;
+    const uint32_t n1 = (uint32_t)N + 1u;
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc)
+        idx[cc] = grid_index(ix + (cc & 1), iy + ((cc >> 1) & 1), iz + ((cc >> 2) & 1), n1, dense, mask);
+}
+
+__device__ __forceinline__ float corner_weight(const float w[3], int cc) {
+    return ((cc & 1) ? w[0] : 1.f - w[0]) * (((cc >> 1) & 1) ? w[1] : 1.f - w[1]) * (((cc >> 2) & 1) ? w[2] : 1.f - w[2]);
+}
+
+// Sample of lane j in tile `tile` of the chunk, its points (x0 then x1) and validity.
+__device__ __forceinline__ bool tile_sample(const EncBwdParams& P, int64_t tile, int j, int64_t& seg, float xs[6]) {
+    seg = P.c0 + tile * 16 + j;
+    const bool valid = tile * 16 + j < P.n;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        xs[a] = valid ? P.x0[a * P.B + seg] : 0.5f;
+        xs[3 + a] = valid ? P.x1[a * P.B + seg] : 0.5f;
+    }
+    return valid;
+}
+
+__global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
     extern __shared__ int32_t s_h[];    // [n_buckets]
-    const int c = blockIdx.y, p = c / P.S, s = c % P.S;
-    const int tid = threadIdx.x, seg_l = tid & 63, lw = tid >> 6;
-    const int L = P.enc.L;
-    const uint32_t mask = (1u << P.enc.log2T) - 1u;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
+    const int L = P.enc.L, n_comb = 2 * P.S;
     for (int i = tid; i < P.n_buckets; i += 256) s_h[i] = 0;
     __syncthreads();
-    const float* xs = p == 0 ? x0 : x1;
-    const int64_t k0 = P.c0 + (int64_t)blockIdx.x * P.Kc, k1 = std::min<int64_t>(P.c0 + P.n, k0 + P.Kc);
-    for (int64_t seg0 = k0; seg0 < k1; seg0 += 64) {
-        const int64_t seg = seg0 + seg_l;
-        if (seg >= k1) continue;
-        EncPoint e;
-        enc_point(P, xs, seg, true, s, lw, e);
+    const int64_t n_tiles = (P.n + 15) / 16;
+    const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
+    for (int64_t tile = (int64_t)blockIdx.x * kBwdTilesPerBlock + w; tile < t_end; tile += 4) {
+        int64_t seg;
+        float xs[6];
+        const bool valid = tile_sample(P, tile, j, seg, xs);
+        for (int u = 0; 4 * u < n_comb; ++u) {
+            const int c = 4 * u + q;
+            const bool live = valid && c < n_comb;
+            double smp[3];
+            float dsdx[3], inside[3];
+            pe_combo_grad(xs, live ? c : 0, P.S, smp, dsdx, inside);
+            for (int l = 0; l < L; ++l) {
+                uint32_t idx[8];
+                float wt[3];
+                level_corners(P.enc, l, smp, idx, wt);
+                if (live)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int l = lw + 4 * v;
-            if (l >= L) continue;
-            const bool dense = (P.enc.dense_mask >> l) & 1u;
-            const uint32_t n1 = (uint32_t)P.enc.res[l] + 1u;
-#pragma unroll
-            for (int cc = 0; cc < 8; ++cc) {
-                const uint32_t idx = grid_index(e.ci[v][0] + (cc & 1), e.ci[v][1] + ((cc >> 1) & 1),
-                                                e.ci[v][2] + ((cc >> 2) & 1), n1, dense, mask);
-                atomicAdd(&s_h[l * P.NBL + (int)(idx >> P.SB)], 1);
+                    for (int cc = 0; cc < 8; ++cc) atomicAdd(&s_h[l * P.NBL + (int)(idx[cc] >> P.SB)], 1);
             }
         }
     }
     __syncthreads();
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    for (int i = tid; i < P.n_buckets; i += 256) P.cnt[(int64_t)i * P.n_blk + blk] = s_h[i];
+    for (int i = tid; i < P.n_buckets; i += 256) P.cnt[(int64_t)i * P.n_blk + blockIdx.x] = s_h[i];
+}
+
+template <int HW>
+__global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
+    constexpr int KQ = HW / 4;                 // MFMA k-steps: lane quarter q covers [q KQ, (q+1) KQ)
+    extern __shared__ int32_t s_cur[];         // [n_buckets]: this block's next output slot per bucket
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
+    const int L = P.enc.L, n_comb = 2 * P.S, E = P.E;
+    const uint32_t kmask = (1u << P.SB) - 1u;
+    for (int i = tid; i < P.n_buckets; i += 256) s_cur[i] = P.cnt[(int64_t)i * P.n_blk + blockIdx.x];
+    __syncthreads();
+    const int64_t n_tiles = (P.n + 15) / 16;
+    const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
+    for (int64_t tile = (int64_t)blockIdx.x * kBwdTilesPerBlock + w; tile < t_end; tile += 4) {
+        int64_t seg;
+        float xs[6];
+        const bool valid = tile_sample(P, tile, j, seg, xs);
+        // B operand: delta_0 of sample j, entries [q KQ, (q+1) KQ)
+        float bd[KQ];
+#pragma unroll
+        for (int t = 0; t < KQ; t += 4) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (valid) v = *reinterpret_cast<const float4*>(P.delta0 + seg * HW + q * KQ + t);
+            bd[t] = v.x; bd[t + 1] = v.y; bd[t + 2] = v.z; bd[t + 3] = v.w;
+        }
+        float dxa[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+        for (int u = 0; 4 * u < n_comb; ++u) {
+            const int c = 4 * u + q;
+            const bool live = valid && c < n_comb;
+            double smp[3];
+            float dsdx[3], inside[3];
+            pe_combo_grad(xs, live ? c : 0, P.S, smp, dsdx, inside);
+            float dpos[3] = {0.f, 0.f, 0.f};
+            // A operand row of lane (q, j): combination 4u + j/4, feature j%4 of the level pair
+            const int ca = 4 * u + (j >> 2);
+            const bool a_live = ca < n_comb;
+            for (int l0 = 0; l0 < L; l0 += 2) {
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                const float* wrow = P.W0t + (size_t)(a_live ? ca * 2 * L + 2 * l0 + (j & 3) : 0) * HW + q * KQ;
+#pragma unroll
+                for (int t = 0; t < KQ; t += 4) {
+                    float4 av = *reinterpret_cast<const float4*>(wrow + t);
+                    if (!a_live) av = make_float4(0.f, 0.f, 0.f, 0.f);
+                    acc = mfma32(av.x, bd[t], acc);
+                    acc = mfma32(av.y, bd[t + 1], acc);
+                    acc = mfma32(av.z, bd[t + 2], acc);
+                    acc = mfma32(av.w, bd[t + 3], acc);
+                }
+                // acc[2k + f] = d enc of (combination c, level l0 + k, feature f), sample j
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int l = l0 + k;
+                    uint32_t idx[8];
+                    float wt[3];
+                    level_corners(P.enc, l, smp, idx, wt);
+                    if (!live) continue;
+                    const float g0 = acc[2 * k], g1 = acc[2 * k + 1];
+                    float dl[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int cc = 0; cc < 8; ++cc) {
+                        const float cw = corner_weight(wt, cc);
+                        const int32_t slot = atomicAdd(&s_cur[l * P.NBL + (int)(idx[cc] >> P.SB)], 1);
+                        if (slot < P.cap) {      // always true: the count pass saw the same additions
+                            P.key[slot] = (uint16_t)(idx[cc] & kmask);
+                            P.val[slot] = make_float2(cw * g0, cw * g1);
+                        }
+                        if (P.dx0) {
+                            const size_t te = ((size_t)l << P.enc.log2T) + idx[cc];
+                            float2 tv;
+                            if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[te]);
+                            else tv = reinterpret_cast<const float2*>(P.enc.tab)[te];
+                            const float gd = g0 * tv.x + g1 * tv.y;
+                            const float fx = (cc & 1) ? wt[0] : 1.f - wt[0];
+                            const float fy = ((cc >> 1) & 1) ? wt[1] : 1.f - wt[1];
+                            const float fz = ((cc >> 2) & 1) ? wt[2] : 1.f - wt[2];
+                            dl[0] += gd * ((cc & 1) ? 1.f : -1.f) * fy * fz;
+                            dl[1] += gd * (((cc >> 1) & 1) ? 1.f : -1.f) * fx * fz;
+                            dl[2] += gd * (((cc >> 2) & 1) ? 1.f : -1.f) * fx * fy;
+                        }
+                    }
+                    if (P.dx0) {
+                        const float N = (float)P.enc.res[l];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) dpos[a] += dl[a] * N;
+                    }
+                }
+            }
+            if (P.dx0 && live) {
+                const int p = c >= P.S ? 1 : 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dxa[p][a] += dpos[a] * dsdx[a] * inside[a];
+            }
+        }
+        if (P.dx0 && valid)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                unsafeAtomicAdd(&P.dx0[a * P.B + seg], dxa[0][a]);
+                unsafeAtomicAdd(&P.dx1[a * P.B + seg], dxa[1][a]);
+            }
+    }
 }
 
 // Exclusive scan of n int32 in place, in chunks of 4096: per-chunk sums, a one-block scan of
@@ -523,134 +659,6 @@ __global__ void __launch_bounds__(256) k_scan_apply(int32_t* __restrict__ a, int
         if (base + k < n) a[base + k] = run;
         run += v[k];
     }
-}
-
-__global__ void __launch_bounds__(256) k_enc_bwd(EncBwdParams P, const float* __restrict__ x0,
-                                                 const float* __restrict__ x1, const float* __restrict__ delta0) {
-    const int L = P.enc.L, FW = 2 * L, HW = P.HW, E = P.E;
-    const int c = blockIdx.y, p = c / P.S, s = c % P.S;
-    const int tid = threadIdx.x, seg_l = tid & 63, lw = tid >> 6;   // levels lw, lw+4, lw+8, lw+12
-    __shared__ float sW[128][33];   // W0[:, chunk]
-    __shared__ float sD[64][129];   // delta_0 tile
-    __shared__ float sE[64][33];    // recomputed encoding
-    __shared__ float sG[64][33];    // d encoding
-    extern __shared__ int32_t s_cur[];   // [n_buckets]: this block's next output slot per bucket
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    for (int i = tid; i < P.n_buckets; i += 256) s_cur[i] = P.cnt[(int64_t)i * P.n_blk + blk];
-    for (int i = tid; i < HW * FW; i += 256) {
-        const int o = i / FW, f = i % FW;
-        sW[o][f] = P.W0[(size_t)o * E + c * FW + f];
-    }
-    const int n_items = HW * FW / 256;   // dW0 items per thread (<= 16)
-    float accW[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) accW[u] = 0.f;
-    float bsum = 0.f;
-    const float* xs = p == 0 ? x0 : x1;
-    float* dxs = p == 0 ? P.dx0 : P.dx1;
-    const int64_t k0 = P.c0 + (int64_t)blockIdx.x * P.Kc, k1 = std::min<int64_t>(P.c0 + P.n, k0 + P.Kc);
-    const uint32_t mask = (1u << P.enc.log2T) - 1u, kmask = (1u << P.SB) - 1u;
-    __syncthreads();
-    for (int64_t seg0 = k0; seg0 < k1; seg0 += 64) {
-        const int64_t seg = seg0 + seg_l;
-        const bool valid = seg < k1;
-        for (int i = tid; i < 64 * HW; i += 256) {
-            const int sm = i / HW, o = i % HW;
-            sD[sm][o] = seg0 + sm < k1 ? delta0[(seg0 + sm) * HW + o] : 0.f;
-        }
-        // (a) features of this thread's sample and levels
-        EncPoint e;
-        enc_point(P, xs, seg, valid, s, lw, e);
-        {
-            // levels lw, lw + 4, ...: all corner gathers in flight together
-            float2 r[4];
-            if (L == 16) {
-                if (P.enc.f16) grid_lookup_n<4, true>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
-                else grid_lookup_n<4, false>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
-            } else {
-                if (P.enc.f16) grid_lookup_n<2, true>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
-                else grid_lookup_n<2, false>(P.enc, lw, 4, e.smp[0], e.smp[1], e.smp[2], r);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int l = lw + 4 * v;
-                if (l < L) {
-                    sE[seg_l][2 * l] = r[v].x;
-                    sE[seg_l][2 * l + 1] = r[v].y;
-                }
-            }
-        }
-        __syncthreads();
-        // (b) d enc = delta_0 . W0[:, chunk]
-        for (int f = lw; f < FW; f += 4) {
-            float sacc = 0.f;
-            for (int o = 0; o < HW; ++o) sacc = fmaf(sD[seg_l][o], sW[o][f], sacc);
-            sG[seg_l][f] = sacc;
-        }
-        __syncthreads();
-        // (c) the table-gradient additions of this sample (and d x)
-        if (valid) {
-            float dpos[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int l = lw + 4 * v;
-                if (l >= L) continue;
-                const int N = P.enc.res[l];
-                const bool dense = (P.enc.dense_mask >> l) & 1u;
-                const uint32_t n1 = (uint32_t)N + 1u;
-                const float g0 = sG[seg_l][2 * l], g1 = sG[seg_l][2 * l + 1];
-                float dl[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                for (int cc = 0; cc < 8; ++cc) {
-                    const uint32_t bx = cc & 1, by = (cc >> 1) & 1, bz = (cc >> 2) & 1;
-                    const uint32_t idx = grid_index(e.ci[v][0] + bx, e.ci[v][1] + by, e.ci[v][2] + bz, n1, dense, mask);
-                    const float fx = bx ? e.cw[v][0] : 1.f - e.cw[v][0];
-                    const float fy = by ? e.cw[v][1] : 1.f - e.cw[v][1];
-                    const float fz = bz ? e.cw[v][2] : 1.f - e.cw[v][2];
-                    const float wt = fx * fy * fz;
-                    const int32_t slot = atomicAdd(&s_cur[l * P.NBL + (int)(idx >> P.SB)], 1);
-                    P.key[slot] = (uint16_t)(idx & kmask);
-                    P.val[slot] = make_float2(wt * g0, wt * g1);
-                    if (dxs) {
-                        float2 tv;
-                        const size_t te = ((size_t)l << P.enc.log2T) + idx;
-                        if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[te]);
-                        else tv = reinterpret_cast<const float2*>(P.enc.tab)[te];
-                        const float gd = g0 * tv.x + g1 * tv.y;
-                        dl[0] += gd * (bx ? 1.f : -1.f) * fy * fz;
-                        dl[1] += gd * (by ? 1.f : -1.f) * fx * fz;
-                        dl[2] += gd * (bz ? 1.f : -1.f) * fx * fy;
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) dpos[a] += dl[a] * (float)N;
-            }
-            if (dxs)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) unsafeAtomicAdd(&dxs[a * P.B + seg], dpos[a] * (float)e.dsdx[a] * e.inside[a]);
-        }
-        // (d) dW0[:, chunk] and db0
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            if (u < n_items) {
-                const int it = tid + 256 * u, o = it % HW, f = it / HW;
-                float sacc = 0.f;
-                for (int sm = 0; sm < 64; ++sm) sacc = fmaf(sD[sm][o], sE[sm][f], sacc);
-                accW[u] += sacc;
-            }
-        }
-        if (c == 0 && tid < HW)
-            for (int sm = 0; sm < 64; ++sm) bsum += sD[sm][tid];
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        if (u < n_items) {
-            const int it = tid + 256 * u, o = it % HW, f = it / HW;
-            unsafeAtomicAdd(&P.gW0[(size_t)o * E + c * FW + f], accW[u]);
-        }
-    }
-    if (c == 0 && tid < HW) unsafeAtomicAdd(&P.gb0[tid], bsum);
 }
 
 // Work list of the reduction: bucket b is cut into parts of at most kReducePart additions;
@@ -872,51 +880,58 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     else if (precision == NIF_PREC_BF16) rc = dispatch_mlp_bwd<P_BF16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     else rc = dispatch_mlp_bwd<P_FP16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     if (rc) return rc;
-    // dW of layers >= 1
+    // weight gradients of every layer (layer 0 from the stored encoding)
     const int64_t Kc = 2048;
     const unsigned ksplit = (unsigned)((B + Kc - 1) / Kc);
-    for (int i = 1; i < m->n_layers; ++i) {
+    for (int i = 0; i < m->n_layers; ++i) {
         const bool out = i == m->n_layers - 1;
         const float* dsrc = out ? m->dz : m->delta + (size_t)i * B * hw;
         const int dstride = out ? 16 : hw;
         const int M_pad = out ? 16 : hw, M_real = m->dims[i + 1];
-        const float* hin = m->acts + (size_t)(i - 1) * B * hw;
-        hipLaunchKernelGGL(k_dw, dim3(ksplit), dim3(256), 0, st, dsrc, dstride, M_pad, M_real, hin, hw, B, Kc,
-                           m->g_mlp + m->w_off[i], m->g_mlp + m->b_off[i]);
+        const float* hin = i == 0 ? m->enc : m->acts + (size_t)(i - 1) * B * hw;
+        const int N = m->dims[i];
+        hipLaunchKernelGGL(k_dw_gemm, dim3(ksplit, (unsigned)((N + 63) / 64)), dim3(256), 0, st, dsrc, dstride, M_pad,
+                           M_real, hin, N, N, B, Kc, m->g_mlp + m->w_off[i], N, m->g_mlp + m->b_off[i]);
     }
     // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
     EncBwdParams ep;
     memset(&ep, 0, sizeof(ep));
     ep.enc = make_net_params(m, NIF_PREC_FP32).enc;
-    ep.W0 = m->mlp_pad_f32 + m->wp_off[0];
+    ep.W0t = m->mlp_pad_f32 + m->wt_off[0];
+    ep.delta0 = m->delta;
+    ep.x0 = x0; ep.x1 = x1;
     ep.HW = hw; ep.E = m->E; ep.S = m->S;
-    ep.g_tables = m->g_tables; ep.gW0 = m->g_mlp + m->w_off[0]; ep.gb0 = m->g_mlp + m->b_off[0];
+    ep.g_tables = m->g_tables;
     ep.dx0 = dx0; ep.dx1 = dx1;
     ep.B = B;
-    ep.Kc = kEncBwdKc;
     const int log2T = m->desc.log2_table;
     ep.SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
     ep.NBL = 1 << (log2T - ep.SB);
     ep.n_buckets = m->desc.levels * ep.NBL;
     ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
+    ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
     const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
+    const size_t lds = sizeof(int32_t) * (size_t)ep.n_buckets;
     for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
         ep.c0 = c0;
         ep.n = std::min<int64_t>(m->bwd_chunk, B - c0);
-        const unsigned nbx = (unsigned)((ep.n + ep.Kc - 1) / ep.Kc);
-        ep.n_blk = (int32_t)(nbx * 2 * m->S);
-        const dim3 grid(nbx, 2 * m->S);
-        const size_t lds = sizeof(int32_t) * (size_t)ep.n_buckets;
-        hipLaunchKernelGGL(k_enc_bwd_count, grid, dim3(256), lds, st, ep, x0, x1);
+        const int64_t n_tiles = (ep.n + 15) / 16;
+        ep.n_blk = (int32_t)((n_tiles + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock);
+        hipLaunchKernelGGL(k_enc_bwd_count, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep);
         const int64_t n_cnt = (int64_t)ep.n_buckets * ep.n_blk;
         const int n_chunks = (int)((n_cnt + 4095) / 4096);
         int32_t* sums = m->bwd_scan;
         int32_t* total = m->bwd_scan + n_chunks;
+        int32_t* parts = total + 1;
         hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, n_chunks, total);
         hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
-        hipLaunchKernelGGL(k_enc_bwd, grid, dim3(256), lds, st, ep, x0, x1, m->delta);
-        int32_t* parts = total + 1;
+        switch (hw) {
+            case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
+            case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
+            case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
+            default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
+        }
         hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, st, ep, total, parts);
         const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
         hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, st, ep, total, parts);
@@ -927,7 +942,7 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
 int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh, int32_t, float* dx0,
                     float* dx1, int32_t precision, hipStream_t st) {
     if (B == 0) return NIF_OK;
-    int rc = forward_launch(m, x0, x1, B, m->zbuf, precision, m->acts, st);
+    int rc = forward_launch(m, x0, x1, B, m->zbuf, precision, m->acts, m->enc, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_pad_dz, dim3(grid_for(B * 16)), dim3(256), 0, st, dh, m->H, B, m->dz);
     if (dx0) hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * B)), dim3(256), 0, st, dx0, 3 * B);
@@ -943,7 +958,7 @@ int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_tra
     hipLaunchKernelGGL(k_count_pos, dim3(grid_for(B)), dim3(256), 0, st, b->hit, B, m->tcount);
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table);
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp);
-    int rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, st);
+    int rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, m->enc, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, m->zbuf, m->H, B, b->hit, b->t, b->n, b->a, b->m,
                        m->s, m->tcount, m->dacc, m->dz);
