@@ -714,13 +714,51 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     const int64_t b_end = b + 1 < P.n_buckets ? (int64_t)P.cnt[(int64_t)(b + 1) * P.n_blk] : (int64_t)*total;
     const int64_t start = b_start + (int64_t)part * kReducePart;
     const int64_t end = std::min<int64_t>(b_end, start + kReducePart);
-    for (int64_t k = start + threadIdx.x; k < end; k += 256) {
-        const uint32_t key = P.key[k];
-        if ((int)(key >> 12) != w) continue;
-        const float2 v = P.val[k];
-        const int e = (int)(key & 4095u);
-        atomicAdd(&s_acc[2 * e], v.x);
-        atomicAdd(&s_acc[2 * e + 1], v.y);
+    // Thread t takes 16 consecutive additions per step (vector loads, coalesced across the
+    // wave): additions next to each other come from neighbouring samples and often hit the
+    // same entry, so equal consecutive keys are summed in registers before the LDS atomic and
+    // the lanes of a wave work 16 additions apart.
+    const int64_t g0 = start >> 4, g1 = (end + 15) >> 4;      // aligned groups of 16
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += 256) {
+        const int64_t base = g << 4;
+        uint32_t kw[8];
+        {
+            const uint4 k0 = *reinterpret_cast<const uint4*>(P.key + base);
+            const uint4 k1 = *reinterpret_cast<const uint4*>(P.key + base + 8);
+            kw[0] = k0.x; kw[1] = k0.y; kw[2] = k0.z; kw[3] = k0.w;
+            kw[4] = k1.x; kw[5] = k1.y; kw[6] = k1.z; kw[7] = k1.w;
+        }
+        float vv[32];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const float4 t = *reinterpret_cast<const float4*>(P.val + base + 2 * r);
+            vv[4 * r] = t.x; vv[4 * r + 1] = t.y; vv[4 * r + 2] = t.z; vv[4 * r + 3] = t.w;
+        }
+        uint32_t cur = 0xffffffffu;
+        float rx = 0.f, ry = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t k = base + r;
+            const uint32_t key = (k >= start && k < end) ? ((kw[r >> 1] >> (16 * (r & 1))) & 0xffffu) : 0xffffffffu;
+            if (key != cur) {
+                if ((int)(cur >> 12) == w) {
+                    const int e = (int)(cur & 4095u);
+                    atomicAdd(&s_acc[2 * e], rx);
+                    atomicAdd(&s_acc[2 * e + 1], ry);
+                }
+                cur = key;
+                rx = vv[2 * r];
+                ry = vv[2 * r + 1];
+            } else {
+                rx += vv[2 * r];
+                ry += vv[2 * r + 1];
+            }
+        }
+        if ((int)(cur >> 12) == w) {
+            const int e = (int)(cur & 4095u);
+            atomicAdd(&s_acc[2 * e], rx);
+            atomicAdd(&s_acc[2 * e + 1], ry);
+        }
     }
     __syncthreads();
     const int l = b / P.NBL, slice = b % P.NBL;
