@@ -33,6 +33,9 @@ struct PoseDev {
     int64_t ref_off;       // into bin_cells
 };
 
+// The deformation and its inverse are evaluated with FP contraction off: every kernel that
+// places lattice vertices or maps points must round identically, whatever the surrounding code.
+#pragma clang fp contract(off)
 __host__ __device__ inline void pose_constants(int kind, float s, float* k0, float* k1) {
     *k0 = 0.f; *k1 = 0.f;
     if (kind == DEF_TWIST) *k0 = 0.6f * s;
@@ -97,6 +100,8 @@ __device__ inline float3 deform_inv(const PoseDev& P, float3 q) {
 // ------------------------------------------------------------------ implicit scenes (FP32)
 enum { SCENE_TORUS = 0, SCENE_SPHERES = 1, SCENE_BLOBS = 2 };
 constexpr int kSceneStride = 8;
+
+#pragma clang fp contract(fast)
 
 __device__ inline float scene_f(int kind, const float* sp, float3 p) {
     if (kind == SCENE_TORUS) {

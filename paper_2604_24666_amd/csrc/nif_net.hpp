@@ -182,95 +182,42 @@ __device__ __forceinline__ void pair_split(uint4 p, uint2& lo, uint2& hi) { lo =
 __device__ __forceinline__ uint32_t sel(bool c, uint32_t a, uint32_t b) { return c ? a : b; }
 __device__ __forceinline__ uint2 sel(bool c, uint2 a, uint2 b) { return make_uint2(c ? a.x : b.x, c ? a.y : b.y); }
 
-// Sample position of PE combination c = point * S + sample of a segment whose rest-space
-// points sit at sp[0..2] (entry) and sp[4..6] (exit): x, (sin 2^k x + 1)/2 or
-// (cos 2^k x + 1)/2 per axis, in FP64, x clamped to [0, 1].
-__device__ __forceinline__ void pe_combo(const float* sp, int c, int S, double out[3]) {
+// Sample positions of increasing PE combinations of one segment: the first sample of each
+// point and frequency run comes from one FP64 sincos, the next frequency by the double-angle
+// recurrence (sin 2a = 2 sin a cos a, cos 2a = (cos a - sin a)(cos a + sin a)).
+struct PEWalk {
+    double sn[3], cs[3];
+    int p, k;                  // point and frequency index held in sn / cs (k < 0: none)
+};
+
+__device__ __forceinline__ void pe_walk(const float* sp, int c, int S, PEWalk& w, double out[3]) {
     const int p = c >= S ? 1 : 0;
     const int s = c - p * S;
-    const int k = s > 0 ? (s - 1) >> 1 : 0;
+    double x[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double v = fmin(fmax((double)sp[4 * p + a], 0.0), 1.0);
-        double sn, cs;
-        sincos(ldexp(v, k), &sn, &cs);
-        out[a] = s == 0 ? v : 0.5 * (((s & 1) ? sn : cs) + 1.0);
+    for (int a = 0; a < 3; ++a) x[a] = fmin(fmax((double)sp[4 * p + a], 0.0), 1.0);
+    if (s == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = x[a];
+        return;
     }
-}
-
-// Interpolated features of levels l0 .. l0+LB-1 (wave-uniform) at one sample position:
-// feat[2k + f] = feature f of level l0 + k.
-template <int LB, bool F16>
-__device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const double smp[3], float feat[2 * LB]) {
-    using E = typename TabTypes<F16>::E;
-    using Pr = typename TabTypes<F16>::Pr;
-    const E* tab = reinterpret_cast<const E*>(ep.tab);
-    const uint32_t mask = (1u << ep.log2T) - 1u;
-    Pr A[LB][4];
-    E B[LB][4];
-    uint32_t swp[LB];       // bit pp: the pair's halves are swapped (hashed level, odd first index)
-    uint32_t ixs[LB];
-    float wx[LB], wy[LB], wz[LB];
+    const int k = (s - 1) >> 1;
+    if (w.p == p && w.k >= 0 && k == w.k + 1) {
 #pragma unroll
-    for (int k = 0; k < LB; ++k) {
-        const int l = l0 + k;
-        const int N = ep.res[l];
-        uint32_t ix, iy, iz;
-        grid_axis(smp[0], N, ix, wx[k]);
-        grid_axis(smp[1], N, iy, wy[k]);
-        grid_axis(smp[2], N, iz, wz[k]);
-        ixs[k] = ix;
-        swp[k] = 0u;
-        const E* tl = tab + ((size_t)l << ep.log2T);
-        if ((ep.dense_mask >> l) & 1u) {
-            const uint32_t n1 = (uint32_t)N + 1u;
-#pragma unroll
-            for (int pp = 0; pp < 4; ++pp) {
-                const uint32_t e = ix + n1 * ((iy + (pp & 1)) + n1 * (iz + (pp >> 1)));
-                __builtin_memcpy(&A[k][pp], tl + e, sizeof(Pr));
-            }
-        } else {
-#pragma unroll
-            for (int pp = 0; pp < 4; ++pp) {
-                const uint32_t hyz = ((iy + (pp & 1)) * 2654435761u) ^ ((iz + (pp >> 1)) * 805459861u);
-                const uint32_t h0 = (ix ^ hyz) & mask;
-                swp[k] |= (h0 & 1u) << pp;
-                __builtin_memcpy(&A[k][pp], tl + (h0 & ~1u), sizeof(Pr));
-            }
-            if (ix & 1u) {
-#pragma unroll
-                for (int pp = 0; pp < 4; ++pp) {
-                    const uint32_t hyz = ((iy + (pp & 1)) * 2654435761u) ^ ((iz + (pp >> 1)) * 805459861u);
-                    B[k][pp] = tl[((ix + 1u) ^ hyz) & mask];
-                }
-            }
+        for (int a = 0; a < 3; ++a) {
+            const double s1 = w.sn[a], c1 = w.cs[a];
+            w.sn[a] = 2.0 * s1 * c1;
+            w.cs[a] = (c1 - s1) * (c1 + s1);
         }
+        w.k = k;
+    } else if (!(w.p == p && w.k == k)) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sincos(ldexp(x[a], k), &w.sn[a], &w.cs[a]);
+        w.p = p;
+        w.k = k;
     }
 #pragma unroll
-    for (int k = 0; k < LB; ++k) {
-        const bool dense = (ep.dense_mask >> (l0 + k)) & 1u;
-        const bool odd = !dense && (ixs[k] & 1u);
-        float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int pp = 0; pp < 4; ++pp) {
-            E lo, hi;
-            pair_split(A[k][pp], lo, hi);
-            const bool swap = (swp[k] >> pp) & 1u;
-            const E e0 = sel(swap, hi, lo);
-            const E e1 = odd ? B[k][pp] : sel(swap, lo, hi);
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const int c = 2 * pp + cx;
-                const float wt = (cx ? wx[k] : 1.f - wx[k]) * (((c >> 1) & 1) ? wy[k] : 1.f - wy[k]) *
-                                 (((c >> 2) & 1) ? wz[k] : 1.f - wz[k]);
-                const float2 v = entry_f2(cx ? e1 : e0);
-                acc.x = fmaf(wt, v.x, acc.x);
-                acc.y = fmaf(wt, v.y, acc.y);
-            }
-        }
-        feat[2 * k] = acc.x;
-        feat[2 * k + 1] = acc.y;
-    }
+    for (int a = 0; a < 3; ++a) out[a] = 0.5 * (((s & 1) ? w.sn[a] : w.cs[a]) + 1.0);
 }
 
 // Features of lane quarter q for one sample: levels [q LQ, (q+1) LQ), 2 features each.
@@ -334,57 +281,165 @@ __device__ __forceinline__ void pe_sample(PEState& st, int s, double out[3]) {
     }
 }
 
+// ------------------------------------------------------------------ fixed-point sample positions
+// A sample position v in [0, 1] as a 32-bit fixed-point fraction: f = round(v 2^32), capped
+// at 2^32 - 1.  At resolution N the cell is floor(f N / 2^32) <= N - 1 and the weight the
+// remaining fraction; against FP64 v N the position differs by at most N 2^-33 (2.4e-7 of a
+// cell at N = 2048), far below the FP32 feature error.
+__device__ __forceinline__ uint32_t to_fix32(double v) {
+    const double t = fmin(fmax(v, 0.0), 1.0) * 4294967296.0 + 0.5;
+    return t >= 4294967295.0 ? 0xffffffffu : (uint32_t)t;
+}
+
+__device__ __forceinline__ void fix_axis(uint32_t f, uint32_t N, uint32_t& i0, float& w) {
+    const uint64_t pos = (uint64_t)f * N;
+    i0 = (uint32_t)(pos >> 32);
+    w = (float)(uint32_t)pos * 2.3283064365386963e-10f;   // 2^-32
+}
+
+// Interpolated features of levels l0 .. l0+LB-1 (wave-uniform) at one fixed-point sample
+// position: feat[2k + f] = feature f of level l0 + k.
+template <int LB, bool F16>
+__device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const uint32_t f[3], float feat[2 * LB]) {
+    using E = typename TabTypes<F16>::E;
+    using Pr = typename TabTypes<F16>::Pr;
+    const E* tab = reinterpret_cast<const E*>(ep.tab);
+    const uint32_t mask = (1u << ep.log2T) - 1u;
+    Pr A[LB][4];
+    E B[LB][4];
+    uint32_t swp[LB];
+    uint32_t ixs[LB];
+    float wx[LB], wy[LB], wz[LB];
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+        const int l = l0 + k;
+        const uint32_t N = (uint32_t)ep.res[l];
+        uint32_t ix, iy, iz;
+        fix_axis(f[0], N, ix, wx[k]);
+        fix_axis(f[1], N, iy, wy[k]);
+        fix_axis(f[2], N, iz, wz[k]);
+        ixs[k] = ix;
+        swp[k] = 0u;
+        const E* tl = tab + ((size_t)l << ep.log2T);
+        if ((ep.dense_mask >> l) & 1u) {
+            const uint32_t n1 = N + 1u;
+#pragma unroll
+            for (int pp = 0; pp < 4; ++pp) {
+                const uint32_t e = ix + n1 * ((iy + (pp & 1)) + n1 * (iz + (pp >> 1)));
+                __builtin_memcpy(&A[k][pp], tl + e, sizeof(Pr));
+            }
+        } else {
+#pragma unroll
+            for (int pp = 0; pp < 4; ++pp) {
+                const uint32_t hyz = ((iy + (pp & 1)) * 2654435761u) ^ ((iz + (pp >> 1)) * 805459861u);
+                const uint32_t h0 = (ix ^ hyz) & mask;
+                swp[k] |= (h0 & 1u) << pp;
+                __builtin_memcpy(&A[k][pp], tl + (h0 & ~1u), sizeof(Pr));
+            }
+            if (ix & 1u) {
+#pragma unroll
+                for (int pp = 0; pp < 4; ++pp) {
+                    const uint32_t hyz = ((iy + (pp & 1)) * 2654435761u) ^ ((iz + (pp >> 1)) * 805459861u);
+                    B[k][pp] = tl[((ix + 1u) ^ hyz) & mask];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+        const bool dense = (ep.dense_mask >> (l0 + k)) & 1u;
+        const bool odd = !dense && (ixs[k] & 1u);
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) {
+            E lo, hi;
+            pair_split(A[k][pp], lo, hi);
+            const bool swap = (swp[k] >> pp) & 1u;
+            const E e0 = sel(swap, hi, lo);
+            const E e1 = odd ? B[k][pp] : sel(swap, lo, hi);
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int c = 2 * pp + cx;
+                const float wt = (cx ? wx[k] : 1.f - wx[k]) * (((c >> 1) & 1) ? wy[k] : 1.f - wy[k]) *
+                                 (((c >> 2) & 1) ? wz[k] : 1.f - wz[k]);
+                const float2 v = entry_f2(cx ? e1 : e0);
+                acc.x = fmaf(wt, v.x, acc.x);
+                acc.y = fmaf(wt, v.y, acc.y);
+            }
+        }
+        feat[2 * k] = acc.x;
+        feat[2 * k + 1] = acc.y;
+    }
+}
+
 // ------------------------------------------------------------------ one MLP pass
-// Evaluates the network on segments [seg_base, seg_base + 16*CB) whose rest-space points sit
-// in s_seg (kSegStride floats each) and writes the 16 padded head outputs to s_z.
-// acts (nullable): hidden activations are also stored to acts[layer][seg_g0 + seg][HW];
-// enc_out (nullable): the first layer's input, enc_out[seg_g0 + seg][E].
-template <int HW, int CB, int PREC>
-__device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg, int seg_base, float* s_z,
-                                         float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid,
-                                         float* enc_out = nullptr) {
+// The wave evaluates segments [seg_base, seg_base + 16*CB) whose rest-space points sit in
+// s_seg (kSegStride floats each).  acc[ob][cb] holds the 16x16 MFMA tile of output rows
+// [16 ob, 16 ob + 16) of column block cb: lane (q, j) has rows 16 ob + 4q + r of segment
+// seg_base + 16 cb + j.
+
+template <int HW, int CB>
+__device__ __forceinline__ void layer1_bias(const NetParams& np, floatx4 (&acc)[HW / 16][CB]) {
+    const int q = lane_id() >> 4;
+#pragma unroll
+    for (int ob = 0; ob < HW / 16; ++ob) {
+        const float4 bb = *reinterpret_cast<const float4*>(np.b[0] + ob * 16 + 4 * q);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
+    }
+}
+
+// Layer 1 restricted to levels [lb, le) (a multiple of LB each), added to acc.  Lane (q, j)
+// takes the PE combinations c = qU .. qU + U - 1 (point-major, 2S in all, U = ceil(2S / 4))
+// of segment j in order, so its samples follow the double-angle recurrence; the wave walks
+// the levels in batches of LB, all lanes on the same level.  MFMA k-index = (combination of the
+// lane's quarter, level, feature), so each lane loads the matching weights W0[row][c 2L + 2l + f].
+// enc_out (nullable): the features are also stored to enc_out[seg_g0 + seg][E].
+template <int HW, int CB, int PREC, int LB>
+__device__ __forceinline__ void layer1_levels(const NetParams& np, const float* s_seg, int seg_base, int lb, int le,
+                                              floatx4 (&acc)[HW / 16][CB], float* enc_out, int64_t seg_g0,
+                                              int64_t n_valid) {
+    static_assert(LB == 2 || LB == 4, "level batch");
     constexpr int OB = HW / 16;
+    constexpr int NF = 2 * LB;               // features per lane per batch
     const int lane = lane_id();
     const int q = lane >> 4, j = lane & 15;
     const int L = np.enc.L;
     const int S = 1 + 2 * np.enc.F;
     const int E = np.E;
-
-    floatx4 acc[OB][CB];
-    {
-        const float* b1 = np.b[0];
-#pragma unroll
-        for (int ob = 0; ob < OB; ++ob) {
-            const float4 bb = *reinterpret_cast<const float4*>(b1 + ob * 16 + 4 * q);
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
-        }
-    }
-    // ---- layer 1: lane (q, j) takes PE combination c = 4u + q (point-major, 2S in all) of
-    // segment j; the wave walks the levels in batches of 4, all lanes on the same level.
-    // MFMA k-index = (combination of the lane's quarter, level, feature), so each lane loads
-    // the matching weights W0[row][c 2L + 2l + f].
     const int n_comb = 2 * S;
-    for (int u = 0; 4 * u < n_comb; ++u) {
-        const int c_raw = 4 * u + q;
+    const int U = (n_comb + 3) >> 2;           // combinations per lane quarter: q U .. q U + U - 1
+    PEWalk pw[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) { pw[cb].p = -1; pw[cb].k = -1; }
+    for (int u = 0; u < U; ++u) {
+        const int c_raw = q * U + u;
         const bool live = c_raw < n_comb;
         const int c = live ? c_raw : 0;
-        double smp[CB][3];
+        uint32_t smp[CB][3];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) pe_combo(s_seg + (seg_base + cb * 16 + j) * kSegStride, c, S, smp[cb]);
-        for (int l0 = 0; l0 < L; l0 += 4) {
-            float feat[CB][8];
+        for (int cb = 0; cb < CB; ++cb) {
+            smp[cb][0] = smp[cb][1] = smp[cb][2] = 0x80000000u;
+            if (live) {
+                double v[3];
+                pe_walk(s_seg + (seg_base + cb * 16 + j) * kSegStride, c, S, pw[cb], v);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) smp[cb][a] = to_fix32(v[a]);
+            }
+        }
+        for (int l0 = lb; l0 < le; l0 += LB) {
+            float feat[CB][NF];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
                 if (np.enc.f16) {
-                    lookup_levels<4, true>(np.enc, l0, smp[cb], feat[cb]);
-                } else {     // FP32 entries are twice the size: two levels per batch
-                    lookup_levels<2, false>(np.enc, l0, smp[cb], feat[cb]);
-                    lookup_levels<2, false>(np.enc, l0 + 2, smp[cb], feat[cb] + 4);
+                    lookup_levels<LB, true>(np.enc, l0, smp[cb], feat[cb]);
+                } else {     // FP32 entries are twice the size: two levels at a time
+#pragma unroll
+                    for (int h = 0; h < LB; h += 2) lookup_levels<2, false>(np.enc, l0 + h, smp[cb], feat[cb] + 2 * h);
                 }
                 if (!live) {
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) feat[cb][t] = 0.f;
+                    for (int t = 0; t < NF; ++t) feat[cb][t] = 0.f;
                 }
             }
             const int e0 = c * 2 * L + 2 * l0;
@@ -394,8 +449,9 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
                     const int64_t seg = seg_g0 + cb * 16 + j;
                     if (live && seg < n_valid) {
                         float4* dst = reinterpret_cast<float4*>(enc_out + seg * E + e0);
-                        dst[0] = make_float4(feat[cb][0], feat[cb][1], feat[cb][2], feat[cb][3]);
-                        dst[1] = make_float4(feat[cb][4], feat[cb][5], feat[cb][6], feat[cb][7]);
+#pragma unroll
+                        for (int h = 0; h < NF / 4; ++h)
+                            dst[h] = make_float4(feat[cb][4 * h], feat[cb][4 * h + 1], feat[cb][4 * h + 2], feat[cb][4 * h + 3]);
                     }
                 }
             }
@@ -403,18 +459,21 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
             for (int ob = 0; ob < OB; ++ob) {
                 if constexpr (PREC == P_FP32) {
                     const float* w = reinterpret_cast<const float*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0;
-                    const float4 w0 = *reinterpret_cast<const float4*>(w);
-                    const float4 w1 = *reinterpret_cast<const float4*>(w + 4);
-                    const float wf[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+                    float wf[NF];
 #pragma unroll
-                    for (int t = 0; t < 8; ++t)
+                    for (int h = 0; h < NF / 4; ++h) {
+                        const float4 wv = *reinterpret_cast<const float4*>(w + 4 * h);
+                        wf[4 * h] = wv.x; wf[4 * h + 1] = wv.y; wf[4 * h + 2] = wv.z; wf[4 * h + 3] = wv.w;
+                    }
+#pragma unroll
+                    for (int t = 0; t < NF; ++t)
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(wf[t], feat[cb][t], acc[ob][cb]);
                 } else {
                     const shortx4* w = reinterpret_cast<const shortx4*>(
                         reinterpret_cast<const uint16_t*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0);
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
+                    for (int t = 0; t < NF / 4; ++t) {
                         const shortx4 wa = w[t];
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) {
@@ -427,6 +486,17 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
             }
         }
     }
+}
+
+// ReLU of the first layer's pre-activations in acc, the hidden layers and the output layer;
+// writes the 16 padded head outputs to s_z.  acts (nullable): hidden activations are also
+// stored to acts[layer][seg_g0 + seg][HW].
+template <int HW, int CB, int PREC>
+__device__ __forceinline__ void mlp_tail(const NetParams& np, floatx4 (&acc)[HW / 16][CB], int seg_base, float* s_z,
+                                         float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid) {
+    constexpr int OB = HW / 16;
+    const int lane = lane_id();
+    const int q = lane >> 4, j = lane & 15;
     // ---- hidden layers 2..n_hidden, output layer
     for (int layer = 1; layer <= np.n_hidden; ++layer) {
         // ReLU of the previous layer's outputs (and optional store)
@@ -511,6 +581,17 @@ __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg
                 for (int r = 0; r < 4; ++r) s_z[(seg_base + cb * 16 + j) * kZStride + 4 * q + r] = out[cb][r];
         }
     }
+}
+
+// Whole network on segments [seg_base, seg_base + 16*CB); acts / enc_out as above.
+template <int HW, int CB, int PREC>
+__device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg, int seg_base, float* s_z,
+                                         float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid,
+                                         float* enc_out = nullptr) {
+    floatx4 acc[HW / 16][CB];
+    layer1_bias<HW, CB>(np, acc);
+    layer1_levels<HW, CB, PREC, 4>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
+    mlp_tail<HW, CB, PREC>(np, acc, seg_base, s_z, acts, act_stride_layer, seg_g0, n_valid);
 }
 
 // Make this wave's LDS writes visible to its other lanes.

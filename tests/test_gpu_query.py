@@ -38,8 +38,13 @@ def _compare(orc, P, m, tab_seen, prm, N, occ, kind, s, o, d, got, sl=slice(None
     say(f"  rays {len(ok)}  grazing {int(graz.sum())}  ambiguous {int((amb & ~graz).sum())}  "
         f"hits {int(ref['hit'][ok].sum())}")
     assert np.array_equal(g["hit"][ok], ref["hit"][ok])
-    assert np.array_equal(g["n_queried"][ok], ref["n_queried"][ok])
-    assert np.array_equal(g["cell"][ok], ref["cell"][ok])
+    for name in ("n_queried", "cell"):
+        bad = np.nonzero(ok & (g[name] != ref[name]))[0]
+        for i in bad[:8]:
+            say(f"    {name} mismatch ray {i}: got {g[name][i]} ref {ref[name][i]}  hit {ref['hit'][i]}  "
+                f"t got {g['t'][i]:.6f} ref {ref['t'][i]:.6f}  nq got {g['n_queried'][i]} ref {ref['n_queried'][i]}  "
+                f"margin {ref['margin'][i]:.3g}")
+        assert len(bad) == 0, name
     h = ok & (ref["hit"] == 1)
     xr = np.stack([g["xr"], g["yr"], g["zr"]], 1)
     nrm = np.stack([g["nx"], g["ny"], g["nz"]], 1)
