@@ -222,7 +222,7 @@ __device__ __forceinline__ void unpark_trav(const Parked& pk, Trav& T) {
 #endif
 
 template <int HW, int PREC>
-__global__ void __launch_bounds__(64, HW >= 128 ? 1 : NIF_QUERY_MIN_WAVES) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
+__global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats,
                                               int pose_times) {
     constexpr int CB = kQueryCB;

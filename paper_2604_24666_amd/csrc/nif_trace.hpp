@@ -25,9 +25,9 @@
 
 namespace nif {
 
-// Contraction of a*b+c into FMA is switched off for the traversal: a ray's walk is resumed
-// in a different kernel from the one that started it, and both must take bit-identical
-// decisions (entry parameters, crossing signs) for the same ray and voxel.
+// Contraction of a*b+c into FMA is switched off for the traversal: the walk is inlined into
+// several kernels (segment tracing, the fused query, the voxel proxy), which must take
+// bit-identical decisions (entry parameters, crossing signs) for the same ray and voxel.
 #pragma clang fp contract(off)
 
 struct Ray {
@@ -193,10 +193,7 @@ __device__ __forceinline__ bool next_segment(const PoseDev& P, const float4* __r
         last = last || !(th < INFINITY);
         const float t_hi = last ? INFINITY : th;
         const int64_t bin = (int64_t)T.ix + (int64_t)P.nb[0] * (T.iy + (int64_t)P.nb[1] * T.iz);
-        // a bin whose t-range ends at or before the last returned entry holds nothing after it
-        // (a resumed walk passes such bins without testing their voxels)
-        const bool skip = !(t_hi > T.last_a);
-        const int32_t s0 = skip ? 0 : bin_start[P.bin_off + bin], s1 = skip ? 0 : bin_start[P.bin_off + bin + 1];
+        const int32_t s0 = bin_start[P.bin_off + bin], s1 = bin_start[P.bin_off + bin + 1];
         float best_a = INFINITY, best_b = 0.f;
         int32_t best_c = 0x7fffffff, best_f = -1;
         for (int32_t e = s0; e < s1; ++e) {

@@ -156,3 +156,34 @@ def test_train_step_rejects_oversized_batches(P):
     P.nif_model_reserve(model.h, 64)
     with pytest.raises(P.NifError):
         _train_step(P, model, _batch(m, 65, 1), 65)
+
+
+def test_backward_over_several_chunks_is_additive(P):
+    """A batch larger than one table-gradient round (2^16 samples): the gradient of the whole
+    batch equals the gradient of its two halves accumulated (the sum is linear in the samples),
+    within FP32 summation-order error."""
+    import torch
+    m = MODELS["blobs128"]
+    tab, prm, _ = model_params(m, 11, scale_tables=300.0)
+    B = (1 << 16) + 4321
+    x0, x1, hit, t, nr, al, mt = _batch(m, B, 12)
+    rng = np.random.default_rng(13)
+    dz = rng.normal(size=(B, m.n_heads)).astype(np.float32)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    P.nif_model_reserve(model.h, B)
+    say(f"backward additivity B={B}")
+    P.nif_backward(model.h, dev_f32(x0), dev_f32(x1), B, dev_f32(dz), None, None, False, P.PREC_FP32)
+    g_t, g_p, _ = [g.clone() for g in model.get_grads()]
+    h = B // 2 + 17
+    parts = [(0, h), (h, B)]
+    for i, (a, b) in enumerate(parts):
+        P.nif_backward(model.h, dev_f32(np.ascontiguousarray(x0[:, a:b])), dev_f32(np.ascontiguousarray(x1[:, a:b])),
+                       b - a, dev_f32(dz[a:b]), None, None, i > 0, P.PREC_FP32)
+    h_t, h_p, _ = model.get_grads()
+    torch.cuda.synchronize()
+    for name, full, acc in (("tables", g_t, h_t), ("mlp", g_p, h_p)):
+        full = full.cpu().numpy().astype(np.float64); acc = acc.cpu().numpy().astype(np.float64)
+        nrm = np.linalg.norm(full - acc) / np.linalg.norm(full)
+        say(f"  {name}: relative difference {nrm:.2e}")
+        assert np.linalg.norm(full) > 0 and nrm <= 1e-5, name
