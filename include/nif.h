@@ -115,6 +115,21 @@ int nif_model_reserve(nif_model* model, int64_t max_batch);
 int nif_voxelize(int32_t scene_kind, const double* params_host, int32_t n_params, int32_t N,
                  uint8_t* occ_dev, nif_stream stream);
 
+/* Ground-truth labels of n rest-space segments [x0, x1] (x0_dev, x1_dev: SoA [3][n] FP32,
+ * device) against the same analytic scene (Methodology: each locally linearized segment is
+ * supervised with the rest geometry along its chord).  The label point is the first point of
+ * the chord where f <= 0: the start if f(x0) <= 0; for spheres the smallest entering root of
+ * the per-sphere quadratic in [0, |x1 - x0|] (unless force_march != 0); otherwise 256 uniform
+ * sign steps and bisection of the first bracket down to 1e-13.  Outputs (device, each
+ * nullable): hit u8[n]; t f32[n] distance from x0 (0 when no hit); normal f32 SoA [3][n]
+ * = grad f / |grad f| at the point; albedo f32 SoA [3][n]; material i32[n] (torus: [x >= 1/2];
+ * spheres: of the sphere with the smallest signed distance; blobs: of the largest
+ * contribution, albedo = contribution-weighted colour); misses get zeros.  Evaluated in FP64.
+ * Copies the parameters to the device and synchronises the stream. */
+int nif_label(int32_t scene_kind, const double* params_host, int32_t n_params, int32_t force_march,
+              const float* x0_dev, const float* x1_dev, int64_t n, uint8_t* hit_dev, float* t_dev,
+              float* normal_dev, float* albedo_dev, int32_t* material_dev, nif_stream stream);
+
 /* ---------------------------------------------------------------- deformed grid
  * Per pose: the deformed lattice vertices V_ijk = D(i/N, j/N, k/N) (faces split along their
  * main diagonal), and an acceleration structure over the occupied deformed voxels

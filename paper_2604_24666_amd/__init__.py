@@ -20,9 +20,9 @@ import torch
 __all__ = ["NifError", "lib", "ModelDesc", "Pose", "Rays", "Hits", "Segments", "Batch", "TrainCfg",
            "nif_model_create", "nif_model_destroy", "nif_model_sizes", "nif_model_set_params",
            "nif_model_get_params", "nif_model_get_grads", "nif_model_zero_grads", "nif_model_reserve",
-           "nif_voxelize", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
+           "nif_voxelize", "nif_label", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
            "nif_encode", "nif_forward", "nif_backward", "nif_train_step",
-           "Model", "Grid", "NifField"]
+           "Model", "Grid", "NifField", "label"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnif.so")
@@ -95,6 +95,7 @@ def lib():
             "nif_model_get_grads": ([P, P, P, P, P], C.c_int),
             "nif_model_zero_grads": ([P, P], C.c_int), "nif_model_reserve": ([P, I64], C.c_int),
             "nif_voxelize": ([I32, P, I32, I32, P, P], C.c_int),
+            "nif_label": ([I32, P, I32, I32, P, P, C.c_int64, P, P, P, P, P, P], C.c_int),
             "nif_build_grid": ([P, I32, P, I32, I32, P, P], C.c_int), "nif_grid_destroy": ([P], C.c_int),
             "nif_grid_info": ([P, I32, P, P, P], C.c_int), "nif_grid_bounds": ([P, I32, P, P], C.c_int), "nif_grid_update": ([P, P, I32, P], C.c_int),
             "nif_trace": ([P, P, I64, I32, P, P], C.c_int),
@@ -178,6 +179,26 @@ def nif_voxelize(scene_kind: int, params, N: int, occ, stream=None):
     import numpy as np
     p = np.ascontiguousarray(params, dtype=np.float64)
     _check(lib().nif_voxelize(scene_kind, p.ctypes.data_as(C.c_void_p), len(p), N, _ptr(occ), _stream(stream)))
+
+
+def nif_label(scene_kind: int, params, x0, x1, n: int, hit=None, t=None, normal=None, albedo=None, material=None,
+              force_march: bool = False, stream=None):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    _check(lib().nif_label(scene_kind, p.ctypes.data_as(C.c_void_p), len(p), int(force_march), _ptr(x0), _ptr(x1), n,
+                           _ptr(hit), _ptr(t), _ptr(normal), _ptr(albedo), _ptr(material), _stream(stream)))
+
+
+def label(scene_kind: int, params, x0, x1, force_march: bool = False):
+    """Labels of rest segments x0, x1 (float32 [3][n] device tensors): dict of device tensors."""
+    n = x0.shape[1]
+    dev = x0.device
+    out = dict(hit=torch.empty(n, dtype=torch.uint8, device=dev), t=torch.empty(n, device=dev),
+               normal=torch.empty((3, n), device=dev), albedo=torch.empty((3, n), device=dev),
+               material=torch.empty(n, dtype=torch.int32, device=dev))
+    nif_label(scene_kind, params, x0, x1, n, out["hit"], out["t"], out["normal"], out["albedo"], out["material"],
+              force_march)
+    return out
 
 
 def nif_build_grid(occ, N: int, kinds, strengths, bins_per_axis: int = 0, stream=None):
