@@ -25,6 +25,8 @@ SCENE_TORUS, SCENE_SPHERES, SCENE_BLOBS = 0, 1, 2
 TABLE_F32, TABLE_F16 = 0, 1
 # MLP arithmetic.
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+# Distance head: ReLU rest-space distance (log-space loss), or sigmoid fraction of the segment.
+DIST_LOG_RELU, DIST_SIGMOID = 0, 1
 
 
 @dataclass
@@ -39,6 +41,7 @@ class ModelDesc:
     hidden_width: int
     hidden_layers: int
     n_materials: int
+    dist_head: int = DIST_LOG_RELU
 
     @property
     def n_samples(self) -> int:          # 1 + 2F positional-encoding samples per point

@@ -52,7 +52,7 @@ def lib():
 class Model(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("pe_freqs", C.c_int32), ("res", C.c_int32 * 32), ("n_layers", C.c_int32),
-                ("dims", C.c_int32 * 16), ("n_materials", C.c_int32)]
+                ("dims", C.c_int32 * 16), ("n_materials", C.c_int32), ("dist_head", C.c_int32)]
 
 
 def model_struct(desc) -> Model:
@@ -66,6 +66,7 @@ def model_struct(desc) -> Model:
     for i, d in enumerate(dims):
         m.dims[i] = d
     m.n_materials = desc.n_materials
+    m.dist_head = getattr(desc, "dist_head", 0)
     return m
 
 
@@ -212,8 +213,10 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
 
 
 def loss_grad(desc, tables, params, s, x0, x1, hit, t, nrm, alb, mat, want_x: bool = False,
-              want_dz: bool = False):
-    """Returns (losses[6], g_tables, g_params, g_s, g_x0, g_x1), plus dL/dz[B][H] if want_dz."""
+              want_dz: bool = False, fixed_weights: bool = False):
+    """Returns (losses[6], g_tables, g_params, g_s, g_x0, g_x1), plus dL/dz[B][H] if want_dz.
+    fixed_weights: every task weighs 1 and s is unused (the ablation without uncertainty
+    weighting)."""
     m = model_struct(desc)
     tab = _f64(tables).reshape(-1); prm = _f64(params); s = _f64(s)
     x0 = _aos(x0); x1 = _aos(x1)
@@ -229,7 +232,7 @@ def loss_grad(desc, tables, params, s, x0, x1, hit, t, nrm, alb, mat, want_x: bo
                         _p(t, C.c_double), _p(nrm, C.c_double), _p(alb, C.c_double), _p(mat, C.c_int32),
                         _p(losses, C.c_double), _p(gt, C.c_double), _p(gp, C.c_double), _p(gs, C.c_double),
                         _p(gx0, C.c_double) if want_x else None, _p(gx1, C.c_double) if want_x else None,
-                        _p(dz, C.c_double) if want_dz else None)
+                        _p(dz, C.c_double) if want_dz else None, C.c_int32(int(fixed_weights)))
     if want_dz:
         return losses, gt.reshape(np.shape(tables)), gp, gs, gx0, gx1, dz
     return losses, gt.reshape(np.shape(tables)), gp, gs, gx0, gx1

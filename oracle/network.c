@@ -20,6 +20,13 @@
  *  - Loss, "Uncertainty-Weighted Multi-Task Loss": regression 0.5 exp(-s) L + 0.5 s,
  *    classification exp(-s) L + 0.5 s; log-space MSE for distance, cosine loss for normals,
  *    L1 on sigmoid albedo, cross-entropy for material and occlusion.
+ *  - Ablation switches, "Accuracy Comparison without Deformation" (Table 1) and the loss
+ *    section's remark that the sigmoid distance output was replaced: dist_head = 1 restores
+ *    a bounded head, sigma(z1) read as the hit's fraction of the rest segment and regressed
+ *    by MSE against t* / l (clamped to [0,1]); fixed_weights = 1 drops the uncertainty
+ *    weighting (every task weighs 1, s is not used and gets no gradient).  F = 0 removes the
+ *    positional encoding.  Readings: the paper names the baselines' parts but not their
+ *    formulas; these are the plainest forms consistent with that description.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -300,8 +307,13 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
                 if (!(z[0] > 0.0)) continue;
                 double e[3] = {x1[0] - x0[0], x1[1] - x0[1], x1[2] - x0[2]};
                 double lr = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-                double dh = z[1] > 0.0 ? z[1] : 0.0;
-                double f = lr > 0.0 ? clamp01(dh / lr) : 0.0;
+                double f;
+                if (m->dist_head == 1) {
+                    f = sigmoid(z[1]);
+                } else {
+                    double dh = z[1] > 0.0 ? z[1] : 0.0;
+                    f = lr > 0.0 ? clamp01(dh / lr) : 0.0;
+                }
                 hit[r] = 1;
                 tout_ray[r] = tin[k] + f * (tou[k] - tin[k]);
                 for (int a = 0; a < 3; ++a) xrest[3 * r + a] = x0[a] + f * e[a];
@@ -336,7 +348,7 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
                    int64_t B, const double* x0, const double* x1, const uint8_t* lhit,
                    const double* lt, const double* ln, const double* la, const int32_t* lm,
                    double* losses, double* g_tables, double* g_params, double* g_s, double* g_x0,
-                   double* g_x1, double* dz_out) {
+                   double* g_x1, double* dz_out, int32_t fixed_weights) {
     const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials, PW = point_width(m);
     int64_t P = 0;
     for (int64_t i = 0; i < B; ++i) P += lhit[i] ? 1 : 0;
@@ -346,6 +358,8 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
     w[2] = 0.5 * exp(-s[2]);
     w[3] = 0.5 * exp(-s[3]);
     w[4] = exp(-s[4]);              /* classification */
+    if (fixed_weights)
+        for (int k = 0; k < 5; ++k) w[k] = 1.0;
     double sum[5] = {0, 0, 0, 0, 0};
     double* enc = (double*)malloc(sizeof(double) * E);
     double* acts = (double*)malloc(sizeof(double) * acts_width(m));
@@ -364,11 +378,24 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
         sum[0] += (z[0] > 0 ? z[0] : 0.0) - z[0] * y + log1p(exp(-fabs(z[0])));
         dz[0] = w[0] * (sigmoid(z[0]) - y) / (double)B;
         if (lhit[i] && P > 0) {
-            /* distance: MSE of logs, ReLU output */
-            double dh = z[1] > 0.0 ? z[1] : 0.0;
-            double r = log(dh + DIST_EPS) - log(lt[i] + DIST_EPS);
-            sum[1] += r * r;
-            if (z[1] > 0.0) dz[1] = w[1] * 2.0 * r / (dh + DIST_EPS) / (double)P;
+            if (m->dist_head == 1) {
+                /* distance: MSE of the sigmoid fraction against t* / l of the rest segment */
+                const double* a0 = x0 + 3 * i;
+                const double* a1 = x1 + 3 * i;
+                double e[3] = {a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]};
+                double lr = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                double tau = lr > 0.0 ? clamp01(lt[i] / lr) : 0.0;
+                double p = sigmoid(z[1]);
+                double r = p - tau;
+                sum[1] += r * r;
+                dz[1] = w[1] * 2.0 * r * p * (1.0 - p) / (double)P;
+            } else {
+                /* distance: MSE of logs, ReLU output */
+                double dh = z[1] > 0.0 ? z[1] : 0.0;
+                double r = log(dh + DIST_EPS) - log(lt[i] + DIST_EPS);
+                sum[1] += r * r;
+                if (z[1] > 0.0) dz[1] = w[1] * 2.0 * r / (dh + DIST_EPS) / (double)P;
+            }
             /* normal: 1 - cosine */
             const double* nt = ln + 3 * i;
             double v[3] = {z[2], z[3], z[4]};
@@ -446,8 +473,12 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
     for (int k = 1; k < 5; ++k) Ls[k] = P > 0 ? sum[k] / (double)P : 0.0;
     double total = 0.0;
     for (int k = 0; k < 5; ++k) {
-        total += w[k] * Ls[k] + 0.5 * s[k];
-        g_s[k] += -w[k] * Ls[k] + 0.5;
+        if (fixed_weights) {
+            total += Ls[k];
+        } else {
+            total += w[k] * Ls[k] + 0.5 * s[k];
+            g_s[k] += -w[k] * Ls[k] + 0.5;
+        }
         losses[k] = Ls[k];
     }
     losses[5] = total;

@@ -28,6 +28,9 @@ typedef struct {
     int32_t n_layers;      /* number of affine layers (hidden layers + output layer) */
     int32_t dims[16];      /* dims[0] = encoding width, dims[n_layers] = head count  */
     int32_t n_materials;
+    int32_t dist_head;     /* 0: ReLU rest-space distance, log-space MSE (the paper's head);
+                              1: sigmoid fraction of the rest segment, MSE (the bounded head
+                              the paper replaces, kept as an ablation switch) */
 } orc_model;
 
 /* deform.c */

@@ -132,10 +132,11 @@ def _forced_params(m, hit_bias, dist_bias, nrm=(0.0, 0.0, 2.0), alb=(0.0, 1.0, -
     return prm
 
 
-@pytest.mark.parametrize("kind", [S.TWIST, S.BEND])
-def test_query_with_always_hit_network_returns_first_segment(orc, kind):
+@pytest.mark.parametrize("kind,dist_head", [(S.TWIST, S.DIST_LOG_RELU), (S.BEND, S.DIST_LOG_RELU),
+                                             (S.TWIST, S.DIST_SIGMOID)])
+def test_query_with_always_hit_network_returns_first_segment(orc, kind, dist_head):
     w = S.workload("torus16")
-    m = w.model
+    m = dataclasses.replace(w.model, dist_head=dist_head)
     sp = S.scene_params(w.scene_kind, w.seed)
     occ = orc.voxelize(w.scene_kind, sp, w.N)
     tab = np.zeros((m.levels, m.table_size, m.feat_dim))
@@ -154,7 +155,10 @@ def test_query_with_always_hit_network_returns_first_segment(orc, kind):
     x0 = orc.deform_inv(kind, 1.0, o64[r] + tin[r, 0:1] * d64[r])
     x1 = orc.deform_inv(kind, 1.0, o64[r] + tout[r, 0:1] * d64[r])
     lr = np.linalg.norm(x1 - x0, axis=1)
-    f = np.clip(dist_bias / lr, 0, 1)
+    if dist_head == S.DIST_SIGMOID:        # the bounded head: the fraction is sigma(z1)
+        f = np.full(len(r), 1 / (1 + math.exp(-dist_bias)))
+    else:
+        f = np.clip(dist_bias / lr, 0, 1)
     assert np.abs(q["t"][r] - (tin[r, 0] + f * (tout[r, 0] - tin[r, 0]))).max() < 1e-12
     assert np.abs(q["xrest"][r] - (x0 + f[:, None] * (x1 - x0))).max() < 1e-12
     assert np.allclose(q["normal"][r], [0, 0, 1]) and np.allclose(q["albedo"][r], [0.5, 1 / (1 + math.e ** -1), 1 / (1 + math.e)])
@@ -218,6 +222,32 @@ def test_constant_network_losses_have_closed_forms(orc):
     assert abs(losses[5] - ref) < 1e-13
 
 
+def test_ablation_heads_and_fixed_weights_have_closed_forms(orc):
+    """Sigmoid distance head: sigma(0) = 1/2 against t*/l clamped to [0,1]; fixed weights: the
+    total is the plain sum of the five task losses and s gets no gradient."""
+    m = _small_model(n_materials=4, dist_head=S.DIST_SIGMOID)
+    B = 64
+    _, _, x0, x1, hit, t, nr, al, mt = _batch(m, B, 63)
+    t = t.copy(); t[:4] = 10.0                            # beyond the segment: target clamps to 1
+    tab = np.zeros((m.levels, m.table_size, m.feat_dim))
+    prm = np.zeros(m.n_mlp_params)
+    b = prm[-m.n_heads:]
+    b[2:5] = [0.0, 0.0, 3.0]
+    s = np.array([0.3, -0.2, 0.1, 0.4, -0.5])
+    L, _, _, gs, _, _ = orc.loss_grad(m, tab, prm, s, x0, x1, hit, t, nr, al, mt, fixed_weights=True)
+    P = hit.astype(bool)
+    tau = np.clip(t / np.linalg.norm(x1 - x0, axis=1), 0, 1)
+    assert P[:4].any() and abs(L[1] - np.mean((0.5 - tau[P]) ** 2)) < 1e-14
+    assert abs(L[0] - math.log(2)) < 1e-15 and abs(L[4] - math.log(4)) < 1e-14
+    assert abs(L[5] - L[:5].sum()) < 1e-13
+    assert np.all(gs == 0.0)
+    # the log-distance head on the same batch is unchanged by the switch of weights only
+    m0 = dataclasses.replace(m, dist_head=S.DIST_LOG_RELU)
+    b[1] = 0.02
+    L0 = orc.loss_grad(m0, tab, prm, np.zeros(5), x0, x1, hit, t, nr, al, mt, fixed_weights=True)[0]
+    assert abs(L0[1] - np.mean((math.log(0.02 + 1e-4) - np.log(t[P] + 1e-4)) ** 2)) < 1e-13
+
+
 def test_uncertainty_weights_are_stationary_at_log_loss(orc):
     """d/ds (0.5 e^-s L + 0.5 s) = 0 at s = log L; d/ds (e^-s L + 0.5 s) = 0 at s = log 2L."""
     m = _small_model()
@@ -231,15 +261,17 @@ def test_uncertainty_weights_are_stationary_at_log_loss(orc):
     assert np.all(orc.loss_grad(m, tab, prm, s_star + 0.1, x0, x1, hit, t, nr, al, mt)[3] > 0)
 
 
-@pytest.mark.parametrize("n_materials", [1, 4])
-def test_gradient_matches_central_finite_differences(orc, n_materials):
-    m = _small_model(n_materials=n_materials)
+@pytest.mark.parametrize("n_materials,dist_head,fixed", [(1, S.DIST_LOG_RELU, False), (4, S.DIST_LOG_RELU, False),
+                                                        (4, S.DIST_SIGMOID, True)])
+def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head, fixed):
+    m = _small_model(n_materials=n_materials, dist_head=dist_head)
     tab, prm, x0, x1, hit, t, nr, al, mt = _batch(m, 20, 62 + n_materials)
     s = np.array([0.1, -0.2, 0.3, 0.0, 0.5])
-    L, gt, gp, gs, gx0, gx1 = orc.loss_grad(m, tab, prm, s, x0, x1, hit, t, nr, al, mt, want_x=True)
+    L, gt, gp, gs, gx0, gx1 = orc.loss_grad(m, tab, prm, s, x0, x1, hit, t, nr, al, mt, want_x=True,
+                                            fixed_weights=fixed)
 
     def total(tab_=tab, prm_=prm, s_=s, x0_=x0, x1_=x1):
-        return orc.loss_grad(m, tab_, prm_, s_, x0_, x1_, hit, t, nr, al, mt)[0][5]
+        return orc.loss_grad(m, tab_, prm_, s_, x0_, x1_, hit, t, nr, al, mt, fixed_weights=fixed)[0][5]
 
     def check(fd, an):
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * scale) + 1e-10
@@ -259,11 +291,13 @@ def test_gradient_matches_central_finite_differences(orc, n_materials):
         t2 = flat.copy(); t2[idx] -= h
         check((total(tab_=t1.reshape(tab.shape)) - total(tab_=t2.reshape(tab.shape))) / (2 * h),
               gt.reshape(-1)[idx])
-    scale = np.abs(gs).max()
+    scale = max(np.abs(gs).max(), 1.0)
     for k in range(5):
         s1 = s.copy(); s1[k] += 1e-6
         s2 = s.copy(); s2[k] -= 1e-6
         check((total(s_=s1) - total(s_=s2)) / 2e-6, gs[k])
+    if dist_head == S.DIST_SIGMOID:
+        return          # the target t*/l is a label computed from x: no gradient flows through it
     scale = max(np.abs(gx0).max(), np.abs(gx1).max())
     for i in range(4):
         for a in range(3):
