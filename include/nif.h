@@ -70,6 +70,14 @@ typedef struct { int32_t kind; float strength; } nif_pose;
  */
 enum { NIF_TABLE_F32 = 0, NIF_TABLE_F16 = 1 };
 enum { NIF_PREC_FP32 = 0, NIF_PREC_BF16 = 1, NIF_PREC_FP16 = 2 };
+/* Distance head ("Uncertainty-Weighted Multi-Task Loss": the bounded sigmoid output is
+ * replaced by a ReLU distance regressed in log space).
+ *   NIF_DIST_LOG_RELU: d = ReLU(z1) is the rest-space distance from the segment's entry point;
+ *                      the hit's fraction of the segment is clamp(d / l, 0, 1), l the rest length;
+ *                      loss (log(d + 1e-4) - log(t* + 1e-4))^2.
+ *   NIF_DIST_SIGMOID:  the ablation baseline: the fraction is sigmoid(z1) itself; loss
+ *                      (sigmoid(z1) - clamp(t* / l, 0, 1))^2. */
+enum { NIF_DIST_LOG_RELU = 0, NIF_DIST_SIGMOID = 1 };
 
 typedef struct {
     int32_t levels;          /* L: 8 or 16 */
@@ -81,6 +89,7 @@ typedef struct {
     int32_t hidden_width;    /* multiple of 16, <= 128 */
     int32_t hidden_layers;   /* 1..8 */
     int32_t n_materials;     /* 1..8 */
+    int32_t dist_head;       /* NIF_DIST_LOG_RELU (the method) or NIF_DIST_SIGMOID (ablation) */
 } nif_model_desc;
 
 /* Allocates parameters (FP32 masters and working copies), gradients and Adam state. */
@@ -244,6 +253,8 @@ typedef struct {
     float lr_table, lr_mlp, lr_s, beta1, beta2, eps;
     int32_t precision;          /* NIF_PREC_* of the MLP */
     float loss_scale_init;      /* 0 = 1 for FP32/BF16, 32768 for FP16 */
+    int32_t fixed_task_weights; /* 1 = ablation without uncertainty weighting: total = sum of
+                                   the five task losses, s neither used nor updated */
 } nif_train_cfg;
 int nif_train_step(nif_model* model, const nif_batch* batch, int64_t B, const nif_train_cfg* cfg,
                    float* losses_dev, nif_stream stream);

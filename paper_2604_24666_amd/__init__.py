@@ -28,6 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnif.so")
 
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+DIST_LOG_RELU, DIST_SIGMOID = 0, 1
 TABLE_F32, TABLE_F16 = 0, 1
 Q_FIRST_HIT, Q_NO_NETWORK, Q_POSE_TIMES = 0, 8, 16
 
@@ -39,7 +40,8 @@ class NifError(RuntimeError):
 class ModelDesc(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("table_dtype", C.c_int32), ("res", C.c_int32 * 32), ("pe_freqs", C.c_int32),
-                ("hidden_width", C.c_int32), ("hidden_layers", C.c_int32), ("n_materials", C.c_int32)]
+                ("hidden_width", C.c_int32), ("hidden_layers", C.c_int32), ("n_materials", C.c_int32),
+                ("dist_head", C.c_int32)]
 
 
 class Pose(C.Structure):
@@ -71,7 +73,7 @@ class Batch(C.Structure):
 class TrainCfg(C.Structure):
     _fields_ = [("lr_table", C.c_float), ("lr_mlp", C.c_float), ("lr_s", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("precision", C.c_int32),
-                ("loss_scale_init", C.c_float)]
+                ("loss_scale_init", C.c_float), ("fixed_task_weights", C.c_int32)]
 
 
 _lib = None
@@ -280,12 +282,13 @@ def nif_train_step(model, batch: Batch, B: int, cfg: TrainCfg, losses, stream=No
 # ------------------------------------------------------------------ convenience objects
 
 def model_desc(levels, log2_table, feat_dim, table_dtype, res, pe_freqs, hidden_width, hidden_layers,
-               n_materials) -> ModelDesc:
+               n_materials, dist_head=0) -> ModelDesc:
     d = ModelDesc()
     d.levels, d.log2_table, d.feat_dim, d.table_dtype = levels, log2_table, feat_dim, table_dtype
     for i, r in enumerate(res):
         d.res[i] = int(r)
     d.pe_freqs, d.hidden_width, d.hidden_layers, d.n_materials = pe_freqs, hidden_width, hidden_layers, n_materials
+    d.dist_head = dist_head
     return d
 
 
@@ -295,7 +298,7 @@ class Model:
     def __init__(self, m, device="cuda"):
         self.spec = m
         self.desc = model_desc(m.levels, m.log2_table, m.feat_dim, m.table_dtype, m.res, m.pe_freqs,
-                               m.hidden_width, m.hidden_layers, m.n_materials)
+                               m.hidden_width, m.hidden_layers, m.n_materials, getattr(m, "dist_head", 0))
         self.n_table, self.n_mlp = nif_model_sizes(self.desc)
         self.H = 8 + m.n_materials
         self.E = 2 * (1 + 2 * m.pe_freqs) * m.levels * m.feat_dim

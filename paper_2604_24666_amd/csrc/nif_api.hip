@@ -61,6 +61,8 @@ static int validate_desc(const nif_model_desc* d) {
         return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
     REQUIRE(d->hidden_layers >= 1 && d->hidden_layers <= 8, "hidden_layers must be in [1, 8]");
     REQUIRE(d->n_materials >= 1 && d->n_materials <= 8, "n_materials must be in [1, 8]");
+    REQUIRE(d->dist_head == NIF_DIST_LOG_RELU || d->dist_head == NIF_DIST_SIGMOID,
+            "dist_head must be NIF_DIST_LOG_RELU or NIF_DIST_SIGMOID");
     return NIF_OK;
 }
 
@@ -331,6 +333,7 @@ int nif_train_step(nif_model* m, const nif_batch* b, int64_t B, const nif_train_
     REQUIRE(b->x0 && b->x1 && b->hit && b->t && b->n && b->a && b->m, "batch arrays must not be null");
     REQUIRE(cfg->precision >= 0 && cfg->precision <= 2, "precision must be NIF_PREC_FP32, _BF16 or _FP16");
     REQUIRE(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps > 0.f, "bad Adam hyper-parameters");
+    REQUIRE(cfg->fixed_task_weights == 0 || cfg->fixed_task_weights == 1, "fixed_task_weights must be 0 or 1");
     if (!m->params_set) return fail(NIF_E_STATE, "model parameters were never set");
     if (B > m->max_batch) return fail(NIF_E_STATE, "batch larger than reserved with nif_model_reserve");
     return nif::train_step_launch(m, b, B, cfg, losses, S(stream));

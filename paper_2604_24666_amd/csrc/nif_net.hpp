@@ -54,6 +54,7 @@ struct NetParams {
     int32_t n_hidden;            // hidden layers
     int32_t E;                   // encoding width (both points)
     int32_t H;                   // real head count
+    int32_t dist_head;           // NIF_DIST_LOG_RELU or NIF_DIST_SIGMOID
 };
 
 __device__ __forceinline__ uint16_t f2bf(float x) {

@@ -131,11 +131,16 @@ __device__ __forceinline__ void write_miss(const nif_hits& o, int64_t r, int nq,
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.f / (1.f + expf(-v)); }
 
 __device__ __forceinline__ void write_hit(const nif_hits& o, int64_t r, const Segment& sg, float3 x0, float3 x1,
-                                          const float* z, int nq, int n_mat) {
+                                          const float* z, int nq, int n_mat, int dist_head) {
     const float ex = x1.x - x0.x, ey = x1.y - x0.y, ez = x1.z - x0.z;
-    const float lr = sqrtf(ex * ex + ey * ey + ez * ez);
-    const float dh = fmaxf(z[1], 0.f);
-    const float f = lr > 0.f ? fminf(fmaxf(dh / lr, 0.f), 1.f) : 0.f;
+    float f;
+    if (dist_head == NIF_DIST_SIGMOID) {
+        f = sigmoidf_(z[1]);               // the bounded head: the fraction itself
+    } else {
+        const float lr = sqrtf(ex * ex + ey * ey + ez * ez);
+        const float dh = fmaxf(z[1], 0.f);
+        f = lr > 0.f ? fminf(fmaxf(dh / lr, 0.f), 1.f) : 0.f;
+    }
     if (o.hit) o.hit[r] = 1;
     if (o.t) o.t[r] = fmaf(f, sg.b - sg.a, sg.a);
     const float nl = fmaxf(sqrtf(z[2] * z[2] + z[3] * z[3] + z[4] * z[4]), 1e-12f);
@@ -271,7 +276,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
             if (z[0] > 0.f) {
                 sg.cell = pk.get(QW_CELL); sg.a = pk.getf(QW_A); sg.b = pk.getf(QW_B);
                 const float* my = s_seg + lane * kSegStride;
-                write_hit(out, r, sg, make_float3(my[0], my[1], my[2]), make_float3(my[4], my[5], my[6]), z, nq, n_mat);
+                write_hit(out, r, sg, make_float3(my[0], my[1], my[2]), make_float3(my[4], my[5], my[6]), z, nq, n_mat, np.dist_head);
                 r = -1;
                 ++n_done;
                 hitnow = true;
@@ -364,7 +369,7 @@ __global__ void __launch_bounds__(256) k_proxy(GridArgs G, RayArgs R, nif_hits o
             z[0] = 1.f;
             // the face normal enters the outputs as z_n; the distance head is 0 so D = t_in
             if (sg.face >= 0) z[2 + (sg.face >> 1)] = (sg.face & 1) ? 1.f : -1.f;
-            write_hit(out, r, sg, x0, x0, z, 1, 1);
+            write_hit(out, r, sg, x0, x0, z, 1, 1, NIF_DIST_LOG_RELU);
             if (out.ar) out.ar[r] = 0.f;
             if (out.ag) out.ag[r] = 0.f;
             if (out.ab) out.ab[r] = 0.f;
@@ -484,6 +489,7 @@ NetParams make_net_params(const nif_model* m, int32_t precision) {
     np.n_hidden = d.hidden_layers;
     np.E = m->E;
     np.H = m->H;
+    np.dist_head = d.dist_head;
     return np;
 }
 

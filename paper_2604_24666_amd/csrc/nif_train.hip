@@ -112,12 +112,14 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H
                                               const float* __restrict__ ln, const float* __restrict__ la,
                                               const int32_t* __restrict__ lm, const float* __restrict__ s,
                                               const int64_t* __restrict__ tcount, double* __restrict__ dacc,
-                                              float* __restrict__ dz) {
+                                              float* __restrict__ dz, const float* __restrict__ x0,
+                                              const float* __restrict__ x1, int dist_head, int fixed) {
     const int M = H - 8;
     const double P = (double)tcount[TC_NPOS];
     const float scale = (float)dacc[DA_SCALE_USED];
-    const float w0 = expf(-s[0]), w1 = 0.5f * expf(-s[1]), w2 = 0.5f * expf(-s[2]), w3 = 0.5f * expf(-s[3]),
-                w4 = expf(-s[4]);
+    float w0 = expf(-s[0]), w1 = 0.5f * expf(-s[1]), w2 = 0.5f * expf(-s[2]), w3 = 0.5f * expf(-s[3]),
+          w4 = expf(-s[4]);
+    if (fixed) w0 = w1 = w2 = w3 = w4 = 1.f;
     const float invB = (float)(1.0 / (double)B), invP = P > 0 ? (float)(1.0 / P) : 0.f;
     double acc[5] = {0, 0, 0, 0, 0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += (int64_t)gridDim.x * blockDim.x) {
@@ -130,10 +132,20 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H
         acc[0] += fmaxf(z0, 0.f) - z0 * y + log1pf(expf(-fabsf(z0)));
         g[0] = w0 * (sigm(z0) - y) * invB;
         if (lhit[i] && P > 0) {
-            const float dh = fmaxf(zi[1], 0.f);
-            const float r = logf(dh + kDistEps) - logf(lt[i] + kDistEps);
-            acc[1] += (double)r * r;
-            if (zi[1] > 0.f) g[1] = w1 * 2.f * r / (dh + kDistEps) * invP;
+            if (dist_head == NIF_DIST_SIGMOID) {
+                const float ex = x1[i] - x0[i], ey = x1[B + i] - x0[B + i], ez = x1[2 * B + i] - x0[2 * B + i];
+                const float lr = sqrtf(ex * ex + ey * ey + ez * ez);
+                const float tau = lr > 0.f ? fminf(fmaxf(lt[i] / lr, 0.f), 1.f) : 0.f;
+                const float p = sigm(zi[1]);
+                const float r = p - tau;
+                acc[1] += (double)r * r;
+                g[1] = w1 * 2.f * r * p * (1.f - p) * invP;
+            } else {
+                const float dh = fmaxf(zi[1], 0.f);
+                const float r = logf(dh + kDistEps) - logf(lt[i] + kDistEps);
+                acc[1] += (double)r * r;
+                if (zi[1] > 0.f) g[1] = w1 * 2.f * r / (dh + kDistEps) * invP;
+            }
             const float nt[3] = {ln[i], ln[B + i], ln[2 * B + i]};
             const float v[3] = {zi[2], zi[3], zi[4]};
             const float vl = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -782,7 +794,7 @@ __global__ void k_check_finite(const float* __restrict__ a, int64_t n, int64_t* 
 
 // Losses, d total / d s, dynamic loss scale, skip decision, Adam bias corrections (one thread).
 __global__ void k_finalize(double* dacc, int64_t* tcount, const float* s, float* g_s, float* losses, int64_t B,
-                           int dynamic, float beta1, float beta2) {
+                           int dynamic, float beta1, float beta2, int fixed) {
     if (threadIdx.x != 0) return;
     const double P = (double)tcount[TC_NPOS];
     double Ls[5], w[5];
@@ -792,8 +804,13 @@ __global__ void k_finalize(double* dacc, int64_t* tcount, const float* s, float*
     w[3] = 0.5 * exp(-(double)s[3]); w[4] = exp(-(double)s[4]);
     double total = 0.0;
     for (int k = 0; k < 5; ++k) {
-        total += w[k] * Ls[k] + 0.5 * s[k];
-        g_s[k] = (float)(-w[k] * Ls[k] + 0.5);
+        if (fixed) {                       // plain sum; s is neither used nor trained
+            total += Ls[k];
+            g_s[k] = 0.f;
+        } else {
+            total += w[k] * Ls[k] + 0.5 * s[k];
+            g_s[k] = (float)(-w[k] * Ls[k] + 0.5);
+        }
         losses[k] = (float)Ls[k];
         losses[6 + k] = s[k];
     }
@@ -999,19 +1016,19 @@ int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_tra
     int rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, m->enc, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, m->zbuf, m->H, B, b->hit, b->t, b->n, b->a, b->m,
-                       m->s, m->tcount, m->dacc, m->dz);
+                       m->s, m->tcount, m->dacc, m->dz, b->x0, b->x1, m->desc.dist_head, cfg->fixed_task_weights);
     if ((rc = backward_core(m, b->x0, b->x1, B, nullptr, nullptr, prec, st))) return rc;
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table, m->tcount);
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp, m->tcount);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, m->s, m->g_s, losses, B,
-                       prec != NIF_PREC_FP32 ? 1 : 0, cfg->beta1, cfg->beta2);
+                       prec != NIF_PREC_FP32 ? 1 : 0, cfg->beta1, cfg->beta2, cfg->fixed_task_weights);
     AdamParams A;
     A.tables = m->tables; A.g_tables = m->g_tables; A.m_tables = m->m_tables; A.v_tables = m->v_tables;
     A.tables_h = m->desc.table_dtype == NIF_TABLE_F16 ? m->tables_h : nullptr;
     A.mlp = m->mlp; A.g_mlp = m->g_mlp; A.m_mlp = m->m_mlp; A.v_mlp = m->v_mlp;
     A.s = m->s; A.g_s = m->g_s; A.m_s = m->m_s; A.v_s = m->v_s;
     A.n_table = m->n_table; A.n_mlp = m->n_mlp;
-    A.lr_table = cfg->lr_table; A.lr_mlp = cfg->lr_mlp; A.lr_s = cfg->lr_s;
+    A.lr_table = cfg->lr_table; A.lr_mlp = cfg->lr_mlp; A.lr_s = cfg->fixed_task_weights ? 0.f : cfg->lr_s;
     A.beta1 = cfg->beta1; A.beta2 = cfg->beta2; A.eps = cfg->eps;
     hipLaunchKernelGGL(k_adam, dim3(grid_for(m->n_table + m->n_mlp + 5)), dim3(256), 0, st, A, m->dacc, m->tcount);
     if ((rc = check_hip(hipGetLastError(), "train step launch"))) return rc;

@@ -92,6 +92,31 @@ def test_query_torus16_fp32(orc, P, kind, s):
     assert n_ok > 3500 and n_hit > 200
 
 
+ABLATIONS = {"sigmoid_head": dict(dist_head=S.DIST_SIGMOID), "no_pe": dict(pe_freqs=0),
+             "no_pe_sigmoid_head": dict(pe_freqs=0, dist_head=S.DIST_SIGMOID)}
+
+
+@pytest.mark.parametrize("variant", list(ABLATIONS))
+def test_query_torus16_ablation_switches(orc, P, variant):
+    """The baselines' switches on the query path: the sigmoid-fraction distance head and F = 0
+    (grid encoding alone), against the oracle under a twist."""
+    import dataclasses
+    import torch
+    w = S.workload("torus16")
+    m = dataclasses.replace(w.model, **ABLATIONS[variant])
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab, prm, seen = model_params(m, w.seed + 101, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, [S.TWIST], [1.0])
+    o, d = S.rays_random(4096, w.seed + 1)
+    say(f"query torus16 ablation {variant}")
+    got = _np(grid.query(model, dev_f32(o), dev_f32(d), offsets([4096])))
+    n_ok, n_hit = _compare(orc, P, m, seen, prm, w.N, occ, S.TWIST, 1.0, o, d, got)
+    assert n_ok > 3500 and n_hit > 50
+
+
 def test_query_voxel_proxy_is_the_first_segment(orc, P):
     import torch
     w = S.workload("torus16")

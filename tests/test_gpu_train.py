@@ -79,13 +79,13 @@ def test_backward_matches_oracle_gradient(orc, P, name):
     _grad_close(dx1.cpu().numpy().T, gx1, "d x1")
 
 
-def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3)):
+def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3), fixed=False):
     import torch
     x0, x1, hit, t, nr, al, mt = batch
     keep = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
             torch.as_tensor(mt).cuda()]
     b = P.Batch(*[k.data_ptr() for k in keep])
-    cfg = P.TrainCfg(lr[0], lr[1], lr[2], 0.9, 0.999, 1e-8, prec, 0.0)
+    cfg = P.TrainCfg(lr[0], lr[1], lr[2], 0.9, 0.999, 1e-8, prec, 0.0, int(fixed))
     losses = torch.zeros(16, device="cuda")
     P.nif_train_step(model.h, b, B, cfg, losses)
     torch.cuda.synchronize()
@@ -125,6 +125,49 @@ def test_train_step_matches_oracle(orc, P, name):
         big = np.abs(g) > 1e-3 * np.abs(g).max()
         assert np.abs(got - ref)[big].max() <= 1e-6 * max(1.0, np.abs(th0).max()) + 1e-7
     assert np.abs(s1 - (s0 - 1e-3 * gs / (np.abs(gs) + 1e-8))).max() <= 1e-6
+
+
+ABLATIONS = {
+    "sigmoid_head_fixed_weights": (dict(dist_head=S.DIST_SIGMOID), True),
+    "no_pe": (dict(pe_freqs=0), False),
+    "no_pe_sigmoid_head_fixed_weights": (dict(pe_freqs=0, dist_head=S.DIST_SIGMOID), True),
+}
+
+
+@pytest.mark.parametrize("variant", list(ABLATIONS))
+def test_train_step_ablation_switches_match_oracle(orc, P, variant):
+    """The baselines' training: sigmoid-fraction distance (MSE against t*/l), unit task
+    weights with s untouched, and F = 0; losses, gradients and the first Adam step."""
+    kw, fixed = ABLATIONS[variant]
+    m = dataclasses.replace(MODELS["torus16"], **kw)
+    say(f"train step fp32 torus16 ablation {variant}")
+    tab, prm, seen = model_params(m, 9, scale_tables=300.0)
+    B = 2048 + 13
+    batch = _batch(m, B, 10)
+    x0, x1, hit, t, nr, al, mt = batch
+    t[:50] = 0.2                              # some targets beyond the segment: t*/l clamps to 1
+    s0 = np.array([0.3, -0.2, 0.1, 0.4, -0.5]) if fixed else np.zeros(5)
+    L, gt, gp, gs, _, _ = orc.loss_grad(m, seen, prm.astype(np.float64), s0, x0.T, x1.T, hit, t, nr.T, al.T, mt,
+                                        fixed_weights=fixed)
+    model = P.Model(m)
+    model.set_params(tab, prm, s0.astype(np.float32))
+    P.nif_model_reserve(model.h, B)
+    losses = _train_step(P, model, batch, B, fixed=fixed)
+    say(f"  losses gpu {np.round(losses[:6], 6)}  oracle {np.round(L, 6)}")
+    assert np.all(np.abs(losses[:6] - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
+    g_t, g_p, g_s = model.get_grads()
+    _grad_close(g_t.cpu().numpy(), gt, "tables", big_frac=1e-2, el_tol=1e-3)
+    _grad_close(g_p.cpu().numpy(), gp, "mlp", big_frac=1e-2, el_tol=1e-3)
+    t1, p1, s1 = [v.cpu().numpy().astype(np.float64) for v in model.get_params()]
+    if fixed:
+        assert np.all(g_s.cpu().numpy() == 0) and np.all(s1 == s0.astype(np.float32))
+    else:
+        assert np.abs(g_s.cpu().numpy() - gs).max() <= 1e-5 * np.abs(gs).max()
+    for got, th0, g, lr in ((t1, tab.reshape(-1).astype(np.float64), gt.reshape(-1), 1e-2),
+                            (p1, prm.astype(np.float64), gp, 1e-3)):
+        ref = th0 - lr * g / (np.abs(g) + 1e-8)
+        big = np.abs(g) > 1e-3 * np.abs(g).max()
+        assert np.abs(got - ref)[big].max() <= 1e-6 * max(1.0, np.abs(th0).max()) + 1e-7
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
