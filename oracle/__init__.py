@@ -189,9 +189,11 @@ def forward(desc, tables, params, x0, x1, with_scale: bool = False):
     return (z, sc) if with_scale else z
 
 
-def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
+def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d, tmax=None) -> dict:
     """Per-ray first-hit outputs; for hits also zhit (raw heads of the hit segment) and
-    seginfo = (t_in, t_out, rest length, |cos| at entry, |cos| at exit) of that segment."""
+    seginfo = (t_in, t_out, rest length, |cos| at entry, |cos| at exit) of that segment.
+    tmax (per ray, optional): occlusion form, hits at D >= tmax and voxels entered at or
+    beyond tmax do not count."""
     m = model_struct(desc)
     tab = _f64(tables).reshape(-1); prm = _f64(params)
     occ = np.ascontiguousarray(occ, dtype=np.uint8)
@@ -201,6 +203,7 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
              albedo=np.zeros((n, 3)), material=np.zeros(n, np.int32), cell=np.zeros(n, np.int32),
              logit=np.zeros(n), n_queried=np.zeros(n, np.int32), margin=np.zeros(n),
              zhit=np.zeros((n, desc.n_heads)), seginfo=np.zeros((n, 5)))
+    tm = None if tmax is None else np.ascontiguousarray(np.broadcast_to(np.asarray(tmax, np.float64), (n,)))
     lib().orc_query_batch(C.byref(m), _p(tab, C.c_double), _p(prm, C.c_double), C.c_int32(N),
                           _p(occ, C.c_uint8), C.c_int32(kind), C.c_double(s), C.c_int64(n),
                           _p(o, C.c_double), _p(d, C.c_double), _p(r["hit"], C.c_uint8),
@@ -208,7 +211,8 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d) -> dict:
                           _p(r["albedo"], C.c_double), _p(r["material"], C.c_int32),
                           _p(r["cell"], C.c_int32), _p(r["logit"], C.c_double),
                           _p(r["n_queried"], C.c_int32), _p(r["margin"], C.c_double),
-                          _p(r["zhit"], C.c_double), _p(r["seginfo"], C.c_double))
+                          _p(r["zhit"], C.c_double), _p(r["seginfo"], C.c_double),
+                          _p(tm, C.c_double) if tm is not None else None)
     return r
 
 

@@ -263,12 +263,15 @@ void orc_forward_batch(const orc_model* m, const double* tables, const double* p
 
 /* First-hit query of n rays under one pose.  Per ray: hit, distance D along the ray,
    rest-space hit point, normal, albedo, material, voxel, hit logit, segments evaluated,
-   and the smallest relative margin |z0| / scale among the evaluated segments. */
+   and the smallest relative margin |z0| / scale among the evaluated segments.
+   tmax (nullable, per ray): the occlusion form of the query used for shadow rays, the
+   renderer integration the introduction and conclusion describe: voxels entered at
+   t_in >= tmax are not visited, and a first hit at D >= tmax is a miss. */
 void orc_query_batch(const orc_model* m, const double* tables, const double* params, int32_t N,
                      const uint8_t* occ, int32_t kind, double s, int64_t n, const double* o,
                      const double* d, uint8_t* hit, double* tout_ray, double* xrest, double* nrm,
                      double* alb, int32_t* mat, int32_t* cell_out, double* logit, int32_t* nq,
-                     double* margin, double* zhit, double* seginfo) {
+                     double* margin, double* zhit, double* seginfo, const double* tmax) {
     const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials;
     double* V = (double*)malloc(sizeof(double) * 3 * (size_t)(N + 1) * (N + 1) * (N + 1));
     orc_lattice_vertices(kind, s, N, V);
@@ -292,7 +295,9 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
             hit[r] = 0; tout_ray[r] = INFINITY; cell_out[r] = -1; mat[r] = -1;
             logit[r] = -INFINITY; nq[r] = 0; margin[r] = INFINITY;
             for (int a = 0; a < 3; ++a) { xrest[3 * r + a] = 0; nrm[3 * r + a] = 0; alb[3 * r + a] = 0; }
+            const double tm = tmax ? tmax[r] : INFINITY;
             for (int k = 0; k < ns; ++k) {
+                if (tin[k] >= tm) break;
                 double p0[3], p1[3], x0[3], x1[3];
                 for (int a = 0; a < 3; ++a) { p0[a] = ro[a] + tin[k] * rd[a]; p1[a] = ro[a] + tou[k] * rd[a]; }
                 orc_deform_inv(kind, s, p0, x0);
@@ -314,8 +319,10 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
                     double dh = z[1] > 0.0 ? z[1] : 0.0;
                     f = lr > 0.0 ? clamp01(dh / lr) : 0.0;
                 }
+                double D = tin[k] + f * (tou[k] - tin[k]);
+                if (D >= tm) break;                 /* the first hit lies beyond tmax */
                 hit[r] = 1;
-                tout_ray[r] = tin[k] + f * (tou[k] - tin[k]);
+                tout_ray[r] = D;
                 for (int a = 0; a < 3; ++a) xrest[3 * r + a] = x0[a] + f * e[a];
                 double nl = sqrt(z[2] * z[2] + z[3] * z[3] + z[4] * z[4]);
                 if (nl < 1e-12) nl = 1e-12;

@@ -166,6 +166,33 @@ def test_query_with_always_hit_network_returns_first_segment(orc, kind, dist_hea
     assert np.all(np.isinf(q["t"][~hit])) and np.all(q["cell"][~hit] == -1)
 
 
+def test_query_tmax_is_the_occlusion_form_of_the_first_hit(orc):
+    """Always-hit network: occluded iff the unbounded first hit lies before tmax; never-hit
+    network: exactly the voxels entered before tmax are evaluated (brute-force hit lists)."""
+    w = S.workload("torus16")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab = np.zeros((m.levels, m.table_size, m.feat_dim))
+    o, d = S.rays_random(300, 53)
+    tmax = np.random.default_rng(54).uniform(1.0, 3.0, 300)
+    always = _forced_params(m, 1.0, 0.01)
+    full = orc.query(m, tab, always, w.N, occ, S.TWIST, 1.0, o, d)
+    occl = orc.query(m, tab, always, w.N, occ, S.TWIST, 1.0, o, d, tmax=tmax)
+    assert full["hit"].sum() > 50
+    expect = (full["hit"] == 1) & (full["t"] < tmax)
+    assert 0 < expect.sum() < full["hit"].sum()
+    assert np.array_equal(occl["hit"].astype(bool), expect)
+    assert np.array_equal(occl["t"][expect], full["t"][expect]) and np.all(np.isinf(occl["t"][~expect]))
+    never = _forced_params(m, -1.0, 0.0)
+    q = orc.query(m, tab, never, w.N, occ, S.TWIST, 1.0, o, d, tmax=tmax)
+    V = orc.lattice_vertices(S.TWIST, 1.0, w.N)
+    cells, tin, tout, cnt, _ = orc.trace(w.N, occ, V, o, d, brute=True, with_flags=False)
+    before = np.array([(tin[i, :cnt[i]] < tmax[i]).sum() for i in range(300)])
+    assert q["hit"].sum() == 0 and np.array_equal(q["n_queried"], before)
+    assert np.any((before > 0) & (before < cnt))
+
+
 def test_query_with_never_hit_network_visits_every_segment(orc):
     w = S.workload("torus16")
     m = w.model
