@@ -237,6 +237,244 @@ def train_leg(steps=5, B=1 << 18):
             "label_ms": label_ms, **res}
 
 
+def _segment_dataset(P, grid, o, d, off, scene_kind, sp, max_seg):
+    """Every occupied-voxel segment of the rays (rest-space chords) with its labels."""
+    import torch
+    tr = grid.trace(o, d, off, max_seg=max_seg)
+    cnt = tr["count"].clamp(max=max_seg)
+    valid = (torch.arange(max_seg, device="cuda")[None, :] < cnt[:, None]).reshape(-1)
+    x0 = tr["x0"].reshape(3, -1)[:, valid].contiguous()
+    x1 = tr["x1"].reshape(3, -1)[:, valid].contiguous()
+    lab = P.label(scene_kind, sp, x0, x1)
+    return {"x0": x0, "x1": x1, "hit": lab["hit"], "t": lab["t"], "n": lab["normal"], "a": lab["albedo"],
+            "m": lab["material"]}
+
+
+def _ground_truth(P, grid, o, d, off, scene_kind, sp, max_seg=64):
+    """Per ray, the first labelled hit along its occupied-voxel segments: distance along the
+    ray (entry + hit fraction of the segment, the local linear approximation) and the
+    rest-space normal there.  Rays with more than max_seg segments are flagged invalid."""
+    import torch
+    tr = grid.trace(o, d, off, max_seg=max_seg)
+    n = o.shape[1]
+    cnt = tr["count"]
+    ok = cnt <= max_seg
+    c = cnt.clamp(max=max_seg)
+    valid = torch.arange(max_seg, device="cuda")[None, :] < c[:, None]
+    x0 = tr["x0"].reshape(3, -1)[:, valid.reshape(-1)].contiguous()
+    x1 = tr["x1"].reshape(3, -1)[:, valid.reshape(-1)].contiguous()
+    lab = P.label(scene_kind, sp, x0, x1)
+    hit = torch.zeros((n, max_seg), dtype=torch.bool, device="cuda")
+    hit[valid] = lab["hit"].bool()
+    lr = (x1 - x0).norm(dim=0)
+    frac = torch.zeros((n, max_seg), device="cuda")
+    frac[valid] = torch.where(lr > 0, (lab["t"] / lr).clamp(0, 1), torch.zeros_like(lr))
+    nrm = torch.zeros((3, n, max_seg), device="cuda")
+    nrm[:, valid] = lab["normal"]
+    any_hit = hit.any(dim=1)
+    first = torch.where(any_hit, hit.int().argmax(dim=1), torch.zeros_like(cnt, dtype=torch.int64))
+    r = torch.arange(n, device="cuda")
+    tin, tout = tr["t_in"][r, first], tr["t_out"][r, first]
+    t = tin + frac[r, first] * (tout - tin)
+    return {"valid": ok, "hit": any_hit & ok, "t": t, "n": nrm[:, r, first]}
+
+
+def _errors(P, model, grid, o, d, off, gt):
+    import torch
+    q = grid.query(model, o, d, off)
+    ph = q["hit"].bool()
+    both = ph & gt["hit"]
+    pn = torch.stack([q["nx"], q["ny"], q["nz"]])
+    cos = (pn * gt["n"]).sum(0).clamp(-1, 1)
+    ang = torch.rad2deg(torch.acos(cos))
+    return {"distance_mae": float((q["t"] - gt["t"]).abs()[both].mean()),
+            "normal_deg": float(ang[both].mean()),
+            "hit_agreement": float((ph == gt["hit"])[gt["valid"]].float().mean()),
+            "rays_compared": int(both.sum())}
+
+
+def _train_model(P, m, ds, steps, B, fixed, seed, tag):
+    """Adam on minibatches of B segments drawn uniformly from the labelled set ds."""
+    import torch
+
+    import nif_synth as S
+    n_seg = ds["x0"].shape[1]
+    model = P.Model(m)
+    model.set_params(S.init_tables(m, seed), S.init_mlp(m, seed))
+    P.nif_model_reserve(model.h, B)
+    cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, P.PREC_FP32, 0.0, int(fixed))
+    losses = torch.zeros(16, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = torch.randint(0, n_seg, (B,), device="cuda", generator=gen)
+        b = {k: (v[:, idx] if v.dim() == 2 else v[idx]).contiguous() for k, v in ds.items()}
+        batch = P.Batch(b["x0"].data_ptr(), b["x1"].data_ptr(), b["hit"].data_ptr(), b["t"].data_ptr(),
+                        b["n"].data_ptr(), b["a"].data_ptr(), b["m"].data_ptr())
+        P.nif_train_step(model.h, batch, B, cfg, losses)
+        if (it + 1) % 500 == 0:
+            torch.cuda.synchronize()
+            log(f"{tag}: step {it + 1}/{steps}, loss {float(losses[5]):.4f}")
+    torch.cuda.synchronize()
+    return model, time.perf_counter() - t0, [float(x) for x in losses[:6].cpu()]
+
+
+def ablation_leg(steps=2000, B=1 << 16):
+    """Table 1 analogue on a synthetic scene: the original LSNIF (trained on the rest pose only),
+    the deformation-aware baseline without the proposed training and encoding changes (F = 0,
+    sigmoid-fraction distance, fixed task weights; trained on a pose distribution) and the
+    proposed model (F = 6, ReLU log distance, uncertainty weighting; same poses).  Errors of
+    the first-hit query against the labelled ground truth on the static rest pose and on
+    unseen deformed poses."""
+    import dataclasses
+
+    import torch
+
+    import nif_synth as S
+    import paper_2604_24666_amd as P
+
+    w = S.workload("spheres64")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    base = w.model
+    baseline = dataclasses.replace(base, pe_freqs=0, dist_head=S.DIST_SIGMOID)
+    nr = 1 << 20
+    o, d = [torch.as_tensor(a).cuda() for a in S.rays_random(nr, w.seed + 7)]
+    # training data: rest pose only, and a pose distribution (rest + 31 random poses)
+    k_dist, s_dist = S.random_poses(31, w.seed + 8, kinds=(S.TWIST, S.BEND, S.TAPER))
+    k_dist = np.concatenate([[S.IDENTITY], k_dist]).astype(np.int32)
+    s_dist = np.concatenate([[0.0], s_dist]).astype(np.float32)
+    data = {}
+    for name, kinds, strengths in (("rest", [S.IDENTITY], [0.0]), ("poses", k_dist, s_dist)):
+        g = P.Grid(occ, w.N, kinds, strengths)
+        off = torch.as_tensor(np.linspace(0, nr, len(kinds) + 1).astype(np.int64)).cuda()
+        data[name] = _segment_dataset(P, g, o, d, off, w.scene_kind, sp, 16)
+        log(f"ablation: {data[name]['x0'].shape[1]} training segments ({name}), "
+            f"hit ratio {float(data[name]['hit'].float().mean()):.3f}")
+        del g
+    # evaluation: pinhole views of the rest pose, and of four unseen deformed poses
+    views = [S.rays_camera(256, az) for az in (0.0, 90.0, 180.0, 270.0)]
+    eo = torch.as_tensor(np.concatenate([v[0] for v in views], 1)).cuda()
+    ed = torch.as_tensor(np.concatenate([v[1] for v in views], 1)).cuda()
+    ne = eo.shape[1]
+    evals = {}
+    for name, kinds, strengths in (("rest", [S.IDENTITY], [0.0]),
+                                   ("deformed", [S.TWIST, S.BEND, S.TAPER, S.TWIST], [0.85, 0.65, 0.9, 0.35])):
+        g = P.Grid(occ, w.N, kinds, strengths)
+        reps = len(kinds)
+        o_e, d_e = eo.repeat(1, reps).contiguous(), ed.repeat(1, reps).contiguous()
+        off = torch.as_tensor(np.arange(reps + 1, dtype=np.int64) * ne).cuda()
+        evals[name] = (g, o_e, d_e, off, _ground_truth(P, g, o_e, d_e, off, w.scene_kind, sp))
+    variants = (("LSNIF", baseline, True, "rest"), ("Deformed", baseline, True, "poses"),
+                ("Proposed", base, False, "poses"))
+    res = {}
+    for vname, m, fixed, dname in variants:
+        model, train_s, losses = _train_model(P, m, data[dname], steps, B, fixed, w.seed + 200, vname)
+        r = {"train_s": train_s, "final_losses": losses}
+        for ename, (g, o_e, d_e, off, gt) in evals.items():
+            r[ename] = _errors(P, model, g, o_e, d_e, off, gt)
+        log(f"ablation {vname}: {r}")
+        res[vname] = r
+        del model
+    return {"workload": f"spheres64 scene (8 spheres, 64^3), 16-level 2^19 FP16 grid, MLP 64x3; {steps} Adam steps of "
+                        f"B = {B} segments drawn from 2^20 random rays through the rest pose (LSNIF) or through the "
+                        f"rest pose and 31 random twist/bend/taper poses (Deformed, Proposed); evaluated on 4 x 256^2 "
+                        f"pinhole rays at the rest pose and at 4 unseen poses against labelled ground truth",
+            **res}
+
+
+def render_leg(steps=1500, B=1 << 16, res=1024, reps=5):
+    """Renderer-style use of a trained field under a deformation: one frame of pinhole primary
+    rays (first hit), shadow rays from every primary hit to a point light (occlusion query
+    with tmax, visibility bit only) and one diffuse bounce per hit (incoherent first-hit
+    rays).  Throughput of each ray population, and agreement of the predicted hits and
+    shadows with the labelled ground truth of the same rays."""
+    import torch
+
+    import nif_synth as S
+    import paper_2604_24666_amd as P
+
+    w = S.workload("spheres64")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    m = w.model
+    # train on rays through the rest pose and 31 random poses (as the proposed model above)
+    nr = 1 << 20
+    o, d = [torch.as_tensor(a).cuda() for a in S.rays_random(nr, w.seed + 7)]
+    kd, sd = S.random_poses(31, w.seed + 8, kinds=(S.TWIST, S.BEND, S.TAPER))
+    kd = np.concatenate([[S.IDENTITY], kd]).astype(np.int32)
+    sd = np.concatenate([[0.0], sd]).astype(np.float32)
+    g = P.Grid(occ, w.N, kd, sd)
+    ds = _segment_dataset(P, g, o, d, torch.as_tensor(np.linspace(0, nr, 33).astype(np.int64)).cuda(),
+                          w.scene_kind, sp, 16)
+    del g, o, d
+    model, train_s, _ = _train_model(P, m, ds, steps, B, False, w.seed + 400, "render model")
+    del ds
+    # one frame under an unseen twist
+    grid = P.Grid(occ, w.N, [S.TWIST], [0.8])
+    po, pd = [torch.as_tensor(a).cuda() for a in S.rays_camera(res, 35.0)]
+    n_p = po.shape[1]
+    off_p = torch.as_tensor(np.array([0, n_p], np.int64)).cuda()
+    prim = grid.query(model, po, pd, off_p)
+    torch.cuda.synchronize()
+    hit = prim["hit"].bool()
+    idx = torch.nonzero(hit).squeeze(1)
+    n_h = int(idx.numel())
+    off_h = torch.as_tensor(np.array([0, n_h], np.int64)).cuda()
+    x = po[:, idx] + prim["t"][idx][None, :] * pd[:, idx]
+    light = torch.tensor([[2.0], [1.5], [3.0]], device="cuda")
+    to_l = light - x
+    dist = to_l.norm(dim=0)
+    sdir = (to_l / dist).contiguous()
+    eps = 2.0 / w.N                                   # leave the hit voxel before looking for occluders
+    so = (x + eps * sdir).contiguous()
+    stmax = (dist - eps).contiguous()
+    sbit = torch.empty(n_h, dtype=torch.uint8, device="cuda")
+    shits = P.Hits(sbit.data_ptr(), *([None] * (len(P.Hits._fields_) - 1)))
+    srays = P.make_rays(so, sdir, off_h, stmax)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w.seed + 500)
+    bdir = torch.randn((3, n_h), device="cuda", generator=gen)
+    bdir = (bdir / bdir.norm(dim=0)).contiguous()
+    bo = (x + eps * bdir).contiguous()
+    bout = P.alloc_hits(n_h, "cuda")
+    bh = P.hits_struct(bout)
+    brays = P.make_rays(bo, bdir, off_h)
+    pout = P.alloc_hits(n_p, "cuda")
+    ph = P.hits_struct(pout)
+    prays = P.make_rays(po, pd, off_p)
+    timings = {}
+    for name, fn, n in (("primary", lambda: P.nif_query(model.h, grid.h, prays, n_p, ph, 0, 0, None), n_p),
+                        ("shadow", lambda: P.nif_query(model.h, grid.h, srays, n_h, shits, 0, 0, None), n_h),
+                        ("bounce", lambda: P.nif_query(model.h, grid.h, brays, n_h, bh, 0, 0, None), n_h)):
+        ms = timed(fn, reps, 2)
+        timings[name] = {"rays": n, "ms": ms, "rays_per_s": n / (ms * 1e-3)}
+        log(f"render {name}: {n} rays in {ms:.3f} ms")
+    # agreement with the labelled ground truth of the same rays
+    gtp = _ground_truth(P, grid, po, pd, off_p, w.scene_kind, sp)
+    gts = _ground_truth(P, grid, so, sdir, off_h, w.scene_kind, sp)
+    occl_gt = gts["hit"] & (gts["t"] < stmax)
+    lit = sbit == 0
+    shade = torch.zeros(n_p, device="cuda")
+    nrm = torch.stack([prim["nx"], prim["ny"], prim["nz"]])[:, idx]
+    alb = torch.stack([prim["ar"], prim["ag"], prim["ab"]])[:, idx].mean(0)
+    shade[idx] = alb * (0.15 + 0.85 * lit.float() * (nrm * sdir).sum(0).abs())
+    valid = gts["valid"]
+    return {"workload": f"spheres64 scene, model trained {steps} steps (B = {B}) on the rest pose and 31 random poses; "
+                        f"frame of {res}^2 pinhole rays under an unseen twist (0.8), shadow rays from every primary "
+                        f"hit to a point light (tmax = distance to the light), one uniform-direction bounce per hit",
+            "train_s": train_s, **timings,
+            "frame_ms": sum(v["ms"] for v in timings.values()),
+            "primary_hit_agreement": float((hit == gtp["hit"])[gtp["valid"]].float().mean()),
+            "shadow_agreement": float(((sbit == 1) == occl_gt)[valid].float().mean()),
+            "shadowed_fraction": float((sbit == 1).float().mean()), "bounce_hit_fraction": float(bout["hit"].float().mean()),
+            "mean_shade": float(shade.mean())}
+
+
 def batched_leg(replays=50, warmup=5):
     """16 poses of uneven ray counts (half pinhole, half secondary) in one persistent launch,
     replayed from a captured graph: aggregate rays/s (median launch) and per-pose completion
@@ -334,7 +572,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (scale for HBM byte counters)")
     ap.add_argument("--legs", default="precision,train,batched",
-                    help="extra measurements: precision,train,batched (empty for none)")
+                    help="extra measurements: precision,train,batched,ablation,render (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design note in DESIGN.md",
@@ -430,6 +668,10 @@ def main():
         res["train"] = train_leg()
     if "batched" in legs:
         res["batched"] = batched_leg()
+    if "ablation" in legs:
+        res["ablation"] = ablation_leg()
+    if "render" in legs:
+        res["render"] = render_leg()
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)

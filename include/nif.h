@@ -168,10 +168,12 @@ int nif_grid_bounds(const nif_grid* grid, int32_t pose, float* lo, float* hi);
 /* ---------------------------------------------------------------- rays
  * Deformed-space rays o + t d, grouped by pose: rays [pose_offsets[p], pose_offsets[p+1])
  * use pose p.  pose_offsets_dev: int64[n_poses + 1] on the device, pose_offsets[0] = 0 and
- * pose_offsets[n_poses] = n_rays.  d need not be unit; t is in units of |d|. */
+ * pose_offsets[n_poses] = n_rays.  d need not be unit; t is in units of |d|.
+ * tmax: nullable float[n_rays] on the device (NULL = unbounded); used by nif_query only. */
 typedef struct {
     const float *ox, *oy, *oz, *dx, *dy, *dz;
     const int64_t* pose_offsets;
+    const float* tmax;
 } nif_rays;
 
 /* Ordered occupied-voxel segments of each ray (Methodology, "Segmented Ray Distance
@@ -194,6 +196,9 @@ int nif_trace(const nif_grid* grid, const nif_rays* rays, int64_t n_rays, int32_
  * accumulation of the paper, which telescopes for one straight ray), its rest-space hit
  * point x0 + f (x1 - x0), normal z_n / |z_n|, albedo sigmoid(z_a), material argmax.
  * Misses: hit 0, t +inf, cell -1, material -1, other fields 0.
+ * With rays->tmax (the occlusion query of shadow rays, for the renderer integration of the
+ * introduction and conclusion): voxels entered at t_in >= tmax are not visited and a first
+ * hit at D >= tmax is reported as a miss; pass only out->hit for a pure visibility bit.
  * Every output pointer is nullable (not written).  Outputs are indexed by ray. */
 typedef struct {
     uint8_t* hit; float* t; float *nx, *ny, *nz; float *ar, *ag, *ab; int32_t* material;
@@ -212,8 +217,8 @@ int nif_query(const nif_model* model, const nif_grid* grid, const nif_rays* rays
               nif_stream stream);
 /* Frequency of the current device's wall clock (the ticks of NIF_Q_POSE_TIMES), in kHz. */
 int nif_wall_clock_khz(int32_t* khz);
-/* Launch shape of the fused query: persistent workgroups (4 waves each) per compute unit,
- * 1..32 (default 8).  Process-wide; chosen by the autotuner. */
+/* Launch shape of the fused query: persistent one-wave workgroups per compute unit,
+ * 1..32 (default 12).  Process-wide. */
 int nif_set_query_blocks_per_cu(int32_t blocks_per_cu);
 
 /* ---------------------------------------------------------------- network on points

@@ -50,7 +50,7 @@ class Pose(C.Structure):
 
 class Rays(C.Structure):
     _fields_ = [("ox", C.c_void_p), ("oy", C.c_void_p), ("oz", C.c_void_p), ("dx", C.c_void_p),
-                ("dy", C.c_void_p), ("dz", C.c_void_p), ("pose_offsets", C.c_void_p)]
+                ("dy", C.c_void_p), ("dz", C.c_void_p), ("pose_offsets", C.c_void_p), ("tmax", C.c_void_p)]
 
 
 class Segments(C.Structure):
@@ -235,10 +235,11 @@ def nif_grid_update(h, kinds, strengths, stream=None):
     _check(lib().nif_grid_update(h, poses, n, _stream(stream)))
 
 
-def make_rays(o, d, pose_offsets) -> Rays:
-    """o, d: float32 [3][n] device tensors; pose_offsets: int64 [P+1] device tensor."""
+def make_rays(o, d, pose_offsets, tmax=None) -> Rays:
+    """o, d: float32 [3][n] device tensors; pose_offsets: int64 [P+1] device tensor;
+    tmax: optional float32 [n] device tensor (occlusion bound of each ray)."""
     return Rays(o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), d[0].data_ptr(), d[1].data_ptr(),
-                d[2].data_ptr(), pose_offsets.data_ptr())
+                d[2].data_ptr(), pose_offsets.data_ptr(), _ptr(tmax))
 
 
 def nif_trace(grid, rays: Rays, n: int, max_seg: int, seg: Segments, stream=None):
@@ -381,13 +382,14 @@ class Grid:
         nif_trace(self.h, make_rays(o, d, pose_offsets), n, max_seg, seg)
         return out
 
-    def query(self, model, o, d, pose_offsets, precision=PREC_FP32, no_network=False, stats=None, out=None):
+    def query(self, model, o, d, pose_offsets, precision=PREC_FP32, no_network=False, stats=None, out=None,
+              tmax=None):
         n = o.shape[1]
         dev = o.device
         if out is None:
             out = alloc_hits(n, dev)
         hits = hits_struct(out)
-        nif_query(model.h if model is not None else None, self.h, make_rays(o, d, pose_offsets), n, hits,
+        nif_query(model.h if model is not None else None, self.h, make_rays(o, d, pose_offsets, tmax), n, hits,
                   Q_NO_NETWORK if no_network else Q_FIRST_HIT, precision, stats)
         return out
 

@@ -30,6 +30,7 @@ struct GridArgs {
 struct RayArgs {
     const float *ox, *oy, *oz, *dx, *dy, *dz;
     const int64_t* off;
+    const float* tmax;          // nullable: occlusion bound per ray
     int32_t n_poses;
     int64_t n;
 };
@@ -130,8 +131,9 @@ __device__ __forceinline__ void write_miss(const nif_hits& o, int64_t r, int nq,
 
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.f / (1.f + expf(-v)); }
 
+// Writes the hit of segment sg; a hit at or beyond tmax is written as a miss instead.
 __device__ __forceinline__ void write_hit(const nif_hits& o, int64_t r, const Segment& sg, float3 x0, float3 x1,
-                                          const float* z, int nq, int n_mat, int dist_head) {
+                                          const float* z, int nq, int n_mat, int dist_head, float tmax) {
     const float ex = x1.x - x0.x, ey = x1.y - x0.y, ez = x1.z - x0.z;
     float f;
     if (dist_head == NIF_DIST_SIGMOID) {
@@ -141,8 +143,13 @@ __device__ __forceinline__ void write_hit(const nif_hits& o, int64_t r, const Se
         const float dh = fmaxf(z[1], 0.f);
         f = lr > 0.f ? fminf(fmaxf(dh / lr, 0.f), 1.f) : 0.f;
     }
+    const float D = fmaf(f, sg.b - sg.a, sg.a);
+    if (D >= tmax) {
+        write_miss(o, r, nq, z[0]);
+        return;
+    }
     if (o.hit) o.hit[r] = 1;
-    if (o.t) o.t[r] = fmaf(f, sg.b - sg.a, sg.a);
+    if (o.t) o.t[r] = D;
     const float nl = fmaxf(sqrtf(z[2] * z[2] + z[3] * z[3] + z[4] * z[4]), 1e-12f);
     if (o.nx) o.nx[r] = z[2] / nl;
     if (o.ny) o.ny[r] = z[3] / nl;
@@ -276,7 +283,8 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
             if (z[0] > 0.f) {
                 sg.cell = pk.get(QW_CELL); sg.a = pk.getf(QW_A); sg.b = pk.getf(QW_B);
                 const float* my = s_seg + lane * kSegStride;
-                write_hit(out, r, sg, make_float3(my[0], my[1], my[2]), make_float3(my[4], my[5], my[6]), z, nq, n_mat, np.dist_head);
+                write_hit(out, r, sg, make_float3(my[0], my[1], my[2]), make_float3(my[4], my[5], my[6]), z, nq, n_mat,
+                          np.dist_head, R.tmax ? R.tmax[r] : INFINITY);
                 r = -1;
                 ++n_done;
                 hitnow = true;
@@ -314,6 +322,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
             bool missed = false;
             if (search) {
                 has = next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad);
+                if (has && R.tmax && sg.a >= R.tmax[r]) has = false;     // occlusion bound reached
                 if (!has) {
                     write_miss(out, r, nq, last_z0);
                     r = -1;
@@ -362,14 +371,15 @@ __global__ void __launch_bounds__(256) k_proxy(GridArgs G, RayArgs R, nif_hits o
         Trav tv;
         trav_init(P, ray, tv);
         Segment sg;
-        if (next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad)) {
+        const float tmax = R.tmax ? R.tmax[r] : INFINITY;
+        if (next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad) && sg.a < tmax) {
             const float3 x0 = deform_inv(P, ray_at(ray, sg.a));
             float z[16];
             for (int i = 0; i < 16; ++i) z[i] = 0.f;
             z[0] = 1.f;
             // the face normal enters the outputs as z_n; the distance head is 0 so D = t_in
             if (sg.face >= 0) z[2 + (sg.face >> 1)] = (sg.face & 1) ? 1.f : -1.f;
-            write_hit(out, r, sg, x0, x0, z, 1, 1, NIF_DIST_LOG_RELU);
+            write_hit(out, r, sg, x0, x0, z, 1, 1, NIF_DIST_LOG_RELU, tmax);
             if (out.ar) out.ar[r] = 0.f;
             if (out.ag) out.ag[r] = 0.f;
             if (out.ab) out.ab[r] = 0.f;
@@ -502,7 +512,7 @@ static GridArgs grid_args(const nif_grid* g) {
 static RayArgs ray_args(const nif_grid* g, const nif_rays* r, int64_t n) {
     RayArgs R;
     R.ox = r->ox; R.oy = r->oy; R.oz = r->oz; R.dx = r->dx; R.dy = r->dy; R.dz = r->dz;
-    R.off = r->pose_offsets; R.n_poses = g->n_poses; R.n = n;
+    R.off = r->pose_offsets; R.tmax = r->tmax; R.n_poses = g->n_poses; R.n = n;
     return R;
 }
 

@@ -28,12 +28,14 @@ def _grazing(orc, N, occ, kind, s, o, d):
     return orc.trace(N, occ, V, o, d, brute=N <= 16)[4] != 0
 
 
-def _compare(orc, P, m, tab_seen, prm, N, occ, kind, s, o, d, got, sl=slice(None)):
+def _compare(orc, P, m, tab_seen, prm, N, occ, kind, s, o, d, got, sl=slice(None), tmax=None, exclude=None):
     s64 = float(np.float32(s))
-    ref = orc.query(m, tab_seen, prm.astype(np.float64), N, occ, kind, s64, o, d)
+    ref = orc.query(m, tab_seen, prm.astype(np.float64), N, occ, kind, s64, o, d, tmax=tmax)
     graz = _grazing(orc, N, occ, kind, s64, o, d)
     amb = ref["margin"] < 1e-4
     ok = ~graz & ~amb
+    if exclude is not None:
+        ok &= ~exclude
     g = {k: v[sl] for k, v in got.items()}
     say(f"  rays {len(ok)}  grazing {int(graz.sum())}  ambiguous {int((amb & ~graz).sum())}  "
         f"hits {int(ref['hit'][ok].sum())}")
@@ -115,6 +117,42 @@ def test_query_torus16_ablation_switches(orc, P, variant):
     got = _np(grid.query(model, dev_f32(o), dev_f32(d), offsets([4096])))
     n_ok, n_hit = _compare(orc, P, m, seen, prm, w.N, occ, S.TWIST, 1.0, o, d, got)
     assert n_ok > 3500 and n_hit > 50
+
+
+def test_query_occlusion_tmax_matches_oracle(orc, P):
+    """Shadow-ray form: per-ray tmax bounds the walk and the hit; the bit alone (every other
+    output pointer null) equals the full query's.  Rays whose unbounded hit distance or any
+    voxel entry lies within 1e-4 of tmax are decided by rounding and are excluded."""
+    import torch
+    w = S.workload("torus16")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, [S.BEND], [1.0])
+    n = 4096
+    o, d = S.rays_random(n, w.seed + 2)
+    tmax = np.random.default_rng(w.seed + 3).uniform(1.0, 3.0, n).astype(np.float32)
+    say("query torus16 occlusion tmax")
+    got = _np(grid.query(model, dev_f32(o), dev_f32(d), offsets([n]), tmax=dev_f32(tmax)))
+    full = orc.query(m, seen, prm.astype(np.float64), w.N, occ, S.BEND, 1.0, o, d)
+    V = orc.lattice_vertices(S.BEND, 1.0, w.N)
+    _, tin, _, cnt, _ = orc.trace(w.N, occ, V, o, d, with_flags=False)
+    near = np.array([np.any(np.abs(tin[i, :cnt[i]] - tmax[i]) < 1e-4) for i in range(n)])
+    near |= np.abs(full["t"] - tmax) < 1e-4
+    n_ok, n_hit = _compare(orc, P, m, seen, prm, w.N, occ, S.BEND, 1.0, o, d, got, tmax=tmax.astype(np.float64),
+                           exclude=near)
+    cut = (full["hit"] == 1) & (full["t"] >= tmax)
+    say(f"  hits beyond tmax (reported as misses) {int(cut.sum())}")
+    assert n_ok > 3500 and n_hit > 100 and cut.sum() > 20
+    bit = torch.empty(n, dtype=torch.uint8, device="cuda")
+    hits = P.Hits(bit.data_ptr(), *([None] * (len(P.Hits._fields_) - 1)))
+    keep = (dev_f32(o), dev_f32(d), offsets([n]), dev_f32(tmax))
+    P.nif_query(model.h, grid.h, P.make_rays(*keep), n, hits, 0, 0, None)
+    torch.cuda.synchronize()
+    assert np.array_equal(bit.cpu().numpy(), got["hit"])
 
 
 def test_query_voxel_proxy_is_the_first_segment(orc, P):
