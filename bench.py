@@ -448,12 +448,22 @@ def render_leg(steps=1500, B=1 << 16, res=1024, reps=5):
     ph = P.hits_struct(pout)
     prays = P.make_rays(po, pd, off_p)
     timings = {}
-    for name, fn, n in (("primary", lambda: P.nif_query(model.h, grid.h, prays, n_p, ph, 0, 0, None), n_p),
-                        ("shadow", lambda: P.nif_query(model.h, grid.h, srays, n_h, shits, 0, 0, None), n_h),
-                        ("bounce", lambda: P.nif_query(model.h, grid.h, brays, n_h, bh, 0, 0, None), n_h)):
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for name, fn, n in (("primary", lambda: P.nif_query(model.h, grid.h, prays, n_p, ph, 0, 0, st), n_p),
+                        ("shadow", lambda: P.nif_query(model.h, grid.h, srays, n_h, shits, 0, 0, st), n_h),
+                        ("bounce", lambda: P.nif_query(model.h, grid.h, brays, n_h, bh, 0, 0, st), n_h)):
+        st.zero_()
         ms = timed(fn, reps, 2)
-        timings[name] = {"rays": n, "ms": ms, "rays_per_s": n / (ms * 1e-3)}
-        log(f"render {name}: {n} rays in {ms:.3f} ms")
+        evals = float(st[1]) / (reps + 2)
+        timings[name] = {"rays": n, "ms": ms, "rays_per_s": n / (ms * 1e-3), "network_evals": evals}
+        log(f"render {name}: {n} rays in {ms:.3f} ms, {evals:.0f} network evaluations")
+    full = grid.query(model, so, sdir, off_h, tmax=stmax)
+    nq = full["n_queried"].float()
+    timings["shadow"]["n_queried_mean_max"] = [float(nq.mean()), float(nq.max())]
+    nq = bout["n_queried"].float()
+    timings["bounce"]["n_queried_mean_max"] = [float(nq.mean()), float(nq.max())]
+    nq = pout["n_queried"].float()
+    timings["primary"]["n_queried_mean_max"] = [float(nq.mean()), float(nq.max())]
     # agreement with the labelled ground truth of the same rays
     gtp = _ground_truth(P, grid, po, pd, off_p, w.scene_kind, sp)
     gts = _ground_truth(P, grid, so, sdir, off_h, w.scene_kind, sp)

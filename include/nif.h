@@ -220,6 +220,11 @@ int nif_wall_clock_khz(int32_t* khz);
 /* Launch shape of the fused query: persistent one-wave workgroups per compute unit,
  * 1..32 (default 12).  Process-wide. */
 int nif_set_query_blocks_per_cu(int32_t blocks_per_cu);
+/* Rays each wave of the fused query walks at a time: 64, or 16 (one network pass of 16
+ * segments per round instead of four: shorter serial chains for launches too small to fill
+ * the GPU), or 0 = chosen from the launch size (16 below 8192 rays per compute unit).
+ * Process-wide; results do not depend on it. */
+int nif_set_query_rays_per_wave(int32_t rays_per_wave);
 
 /* ---------------------------------------------------------------- network on points
  * psi encoding of n rest-space points (SoA [3][n]) -> out[n][(1+2F) L feat_dim], FP32. */

@@ -102,7 +102,7 @@ def lib():
             "nif_grid_info": ([P, I32, P, P, P], C.c_int), "nif_grid_bounds": ([P, I32, P, P], C.c_int), "nif_grid_update": ([P, P, I32, P], C.c_int),
             "nif_trace": ([P, P, I64, I32, P, P], C.c_int),
             "nif_query": ([P, P, P, I64, P, U32, I32, P, P], C.c_int),
-            "nif_set_query_blocks_per_cu": ([I32], C.c_int),
+            "nif_set_query_blocks_per_cu": ([I32], C.c_int), "nif_set_query_rays_per_wave": ([I32], C.c_int),
             "nif_wall_clock_khz": ([C.POINTER(C.c_int32)], C.c_int),
             "nif_encode": ([P, P, I64, P, P], C.c_int),
             "nif_forward": ([P, P, P, I64, P, I32, P], C.c_int),
@@ -260,6 +260,11 @@ def nif_wall_clock_khz() -> int:
 
 def nif_set_query_blocks_per_cu(v: int):
     _check(lib().nif_set_query_blocks_per_cu(int(v)))
+
+
+def nif_set_query_rays_per_wave(v: int):
+    """0 = by launch size, else 16 or 64 rays per wave of the fused query."""
+    _check(lib().nif_set_query_rays_per_wave(int(v)))
 
 
 def nif_encode(model, x, n: int, out, stream=None):

@@ -295,6 +295,11 @@ int nif_set_query_blocks_per_cu(int32_t v) {
     return nif::set_query_blocks_per_cu(v);
 }
 
+int nif_set_query_rays_per_wave(int32_t v) {
+    REQUIRE(v == 0 || v == 16 || v == 64, "rays_per_wave must be 0, 16 or 64");
+    return nif::set_query_rays_per_wave(v);
+}
+
 int nif_encode(const nif_model* m, const float* x, int64_t n, float* out, nif_stream stream) {
     REQUIRE(m, "model is null");
     REQUIRE(n >= 0, "n must be >= 0");

@@ -233,12 +233,15 @@ __device__ __forceinline__ void unpark_trav(const Parked& pk, Trav& T) {
 #define NIF_QUERY_MIN_WAVES 2
 #endif
 
-template <int HW, int PREC>
+// RPW rays per wave (64, or 16 for launches too small to hide the latency of a network round:
+// then a round is one pass of 16 segments instead of four, and four times as many waves run).
+template <int HW, int PREC, int RPW>
 __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats,
                                               int pose_times) {
+    static_assert(RPW == 16 || RPW == 64, "rays per wave");
     constexpr int CB = kQueryCB;
-    constexpr int PASSES = 4 / CB;
+    constexpr int PASSES = RPW / 16 / CB;
     __shared__ int32_t s_park[QW_WORDS * 64];
     __shared__ float s_seg[64 * kSegStride];
     __shared__ float s_z[64 * kZStride];
@@ -295,7 +298,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
 
         // ---- give every lane a segment, taking new rays as old ones finish or miss
         for (;;) {
-            const bool need = !exhausted && r < 0;
+            const bool need = !exhausted && r < 0 && lane < RPW;
             const uint64_t m = ballot(need);
             if (m) {
                 const int leader = __ffsll((unsigned long long)m) - 1;
@@ -526,14 +529,24 @@ int trace_launch(const nif_grid* g, const nif_rays* r, int64_t n, int32_t max_se
 
 // Persistent grid size of the fused query: one-wave workgroups per compute unit (tunable).
 static int g_query_blocks_per_cu = 12;
+// Rays per wave: 0 = by launch size, else 16 or 64.
+static int g_query_rays_per_wave = 0;
+
+// Below this many rays per compute unit a launch is latency-bound (the serial chain of
+// network rounds of its longest rays sets the time), and 16-ray waves finish it sooner.
+static constexpr int64_t kSmallLaunchRaysPerCU = 8192;
 
 template <int HW, int PREC>
 static void launch_query(const NetParams& np, const GridArgs& G, const RayArgs& R, const nif_hits& out, int64_t* ctr,
                          int64_t* stats, int pt, hipStream_t st) {
-    const int64_t waves = (R.n + 63) / 64;
-    const int64_t blocks = std::min<int64_t>(waves, (int64_t)device_cus() * g_query_blocks_per_cu);
-    hipLaunchKernelGGL((k_query<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(64), 0, st, np, G, R, out, ctr,
-                       stats, pt);
+    int rpw = g_query_rays_per_wave;
+    if (rpw == 0) rpw = R.n < kSmallLaunchRaysPerCU * device_cus() ? 16 : 64;
+    const int64_t waves = (R.n + rpw - 1) / rpw;
+    const int64_t blocks = std::max<int64_t>(std::min<int64_t>(waves, (int64_t)device_cus() * g_query_blocks_per_cu), 1);
+    if (rpw == 16)
+        hipLaunchKernelGGL((k_query<HW, PREC, 16>), dim3((unsigned)blocks), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
+    else
+        hipLaunchKernelGGL((k_query<HW, PREC, 64>), dim3((unsigned)blocks), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
 }
 
 template <int PREC>
@@ -574,6 +587,11 @@ int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64
 
 int set_query_blocks_per_cu(int v) {
     g_query_blocks_per_cu = v;
+    return NIF_OK;
+}
+
+int set_query_rays_per_wave(int v) {
+    g_query_rays_per_wave = v;
     return NIF_OK;
 }
 

@@ -155,6 +155,33 @@ def test_query_occlusion_tmax_matches_oracle(orc, P):
     assert np.array_equal(bit.cpu().numpy(), got["hit"])
 
 
+def test_query_rays_per_wave_does_not_change_results(P):
+    """16-ray and 64-ray waves evaluate the same segments with the same arithmetic: every
+    output is bit-identical, for a small and a large launch of the sphere workload."""
+    import torch
+    w = S.workload("spheres64")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    tab, prm, _ = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    grid = P.Grid(occ, w.N, [S.TWIST, S.BEND], [0.7, 0.9])
+    for n in (3001, 300001):
+        o, d = S.rays_inside(n, w.seed + n)
+        off = offsets([n // 2, n - n // 2])
+        outs = []
+        for rpw in (16, 64, 0):
+            P.nif_set_query_rays_per_wave(rpw)
+            outs.append(_np(grid.query(model, dev_f32(o), dev_f32(d), off)))
+        P.nif_set_query_rays_per_wave(0)
+        say(f"rays per wave n={n}: hits {int(outs[0]['hit'].sum())}")
+        for k in outs[0]:
+            for other in outs[1:]:
+                assert np.array_equal(outs[0][k], other[k], equal_nan=True), k
+
+
 def test_query_voxel_proxy_is_the_first_segment(orc, P):
     import torch
     w = S.workload("torus16")
