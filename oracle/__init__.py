@@ -108,6 +108,16 @@ def jacdet(kind: int, s: float, p) -> np.ndarray:
     return out
 
 
+def deform_normal(kind: int, s: float, p, n) -> np.ndarray:
+    """Unit deformed-space normals (J^-1)^T n at rest points p (rows)."""
+    p = _aos(p).reshape(-1, 3); n = _aos(n).reshape(-1, 3)
+    out = np.empty_like(p)
+    for i in range(len(p)):
+        lib().orc_deform_normal(C.c_int(kind), C.c_double(s), _p(p[i], C.c_double), _p(n[i], C.c_double),
+                                _p(out[i], C.c_double))
+    return out
+
+
 def scene_f(kind: int, sp, p) -> np.ndarray:
     sp = _f64(sp); p = _aos(p).reshape(-1, 3)
     out = np.empty(len(p))
@@ -191,7 +201,8 @@ def forward(desc, tables, params, x0, x1, with_scale: bool = False):
 
 def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d, tmax=None) -> dict:
     """Per-ray first-hit outputs; for hits also zhit (raw heads of the hit segment) and
-    seginfo = (t_in, t_out, rest length, |cos| at entry, |cos| at exit) of that segment.
+    seginfo = (t_in, t_out, rest length, |cos| at entry, |cos| at exit) of that segment, and
+    dnormal, the normal carried to deformed space.
     tmax (per ray, optional): occlusion form, hits at D >= tmax and voxels entered at or
     beyond tmax do not count."""
     m = model_struct(desc)
@@ -202,7 +213,7 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d, tmax=Non
     r = dict(hit=np.zeros(n, np.uint8), t=np.zeros(n), xrest=np.zeros((n, 3)), normal=np.zeros((n, 3)),
              albedo=np.zeros((n, 3)), material=np.zeros(n, np.int32), cell=np.zeros(n, np.int32),
              logit=np.zeros(n), n_queried=np.zeros(n, np.int32), margin=np.zeros(n),
-             zhit=np.zeros((n, desc.n_heads)), seginfo=np.zeros((n, 5)))
+             zhit=np.zeros((n, desc.n_heads)), seginfo=np.zeros((n, 5)), dnormal=np.zeros((n, 3)))
     tm = None if tmax is None else np.ascontiguousarray(np.broadcast_to(np.asarray(tmax, np.float64), (n,)))
     lib().orc_query_batch(C.byref(m), _p(tab, C.c_double), _p(prm, C.c_double), C.c_int32(N),
                           _p(occ, C.c_uint8), C.c_int32(kind), C.c_double(s), C.c_int64(n),
@@ -212,7 +223,7 @@ def query(desc, tables, params, N: int, occ, kind: int, s: float, o, d, tmax=Non
                           _p(r["cell"], C.c_int32), _p(r["logit"], C.c_double),
                           _p(r["n_queried"], C.c_int32), _p(r["margin"], C.c_double),
                           _p(r["zhit"], C.c_double), _p(r["seginfo"], C.c_double),
-                          _p(tm, C.c_double) if tm is not None else None)
+                          _p(tm, C.c_double) if tm is not None else None, _p(r["dnormal"], C.c_double))
     return r
 
 

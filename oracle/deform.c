@@ -10,6 +10,11 @@
  *   twist: rotation about the z axis through the centre by theta = 0.6 s z radians;
  *   bend : circular bend in the x-z plane, curvature kappa = s / 1.5 (radius 1.5 at s=1);
  *   taper: x,y scaled about the centre by sigma(z) = 1 - 0.5 s z.
+ *
+ * Deformed-space normals (the network predicts rest-space normals; a renderer working in
+ * deformed space needs the normal of the deformed surface): a normal transforms with the
+ * inverse transpose of the Jacobian J = dD/dp at the rest point.  J is taken by central
+ * differences of D (step 1e-6, error ~1e-10), inverted with the adjugate formula.
  */
 #include <math.h>
 #include "oracle.h"
@@ -66,4 +71,36 @@ double orc_deform_jacdet(int kind, double s, const double p[3]) {
     if (kind == ORC_BEND) return 1.0 - (s / 1.5) * (p[0] - CX);
     if (kind == ORC_TAPER) { double sg = 1.0 - 0.5 * s * p[2]; return sg * sg; }
     return 1.0;
+}
+
+/* Unit normal of the deformed surface at D(p), from the rest-space normal n at p. */
+void orc_deform_normal(int kind, double s, const double p[3], const double n[3], double out[3]) {
+    const double h = 1e-6;
+    double J[3][3];
+    for (int c = 0; c < 3; ++c) {
+        double a[3] = {p[0], p[1], p[2]}, b[3] = {p[0], p[1], p[2]}, qa[3], qb[3];
+        a[c] += h; b[c] -= h;
+        orc_deform(kind, s, a, qa);
+        orc_deform(kind, s, b, qb);
+        for (int r = 0; r < 3; ++r) J[r][c] = (qa[r] - qb[r]) / (2.0 * h);
+    }
+    /* inverse by adjugate / determinant */
+    double A[3][3];
+    A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+    double v[3];
+    for (int r = 0; r < 3; ++r) {           /* (J^-1)^T n: row r of the transpose = column r of J^-1 */
+        v[r] = 0.0;
+        for (int k = 0; k < 3; ++k) v[r] += (A[k][r] / det) * n[k];
+    }
+    double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int r = 0; r < 3; ++r) out[r] = l > 0.0 ? v[r] / l : 0.0;
 }

@@ -264,6 +264,7 @@ void orc_forward_batch(const orc_model* m, const double* tables, const double* p
 /* First-hit query of n rays under one pose.  Per ray: hit, distance D along the ray,
    rest-space hit point, normal, albedo, material, voxel, hit logit, segments evaluated,
    and the smallest relative margin |z0| / scale among the evaluated segments.
+   dnrm (nullable): the normal carried to deformed space, (J^-1)^T n at the rest hit point.
    tmax (nullable, per ray): the occlusion form of the query used for shadow rays, the
    renderer integration the introduction and conclusion describe: voxels entered at
    t_in >= tmax are not visited, and a first hit at D >= tmax is a miss. */
@@ -271,7 +272,8 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
                      const uint8_t* occ, int32_t kind, double s, int64_t n, const double* o,
                      const double* d, uint8_t* hit, double* tout_ray, double* xrest, double* nrm,
                      double* alb, int32_t* mat, int32_t* cell_out, double* logit, int32_t* nq,
-                     double* margin, double* zhit, double* seginfo, const double* tmax) {
+                     double* margin, double* zhit, double* seginfo, const double* tmax,
+                     double* dnrm) {
     const int E = m->dims[0], H = m->dims[m->n_layers], M = m->n_materials;
     double* V = (double*)malloc(sizeof(double) * 3 * (size_t)(N + 1) * (N + 1) * (N + 1));
     orc_lattice_vertices(kind, s, N, V);
@@ -327,6 +329,7 @@ void orc_query_batch(const orc_model* m, const double* tables, const double* par
                 double nl = sqrt(z[2] * z[2] + z[3] * z[3] + z[4] * z[4]);
                 if (nl < 1e-12) nl = 1e-12;
                 for (int a = 0; a < 3; ++a) { nrm[3 * r + a] = z[2 + a] / nl; alb[3 * r + a] = sigmoid(z[5 + a]); }
+                if (dnrm) orc_deform_normal(kind, s, xrest + 3 * r, nrm + 3 * r, dnrm + 3 * r);
                 if (M == 1) mat[r] = z[8] > 0.0 ? 1 : 0;
                 else {
                     int best = 0;

@@ -37,6 +37,7 @@ typedef struct {
 void orc_deform(int kind, double s, const double p[3], double q[3]);
 void orc_deform_inv(int kind, double s, const double q[3], double p[3]);
 double orc_deform_jacdet(int kind, double s, const double p[3]);
+void orc_deform_normal(int kind, double s, const double p[3], const double n[3], double out[3]);
 
 /* scene.c */
 double orc_scene_f(int kind, const double* sp, const double p[3]);

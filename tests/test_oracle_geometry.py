@@ -84,6 +84,40 @@ def test_jacobian_determinant_matches_finite_differences(orc, kind):
     assert det.min() > 0.0                                  # orientation preserving on the cube
 
 
+@pytest.mark.parametrize("kind", KINDS)
+def test_deformed_normals_are_orthogonal_to_deformed_tangent_planes(orc, kind):
+    """The deformed normal is unit, orthogonal to the images of two rest tangents (taken by
+    deforming points of the rest tangent plane, not through the Jacobian) and on the side
+    that the image of the rest normal direction points to."""
+    rng = np.random.default_rng(11)
+    p = _cube_points(100, 4)
+    n = rng.normal(size=(100, 3)); n /= np.linalg.norm(n, axis=1, keepdims=True)
+    t1 = np.cross(n, rng.normal(size=(100, 3))); t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(n, t1)
+    nd = orc.deform_normal(kind, 1.0, p, n)
+    assert np.abs(np.linalg.norm(nd, axis=1) - 1).max() < 1e-12
+    e = 1e-4
+    for t in (t1, t2):
+        img = orc.deform(kind, 1.0, p + e * t) - orc.deform(kind, 1.0, p - e * t)
+        cos = np.abs((img * nd).sum(1)) / np.linalg.norm(img, axis=1)
+        assert cos.max() < 1e-7
+    out = orc.deform(kind, 1.0, p + e * n) - orc.deform(kind, 1.0, p)
+    assert ((out * nd).sum(1) > 0).all()
+
+
+def test_deformed_normals_on_the_twist_axis_are_rotated(orc):
+    """On the twist axis the Jacobian is the rotation by 0.6 z: normals turn by that angle."""
+    rng = np.random.default_rng(12)
+    z = rng.uniform(0, 1, 50)
+    p = np.stack([np.full(50, 0.5), np.full(50, 0.5), z], 1)
+    n = rng.normal(size=(50, 3)); n /= np.linalg.norm(n, axis=1, keepdims=True)
+    th = 0.6 * z
+    ref = np.stack([np.cos(th) * n[:, 0] - np.sin(th) * n[:, 1], np.sin(th) * n[:, 0] + np.cos(th) * n[:, 1],
+                    n[:, 2]], 1)
+    assert np.abs(orc.deform_normal(S.TWIST, 1.0, p, n) - ref).max() < 1e-9
+    assert np.abs(orc.deform_normal(S.IDENTITY, 0.0, p, n) - n).max() < 1e-9
+
+
 # ------------------------------------------------------------------ scenes, voxelization, labels
 
 def test_sphere_voxelization_is_subset_of_exact_interval_test(orc):
