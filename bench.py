@@ -470,7 +470,7 @@ def render_leg(steps=1500, B=1 << 16, res=1024, reps=5):
     occl_gt = gts["hit"] & (gts["t"] < stmax)
     lit = sbit == 0
     shade = torch.zeros(n_p, device="cuda")
-    nrm = torch.stack([prim["nx"], prim["ny"], prim["nz"]])[:, idx]
+    nrm = torch.stack([prim["dnx"], prim["dny"], prim["dnz"]])[:, idx]      # deformed-space normals
     alb = torch.stack([prim["ar"], prim["ag"], prim["ab"]])[:, idx].mean(0)
     shade[idx] = alb * (0.15 + 0.85 * lit.float() * (nrm * sdir).sum(0).abs())
     valid = gts["valid"]

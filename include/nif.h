@@ -203,6 +203,8 @@ int nif_trace(const nif_grid* grid, const nif_rays* rays, int64_t n_rays, int32_
 typedef struct {
     uint8_t* hit; float* t; float *nx, *ny, *nz; float *ar, *ag, *ab; int32_t* material;
     int32_t* cell; float* hit_logit; int32_t* n_queried; float *xr, *yr, *zr;
+    float *dnx, *dny, *dnz;     /* the normal carried to deformed space: (dD/dx)^-T n at the
+                                   rest hit point, normalized (for shading the posed surface) */
 } nif_hits;
 enum { NIF_Q_FIRST_HIT = 0, NIF_Q_NO_NETWORK = 8, NIF_Q_POSE_TIMES = 16 };
 /* flags: NIF_Q_FIRST_HIT, or NIF_Q_NO_NETWORK (the voxel proxy: first occupied voxel is

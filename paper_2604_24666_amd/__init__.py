@@ -62,7 +62,8 @@ class Hits(C.Structure):
     _fields_ = [("hit", C.c_void_p), ("t", C.c_void_p), ("nx", C.c_void_p), ("ny", C.c_void_p),
                 ("nz", C.c_void_p), ("ar", C.c_void_p), ("ag", C.c_void_p), ("ab", C.c_void_p),
                 ("material", C.c_void_p), ("cell", C.c_void_p), ("hit_logit", C.c_void_p),
-                ("n_queried", C.c_void_p), ("xr", C.c_void_p), ("yr", C.c_void_p), ("zr", C.c_void_p)]
+                ("n_queried", C.c_void_p), ("xr", C.c_void_p), ("yr", C.c_void_p), ("zr", C.c_void_p),
+                ("dnx", C.c_void_p), ("dny", C.c_void_p), ("dnz", C.c_void_p)]
 
 
 class Batch(C.Structure):
@@ -412,7 +413,8 @@ def alloc_hits(n, dev):
     return dict(hit=torch.empty(n, dtype=torch.uint8, device=dev), t=f(), nx=f(), ny=f(), nz=f(), ar=f(),
                 ag=f(), ab=f(), material=torch.empty(n, dtype=torch.int32, device=dev),
                 cell=torch.empty(n, dtype=torch.int32, device=dev), hit_logit=f(),
-                n_queried=torch.empty(n, dtype=torch.int32, device=dev), xr=f(), yr=f(), zr=f())
+                n_queried=torch.empty(n, dtype=torch.int32, device=dev), xr=f(), yr=f(), zr=f(),
+                dnx=f(), dny=f(), dnz=f())
 
 
 def hits_struct(out) -> Hits:

@@ -97,6 +97,40 @@ __device__ inline float3 deform_inv(const PoseDev& P, float3 q) {
     return p;
 }
 
+// Normal of the deformed surface at D(p) from the rest-space normal n at p: (dD/dp)^-T n,
+// normalized.  With the Jacobian's columns a, b, c, J^-T n is proportional to
+// n.x (b x c) + n.y (c x a) + n.z (a x b) (the cofactor rows; det J > 0 for every pose).
+__device__ inline float3 deform_normal(const PoseDev& P, float3 p, float3 n) {
+    float3 a = make_float3(1.f, 0.f, 0.f), b = make_float3(0.f, 1.f, 0.f), c = make_float3(0.f, 0.f, 1.f);
+    if (P.kind == DEF_TWIST) {
+        float sn, cs;
+        sincosf(P.k0 * p.z, &sn, &cs);
+        const float u = p.x - kCx, v = p.y - kCy;
+        a = make_float3(cs, sn, 0.f);
+        b = make_float3(-sn, cs, 0.f);
+        c = make_float3(P.k0 * (-sn * u - cs * v), P.k0 * (cs * u - sn * v), 1.f);
+    } else if (P.kind == DEF_BEND && P.k0 > 0.f) {
+        float sn, cs;
+        sincosf(P.k0 * (p.z - kCz), &sn, &cs);
+        const float w = 1.f - P.k0 * (p.x - kCx);
+        a = make_float3(cs, 0.f, -sn);
+        c = make_float3(sn * w, 0.f, cs * w);
+    } else if (P.kind == DEF_TAPER) {
+        const float sg = 1.f - P.k0 * p.z;
+        a = make_float3(sg, 0.f, 0.f);
+        b = make_float3(0.f, sg, 0.f);
+        c = make_float3(-P.k0 * (p.x - kCx), -P.k0 * (p.y - kCy), 1.f);
+    }
+    const float3 bc = make_float3(b.y * c.z - b.z * c.y, b.z * c.x - b.x * c.z, b.x * c.y - b.y * c.x);
+    const float3 ca = make_float3(c.y * a.z - c.z * a.y, c.z * a.x - c.x * a.z, c.x * a.y - c.y * a.x);
+    const float3 ab = make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+    float3 m = make_float3(n.x * bc.x + n.y * ca.x + n.z * ab.x, n.x * bc.y + n.y * ca.y + n.z * ab.y,
+                           n.x * bc.z + n.y * ca.z + n.z * ab.z);
+    const float l = sqrtf(m.x * m.x + m.y * m.y + m.z * m.z);
+    const float il = l > 0.f ? 1.f / l : 0.f;
+    return make_float3(m.x * il, m.y * il, m.z * il);
+}
+
 // ------------------------------------------------------------------ implicit scenes (FP32)
 enum { SCENE_TORUS = 0, SCENE_SPHERES = 1, SCENE_BLOBS = 2 };
 constexpr int kSceneStride = 8;

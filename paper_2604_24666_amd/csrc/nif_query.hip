@@ -127,13 +127,17 @@ __device__ __forceinline__ void write_miss(const nif_hits& o, int64_t r, int nq,
     if (o.xr) o.xr[r] = 0.f;
     if (o.yr) o.yr[r] = 0.f;
     if (o.zr) o.zr[r] = 0.f;
+    if (o.dnx) o.dnx[r] = 0.f;
+    if (o.dny) o.dny[r] = 0.f;
+    if (o.dnz) o.dnz[r] = 0.f;
 }
 
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.f / (1.f + expf(-v)); }
 
 // Writes the hit of segment sg; a hit at or beyond tmax is written as a miss instead.
 __device__ __forceinline__ void write_hit(const nif_hits& o, int64_t r, const Segment& sg, float3 x0, float3 x1,
-                                          const float* z, int nq, int n_mat, int dist_head, float tmax) {
+                                          const float* z, int nq, int n_mat, int dist_head, float tmax,
+                                          const PoseDev& P) {
     const float ex = x1.x - x0.x, ey = x1.y - x0.y, ez = x1.z - x0.z;
     float f;
     if (dist_head == NIF_DIST_SIGMOID) {
@@ -171,6 +175,13 @@ __device__ __forceinline__ void write_hit(const nif_hits& o, int64_t r, const Se
     if (o.xr) o.xr[r] = fmaf(f, ex, x0.x);
     if (o.yr) o.yr[r] = fmaf(f, ey, x0.y);
     if (o.zr) o.zr[r] = fmaf(f, ez, x0.z);
+    if (o.dnx || o.dny || o.dnz) {
+        const float3 xh = make_float3(fmaf(f, ex, x0.x), fmaf(f, ey, x0.y), fmaf(f, ez, x0.z));
+        const float3 dn = deform_normal(P, xh, make_float3(z[2] / nl, z[3] / nl, z[4] / nl));
+        if (o.dnx) o.dnx[r] = dn.x;
+        if (o.dny) o.dny[r] = dn.y;
+        if (o.dnz) o.dnz[r] = dn.z;
+    }
 }
 
 __device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t a, int64_t b, int64_t c) {
@@ -287,7 +298,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
                 sg.cell = pk.get(QW_CELL); sg.a = pk.getf(QW_A); sg.b = pk.getf(QW_B);
                 const float* my = s_seg + lane * kSegStride;
                 write_hit(out, r, sg, make_float3(my[0], my[1], my[2]), make_float3(my[4], my[5], my[6]), z, nq, n_mat,
-                          np.dist_head, R.tmax ? R.tmax[r] : INFINITY);
+                          np.dist_head, R.tmax ? R.tmax[r] : INFINITY, P);
                 r = -1;
                 ++n_done;
                 hitnow = true;
@@ -382,7 +393,7 @@ __global__ void __launch_bounds__(256) k_proxy(GridArgs G, RayArgs R, nif_hits o
             z[0] = 1.f;
             // the face normal enters the outputs as z_n; the distance head is 0 so D = t_in
             if (sg.face >= 0) z[2 + (sg.face >> 1)] = (sg.face & 1) ? 1.f : -1.f;
-            write_hit(out, r, sg, x0, x0, z, 1, 1, NIF_DIST_LOG_RELU, tmax);
+            write_hit(out, r, sg, x0, x0, z, 1, 1, NIF_DIST_LOG_RELU, tmax, P);
             if (out.ar) out.ar[r] = 0.f;
             if (out.ag) out.ag[r] = 0.f;
             if (out.ab) out.ab[r] = 0.f;

@@ -54,10 +54,12 @@ def _compare(orc, P, m, tab_seen, prm, N, occ, kind, s, o, d, got, sl=slice(None
     # a normal is z_n / |z_n|: its error grows as 1 / |z_n| for small predicted vectors
     zn = np.linalg.norm(ref["zhit"][h][:, 2:5], axis=1)
     zn_rms = np.sqrt(np.mean(zn ** 2)) if len(zn) else 1.0
+    dnrm = np.stack([g["dnx"], g["dny"], g["dnz"]], 1)
     errs = {"t": np.abs(g["t"][h] - ref["t"][h]), "xrest": np.abs(xr[h] - ref["xrest"][h]).max(1, initial=0),
             "normal": np.abs(nrm[h] - ref["normal"][h]).max(1, initial=0) * np.minimum(zn / zn_rms, 1.0),
+            "dnormal": np.abs(dnrm[h] - ref["dnormal"][h]).max(1, initial=0) * np.minimum(zn / zn_rms, 1.0),
             "albedo": np.abs(alb[h] - ref["albedo"][h]).max(1, initial=0)}
-    bounds = {"t": 2e-4, "xrest": 2e-4, "normal": 1e-2, "albedo": 5e-4}
+    bounds = {"t": 2e-4, "xrest": 2e-4, "normal": 1e-2, "dnormal": 1e-2, "albedo": 5e-4}
     for k, e in errs.items():
         if len(e):
             say(f"    {k:7s} p50 {np.quantile(e, .5):.2e}  p99 {np.quantile(e, .99):.2e}  max {e.max():.2e}")
