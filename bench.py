@@ -111,6 +111,33 @@ def cpu_baseline(ctx, sample_stride: int = 16):
                       f"FP64 oracle, {dt:.1f} s"}
 
 
+def tuned_query_shape(key: str, model, grid, rays, n: int, hits, precision: int = 0, cache_path=None):
+    """Launch shape for a workload `key` on this GPU architecture: read from the JSON cache
+    (NIF_TUNE_CACHE, default ~/.cache/nif_tune.json) or found by nif_autotune_query and
+    stored; applied process-wide.  Returns (workgroups per CU, rays per wave)."""
+    import torch
+
+    import paper_2604_24666_amd as P
+    path = cache_path or os.environ.get("NIF_TUNE_CACHE", os.path.expanduser("~/.cache/nif_tune.json"))
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    full = f"{arch}/{key}/prec{precision}"
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    if full in cache:
+        bpc, rpw = cache[full]["blocks_per_cu"], cache[full]["rays_per_wave"]
+        P.nif_set_query_blocks_per_cu(bpc)
+        P.nif_set_query_rays_per_wave(rpw)
+        return bpc, rpw
+    bpc, rpw, ms = P.nif_autotune_query(model, grid, rays, n, hits, precision)
+    cache[full] = {"blocks_per_cu": bpc, "rays_per_wave": rpw, "ms": ms, "n_rays": int(n)}
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    return bpc, rpw
+
+
 def timed(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -530,6 +557,8 @@ def batched_leg(replays=50, warmup=5):
     khz = P.nif_wall_clock_khz()
     res = {}
     for prec, name in ((1, "bf16"), (0, "fp32")):
+        shape = tuned_query_shape("blobs128_b", model.h, grid.h, rays, n, hits, prec)
+        torch.cuda.synchronize()
         s_cap = torch.cuda.Stream()
         call = lambda: P.nif_query(model.h, grid.h, rays, n, hits, P.Q_POSE_TIMES, prec, stats, stream=s_cap)
         with torch.cuda.stream(s_cap):
@@ -558,7 +587,8 @@ def batched_leg(replays=50, warmup=5):
         res[name] = {"rays_per_s": n / (ms * 1e-3), "ms_per_launch_median": ms,
                      "pose_latency_ms_p50": float(np.quantile(lat, 0.5)),
                      "pose_latency_ms_p99": float(np.quantile(lat, 0.99)),
-                     "hit_rate": float(out["hit"].float().mean().item())}
+                     "hit_rate": float(out["hit"].float().mean().item()),
+                     "launch_shape": {"blocks_per_cu": shape[0], "rays_per_wave": shape[1]}}
         log(f"batched leg {name}: {ms:.2f} ms per launch, pose latency p50 {res[name]['pose_latency_ms_p50']:.2f} "
             f"p99 {res[name]['pose_latency_ms_p99']:.2f} ms")
         del g
@@ -617,6 +647,9 @@ def main():
     def query():
         P.nif_query(model.h, grid.h, rays, n, hits, 0, args.precision, stats)
 
+    rebuild()
+    shape = tuned_query_shape(args.workload, model.h, grid.h, rays, n, hits, args.precision)
+    log(f"launch shape: {shape[0]} workgroups per CU, {shape[1]} rays per wave")
     for i in range(args.warmup):
         if not args.no_rebuild:
             rebuild()
@@ -658,6 +691,7 @@ def main():
         "config": {"workload": f"{args.workload}: 8 spheres at 64^3, 24 poses (twist/bend/taper x 8 strengths), "
                                f"24 x 1024^2 pinhole rays, 16-level 2^19 FP16 hash grid, F=6, MLP 832-64x3-12",
                    "rays_per_step": n, "poses": len(ctx["kinds"]), "grid_rebuilt_each_step": not args.no_rebuild},
+        "launch_shape": {"blocks_per_cu": shape[0], "rays_per_wave": shape[1], "chosen_by": "nif_autotune_query"},
         "query_kernel_ms": float(q_ms.mean()), "grid_rebuild_ms": float(b_ms.mean()),
         "network_evals_per_step": float(evals_per_launch), "hit_rate": hit_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -672,6 +706,8 @@ def main():
         cpu = cpu_baseline(ctx)
     del ctx, grid, model, out, hits, rays
     torch.cuda.empty_cache()
+    P.nif_set_query_blocks_per_cu(12)           # the legs below use the default launch shape
+    P.nif_set_query_rays_per_wave(0)            # unless they tune their own
     if "precision" in legs:
         res["precision_compare"] = precision_leg()
     if "train" in legs:

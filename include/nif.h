@@ -227,6 +227,17 @@ int nif_set_query_blocks_per_cu(int32_t blocks_per_cu);
  * the GPU), or 0 = chosen from the launch size (16 below 8192 rays per compute unit).
  * Process-wide; results do not depend on it. */
 int nif_set_query_rays_per_wave(int32_t rays_per_wave);
+/* Autotuner of the fused query's launch shape: runs nif_query on the caller's rays (flags 0,
+ * no stats) once to warm up and `reps` times timed with device events, for every pair of
+ * workgroups per CU in {4, 6, 8, 10, 12, 14, 16, 20, 24} and rays per wave in {16, 64}; keeps
+ * the fastest pair process-wide (as the two setters above would) and returns it in
+ * best[0] (workgroups per CU), best[1] (rays per wave), with its time per launch in
+ * *best_ms (nullable).  Outputs are those of the last launch (they do not depend on the
+ * shape).  Synchronises the stream; not for graph capture.  On an error the previous shape
+ * is kept. */
+int nif_autotune_query(const nif_model* model, const nif_grid* grid, const nif_rays* rays, int64_t n_rays,
+                       const nif_hits* out, int32_t precision, int32_t reps, int32_t* best, float* best_ms,
+                       nif_stream stream);
 
 /* ---------------------------------------------------------------- network on points
  * psi encoding of n rest-space points (SoA [3][n]) -> out[n][(1+2F) L feat_dim], FP32. */

@@ -104,6 +104,7 @@ def lib():
             "nif_trace": ([P, P, I64, I32, P, P], C.c_int),
             "nif_query": ([P, P, P, I64, P, U32, I32, P, P], C.c_int),
             "nif_set_query_blocks_per_cu": ([I32], C.c_int), "nif_set_query_rays_per_wave": ([I32], C.c_int),
+            "nif_autotune_query": ([P, P, P, I64, P, I32, I32, P, P, P], C.c_int),
             "nif_wall_clock_khz": ([C.POINTER(C.c_int32)], C.c_int),
             "nif_encode": ([P, P, I64, P, P], C.c_int),
             "nif_forward": ([P, P, P, I64, P, I32, P], C.c_int),
@@ -261,6 +262,17 @@ def nif_wall_clock_khz() -> int:
 
 def nif_set_query_blocks_per_cu(v: int):
     _check(lib().nif_set_query_blocks_per_cu(int(v)))
+
+
+def nif_autotune_query(model, grid, rays: Rays, n: int, hits: Hits, precision: int = 0, reps: int = 2,
+                       stream=None):
+    """Times the launch shapes of the fused query on these rays and keeps the fastest;
+    returns (workgroups per CU, rays per wave, ms per launch)."""
+    best = (C.c_int32 * 2)()
+    ms = C.c_float()
+    _check(lib().nif_autotune_query(model, grid, C.byref(rays), n, C.byref(hits), precision, reps, best,
+                                    C.byref(ms), _stream(stream)))
+    return int(best[0]), int(best[1]), float(ms.value)
 
 
 def nif_set_query_rays_per_wave(v: int):

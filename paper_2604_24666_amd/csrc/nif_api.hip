@@ -295,6 +295,19 @@ int nif_set_query_blocks_per_cu(int32_t v) {
     return nif::set_query_blocks_per_cu(v);
 }
 
+int nif_autotune_query(const nif_model* m, const nif_grid* g, const nif_rays* rays, int64_t n, const nif_hits* out,
+                       int32_t precision, int32_t reps, int32_t* best, float* best_ms, nif_stream stream) {
+    REQUIRE(g && m, "model and grid must not be null");
+    int rc = validate_rays(rays, n);
+    if (rc) return rc;
+    REQUIRE(out && best, "out and best must not be null");
+    REQUIRE(n >= 1, "n_rays must be >= 1");
+    REQUIRE(precision >= 0 && precision <= 2, "precision must be NIF_PREC_FP32, _BF16 or _FP16");
+    REQUIRE(reps >= 1 && reps <= 100, "reps must be in [1, 100]");
+    if (!m->params_set) return fail(NIF_E_STATE, "model parameters were never set");
+    return nif::autotune_query(m, g, rays, n, out, precision, reps, best, best_ms, S(stream));
+}
+
 int nif_set_query_rays_per_wave(int32_t v) {
     REQUIRE(v == 0 || v == 16 || v == 64, "rays_per_wave must be 0, 16 or 64");
     return nif::set_query_rays_per_wave(v);

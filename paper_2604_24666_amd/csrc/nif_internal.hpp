@@ -92,6 +92,8 @@ int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64
                  hipStream_t st);
 int set_query_blocks_per_cu(int v);
 int set_query_rays_per_wave(int v);
+int autotune_query(const nif_model* m, const nif_grid* g, const nif_rays* r, int64_t n, const nif_hits* out,
+                   int32_t precision, int32_t reps, int32_t* best, float* best_ms, hipStream_t st);
 int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st);
 int label_launch(int kind, const double* params_host, int32_t n_params, int force_march, const float* x0,
                  const float* x1, int64_t n, uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat,

@@ -606,6 +606,47 @@ int set_query_rays_per_wave(int v) {
     return NIF_OK;
 }
 
+// Times the fused query on the caller's rays for every launch shape of the search space
+// (workgroups per CU x rays per wave), keeps the fastest process-wide and reports it.
+int autotune_query(const nif_model* m, const nif_grid* g, const nif_rays* r, int64_t n, const nif_hits* out,
+                   int32_t precision, int32_t reps, int32_t* best, float* best_ms, hipStream_t st) {
+    static const int kBpc[] = {4, 6, 8, 10, 12, 14, 16, 20, 24};
+    static const int kRpw[] = {16, 64};
+    const int save_bpc = g_query_blocks_per_cu, save_rpw = g_query_rays_per_wave;
+    hipEvent_t e0, e1;
+    int rc = check_hip(hipEventCreate(&e0), "event");
+    if (rc) return rc;
+    if ((rc = check_hip(hipEventCreate(&e1), "event"))) { (void)hipEventDestroy(e0); return rc; }
+    float best_t = INFINITY;
+    int bb = save_bpc, br = save_rpw;
+    for (int rpw : kRpw) {
+        for (int bpc : kBpc) {
+            g_query_blocks_per_cu = bpc;
+            g_query_rays_per_wave = rpw;
+            if ((rc = query_launch(m, g, r, n, out, 0, precision, nullptr, st))) break;    // warm-up
+            if ((rc = check_hip(hipEventRecord(e0, st), "event record"))) break;
+            for (int i = 0; i < reps && !rc; ++i) rc = query_launch(m, g, r, n, out, 0, precision, nullptr, st);
+            if (rc) break;
+            if ((rc = check_hip(hipEventRecord(e1, st), "event record"))) break;
+            if ((rc = check_hip(hipEventSynchronize(e1), "event sync"))) break;
+            float ms = 0.f;
+            if ((rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed"))) break;
+            ms /= (float)reps;
+            if (ms < best_t) { best_t = ms; bb = bpc; br = rpw; }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_query_blocks_per_cu = rc ? save_bpc : bb;
+    g_query_rays_per_wave = rc ? save_rpw : br;
+    if (rc) return rc;
+    best[0] = bb;
+    best[1] = br;
+    if (best_ms) *best_ms = best_t;
+    return NIF_OK;
+}
+
 int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hipStream_t st) {
     if (n == 0) return NIF_OK;
     const NetParams np = make_net_params(m, NIF_PREC_FP32);

@@ -184,6 +184,38 @@ def test_query_rays_per_wave_does_not_change_results(P):
                 assert np.array_equal(outs[0][k], other[k], equal_nan=True), k
 
 
+def test_autotuner_picks_a_shape_of_its_space_and_keeps_results(P):
+    import torch
+    w = S.workload("torus16")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    tab, prm, _ = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    grid = P.Grid(occ, w.N, [S.TWIST, S.TAPER], [1.0, 0.5])
+    n = 20000
+    o, d = S.rays_random(n, w.seed + 5)
+    keep = (dev_f32(o), dev_f32(d), offsets([n // 3, n - n // 3]))
+    rays = P.make_rays(*keep)
+    ref = _np(grid.query(model, *keep))
+    out = P.alloc_hits(n, "cuda")
+    bpc, rpw, ms = P.nif_autotune_query(model.h, grid.h, rays, n, P.hits_struct(out), 0, 1)
+    say(f"autotuned: {bpc} workgroups per CU, {rpw} rays per wave, {ms:.3f} ms")
+    assert bpc in (4, 6, 8, 10, 12, 14, 16, 20, 24) and rpw in (16, 64) and 0 < ms < 1e3
+    got = _np(out)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k], equal_nan=True), k
+    again = _np(grid.query(model, *keep))
+    for k in ref:
+        assert np.array_equal(ref[k], again[k], equal_nan=True), k
+    with pytest.raises(P.NifError):
+        P.nif_autotune_query(model.h, grid.h, rays, n, P.hits_struct(out), 0, 0)
+    P.nif_set_query_blocks_per_cu(12)
+    P.nif_set_query_rays_per_wave(0)
+
+
 def test_query_voxel_proxy_is_the_first_segment(orc, P):
     import torch
     w = S.workload("torus16")
