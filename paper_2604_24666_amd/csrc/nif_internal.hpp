@@ -37,6 +37,10 @@ struct nif_model {
     std::vector<int64_t> wp_off, bp_off;// offsets in the padded working copies
     std::vector<int64_t> wt_off;        // transposed padded copy of layer i: [in][out_pad]
     int64_t n_mlp_pad = 0;
+    int64_t n_w0l = 0;                  // first-layer weights in the fused kernels' lane order
+    float* w0l_f32 = nullptr;           //   [HW/16][U][L/4][2][64 lanes][4], U = ceil(2S/4)
+    uint16_t* w0l_bf16 = nullptr;
+    __half* w0l_f16 = nullptr;
     // parameters
     float* tables = nullptr;            // FP32 master [L][T][Fd]
     __half* tables_h = nullptr;         // FP16 working copy (table_dtype == F16)

@@ -51,6 +51,38 @@ __global__ void k_sync_mlp(LayerMap lm, const float* __restrict__ src, float* __
     }
 }
 
+// First-layer weights in the order the fused kernels read them, so that each of a wave's
+// weight loads is one contiguous block (8 or 4 whole cache lines) instead of 64 scattered rows.
+// Lane (q, j) of MFMA block ob, at the u-th PE combination of its quarter (c = qU + u) and
+// level batch lb (levels 4lb .. 4lb+3), reads W0[ob 16 + j][c 2L + 8 lb + 4h + k] as element
+// k of half h; combinations past 2S are zero.
+__global__ void k_sync_w0l(const float* __restrict__ w0, int E, int HW, int U, int L, int n_comb,
+                           float* __restrict__ f32, uint16_t* __restrict__ bf16, __half* __restrict__ f16, int64_t n) {
+    const int NLB = L >> 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        const int k = (int)(r & 3); r >>= 2;
+        const int lane = (int)(r & 63); r >>= 6;
+        const int h = (int)(r & 1); r >>= 1;
+        const int lb = (int)(r % NLB); r /= NLB;
+        const int u = (int)(r % U); r /= U;
+        const int ob = (int)r;
+        const int q = lane >> 4, j = lane & 15;
+        const int c = q * U + u;
+        const float v = c < n_comb ? w0[(int64_t)(ob * 16 + j) * E + c * 2 * L + 8 * lb + 4 * h + k] : 0.f;
+        f32[i] = v;
+        bf16[i] = f2bf(v);
+        f16[i] = __float2half_rn(v);
+    }
+}
+
+static int sync_w0l(nif_model* m, hipStream_t st) {
+    const int L = m->desc.levels, HW = m->desc.hidden_width, n_comb = 2 * m->S, U = (n_comb + 3) >> 2;
+    hipLaunchKernelGGL(k_sync_w0l, dim3(256), dim3(256), 0, st, m->mlp_pad_f32 + m->wp_off[0], m->E, HW, U, L, n_comb,
+                       m->w0l_f32, m->w0l_bf16, m->w0l_f16, m->n_w0l);
+    return check_hip(hipGetLastError(), "k_sync_w0l");
+}
+
 static LayerMap layer_map(const nif_model* m) {
     LayerMap lm;
     memset(&lm, 0, sizeof(lm));
@@ -66,7 +98,8 @@ static LayerMap layer_map(const nif_model* m) {
 int model_sync_mlp(nif_model* m, hipStream_t st) {
     hipLaunchKernelGGL(k_sync_mlp, dim3(64, m->n_layers), dim3(256), 0, st, layer_map(m), m->mlp, m->mlp_pad_f32,
                        m->mlp_pad_bf16, m->mlp_pad_f16);
-    return check_hip(hipGetLastError(), "k_sync_mlp");
+    const int rc = check_hip(hipGetLastError(), "k_sync_mlp");
+    return rc ? rc : sync_w0l(m, st);
 }
 
 int model_sync_working(nif_model* m, hipStream_t st) {
@@ -75,9 +108,7 @@ int model_sync_working(nif_model* m, hipStream_t st) {
         int rc = check_hip(hipGetLastError(), "k_sync_tables");
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_sync_mlp, dim3(64, m->n_layers), dim3(256), 0, st, layer_map(m), m->mlp, m->mlp_pad_f32,
-                       m->mlp_pad_bf16, m->mlp_pad_f16);
-    return check_hip(hipGetLastError(), "k_sync_mlp");
+    return model_sync_mlp(m, st);
 }
 
 template <typename T>
@@ -117,6 +148,7 @@ int model_alloc(nif_model* m) {
     }
     m->n_mlp = off;
     m->n_mlp_pad = offp;
+    m->n_w0l = (int64_t)(d.hidden_width / 16) * ((2 * m->S + 3) / 4) * (d.levels / 4) * 2 * 64 * 4;
     int rc;
     if ((rc = dalloc(&m->tables, m->n_table, "tables"))) return rc;
     if (d.table_dtype == NIF_TABLE_F16 && (rc = dalloc(&m->tables_h, m->n_table, "fp16 tables"))) return rc;
@@ -124,6 +156,9 @@ int model_alloc(nif_model* m) {
     if ((rc = dalloc(&m->mlp_pad_f32, m->n_mlp_pad, "mlp f32"))) return rc;
     if ((rc = dalloc(&m->mlp_pad_bf16, m->n_mlp_pad, "mlp bf16"))) return rc;
     if ((rc = dalloc(&m->mlp_pad_f16, m->n_mlp_pad, "mlp f16"))) return rc;
+    if ((rc = dalloc(&m->w0l_f32, m->n_w0l, "first layer f32"))) return rc;
+    if ((rc = dalloc(&m->w0l_bf16, m->n_w0l, "first layer bf16"))) return rc;
+    if ((rc = dalloc(&m->w0l_f16, m->n_w0l, "first layer f16"))) return rc;
     if ((rc = dalloc(&m->s, 8, "s"))) return rc;
     if ((rc = dalloc(&m->g_tables, m->n_table, "table grads"))) return rc;
     if ((rc = dalloc(&m->g_mlp, m->n_mlp, "mlp grads"))) return rc;
@@ -144,7 +179,7 @@ void model_free(nif_model* m) {
     void* ps[] = {m->tables, m->tables_h, m->mlp, m->mlp_pad_f32, m->mlp_pad_bf16, m->mlp_pad_f16, m->s,
                   m->g_tables, m->g_mlp, m->g_s, m->m_tables, m->v_tables, m->m_mlp, m->v_mlp,
                   m->m_s, m->v_s, m->counters, m->dacc, m->tcount, m->zbuf, m->dz, m->acts, m->delta,
-                  m->enc, m->bwd_cnt, m->bwd_scan, m->bwd_key, m->bwd_val};
+                  m->enc, m->bwd_cnt, m->bwd_scan, m->bwd_key, m->bwd_val, m->w0l_f32, m->w0l_bf16, m->w0l_f16};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }

@@ -50,6 +50,7 @@ struct EncParams {
 struct NetParams {
     EncParams enc;
     const void* W[kMaxLayers];   // padded weights in the MLP precision, row-major [out][in]
+    const void* W0L;             // the first layer again, in lane order (see k_sync_w0l)
     const float* b[kMaxLayers];  // padded FP32 biases
     int32_t n_hidden;            // hidden layers
     int32_t E;                   // encoding width (both points)
@@ -400,7 +401,7 @@ template <int HW, int CB, int PREC, int LB>
 __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* s_seg, int seg_base, int lb, int le,
                                               floatx4 (&acc)[HW / 16][CB], float* enc_out, int64_t seg_g0,
                                               int64_t n_valid) {
-    static_assert(LB == 2 || LB == 4, "level batch");
+    static_assert(LB == 4, "level batch of the lane-ordered first-layer weights");
     constexpr int OB = HW / 16;
     constexpr int NF = 2 * LB;               // features per lane per batch
     const int lane = lane_id();
@@ -458,12 +459,14 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
             }
 #pragma unroll
             for (int ob = 0; ob < OB; ++ob) {
+                // lane-ordered weights: half h of this lane's 8 at wl + (h 64 + lane) 4
+                const size_t wl = (((size_t)ob * U + u) * (L >> 2) + (l0 >> 2)) * 512;
                 if constexpr (PREC == P_FP32) {
-                    const float* w = reinterpret_cast<const float*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0;
+                    const float* w = reinterpret_cast<const float*>(np.W0L) + wl + lane * 4;
                     float wf[NF];
 #pragma unroll
                     for (int h = 0; h < NF / 4; ++h) {
-                        const float4 wv = *reinterpret_cast<const float4*>(w + 4 * h);
+                        const float4 wv = *reinterpret_cast<const float4*>(w + h * 256);
                         wf[4 * h] = wv.x; wf[4 * h + 1] = wv.y; wf[4 * h + 2] = wv.z; wf[4 * h + 3] = wv.w;
                     }
 #pragma unroll
@@ -471,11 +474,10 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(wf[t], feat[cb][t], acc[ob][cb]);
                 } else {
-                    const shortx4* w = reinterpret_cast<const shortx4*>(
-                        reinterpret_cast<const uint16_t*>(np.W[0]) + (size_t)(ob * 16 + j) * E + e0);
+                    const uint16_t* w = reinterpret_cast<const uint16_t*>(np.W0L) + wl + lane * 4;
 #pragma unroll
                     for (int t = 0; t < NF / 4; ++t) {
-                        const shortx4 wa = w[t];
+                        const shortx4 wa = *reinterpret_cast<const shortx4*>(w + t * 256);
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) {
                             const shortx4 fb = pack4<PREC>(feat[cb][4 * t], feat[cb][4 * t + 1], feat[cb][4 * t + 2],

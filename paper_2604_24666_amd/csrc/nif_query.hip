@@ -510,6 +510,8 @@ NetParams make_net_params(const nif_model* m, int32_t precision) {
         else np.W[i] = m->mlp_pad_f16 + m->wp_off[i];
         np.b[i] = m->mlp_pad_f32 + m->bp_off[i];
     }
+    np.W0L = precision == NIF_PREC_FP32 ? (const void*)m->w0l_f32
+           : precision == NIF_PREC_BF16 ? (const void*)m->w0l_bf16 : (const void*)m->w0l_f16;
     np.n_hidden = d.hidden_layers;
     np.E = m->E;
     np.H = m->H;
