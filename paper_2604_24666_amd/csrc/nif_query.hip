@@ -260,7 +260,15 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
     const Parked pk{s_park, lane};
     const int n_mat = np.H - 8;
 
-    bool exhausted = false;
+    // Rays are dealt in 8 contiguous ranges, one per XCD: workgroups are dispatched to the
+    // XCDs round-robin, so workgroup b starts on range b mod 8 and the waves sharing an L2
+    // walk neighbouring rays (coherent rays touch the same table lines).  A wave whose range
+    // runs dry moves on to the next one, so the load still balances across the chip.
+    const int home = (int)(blockIdx.x & 7);
+    const int64_t span = (R.n + 7) / 8;
+    int cur = 0;                                   // ranges tried (wave-uniform); 8 = none left
+    int rid = home;
+    int64_t lo = std::min<int64_t>((int64_t)rid * span, R.n), hi = std::min<int64_t>(lo + span, R.n);
     int bad = 0;
     int64_t n_done = 0, n_eval = 0;
     if (pose_times && lane == 0) atomicMin((unsigned long long*)&stats[4], (unsigned long long)wall_clock64());
@@ -309,18 +317,17 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
 
         // ---- give every lane a segment, taking new rays as old ones finish or miss
         for (;;) {
-            const bool need = !exhausted && r < 0 && lane < RPW;
+            const bool need = cur < 8 && r < 0 && lane < RPW;
             const uint64_t m = ballot(need);
             if (m) {
                 const int leader = __ffsll((unsigned long long)m) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd((unsigned long long*)&counters[0], (unsigned long long)popc64(m));
+                if (lane == leader) base = atomicAdd((unsigned long long*)&counters[rid], (unsigned long long)popc64(m));
                 base = __shfl(base, leader);
                 if (need) {
-                    r = (int64_t)base + rank_below(m);
-                    if (r >= R.n) {
+                    r = lo + (int64_t)base + rank_below(m);
+                    if (r >= hi) {
                         r = -1;
-                        exhausted = true;
                     } else {
                         ray = load_ray(R, r);
                         pose = find_pose(R.off, R.n_poses, r);
@@ -330,9 +337,18 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
                         last_z0 = -INFINITY;
                     }
                 }
+                if (lo + (int64_t)base + popc64(m) >= hi) {       // this range is used up: next one
+                    ++cur;
+                    rid = (home + cur) & 7;
+                    lo = std::min<int64_t>((int64_t)rid * span, R.n);
+                    hi = std::min<int64_t>(lo + span, R.n);
+                }
             }
             const bool search = r >= 0 && !has;
-            if (!ballot(search)) break;
+            if (!ballot(search)) {
+                if (cur < 8 && ballot(r < 0 && lane < RPW)) continue;   // lanes still to fill
+                break;
+            }
             bool missed = false;
             if (search) {
                 has = next_segment(P, G.V, G.bin_start, G.bin_cells, G.N, ray, tv, sg, &bad);
@@ -585,7 +601,7 @@ int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64
         hipLaunchKernelGGL(k_proxy, dim3((unsigned)blocks), dim3(256), 0, st, G, R, *out, stats);
         return check_hip(hipGetLastError(), "k_proxy launch");
     }
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, m->counters, 4);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, m->counters, 8);
     const int pt = (flags & NIF_Q_POSE_TIMES) && stats ? 1 : 0;
     if (pt) hipLaunchKernelGGL(k_reset_pose_times, dim3(1), dim3(256), 0, st, stats, g->n_poses);
     int rc;
