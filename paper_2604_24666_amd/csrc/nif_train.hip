@@ -52,7 +52,7 @@ int model_reserve(nif_model* m, int64_t B) {
         const int64_t n_add = chunk * 2 * m->S * L * 8;
         const int64_t n_cnt = n_buckets * n_blk;
         const size_t sz[4] = {sizeof(int32_t) * (size_t)n_cnt,
-                              sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 2 + n_buckets),
+                              sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 3 + n_buckets),
                               sizeof(uint16_t) * (size_t)n_add, sizeof(float2) * (size_t)n_add};
         void** ptr[4] = {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val};
         for (int i = 0; i < 4; ++i)
@@ -422,6 +422,7 @@ struct EncBwdParams {
     uint16_t* key;       // additions: entry within the bucket
     float2* val;         // additions: value per feature
     int64_t cap;         // capacity of key / val
+    uint32_t* vmax;      // bits of the largest |value| of the chunk's additions (+inf if not finite)
 };
 
 
@@ -482,6 +483,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
     const int L = P.enc.L, n_comb = 2 * P.S;
     for (int i = tid; i < P.n_buckets; i += 256) s_h[i] = 0;
+    if (blockIdx.x == 0 && tid == 0) *P.vmax = 0u;
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
     const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
@@ -533,6 +535,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
             bd[t] = v.x; bd[t + 1] = v.y; bd[t + 2] = v.z; bd[t + 3] = v.w;
         }
         float dxa[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+        float vmx = 0.f;                       // largest |addition| of this lane (inf if not finite)
         for (int u = 0; 4 * u < n_comb; ++u) {
             const int c = 4 * u + q;
             const bool live = valid && c < n_comb;
@@ -570,8 +573,11 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
                         const float cw = corner_weight(wt, cc);
                         const int32_t slot = atomicAdd(&s_cur[l * P.NBL + (int)(idx[cc] >> P.SB)], 1);
                         if (slot < P.cap) {      // always true: the count pass saw the same additions
+                            const float v0 = cw * g0, v1 = cw * g1;
                             P.key[slot] = (uint16_t)(idx[cc] & kmask);
-                            P.val[slot] = make_float2(cw * g0, cw * g1);
+                            P.val[slot] = make_float2(v0, v1);
+                            const float a = fmaxf(fabsf(v0), fabsf(v1));
+                            vmx = (isfinite(v0) && isfinite(v1)) ? fmaxf(vmx, a) : INFINITY;
                         }
                         if (P.dx0) {
                             const size_t te = ((size_t)l << P.enc.log2T) + idx[cc];
@@ -606,6 +612,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
                 unsafeAtomicAdd(&P.dx0[a * P.B + seg], dxa[0][a]);
                 unsafeAtomicAdd(&P.dx1[a * P.B + seg], dxa[1][a]);
             }
+        for (int off = 32; off > 0; off >>= 1) vmx = fmaxf(vmx, __shfl_xor(vmx, off));
+        if (lane == 0 && vmx > 0.f) atomicMax(P.vmax, __float_as_uint(vmx));   // non-negative: bits order as values
     }
 }
 
@@ -707,9 +715,13 @@ __global__ void __launch_bounds__(1024) k_enc_bwd_parts(EncBwdParams P, const in
 // Block (i, w): part i of the work list, window w (4096 entries) of its bucket.  A bucket cut
 // into one part is added to the table gradient directly; parts of a bucket cut into several
 // add their nonzero window entries with atomics.
+// The window is summed in 64-bit fixed point with integer LDS atomics (several times the rate
+// of floating-point LDS atomics): with |value| < 2^e over the chunk and at most N additions,
+// the scale 2^s, s = 62 - e - ceil(log2 N), keeps every partial sum below 2^62 while the unit
+// is 2^-34 of the largest addition; the sum is exact in that unit and independent of order.
 __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const int32_t* __restrict__ total,
                                                         const int32_t* __restrict__ parts) {
-    __shared__ float s_acc[2 * 4096];
+    __shared__ unsigned long long s_acc[2 * 4096];
     const int i = blockIdx.x, w = blockIdx.y;
     if (i >= parts[P.n_buckets]) return;
     int lo = 0, hi = P.n_buckets - 1;                    // bucket b: parts[b] <= i < parts[b + 1]
@@ -720,7 +732,14 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     const int b = lo;
     const int n_parts = parts[b + 1] - parts[b], part = i - parts[b];
     const int wn = P.SB < 12 ? (1 << P.SB) : 4096;   // entries per window
-    for (int k = threadIdx.x; k < 2 * wn; k += 256) s_acc[k] = 0.f;
+    for (int k = threadIdx.x; k < 2 * wn; k += 256) s_acc[k] = 0ull;
+    const float vmax = __uint_as_float(*P.vmax);
+    const bool finite = isfinite(vmax);
+    int ev = 0;
+    if (vmax > 0.f && finite) (void)frexpf(vmax, &ev);          // vmax < 2^ev
+    int nb = 0;
+    while (nb < 40 && ((int64_t)1 << nb) < (int64_t)*total + 1) ++nb;
+    const int sc = 62 - ev - nb;
     __syncthreads();
     const int64_t b_start = P.cnt[(int64_t)b * P.n_blk];
     const int64_t b_end = b + 1 < P.n_buckets ? (int64_t)P.cnt[(int64_t)(b + 1) * P.n_blk] : (int64_t)*total;
@@ -755,8 +774,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
             if (key != cur) {
                 if ((int)(cur >> 12) == w) {
                     const int e = (int)(cur & 4095u);
-                    atomicAdd(&s_acc[2 * e], rx);
-                    atomicAdd(&s_acc[2 * e + 1], ry);
+                    atomicAdd(&s_acc[2 * e], (unsigned long long)llrint(ldexp((double)rx, sc)));
+                    atomicAdd(&s_acc[2 * e + 1], (unsigned long long)llrint(ldexp((double)ry, sc)));
                 }
                 cur = key;
                 rx = vv[2 * r];
@@ -768,18 +787,20 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
         }
         if ((int)(cur >> 12) == w) {
             const int e = (int)(cur & 4095u);
-            atomicAdd(&s_acc[2 * e], rx);
-            atomicAdd(&s_acc[2 * e + 1], ry);
+            atomicAdd(&s_acc[2 * e], (unsigned long long)llrint(ldexp((double)rx, sc)));
+            atomicAdd(&s_acc[2 * e + 1], (unsigned long long)llrint(ldexp((double)ry, sc)));
         }
     }
     __syncthreads();
     const int l = b / P.NBL, slice = b % P.NBL;
     float* g = P.g_tables + (((size_t)l << P.enc.log2T) + ((size_t)slice << P.SB) + (size_t)w * 4096) * 2;
+    // a non-finite addition poisons the window, so the step's finiteness check skips the update
+    auto value = [&](int k) { return finite ? (float)ldexp((double)(long long)s_acc[k], -sc) : NAN; };
     if (n_parts == 1) {
-        for (int k = threadIdx.x; k < 2 * wn; k += 256) g[k] += s_acc[k];
+        for (int k = threadIdx.x; k < 2 * wn; k += 256) g[k] += value(k);
     } else {
         for (int k = threadIdx.x; k < 2 * wn; k += 256)
-            if (s_acc[k] != 0.f) unsafeAtomicAdd(&g[k], s_acc[k]);
+            if (s_acc[k] != 0ull || !finite) unsafeAtomicAdd(&g[k], value(k));
     }
 }
 
@@ -965,6 +986,7 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     ep.n_buckets = m->desc.levels * ep.NBL;
     ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
     ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
+    ep.vmax = nullptr;
     const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
     const size_t lds = sizeof(int32_t) * (size_t)ep.n_buckets;
     for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
@@ -972,12 +994,13 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         ep.n = std::min<int64_t>(m->bwd_chunk, B - c0);
         const int64_t n_tiles = (ep.n + 15) / 16;
         ep.n_blk = (int32_t)((n_tiles + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock);
-        hipLaunchKernelGGL(k_enc_bwd_count, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep);
         const int64_t n_cnt = (int64_t)ep.n_buckets * ep.n_blk;
         const int n_chunks = (int)((n_cnt + 4095) / 4096);
         int32_t* sums = m->bwd_scan;
         int32_t* total = m->bwd_scan + n_chunks;
         int32_t* parts = total + 1;
+        ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
+        hipLaunchKernelGGL(k_enc_bwd_count, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep);
         hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, n_chunks, total);
         hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
