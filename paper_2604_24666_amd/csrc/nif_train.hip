@@ -511,14 +511,19 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
     for (int i = tid; i < P.n_buckets; i += 256) P.cnt[(int64_t)i * P.n_blk + blockIdx.x] = s_h[i];
 }
 
+// Block (x, y): the samples of tile group x, levels 2y and 2y + 1 only, so that a block
+// writes into the 2 NBL buckets of one level pair: the lines it leaves partly written at any
+// time stay few enough to complete in L2 before eviction.
 template <int HW>
 __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     constexpr int KQ = HW / 4;                 // MFMA k-steps: lane quarter q covers [q KQ, (q+1) KQ)
-    extern __shared__ int32_t s_cur[];         // [n_buckets]: this block's next output slot per bucket
+    extern __shared__ int32_t s_cur[];         // [2 NBL]: this block's next output slot per bucket
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
     const int L = P.enc.L, n_comb = 2 * P.S, E = P.E;
+    const int lp = (int)blockIdx.y * 2;        // first level of this block's pair
+    const int b0 = lp * P.NBL;                 // first bucket of the pair
     const uint32_t kmask = (1u << P.SB) - 1u;
-    for (int i = tid; i < P.n_buckets; i += 256) s_cur[i] = P.cnt[(int64_t)i * P.n_blk + blockIdx.x];
+    for (int i = tid; i < 2 * P.NBL; i += 256) s_cur[i] = P.cnt[(int64_t)(b0 + i) * P.n_blk + blockIdx.x];
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
     const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
@@ -546,7 +551,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
             // A operand row of lane (q, j): combination 4u + j/4, feature j%4 of the level pair
             const int ca = 4 * u + (j >> 2);
             const bool a_live = ca < n_comb;
-            for (int l0 = 0; l0 < L; l0 += 2) {
+            {
+                const int l0 = lp;
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                 const float* wrow = P.W0t + (size_t)(a_live ? ca * 2 * L + 2 * l0 + (j & 3) : 0) * HW + q * KQ;
 #pragma unroll
@@ -571,7 +577,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
 #pragma unroll
                     for (int cc = 0; cc < 8; ++cc) {
                         const float cw = corner_weight(wt, cc);
-                        const int32_t slot = atomicAdd(&s_cur[l * P.NBL + (int)(idx[cc] >> P.SB)], 1);
+                        const int32_t slot = atomicAdd(&s_cur[(l - lp) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
                         if (slot < P.cap) {      // always true: the count pass saw the same additions
                             const float v0 = cw * g0, v1 = cw * g1;
                             P.key[slot] = (uint16_t)(idx[cc] & kmask);
@@ -1004,11 +1010,13 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, n_chunks, total);
         hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
+        const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
+        const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL;
         switch (hw) {
-            case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
-            case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
-            case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
-            default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep); break;
+            case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, st, ep); break;
+            case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, st, ep); break;
+            case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, fg, dim3(256), lds_f, st, ep); break;
+            default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, fg, dim3(256), lds_f, st, ep); break;
         }
         hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, st, ep, total, parts);
         const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
