@@ -65,6 +65,8 @@ struct nif_model {
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
     uint16_t* bwd_key = nullptr;        // table-gradient additions: entry within the bucket
     float2* bwd_val = nullptr;          //                            value per feature
+    float* dw_part = nullptr;           // weight-gradient partial sums per K slice
+    int64_t dw_part_n = 0;              //   capacity in floats
     double* dacc = nullptr;             // [16] loss sums, loss scale, Adam bias corrections
     int64_t* tcount = nullptr;          // [16] positives, step, clean steps, flags
     int32_t step = 0;

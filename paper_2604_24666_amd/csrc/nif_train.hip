@@ -35,6 +35,34 @@ constexpr int kGrowInterval = 1000;
 constexpr int64_t kEncBwdChunk = 1 << 16;  // samples per count/fill/reduce round
 constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
 
+// Arguments of the weight-gradient kernels (k_dw_part, k_dw_sum).
+struct DwArgs {
+    const float* d; int dstride; int M_pad; int M_real;
+    const float* h; int hstride; int N;
+    int64_t B, Kc;
+    int n_cb, ks;                // column tiles of 64, K slices per chunk
+    float* part;                 // [slot][M_pad][N] then [slot][M_pad] bias sums
+    int64_t n_slots;
+};
+
+// Launch shape of one layer's weight gradient: about two blocks per compute unit.
+static DwArgs dw_shape(int M_pad, int N, int64_t B, int cus) {
+    DwArgs A;
+    memset(&A, 0, sizeof(A));
+    A.M_pad = M_pad; A.N = N; A.B = B;
+    A.n_cb = (N + 63) / 64;
+    A.ks = A.n_cb >= 4 ? 1 : 4 / A.n_cb;
+    const int n_cg = (A.n_cb + 3) / 4;
+    const int64_t target = 2LL * cus;
+    int64_t nch = std::max<int64_t>(1, (target + n_cg - 1) / n_cg);
+    A.Kc = std::max<int64_t>(16, (((B + nch - 1) / nch) + 15) / 16 * 16);
+    nch = (B + A.Kc - 1) / A.Kc;
+    A.n_slots = nch * A.ks;
+    return A;
+}
+
+static int64_t dw_part_floats(const DwArgs& A) { return A.n_slots * A.M_pad * ((int64_t)A.N + 1); }
+
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
     for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta, &m->enc})
@@ -70,6 +98,22 @@ int model_reserve(nif_model* m, int64_t B) {
             (void)hipGetLastError();
             return fail(NIF_E_OOM, "training scratch allocation failed");
         }
+    {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        int64_t need = 0;
+        for (int i = 0; i < m->n_layers; ++i) {
+            const bool out = i == m->n_layers - 1;
+            need = std::max(need, dw_part_floats(dw_shape(out ? 16 : (int)hw, m->dims[i], B, cus)));
+        }
+        if (m->dw_part) { (void)hipFree(m->dw_part); m->dw_part = nullptr; }
+        if (hipMalloc((void**)&m->dw_part, sizeof(float) * (size_t)need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(NIF_E_OOM, "weight-gradient scratch allocation failed");
+        }
+        m->dw_part_n = need;
+    }
     m->max_batch = B;
     return NIF_OK;
 }
@@ -305,80 +349,139 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
     }
 }
 
-// ------------------------------------------------------------------ weight gradients (MFMA)
-// gW[m][n] += sum over samples b of d[b][m] * h[b][n] (gW row stride ldw), gb[m] += sum d[b][m].
-// Block (sample split, 64-column tile): 32-sample K tiles of d and h are staged in LDS
-// transposed ([row][sample], sample contiguous) so that each lane reads its operand runs
-// with 128-bit LDS loads; the k index of v_mfma_f32_16x16x4f32 is permuted so that lane
-// quarter q covers samples [8q, 8q+8) of the tile.  Wave w owns row tiles 2w, 2w+1 (rows
-// < 128) and the four 16-column tiles; the block's sums are added with atomics.
-constexpr int kDwKt = 32;
 
-__global__ void __launch_bounds__(256) k_dw_gemm(const float* __restrict__ d, int dstride, int M_pad, int M_real,
-                                                 const float* __restrict__ h, int hstride, int N, int64_t B,
-                                                 int64_t Kc, float* __restrict__ gW, int ldw, float* __restrict__ gb) {
-    __shared__ float sA[128][kDwKt + 4];
-    __shared__ float sB[64][kDwKt + 4];
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
-    const int n0 = blockIdx.y * 64;
-    const int64_t k0 = (int64_t)blockIdx.x * Kc, k1 = std::min<int64_t>(B, k0 + Kc);
-    floatx4 acc[2][4];
+// Weight gradient dW = D^T H of one layer as K-sliced partial sums on MFMA, read straight
+// from the row-major [K][*] operands.  A wave owns MT 16-row tiles x 4 16-column tiles
+// (MT = M_pad / 16) with a permuted mapping that makes every operand fetch contiguous: MFMA
+// row r of tile mt is output row MT r + mt and column c of tile nt is output column
+// n0 + 4c + nt, so lane (q, j) reads D[k][MT j .. MT j + MT) and H[k][n0 + 4j .. + 4) of its
+// own k (one k per lane quarter q).  Block (x, y): K chunk x, column group y of 4 x 64
+// columns; when the layer has fewer than 4 column tiles, the spare waves take further
+// slices of the chunk.  Partials (and the bias sums of column group 0) go to a scratch slot
+// per (chunk, slice); k_dw_sum adds the slots into the gradient, without atomics.
+template <int MT>
+__global__ void __launch_bounds__(256) k_dw_part(DwArgs A) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    const int cb = A.ks > 1 ? w % A.n_cb : (int)blockIdx.y * 4 + w;      // column tile
+    const int sub = A.ks > 1 ? w / A.n_cb : 0;                           // K slice within the chunk
+    if (cb >= A.n_cb || sub >= A.ks) return;
+    const int64_t kc0 = (int64_t)blockIdx.x * A.Kc, kc1 = std::min<int64_t>(A.B, kc0 + A.Kc);
+    const int64_t ksz = (A.Kc + A.ks - 1) / A.ks;
+    const int64_t k0 = kc0 + sub * ksz, k1 = std::min<int64_t>(kc1, k0 + ksz);
+    const int n0 = cb * 64;
+    floatx4 acc[MT][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MT; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
-    for (int64_t kb = k0; kb < k1; kb += kDwKt) {
-        for (int i = tid; i < kDwKt * M_pad; i += 256) {
-            const int sm = i / M_pad, mm = i % M_pad;
-            sA[mm][sm] = kb + sm < k1 ? d[(kb + sm) * dstride + mm] : 0.f;
-        }
-        for (int i = tid; i < kDwKt * 64; i += 256) {
-            const int sm = i >> 6, nn = i & 63;
-            sB[nn][sm] = (kb + sm < k1 && n0 + nn < N) ? h[(kb + sm) * hstride + n0 + nn] : 0.f;
-        }
-        __syncthreads();
-        if (blockIdx.y == 0 && tid < M_pad)
-            for (int sm = 0; sm < kDwKt; ++sm) bsum += sA[tid][sm];
-        float bf[4][8];
+    float bs[MT];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float4 u0 = *reinterpret_cast<const float4*>(&sB[c * 16 + j][8 * q]);
-            const float4 u1 = *reinterpret_cast<const float4*>(&sB[c * 16 + j][8 * q + 4]);
-            bf[c][0] = u0.x; bf[c][1] = u0.y; bf[c][2] = u0.z; bf[c][3] = u0.w;
-            bf[c][4] = u1.x; bf[c][5] = u1.y; bf[c][6] = u1.z; bf[c][7] = u1.w;
+    for (int a = 0; a < MT; ++a) bs[a] = 0.f;
+    const bool ncol_ok = n0 + 4 * j + 3 < A.N;
+    for (int64_t kb = k0; kb < k1; kb += 4) {
+        const int64_t k = kb + q;
+        float av[MT], bv[4];
+        if (k < k1) {
+            const float* dr = A.d + k * A.dstride + MT * j;
+            if constexpr (MT >= 4) {
+#pragma unroll
+                for (int t = 0; t < MT; t += 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(dr + t);
+                    av[t] = v.x; av[t + 1] = v.y; av[t + 2] = v.z; av[t + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < MT; ++t) av[t] = dr[t];
+            }
+            const float* hr = A.h + k * A.hstride + n0 + 4 * j;
+            if (ncol_ok) {
+                const float4 v = *reinterpret_cast<const float4*>(hr);
+                bv[0] = v.x; bv[1] = v.y; bv[2] = v.z; bv[3] = v.w;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) bv[t] = n0 + 4 * j + t < A.N ? hr[t] : 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < MT; ++t) av[t] = 0.f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bv[t] = 0.f;
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int mt = 2 * w + a;
-            if (mt * 16 >= M_pad) continue;
-            const float4 v0 = *reinterpret_cast<const float4*>(&sA[mt * 16 + j][8 * q]);
-            const float4 v1 = *reinterpret_cast<const float4*>(&sA[mt * 16 + j][8 * q + 4]);
-            const float af[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        for (int a = 0; a < MT; ++a) {
+            bs[a] += av[a];
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(af[t], bf[c][t], acc[a][c]);
+            for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(av[a], bv[c], acc[a][c]);
         }
-        __syncthreads();
     }
+    const int64_t slot = (int64_t)blockIdx.x * A.ks + sub;
+    float* P = A.part + slot * A.M_pad * A.N;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int mt = 2 * w + a;
-        if (mt * 16 >= M_pad) continue;
+    for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int col = n0 + c * 16 + j;
-            if (col >= N) continue;
+        for (int r = 0; r < 4; ++r) {
+            const int row = MT * (4 * q + r) + a;
+            const int col = n0 + 4 * j;
+            float* dst = P + (int64_t)row * A.N + col;
+            if (ncol_ok) {
+                *reinterpret_cast<float4*>(dst) = make_float4(acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]);
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = mt * 16 + 4 * q + r;
-                if (row < M_real) unsafeAtomicAdd(&gW[(size_t)row * ldw + col], acc[a][c][r]);
+                for (int c = 0; c < 4; ++c)
+                    if (col + c < A.N) dst[c] = acc[a][c][r];
             }
         }
+    if (cb == 0) {             // bias: sum of D over the slice, rows MT j + a (lanes of one j sum their k)
+        float* pb = A.part + A.n_slots * A.M_pad * A.N + slot * A.M_pad;
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+            float v = bs[a];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (q == 0) pb[MT * j + a] = v;
+        }
     }
-    if (blockIdx.y == 0 && tid < M_real) unsafeAtomicAdd(&gb[tid], bsum);
 }
+
+// gW[m][n] += sum over slots of part[slot][m][n] (m < M_real), gb[m] likewise.  Block: 64
+// consecutive outputs x 4 groups of slots (the groups' sums meet in LDS).
+__global__ void __launch_bounds__(256) k_dw_sum(DwArgs A, float* __restrict__ gW, int ldw, float* __restrict__ gb) {
+    __shared__ float red[4][64];
+    const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t n_out = (int64_t)A.M_real * A.N;
+    const int64_t i = (int64_t)blockIdx.x * 64 + o;
+    const bool is_w = i < n_out, live = i < n_out + A.M_real;
+    const float* p = nullptr;
+    int64_t stride = 0;
+    if (is_w) {
+        p = A.part + (i / A.N) * A.N + i % A.N;
+        stride = (int64_t)A.M_pad * A.N;
+    } else if (live) {
+        p = A.part + A.n_slots * A.M_pad * A.N + (i - n_out);
+        stride = A.M_pad;
+    }
+    float s = 0.f;
+    if (live) {
+        int64_t t = g;
+        float s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        for (; t + 12 < A.n_slots; t += 16) {
+            s += p[t * stride];
+            s1 += p[(t + 4) * stride];
+            s2 += p[(t + 8) * stride];
+            s3 += p[(t + 12) * stride];
+        }
+        for (; t < A.n_slots; t += 4) s += p[t * stride];
+        s += s1 + s2 + s3;
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && live) {
+        const float v = red[0][o] + red[1][o] + red[2][o] + red[3][o];
+        if (is_w) gW[(i / A.N) * ldw + i % A.N] += v;
+        else gb[i - n_out] += v;
+    }
+}
+
 
 // ------------------------------------------------------------------ encoding backward
 // The table gradient is a scatter-add: every (sample, PE combination, level, corner) adds
@@ -398,7 +501,7 @@ __global__ void __launch_bounds__(256) k_dw_gemm(const float* __restrict__ d, in
 // lanes on the same level.  d enc = W0^T delta_0 is formed on MFMA in the same layout: the
 // 16 output rows of one step are (combination 4u + r/4, features of the level pair), so
 // lane (q, j) receives exactly the four d enc values of its own combination and sample.
-// dW0 comes from the stored encoding (k_dw_gemm).  Samples are processed in chunks so the
+// dW0 comes from the stored encoding (k_dw_part, k_dw_sum).  Samples are processed in chunks so the
 // addition buffer stays bounded.
 
 struct EncBwdParams {
@@ -519,7 +622,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     constexpr int KQ = HW / 4;                 // MFMA k-steps: lane quarter q covers [q KQ, (q+1) KQ)
     extern __shared__ int32_t s_cur[];         // [2 NBL]: this block's next output slot per bucket
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
-    const int L = P.enc.L, n_comb = 2 * P.S, E = P.E;
+    const int L = P.enc.L, n_comb = 2 * P.S;
     const int lp = (int)blockIdx.y * 2;        // first level of this block's pair
     const int b0 = lp * P.NBL;                 // first bucket of the pair
     const uint32_t kmask = (1u << P.SB) - 1u;
@@ -963,17 +1066,29 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     else rc = dispatch_mlp_bwd<P_FP16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     if (rc) return rc;
     // weight gradients of every layer (layer 0 from the stored encoding)
-    const int64_t Kc = 2048;
-    const unsigned ksplit = (unsigned)((B + Kc - 1) / Kc);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
     for (int i = 0; i < m->n_layers; ++i) {
         const bool out = i == m->n_layers - 1;
-        const float* dsrc = out ? m->dz : m->delta + (size_t)i * B * hw;
-        const int dstride = out ? 16 : hw;
-        const int M_pad = out ? 16 : hw, M_real = m->dims[i + 1];
-        const float* hin = i == 0 ? m->enc : m->acts + (size_t)(i - 1) * B * hw;
-        const int N = m->dims[i];
-        hipLaunchKernelGGL(k_dw_gemm, dim3(ksplit, (unsigned)((N + 63) / 64)), dim3(256), 0, st, dsrc, dstride, M_pad,
-                           M_real, hin, N, N, B, Kc, m->g_mlp + m->w_off[i], N, m->g_mlp + m->b_off[i]);
+        DwArgs A = dw_shape(out ? 16 : hw, m->dims[i], B, cus);
+        A.d = out ? m->dz : m->delta + (size_t)i * B * hw;
+        A.dstride = out ? 16 : hw;
+        A.M_real = m->dims[i + 1];
+        A.h = i == 0 ? m->enc : m->acts + (size_t)(i - 1) * B * hw;
+        A.hstride = m->dims[i];
+        A.part = m->dw_part;
+        if (dw_part_floats(A) > m->dw_part_n) return fail(NIF_E_STATE, "weight-gradient scratch too small");
+        const dim3 grid((unsigned)((B + A.Kc - 1) / A.Kc), (unsigned)(A.ks > 1 ? 1 : (A.n_cb + 3) / 4));
+        switch (A.M_pad / 16) {
+            case 1: hipLaunchKernelGGL(k_dw_part<1>, grid, dim3(256), 0, st, A); break;
+            case 2: hipLaunchKernelGGL(k_dw_part<2>, grid, dim3(256), 0, st, A); break;
+            case 4: hipLaunchKernelGGL(k_dw_part<4>, grid, dim3(256), 0, st, A); break;
+            default: hipLaunchKernelGGL(k_dw_part<8>, grid, dim3(256), 0, st, A); break;
+        }
+        const int64_t n_out = (int64_t)A.M_real * A.N + A.M_real;
+        hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((n_out + 63) / 64)), dim3(256), 0, st, A,
+                           m->g_mlp + m->w_off[i], A.N, m->g_mlp + m->b_off[i]);
     }
     // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
     EncBwdParams ep;
