@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 KQUERY_SOURCES = ["csrc/nif_query.hip", "csrc/nif_net.hpp", "csrc/nif_trace.hpp", "csrc/nif_device.hpp",
                   "csrc/nif_internal.hpp", "build.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "ef32949a6190a51f12b9f6dc5fa50fb8a8c47a1779e7394a495445a50c7005b4",
-    "fetch_kib": 1.1497e8, "write_kib": 1.70192e6,          # per k_query<64, FP32> launch, default workload
+    "sources_sha256": "07225ae642504d172bee8dd4b13b8801b599994db96136b1bf2da77b38bc77eb",
+    "fetch_kib": 1.11824e8, "write_kib": 1.96452e6,         # per k_query<64, FP32, 64> launch, default workload
     "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
 }
 
