@@ -70,6 +70,26 @@ def test_fp32_heads_match_oracle(orc, P, name):
         assert e.max() <= 1e-5
 
 
+def test_fp32_heads_at_the_training_batch_size_sampled(orc, P):
+    """The training forward's size and model (B = 2^18 point pairs, MLP 832-128x4-12): every
+    head of 1500 sampled rows against the oracle, to the FP32 bar."""
+    m = S.workload("blobs128").model
+    tab, prm, seen = model_params(m, 23, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    B = 1 << 18
+    x0, x1 = _points(B, 24)
+    got = model.forward(dev_f32(x0), dev_f32(x1), P.PREC_FP32).cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(25).choice(B, 1500, replace=False))
+    idx[-1] = B - 1                                   # the last row of the last tile
+    ref = orc.forward(m, seen, prm.astype(np.float64), x0[:, idx].T.astype(np.float64),
+                      x1[:, idx].T.astype(np.float64))
+    rms = np.sqrt(np.mean(ref ** 2, axis=0, keepdims=True))
+    e = np.abs(got[idx] - ref) / np.maximum(np.abs(ref), rms)
+    say(f"forward fp32 blobs128 B={B} sampled: max rel err {e.max():.3e}")
+    assert e.max() <= 1e-5
+
+
 @pytest.mark.parametrize("prec,p99", [(1, 3e-2), (2, 4e-3)])
 @pytest.mark.parametrize("name", ["spheres64_p", "spheres64"])
 def test_low_precision_heads_error_per_head(orc, P, name, prec, p99):

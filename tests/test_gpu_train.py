@@ -201,14 +201,15 @@ def test_train_step_rejects_oversized_batches(P):
         _train_step(P, model, _batch(m, 65, 1), 65)
 
 
-def test_backward_over_several_chunks_is_additive(P):
-    """A batch larger than one table-gradient round (2^16 samples): the gradient of the whole
-    batch equals the gradient of its two halves accumulated (the sum is linear in the samples),
-    within FP32 summation-order error."""
+@pytest.mark.parametrize("B", [(1 << 16) + 4321, 1 << 18])
+def test_backward_over_several_chunks_is_additive(P, B):
+    """Batches larger than one table-gradient round (2^16 samples), up to the training batch of
+    the benchmark (2^18, four rounds): the gradient of the whole batch equals the gradient of its
+    two halves accumulated (the sum is linear in the samples), within FP32 summation-order
+    error."""
     import torch
     m = MODELS["blobs128"]
     tab, prm, _ = model_params(m, 11, scale_tables=300.0)
-    B = (1 << 16) + 4321
     x0, x1, hit, t, nr, al, mt = _batch(m, B, 12)
     rng = np.random.default_rng(13)
     dz = rng.normal(size=(B, m.n_heads)).astype(np.float32)
