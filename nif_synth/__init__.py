@@ -18,7 +18,7 @@ from typing import List
 import numpy as np
 
 # Deformation kinds; the numeric values are the ones the C interfaces use.
-IDENTITY, TWIST, BEND, TAPER = 0, 1, 2, 3
+IDENTITY, TWIST, BEND, TAPER, TWIST_BEND = 0, 1, 2, 3, 4
 # Scene kinds (implicit-surface families).
 SCENE_TORUS, SCENE_SPHERES, SCENE_BLOBS = 0, 1, 2
 # Table storage types.

@@ -9,7 +9,9 @@
  * s in [0, 1] per pose:
  *   twist: rotation about the z axis through the centre by theta = 0.6 s z radians;
  *   bend : circular bend in the x-z plane, curvature kappa = s / 1.5 (radius 1.5 at s=1);
- *   taper: x,y scaled about the centre by sigma(z) = 1 - 0.5 s z.
+ *   taper: x,y scaled about the centre by sigma(z) = 1 - 0.5 s z;
+ *   twist-bend: the twist followed by the bend, both at strength s (a composed pose: the
+ *   method only needs D and its inverse, so compositions are poses like any other).
  *
  * Deformed-space normals (the network predicts rest-space normals; a renderer working in
  * deformed space needs the normal of the deformed surface): a normal transforms with the
@@ -24,6 +26,12 @@
 #define CZ 0.5
 
 void orc_deform(int kind, double s, const double p[3], double q[3]) {
+    if (kind == ORC_TWIST_BEND) {
+        double t[3];
+        orc_deform(ORC_TWIST, s, p, t);
+        orc_deform(ORC_BEND, s, t, q);
+        return;
+    }
     q[0] = p[0]; q[1] = p[1]; q[2] = p[2];
     if (kind == ORC_TWIST) {
         double th = 0.6 * s * p[2];
@@ -46,6 +54,12 @@ void orc_deform(int kind, double s, const double p[3], double q[3]) {
 }
 
 void orc_deform_inv(int kind, double s, const double q[3], double p[3]) {
+    if (kind == ORC_TWIST_BEND) {
+        double t[3];
+        orc_deform_inv(ORC_BEND, s, q, t);
+        orc_deform_inv(ORC_TWIST, s, t, p);
+        return;
+    }
     p[0] = q[0]; p[1] = q[1]; p[2] = q[2];
     if (kind == ORC_TWIST) {
         double th = 0.6 * s * q[2];       /* z is unchanged, so the angle is known */
@@ -68,6 +82,11 @@ void orc_deform_inv(int kind, double s, const double q[3], double p[3]) {
 }
 
 double orc_deform_jacdet(int kind, double s, const double p[3]) {
+    if (kind == ORC_TWIST_BEND) {                 /* det of a product: twist (1) times bend at twist(p) */
+        double t[3];
+        orc_deform(ORC_TWIST, s, p, t);
+        return orc_deform_jacdet(ORC_TWIST, s, p) * orc_deform_jacdet(ORC_BEND, s, t);
+    }
     if (kind == ORC_BEND) return 1.0 - (s / 1.5) * (p[0] - CX);
     if (kind == ORC_TAPER) { double sg = 1.0 - 0.5 * s * p[2]; return sg * sg; }
     return 1.0;

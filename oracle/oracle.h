@@ -16,6 +16,7 @@
 #define ORC_TWIST 1
 #define ORC_BEND 2
 #define ORC_TAPER 3
+#define ORC_TWIST_BEND 4
 
 #define ORC_SCENE_TORUS 0
 #define ORC_SCENE_SPHERES 1

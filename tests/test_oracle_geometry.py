@@ -7,7 +7,7 @@ import pytest
 
 import nif_synth as S
 
-KINDS = [S.TWIST, S.BEND, S.TAPER]
+KINDS = [S.TWIST, S.BEND, S.TAPER, S.TWIST_BEND]
 
 
 def _cube_points(n=4000, seed=0):
@@ -30,6 +30,23 @@ def test_zero_strength_is_identity(orc, kind):
     p = _cube_points()
     assert np.array_equal(orc.deform(kind, 0.0, p), p)
     assert np.array_equal(orc.deform_inv(kind, 0.0, p), p)
+
+
+def test_twist_bend_is_the_bend_on_the_twist_axis_and_keeps_the_twist_radius_at_zero_bend(orc):
+    """Points on the twist axis are fixed by the twist, so the composed pose moves them as the
+    bend alone; the composed pose also preserves every rest point's distance to the axis
+    through the image of the vertical axis (twist: rotation, bend: isometric per fibre)."""
+    z = np.linspace(0.0, 1.0, 41)
+    p = np.stack([np.full_like(z, 0.5), np.full_like(z, 0.5), z], 1)
+    for s in (0.3, 1.0):
+        assert np.abs(orc.deform(S.TWIST_BEND, s, p) - orc.deform(S.BEND, s, p)).max() < 1e-15
+    q = _cube_points(300, 5)
+    tb = orc.deform(S.TWIST_BEND, 1.0, q)
+    # undoing the bend leaves the twisted point: same height and radius about the axis
+    t = orc.deform_inv(S.BEND, 1.0, tb)
+    assert np.abs(t[:, 2] - q[:, 2]).max() < 1e-12
+    r0 = np.hypot(q[:, 0] - 0.5, q[:, 1] - 0.5)
+    assert np.abs(np.hypot(t[:, 0] - 0.5, t[:, 1] - 0.5) - r0).max() < 1e-12
 
 
 def test_twist_preserves_height_and_radius_and_turns_by_0p6z(orc):
@@ -279,7 +296,7 @@ def test_identity_pose_hit_lists_equal_textbook_dda(orc):
     assert compared > 700
 
 
-@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 1.0), (S.BEND, 0.3)])
+@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 1.0), (S.BEND, 0.3), (S.TWIST_BEND, 1.0)])
 def test_walk_equals_brute_force_on_small_lattices(orc, kind, s):
     w = S.workload("torus16")
     sp = S.scene_params(w.scene_kind, w.seed)
