@@ -52,9 +52,11 @@ typedef void* nif_stream;
  * inverse deformation).  Kinds and strength s in [0, 1]; pivot at the cube centre c:
  *   TWIST: rotation about the z axis through c by 0.6 s z radians;
  *   BEND : circular bend in the x-z plane with curvature s / 1.5;
- *   TAPER: x, y scaled about c by 1 - 0.5 s z.
+ *   TAPER: x, y scaled about c by 1 - 0.5 s z;
+ *   TWIST_BEND: the twist followed by the bend, both at strength s (a composed pose).
  */
-enum { NIF_DEFORM_IDENTITY = 0, NIF_DEFORM_TWIST = 1, NIF_DEFORM_BEND = 2, NIF_DEFORM_TAPER = 3 };
+enum { NIF_DEFORM_IDENTITY = 0, NIF_DEFORM_TWIST = 1, NIF_DEFORM_BEND = 2, NIF_DEFORM_TAPER = 3,
+       NIF_DEFORM_TWIST_BEND = 4 };
 typedef struct { int32_t kind; float strength; } nif_pose;
 
 /* ---------------------------------------------------------------- model

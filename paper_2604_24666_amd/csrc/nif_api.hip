@@ -201,7 +201,7 @@ int nif_build_grid(const uint8_t* occ, int32_t N, const nif_pose* poses, int32_t
     REQUIRE(bins_per_axis >= 0 && bins_per_axis <= 4096, "bins_per_axis must be in [0, 4096]");
     REQUIRE(out, "out is null");
     for (int p = 0; p < n_poses; ++p) {
-        REQUIRE(poses[p].kind >= 0 && poses[p].kind <= 3, "unknown deformation kind");
+        REQUIRE(poses[p].kind >= 0 && poses[p].kind <= 4, "unknown deformation kind");
         REQUIRE(poses[p].strength >= 0.f && poses[p].strength <= 1.f, "pose strength must be in [0, 1]");
     }
     nif_grid* g = new nif_grid();
@@ -226,7 +226,7 @@ int nif_grid_update(nif_grid* g, const nif_pose* poses, int32_t n_poses, nif_str
     REQUIRE(g, "grid is null");
     REQUIRE(poses && n_poses == g->n_poses, "n_poses must equal the grid's pose count");
     for (int p = 0; p < n_poses; ++p) {
-        REQUIRE(poses[p].kind >= 0 && poses[p].kind <= 3, "unknown deformation kind");
+        REQUIRE(poses[p].kind >= 0 && poses[p].kind <= 4, "unknown deformation kind");
         REQUIRE(poses[p].strength >= 0.f && poses[p].strength <= 1.f, "pose strength must be in [0, 1]");
     }
     return nif::grid_update(g, poses, S(stream));

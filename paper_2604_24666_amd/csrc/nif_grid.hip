@@ -310,7 +310,7 @@ static void set_pose_params(std::vector<PoseDev>& P, const nif_pose* poses) {
     for (size_t p = 0; p < P.size(); ++p) {
         P[p].kind = poses[p].kind;
         P[p].s = poses[p].strength;
-        pose_constants(P[p].kind, P[p].s, &P[p].k0, &P[p].k1);
+        pose_constants(P[p].kind, P[p].s, &P[p].k0, &P[p].k1, &P[p].k2);
     }
 }
 

@@ -93,7 +93,7 @@ def test_voxelization_matches_oracle(orc, P, name, N):
 
 
 @pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 1.0), (S.IDENTITY, 0.0),
-                                    (S.BEND, 0.05), (S.TWIST, 0.37)])
+                                    (S.BEND, 0.05), (S.TWIST, 0.37), (S.TWIST_BEND, 1.0), (S.TWIST_BEND, 0.4)])
 def test_hit_lists_torus16(orc, P, kind, s):
     w = S.workload("torus16")
     sp = S.scene_params(w.scene_kind, w.seed)
@@ -107,7 +107,7 @@ def test_hit_lists_torus16(orc, P, kind, s):
     assert n_seg > 2000
 
 
-@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 0.625), (S.TAPER, 1.0)])
+@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 0.625), (S.TAPER, 1.0), (S.TWIST_BEND, 0.8)])
 def test_hit_lists_spheres64_sampled(orc, P, kind, s):
     w = S.workload("spheres64")
     sp = S.scene_params(w.scene_kind, w.seed)

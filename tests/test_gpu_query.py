@@ -75,7 +75,7 @@ def _np(out):
             for k, v in out.items()}
 
 
-@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 0.5)])
+@pytest.mark.parametrize("kind,s", [(S.TWIST, 1.0), (S.BEND, 1.0), (S.TAPER, 0.5), (S.TWIST_BEND, 1.0)])
 def test_query_torus16_fp32(orc, P, kind, s):
     import torch
     w = S.workload("torus16")
