@@ -42,6 +42,7 @@ class ModelDesc:
     hidden_layers: int
     n_materials: int
     dist_head: int = DIST_LOG_RELU
+    per_sample_tables: int = 0           # 1: one table set per PE sample
 
     @property
     def n_samples(self) -> int:          # 1 + 2F positional-encoding samples per point
@@ -67,6 +68,10 @@ class ModelDesc:
     @property
     def table_size(self) -> int:
         return 1 << self.log2_table
+
+    @property
+    def table_levels(self) -> int:       # table sets x levels: the first axis of the tables
+        return self.levels * (self.n_samples if self.per_sample_tables else 1)
 
 
 def level_resolutions(levels: int, n_min: int, n_max: int) -> List[int]:
@@ -245,9 +250,9 @@ def uneven_counts(n_poses: int, seed: int, lo: int = 65536, hi: int = 1048576):
 # ----------------------------------------------------------------------------- weights
 
 def init_tables(m: ModelDesc, seed: int) -> np.ndarray:
-    """FP32 master tables [L][T][Fd], uniform in (-1e-4, 1e-4)."""
+    """FP32 master tables [sets x L][T][Fd], uniform in (-1e-4, 1e-4)."""
     rng = np.random.default_rng(seed)
-    return rng.uniform(-1e-4, 1e-4, size=(m.levels, m.table_size, m.feat_dim)).astype(np.float32)
+    return rng.uniform(-1e-4, 1e-4, size=(m.table_levels, m.table_size, m.feat_dim)).astype(np.float32)
 
 
 def init_mlp(m: ModelDesc, seed: int) -> np.ndarray:

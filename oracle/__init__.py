@@ -52,7 +52,8 @@ def lib():
 class Model(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("pe_freqs", C.c_int32), ("res", C.c_int32 * 32), ("n_layers", C.c_int32),
-                ("dims", C.c_int32 * 16), ("n_materials", C.c_int32), ("dist_head", C.c_int32)]
+                ("dims", C.c_int32 * 16), ("n_materials", C.c_int32), ("dist_head", C.c_int32),
+                ("per_sample_tables", C.c_int32)]
 
 
 def model_struct(desc) -> Model:
@@ -67,6 +68,7 @@ def model_struct(desc) -> Model:
         m.dims[i] = d
     m.n_materials = desc.n_materials
     m.dist_head = getattr(desc, "dist_head", 0)
+    m.per_sample_tables = getattr(desc, "per_sample_tables", 0)
     return m
 
 

@@ -20,6 +20,8 @@
  *  - Loss, "Uncertainty-Weighted Multi-Task Loss": regression 0.5 exp(-s) L + 0.5 s,
  *    classification exp(-s) L + 0.5 s; log-space MSE for distance, cosine loss for normals,
  *    L1 on sigmoid albedo, cross-entropy for material and occlusion.
+ *  - Per-sample tables (the other reading of one table set serving every sample of Eq. (1)):
+ *    with per_sample_tables, PE sample s reads table set s, laid out [set][level][T][Fd].
  *  - Ablation switches, "Accuracy Comparison without Deformation" (Table 1) and the loss
  *    section's remark that the sigmoid distance output was replaced: dist_head = 1 restores
  *    a bounded head, sigma(z1) read as the hit's fraction of the rest segment and regressed
@@ -39,6 +41,8 @@ static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 static double sigmoid(double v) { return 1.0 / (1.0 + exp(-v)); }
 
 static int n_samples(const orc_model* m) { return 1 + 2 * m->pe_freqs; }
+/* Table set of PE sample s: one set shared by all samples, or one per sample. */
+static int table_set(const orc_model* m, int s) { return m->per_sample_tables ? s : 0; }
 static int point_width(const orc_model* m) { return n_samples(m) * m->levels * m->feat_dim; }
 
 /* Sample s of gamma(x) for one coordinate, and its derivative d sample / d x. */
@@ -92,7 +96,7 @@ void orc_encode_point(const orc_model* m, const double* tables, const double xin
                     v[a] = i0[a] + bit;
                     wt *= bit ? w[a] : 1.0 - w[a];
                 }
-                const double* e = tables + ((int64_t)l * T + grid_index(m, l, v)) * Fd;
+                const double* e = tables + (((int64_t)table_set(m, s) * L + l) * T + grid_index(m, l, v)) * Fd;
                 for (int f = 0; f < Fd; ++f) o[f] += wt * e[f];
             }
         }
@@ -128,7 +132,7 @@ static void encode_point_backward(const orc_model* m, const double* tables, cons
                     f1[a] = bit ? w[a] : 1.0 - w[a];
                 }
                 double wt = f1[0] * f1[1] * f1[2];
-                int64_t base = ((int64_t)l * T + grid_index(m, l, v)) * Fd;
+                int64_t base = (((int64_t)table_set(m, s) * L + l) * T + grid_index(m, l, v)) * Fd;
                 double gdot = 0.0;
                 for (int f = 0; f < Fd; ++f) {
                     if (gtab) gtab[base + f] += wt * g[f];

@@ -32,6 +32,7 @@ typedef struct {
     int32_t dist_head;     /* 0: ReLU rest-space distance, log-space MSE (the paper's head);
                               1: sigmoid fraction of the rest segment, MSE (the bounded head
                               the paper replaces, kept as an ablation switch) */
+    int32_t per_sample_tables; /* 0: one table set for every PE sample; 1: set s for sample s */
 } orc_model;
 
 /* deform.c */

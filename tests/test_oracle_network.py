@@ -64,6 +64,34 @@ def test_no_frequencies_is_plain_grid_encoding(orc):
     assert orc.encode(m, tab, x).shape == (32, m.levels * m.feat_dim)
 
 
+def test_per_sample_tables_reduce_to_the_shared_table_and_stay_local(orc):
+    """Per-sample tables holding S copies of one table encode exactly like the shared table;
+    the table gradient summed over the copies is the shared gradient; changing set s moves
+    only the features of PE sample s."""
+    m = _small_model()
+    mp = dataclasses.replace(m, per_sample_tables=1)
+    S_ = m.n_samples
+    tab = S.init_tables(m, 5).astype(np.float64) * 1e3
+    tabp = np.concatenate([tab] * S_, axis=0)
+    x = np.random.default_rng(6).uniform(-0.05, 1.05, (50, 3))
+    a = orc.encode(m, tab, x)
+    b = orc.encode(mp, tabp, x)
+    assert np.array_equal(a, b)
+    tabq = tabp.copy()
+    k = 3
+    tabq[k * m.levels:(k + 1) * m.levels] *= -2.0
+    c = orc.encode(mp, tabq, x).reshape(50, S_, m.levels, m.feat_dim)
+    a4 = a.reshape(50, S_, m.levels, m.feat_dim)
+    same = np.ones(S_, bool); same[k] = False
+    assert np.array_equal(c[:, same], a4[:, same]) and np.allclose(c[:, k], -2.0 * a4[:, k])
+    _, _, x0, x1, hit, t, nr, al, mt = _batch(m, 24, 64)
+    prm = S.init_mlp(m, 7).astype(np.float64)
+    g = orc.loss_grad(m, tab, prm, np.zeros(5), x0, x1, hit, t, nr, al, mt)[1]
+    gp = orc.loss_grad(mp, tabp, prm, np.zeros(5), x0, x1, hit, t, nr, al, mt)[1]
+    gsum = gp.reshape(S_, m.levels, m.table_size, m.feat_dim).sum(0)
+    assert np.abs(gsum - g).max() <= 1e-12 * np.abs(g).max()
+
+
 def test_points_are_clamped_to_the_unit_cube(orc):
     m = _small_model()
     rng = np.random.default_rng(2)
@@ -288,10 +316,12 @@ def test_uncertainty_weights_are_stationary_at_log_loss(orc):
     assert np.all(orc.loss_grad(m, tab, prm, s_star + 0.1, x0, x1, hit, t, nr, al, mt)[3] > 0)
 
 
-@pytest.mark.parametrize("n_materials,dist_head,fixed", [(1, S.DIST_LOG_RELU, False), (4, S.DIST_LOG_RELU, False),
-                                                        (4, S.DIST_SIGMOID, True)])
-def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head, fixed):
-    m = _small_model(n_materials=n_materials, dist_head=dist_head)
+@pytest.mark.parametrize("n_materials,dist_head,fixed,per_sample", [(1, S.DIST_LOG_RELU, False, 0),
+                                                                   (4, S.DIST_LOG_RELU, False, 0),
+                                                                   (4, S.DIST_SIGMOID, True, 0),
+                                                                   (4, S.DIST_LOG_RELU, False, 1)])
+def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head, fixed, per_sample):
+    m = _small_model(n_materials=n_materials, dist_head=dist_head, per_sample_tables=per_sample)
     tab, prm, x0, x1, hit, t, nr, al, mt = _batch(m, 20, 62 + n_materials)
     s = np.array([0.1, -0.2, 0.3, 0.0, 0.5])
     L, gt, gp, gs, gx0, gx1 = orc.loss_grad(m, tab, prm, s, x0, x1, hit, t, nr, al, mt, want_x=True,
