@@ -65,7 +65,8 @@ typedef struct { int32_t kind; float strength; } nif_pose;
  * followed by an MLP with ReLU hidden layers and 8 + n_materials outputs:
  * [hit logit, distance, normal(3), albedo(3), material logits].
  * Canonical FP32 parameter layouts (the ones nif_model_set_params takes):
- *   tables: [levels][2^log2_table][feat_dim]
+ *   tables: [sets][levels][2^log2_table][feat_dim], sets = 1 + 2 pe_freqs with per_sample_tables
+ *           else 1
  *   mlp   : per layer W[out][in] row-major then b[out]; layer widths
  *           E = 2 (1 + 2 pe_freqs) levels feat_dim, hidden_width x hidden_layers, 8 + n_materials
  *   s     : [5] log-variances of the tasks (hit, distance, normal, albedo, material)
@@ -92,6 +93,8 @@ typedef struct {
     int32_t hidden_layers;   /* 1..8 */
     int32_t n_materials;     /* 1..8 */
     int32_t dist_head;       /* NIF_DIST_LOG_RELU (the method) or NIF_DIST_SIGMOID (ablation) */
+    int32_t per_sample_tables; /* 0: one table set serves every PE sample (Eq. (1) as read here);
+                                  1: PE sample s reads its own set s; tables [sets][L][T][feat_dim] */
 } nif_model_desc;
 
 /* Allocates parameters (FP32 masters and working copies), gradients and Adam state. */

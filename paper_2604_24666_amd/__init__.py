@@ -41,7 +41,7 @@ class ModelDesc(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("table_dtype", C.c_int32), ("res", C.c_int32 * 32), ("pe_freqs", C.c_int32),
                 ("hidden_width", C.c_int32), ("hidden_layers", C.c_int32), ("n_materials", C.c_int32),
-                ("dist_head", C.c_int32)]
+                ("dist_head", C.c_int32), ("per_sample_tables", C.c_int32)]
 
 
 class Pose(C.Structure):
@@ -301,13 +301,14 @@ def nif_train_step(model, batch: Batch, B: int, cfg: TrainCfg, losses, stream=No
 # ------------------------------------------------------------------ convenience objects
 
 def model_desc(levels, log2_table, feat_dim, table_dtype, res, pe_freqs, hidden_width, hidden_layers,
-               n_materials, dist_head=0) -> ModelDesc:
+               n_materials, dist_head=0, per_sample_tables=0) -> ModelDesc:
     d = ModelDesc()
     d.levels, d.log2_table, d.feat_dim, d.table_dtype = levels, log2_table, feat_dim, table_dtype
     for i, r in enumerate(res):
         d.res[i] = int(r)
     d.pe_freqs, d.hidden_width, d.hidden_layers, d.n_materials = pe_freqs, hidden_width, hidden_layers, n_materials
     d.dist_head = dist_head
+    d.per_sample_tables = per_sample_tables
     return d
 
 
@@ -317,7 +318,8 @@ class Model:
     def __init__(self, m, device="cuda"):
         self.spec = m
         self.desc = model_desc(m.levels, m.log2_table, m.feat_dim, m.table_dtype, m.res, m.pe_freqs,
-                               m.hidden_width, m.hidden_layers, m.n_materials, getattr(m, "dist_head", 0))
+                               m.hidden_width, m.hidden_layers, m.n_materials, getattr(m, "dist_head", 0),
+                               getattr(m, "per_sample_tables", 0))
         self.n_table, self.n_mlp = nif_model_sizes(self.desc)
         self.H = 8 + m.n_materials
         self.E = 2 * (1 + 2 * m.pe_freqs) * m.levels * m.feat_dim

@@ -63,6 +63,7 @@ static int validate_desc(const nif_model_desc* d) {
     REQUIRE(d->n_materials >= 1 && d->n_materials <= 8, "n_materials must be in [1, 8]");
     REQUIRE(d->dist_head == NIF_DIST_LOG_RELU || d->dist_head == NIF_DIST_SIGMOID,
             "dist_head must be NIF_DIST_LOG_RELU or NIF_DIST_SIGMOID");
+    REQUIRE(d->per_sample_tables == 0 || d->per_sample_tables == 1, "per_sample_tables must be 0 or 1");
     return NIF_OK;
 }
 
@@ -74,7 +75,8 @@ int nif_model_sizes(const nif_model_desc* d, int64_t* n_table, int64_t* n_mlp) {
     int64_t n = 0, prev = E;
     for (int i = 0; i < d->hidden_layers; ++i) { n += (int64_t)d->hidden_width * prev + d->hidden_width; prev = d->hidden_width; }
     n += H * prev + H;
-    if (n_table) *n_table = (int64_t)d->levels * ((int64_t)1 << d->log2_table) * d->feat_dim;
+    if (n_table) *n_table = (int64_t)(d->per_sample_tables ? 1 + 2 * d->pe_freqs : 1) * d->levels *
+                            ((int64_t)1 << d->log2_table) * d->feat_dim;
     if (n_mlp) *n_mlp = n;
     return NIF_OK;
 }

@@ -126,7 +126,7 @@ int model_alloc(nif_model* m) {
     m->S = 1 + 2 * d.pe_freqs;
     m->E = 2 * m->S * d.levels * d.feat_dim;
     m->H = 8 + d.n_materials;
-    m->n_table = (int64_t)d.levels * ((int64_t)1 << d.log2_table) * d.feat_dim;
+    m->n_table = (int64_t)(d.per_sample_tables ? m->S : 1) * d.levels * ((int64_t)1 << d.log2_table) * d.feat_dim;
     m->dims.clear();
     m->dims.push_back(m->E);
     for (int i = 0; i < d.hidden_layers; ++i) m->dims.push_back(d.hidden_width);

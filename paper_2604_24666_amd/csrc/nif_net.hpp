@@ -40,12 +40,20 @@ constexpr int kZStride = 17;     // LDS floats per segment of head outputs (16 +
 constexpr int kQueryCB = NIF_QUERY_CB;      // 16-segment column blocks per MLP pass in the fused query
 
 struct EncParams {
-    const void* tab;        // [L][T][2] FP32 or FP16
+    const void* tab;        // [sets][L][T][2] FP32 or FP16
     int32_t f16;
     int32_t L, log2T, F;
     int32_t res[16];
     uint32_t dense_mask;    // bit l: level l indexed densely
+    int64_t set_stride;     // entries per table set: L T with one set per PE sample, else 0
 };
+
+// First entry of the table set that PE sample s reads.
+__device__ __forceinline__ size_t set_offset(const EncParams& ep, int s) { return (size_t)s * (size_t)ep.set_stride; }
+// Table set entry offset of PE combination c (point-major: c = p S + s).
+__device__ __forceinline__ size_t combo_set_offset(const EncParams& ep, int c, int S) {
+    return set_offset(ep, c >= S ? c - S : c);
+}
 
 struct NetParams {
     EncParams enc;
@@ -114,9 +122,9 @@ __device__ __forceinline__ float2 table_entry(const void* tab, size_t e) {
 // All 8 NL corner gathers are issued before any is used, so they are in flight together.
 template <int NL, bool F16>
 __device__ __forceinline__ void grid_lookup_n(const EncParams& ep, int l0, int dl, double sx, double sy, double sz,
-                                              float2 out[NL]) {
+                                              float2 out[NL], size_t set_off = 0) {
     const uint32_t mask = (1u << ep.log2T) - 1u;
-    uint32_t idx[NL][8];
+    size_t idx[NL][8];
     float wx[NL], wy[NL], wz[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -128,7 +136,7 @@ __device__ __forceinline__ void grid_lookup_n(const EncParams& ep, int l0, int d
         grid_axis(sx, N, ix, wx[k]);
         grid_axis(sy, N, iy, wy[k]);
         grid_axis(sz, N, iz, wz[k]);
-        const uint32_t base = (uint32_t)l << ep.log2T;
+        const size_t base = set_off + ((size_t)l << ep.log2T);
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             idx[k][c] = base + grid_index(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1), n1, dense, mask);
@@ -302,7 +310,8 @@ __device__ __forceinline__ void fix_axis(uint32_t f, uint32_t N, uint32_t& i0, f
 // Interpolated features of levels l0 .. l0+LB-1 (wave-uniform) at one fixed-point sample
 // position: feat[2k + f] = feature f of level l0 + k.
 template <int LB, bool F16>
-__device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const uint32_t f[3], float feat[2 * LB]) {
+__device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const uint32_t f[3], float feat[2 * LB],
+                                              size_t set_off = 0) {
     using E = typename TabTypes<F16>::E;
     using Pr = typename TabTypes<F16>::Pr;
     const E* tab = reinterpret_cast<const E*>(ep.tab);
@@ -322,7 +331,7 @@ __device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const
         fix_axis(f[2], N, iz, wz[k]);
         ixs[k] = ix;
         swp[k] = 0u;
-        const E* tl = tab + ((size_t)l << ep.log2T);
+        const E* tl = tab + set_off + ((size_t)l << ep.log2T);
         if ((ep.dense_mask >> l) & 1u) {
             const uint32_t n1 = N + 1u;
 #pragma unroll
@@ -418,6 +427,7 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
         const int c_raw = q * U + u;
         const bool live = c_raw < n_comb;
         const int c = live ? c_raw : 0;
+        const size_t soff = combo_set_offset(np.enc, c, S);
         uint32_t smp[CB][3];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -434,10 +444,10 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
                 if (np.enc.f16) {
-                    lookup_levels<LB, true>(np.enc, l0, smp[cb], feat[cb]);
+                    lookup_levels<LB, true>(np.enc, l0, smp[cb], feat[cb], soff);
                 } else {     // FP32 entries are twice the size: two levels at a time
 #pragma unroll
-                    for (int h = 0; h < LB; h += 2) lookup_levels<2, false>(np.enc, l0 + h, smp[cb], feat[cb] + 2 * h);
+                    for (int h = 0; h < LB; h += 2) lookup_levels<2, false>(np.enc, l0 + h, smp[cb], feat[cb] + 2 * h, soff);
                 }
                 if (!live) {
 #pragma unroll

@@ -444,8 +444,8 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
             pe_sample(pe, s, smp);
             for (int l0 = 0; l0 < ep.L; l0 += 4) {
                 float2 f[4];
-                if (ep.f16) grid_lookup_n<4, true>(ep, l0, 1, smp[0], smp[1], smp[2], f);
-                else grid_lookup_n<4, false>(ep, l0, 1, smp[0], smp[1], smp[2], f);
+                if (ep.f16) grid_lookup_n<4, true>(ep, l0, 1, smp[0], smp[1], smp[2], f, set_offset(ep, s));
+                else grid_lookup_n<4, false>(ep, l0, 1, smp[0], smp[1], smp[2], f, set_offset(ep, s));
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     out[i * W + (s * ep.L + l0 + k) * 2] = f[k].x;
@@ -515,6 +515,7 @@ NetParams make_net_params(const nif_model* m, int32_t precision) {
     np.enc.log2T = d.log2_table;
     np.enc.F = d.pe_freqs;
     np.enc.dense_mask = 0;
+    np.enc.set_stride = d.per_sample_tables ? ((int64_t)d.levels << d.log2_table) : 0;
     for (int l = 0; l < d.levels; ++l) {
         np.enc.res[l] = d.res[l];
         const uint64_t n1 = (uint64_t)d.res[l] + 1;

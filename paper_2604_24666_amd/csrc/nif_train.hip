@@ -74,7 +74,7 @@ int model_reserve(nif_model* m, int64_t B) {
         // encoding-backward additions: per chunk of samples, one per (sample, PE chunk, level, corner)
         const int log2T = m->desc.log2_table, L = m->desc.levels;
         const int SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
-        const int64_t n_buckets = (int64_t)L * (1 << (log2T - SB));
+        const int64_t n_buckets = (int64_t)L * (m->desc.per_sample_tables ? m->S : 1) * (1 << (log2T - SB));
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(B, kEncBwdChunk));
         const int64_t n_blk = ((chunk + 15) / 16 + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock;
         const int64_t n_add = chunk * 2 * m->S * L * 8;
@@ -581,12 +581,27 @@ __device__ __forceinline__ bool tile_sample(const EncBwdParams& P, int64_t tile,
     return valid;
 }
 
+// Buckets of one level pair: table set s (one per PE sample with per-sample tables, else one),
+// level lp + k, slice: local index (s 2 + k) NBL + slice, global ((s L + lp + k) NBL + slice).
+__device__ __forceinline__ int64_t pair_bucket_global(const EncBwdParams& P, int lp, int i) {
+    const int s = i / (2 * P.NBL), r = i % (2 * P.NBL);
+    return ((int64_t)s * P.enc.L + lp + r / P.NBL) * P.NBL + r % P.NBL;
+}
+__device__ __forceinline__ int n_table_sets(const EncBwdParams& P) { return P.enc.set_stride ? P.S : 1; }
+// Table set of PE combination c (point-major).
+__device__ __forceinline__ int combo_set(const EncBwdParams& P, int c) {
+    return P.enc.set_stride ? (c >= P.S ? c - P.S : c) : 0;
+}
+
+// Block (x, y): the samples of tile group x, levels 2y and 2y + 1 (as the fill below).
 __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
-    extern __shared__ int32_t s_h[];    // [n_buckets]
+    extern __shared__ int32_t s_h[];    // [sets][2][NBL]
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
-    const int L = P.enc.L, n_comb = 2 * P.S;
-    for (int i = tid; i < P.n_buckets; i += 256) s_h[i] = 0;
-    if (blockIdx.x == 0 && tid == 0) *P.vmax = 0u;
+    const int n_comb = 2 * P.S;
+    const int lp = (int)blockIdx.y * 2;
+    const int nloc = 2 * P.NBL * n_table_sets(P);
+    for (int i = tid; i < nloc; i += 256) s_h[i] = 0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *P.vmax = 0u;
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
     const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
@@ -600,18 +615,19 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
             double smp[3];
             float dsdx[3], inside[3];
             pe_combo_grad(xs, live ? c : 0, P.S, smp, dsdx, inside);
-            for (int l = 0; l < L; ++l) {
+            const int sb = combo_set(P, live ? c : 0) * 2;
+            for (int k = 0; k < 2; ++k) {
                 uint32_t idx[8];
                 float wt[3];
-                level_corners(P.enc, l, smp, idx, wt);
+                level_corners(P.enc, lp + k, smp, idx, wt);
                 if (live)
 #pragma unroll
-                    for (int cc = 0; cc < 8; ++cc) atomicAdd(&s_h[l * P.NBL + (int)(idx[cc] >> P.SB)], 1);
+                    for (int cc = 0; cc < 8; ++cc) atomicAdd(&s_h[(sb + k) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
             }
         }
     }
     __syncthreads();
-    for (int i = tid; i < P.n_buckets; i += 256) P.cnt[(int64_t)i * P.n_blk + blockIdx.x] = s_h[i];
+    for (int i = tid; i < nloc; i += 256) P.cnt[pair_bucket_global(P, lp, i) * P.n_blk + blockIdx.x] = s_h[i];
 }
 
 // Block (x, y): the samples of tile group x, levels 2y and 2y + 1 only, so that a block
@@ -620,13 +636,13 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
 template <int HW>
 __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     constexpr int KQ = HW / 4;                 // MFMA k-steps: lane quarter q covers [q KQ, (q+1) KQ)
-    extern __shared__ int32_t s_cur[];         // [2 NBL]: this block's next output slot per bucket
+    extern __shared__ int32_t s_cur[];         // [sets][2][NBL]: this block's next output slot per bucket
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
     const int L = P.enc.L, n_comb = 2 * P.S;
     const int lp = (int)blockIdx.y * 2;        // first level of this block's pair
-    const int b0 = lp * P.NBL;                 // first bucket of the pair
     const uint32_t kmask = (1u << P.SB) - 1u;
-    for (int i = tid; i < 2 * P.NBL; i += 256) s_cur[i] = P.cnt[(int64_t)(b0 + i) * P.n_blk + blockIdx.x];
+    const int nloc = 2 * P.NBL * n_table_sets(P);
+    for (int i = tid; i < nloc; i += 256) s_cur[i] = P.cnt[pair_bucket_global(P, lp, i) * P.n_blk + blockIdx.x];
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
     const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
@@ -680,7 +696,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
 #pragma unroll
                     for (int cc = 0; cc < 8; ++cc) {
                         const float cw = corner_weight(wt, cc);
-                        const int32_t slot = atomicAdd(&s_cur[(l - lp) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
+                        const int32_t slot = atomicAdd(&s_cur[(combo_set(P, c) * 2 + l - lp) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
                         if (slot < P.cap) {      // always true: the count pass saw the same additions
                             const float v0 = cw * g0, v1 = cw * g1;
                             P.key[slot] = (uint16_t)(idx[cc] & kmask);
@@ -689,7 +705,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
                             vmx = (isfinite(v0) && isfinite(v1)) ? fmaxf(vmx, a) : INFINITY;
                         }
                         if (P.dx0) {
-                            const size_t te = ((size_t)l << P.enc.log2T) + idx[cc];
+                            const size_t te = (size_t)combo_set(P, c) * (size_t)P.enc.set_stride +
+                                              ((size_t)l << P.enc.log2T) + idx[cc];
                             float2 tv;
                             if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[te]);
                             else tv = reinterpret_cast<const float2*>(P.enc.tab)[te];
@@ -1104,12 +1121,12 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     const int log2T = m->desc.log2_table;
     ep.SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
     ep.NBL = 1 << (log2T - ep.SB);
-    ep.n_buckets = m->desc.levels * ep.NBL;
+    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
+    ep.n_buckets = m->desc.levels * n_sets * ep.NBL;
     ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
     ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
     ep.vmax = nullptr;
     const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
-    const size_t lds = sizeof(int32_t) * (size_t)ep.n_buckets;
     for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
         ep.c0 = c0;
         ep.n = std::min<int64_t>(m->bwd_chunk, B - c0);
@@ -1121,12 +1138,12 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         int32_t* total = m->bwd_scan + n_chunks;
         int32_t* parts = total + 1;
         ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
-        hipLaunchKernelGGL(k_enc_bwd_count, dim3((unsigned)ep.n_blk), dim3(256), lds, st, ep);
+        const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
+        const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL * n_sets;
+        hipLaunchKernelGGL(k_enc_bwd_count, fg, dim3(256), lds_f, st, ep);
         hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, n_chunks, total);
         hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
-        const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
-        const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL;
         switch (hw) {
             case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, st, ep); break;
             case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, st, ep); break;

@@ -58,7 +58,8 @@ def test_model_sizes_match_the_canonical_layout(P):
 @pytest.mark.parametrize("kw,code", [(dict(feat_dim=3), 1), (dict(levels=6), 1), (dict(log2_table=30), 1),
                                      (dict(hidden_width=48), 2), (dict(hidden_layers=0), 1),
                                      (dict(n_materials=0), 1), (dict(table_dtype=7), 1),
-                                     (dict(res=[0] * 8), 1), (dict(pe_freqs=-1), 1), (dict(dist_head=2), 1)])
+                                     (dict(res=[0] * 8), 1), (dict(pe_freqs=-1), 1), (dict(dist_head=2), 1),
+                                     (dict(per_sample_tables=2), 1)])
 def test_bad_model_descriptions_are_rejected(P, kw, code):
     L = P.lib()
     d = _desc(P, **kw)

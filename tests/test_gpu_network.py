@@ -22,6 +22,9 @@ MODELS = {
     "spheres64_p": S.workload("spheres64_p").model,
     "small16": dataclasses.replace(S.workload("torus16").model, hidden_width=16, hidden_layers=1, n_materials=3),
     "w32": dataclasses.replace(S.workload("spheres64").model, hidden_width=32, hidden_layers=2, pe_freqs=2),
+    "torus16_per_sample": dataclasses.replace(S.workload("torus16").model, per_sample_tables=1),
+    "w32_per_sample": dataclasses.replace(S.workload("spheres64").model, hidden_width=32, hidden_layers=2,
+                                          pe_freqs=2, log2_table=16, per_sample_tables=1),
 }
 
 
@@ -36,7 +39,7 @@ def _points(n, seed):
     return x0, x1
 
 
-@pytest.mark.parametrize("name", ["torus16", "spheres64"])
+@pytest.mark.parametrize("name", ["torus16", "spheres64", "torus16_per_sample", "w32_per_sample"])
 def test_encoding_matches_oracle(orc, P, name):
     m = MODELS[name]
     say(f"encode {name}")

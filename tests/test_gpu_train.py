@@ -49,6 +49,7 @@ def _grad_close(got, ref, name, big_frac=1e-3, el_tol=1e-4):
 
 MODELS = {
     "torus16": dataclasses.replace(S.workload("torus16").model, hidden_width=32),
+    "torus16_per_sample": dataclasses.replace(S.workload("torus16").model, hidden_width=32, per_sample_tables=1),
     "spheres64": S.workload("spheres64").model,
     "blobs128": S.workload("blobs128").model,
 }
@@ -131,6 +132,7 @@ ABLATIONS = {
     "sigmoid_head_fixed_weights": (dict(dist_head=S.DIST_SIGMOID), True),
     "no_pe": (dict(pe_freqs=0), False),
     "no_pe_sigmoid_head_fixed_weights": (dict(pe_freqs=0, dist_head=S.DIST_SIGMOID), True),
+    "per_sample_tables": (dict(per_sample_tables=1), False),
 }
 
 
