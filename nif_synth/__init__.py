@@ -43,14 +43,19 @@ class ModelDesc:
     n_materials: int
     dist_head: int = DIST_LOG_RELU
     per_sample_tables: int = 0           # 1: one table set per PE sample
+    concat_encoding: int = 0             # 1: [phi(x), gamma(x)] instead of phi(gamma(x))
 
     @property
-    def n_samples(self) -> int:          # 1 + 2F positional-encoding samples per point
-        return 1 + 2 * self.pe_freqs
+    def n_samples(self) -> int:          # PE samples per point that go through the grid
+        return 1 if self.concat_encoding else 1 + 2 * self.pe_freqs
 
     @property
-    def enc_width(self) -> int:          # two points (entry, exit) x samples x levels x features
-        return 2 * self.n_samples * self.levels * self.feat_dim
+    def gamma_width(self) -> int:        # raw PE values per point appended by the concatenated form
+        return 3 * (1 + 2 * self.pe_freqs) if self.concat_encoding else 0
+
+    @property
+    def enc_width(self) -> int:          # two points (entry, exit) x (samples x levels x features + gamma)
+        return 2 * (self.n_samples * self.levels * self.feat_dim + self.gamma_width)
 
     @property
     def n_heads(self) -> int:            # hit, dist, normal(3), albedo(3), material logits

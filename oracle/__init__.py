@@ -53,7 +53,7 @@ class Model(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("pe_freqs", C.c_int32), ("res", C.c_int32 * 32), ("n_layers", C.c_int32),
                 ("dims", C.c_int32 * 16), ("n_materials", C.c_int32), ("dist_head", C.c_int32),
-                ("per_sample_tables", C.c_int32)]
+                ("per_sample_tables", C.c_int32), ("concat_encoding", C.c_int32)]
 
 
 def model_struct(desc) -> Model:
@@ -69,6 +69,7 @@ def model_struct(desc) -> Model:
     m.n_materials = desc.n_materials
     m.dist_head = getattr(desc, "dist_head", 0)
     m.per_sample_tables = getattr(desc, "per_sample_tables", 0)
+    m.concat_encoding = getattr(desc, "concat_encoding", 0)
     return m
 
 
@@ -182,7 +183,7 @@ def encode(desc, tables, x) -> np.ndarray:
     m = model_struct(desc)
     tab = _f64(tables).reshape(-1)
     x = _aos(x)
-    W = (1 + 2 * desc.pe_freqs) * desc.levels * desc.feat_dim
+    W = (1 if getattr(desc, "concat_encoding", 0) else 1 + 2 * desc.pe_freqs) * desc.levels * desc.feat_dim
     out = np.empty((len(x), W))
     lib().orc_encode_batch(C.byref(m), _p(tab, C.c_double), C.c_int64(len(x)), _p(x, C.c_double),
                            _p(out, C.c_double))

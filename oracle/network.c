@@ -20,6 +20,9 @@
  *  - Loss, "Uncertainty-Weighted Multi-Task Loss": regression 0.5 exp(-s) L + 0.5 s,
  *    classification exp(-s) L + 0.5 s; log-space MSE for distance, cosine loss for normals,
  *    L1 on sigmoid albedo, cross-entropy for material and occlusion.
+ *  - Concatenated encoding (the other reading of Eq. (1)): with concat_encoding the grid runs
+ *    on the point itself and the raw gamma values are appended: [phi(x0), phi(x1), gamma(x0),
+ *    gamma(x1)].
  *  - Per-sample tables (the other reading of one table set serving every sample of Eq. (1)):
  *    with per_sample_tables, PE sample s reads table set s, laid out [set][level][T][Fd].
  *  - Ablation switches, "Accuracy Comparison without Deformation" (Table 1) and the loss
@@ -40,7 +43,11 @@
 static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 static double sigmoid(double v) { return 1.0 / (1.0 + exp(-v)); }
 
-static int n_samples(const orc_model* m) { return 1 + 2 * m->pe_freqs; }
+/* PE samples that go through the grid: all 1 + 2F of them for psi = phi(gamma(x)), only x
+   itself for the concatenated [gamma, phi] reading. */
+static int n_samples(const orc_model* m) { return m->concat_encoding ? 1 : 1 + 2 * m->pe_freqs; }
+/* Raw gamma values per point that the concatenated reading appends: 3 (1 + 2F). */
+static int gamma_width(const orc_model* m) { return m->concat_encoding ? 3 * (1 + 2 * m->pe_freqs) : 0; }
 /* Table set of PE sample s: one set shared by all samples, or one per sample. */
 static int table_set(const orc_model* m, int s) { return m->per_sample_tables ? s : 0; }
 static int point_width(const orc_model* m) { return n_samples(m) * m->levels * m->feat_dim; }
@@ -197,10 +204,33 @@ static int64_t acts_width(const orc_model* m) {
     return s;
 }
 
+/* gamma(x) of Eq. (1) as raw values on the clamped point: value 3 s + a is sample s of
+   coordinate a (s = 0: x; s = 2k + 1: sin 2^k x; s = 2k + 2: cos 2^k x), and its derivative. */
+static void gamma_raw(const orc_model* m, const double xin[3], double* out, double* dout) {
+    for (int s = 0; s < 1 + 2 * m->pe_freqs; ++s)
+        for (int a = 0; a < 3; ++a) {
+            double x = clamp01(xin[a]), v, dv;
+            if (s == 0) { v = x; dv = 1.0; }
+            else {
+                double f = ldexp(1.0, (s - 1) / 2);
+                if ((s - 1) % 2 == 0) { v = sin(f * x); dv = f * cos(f * x); }
+                else { v = cos(f * x); dv = -f * sin(f * x); }
+            }
+            out[3 * s + a] = v;
+            if (dout) dout[3 * s + a] = dv;
+        }
+}
+
+/* MLP input of a segment: psi(x0) ++ psi(x1), or with the concatenated reading
+   phi(x0) ++ phi(x1) ++ gamma(x0) ++ gamma(x1). */
 static void features(const orc_model* m, const double* tables, const double x0[3],
                      const double x1[3], double* enc) {
     orc_encode_point(m, tables, x0, enc);
     orc_encode_point(m, tables, x1, enc + point_width(m));
+    if (m->concat_encoding) {
+        gamma_raw(m, x0, enc + 2 * point_width(m), NULL);
+        gamma_raw(m, x1, enc + 2 * point_width(m) + gamma_width(m), NULL);
+    }
 }
 
 /* ------------------------------------------------------------------ batch entry points */
@@ -481,6 +511,23 @@ void orc_loss_grad(const orc_model* m, const double* tables, const double* param
         /* dcur now holds d loss / d encoding */
         encode_point_backward(m, tables, x0 + 3 * i, dcur, g_tables, g_x0 ? g_x0 + 3 * i : NULL);
         encode_point_backward(m, tables, x1 + 3 * i, dcur + PW, g_tables, g_x1 ? g_x1 + 3 * i : NULL);
+        if (m->concat_encoding) {        /* gamma part: d x_a += d gamma * d gamma / d x_a inside the cube */
+            const int GW = gamma_width(m);
+            double* val = (double*)malloc(sizeof(double) * GW);
+            double* der = (double*)malloc(sizeof(double) * GW);
+            for (int p = 0; p < 2; ++p) {
+                const double* xp = (p ? x1 : x0) + 3 * i;
+                double* gx = p ? (g_x1 ? g_x1 + 3 * i : NULL) : (g_x0 ? g_x0 + 3 * i : NULL);
+                if (!gx) continue;
+                gamma_raw(m, xp, val, der);
+                const double* dg = dcur + 2 * PW + p * GW;
+                for (int v = 0; v < GW; ++v) {
+                    const int a = v % 3;
+                    if (xp[a] >= 0.0 && xp[a] <= 1.0) gx[a] += dg[v] * der[v];
+                }
+            }
+            free(val); free(der);
+        }
     }
     double Ls[5];
     Ls[0] = sum[0] / (double)B;

@@ -33,6 +33,7 @@ typedef struct {
                               1: sigmoid fraction of the rest segment, MSE (the bounded head
                               the paper replaces, kept as an ablation switch) */
     int32_t per_sample_tables; /* 0: one table set for every PE sample; 1: set s for sample s */
+    int32_t concat_encoding;   /* 0: psi = phi(gamma(x)); 1: [phi(x), gamma(x)] (raw gamma) */
 } orc_model;
 
 /* deform.c */

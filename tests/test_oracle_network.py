@@ -92,6 +92,40 @@ def test_per_sample_tables_reduce_to_the_shared_table_and_stay_local(orc):
     assert np.abs(gsum - g).max() <= 1e-12 * np.abs(g).max()
 
 
+def test_concatenated_encoding_is_the_plain_grid_and_the_raw_pe(orc):
+    """[phi(x0), phi(x1), gamma(x0), gamma(x1)]: the grid parts equal the F = 0 encoding of the
+    points themselves; the gamma parts are x, sin 2^k x, cos 2^k x of the clamped coordinates
+    in (sample, axis) order; the heads see exactly that vector."""
+    m = _small_model(concat_encoding=1, pe_freqs=3)
+    m0 = _small_model(pe_freqs=0)
+    tab = S.init_tables(m, 8).astype(np.float64) * 1e3
+    rng = np.random.default_rng(9)
+    x0 = rng.uniform(-0.05, 1.05, (40, 3)); x1 = rng.uniform(-0.05, 1.05, (40, 3))
+    assert m.enc_width == 2 * (m.levels * m.feat_dim + 3 * 7)
+    g0 = orc.encode(m0, tab, x0)
+    assert np.array_equal(orc.encode(m, tab, x0), g0)
+    # a one-layer probe: identity rows read the encoding back through forward()
+    E = m.enc_width
+    probe = dataclasses.replace(m, hidden_layers=1, hidden_width=16)
+    prm = np.zeros(probe.n_mlp_params)
+    W = prm[:16 * E].reshape(16, E)
+    pw = m.levels * m.feat_dim
+    cols = [2 * pw + 3 * s + a for s in (0, 1, 2, 6) for a in range(3)] + [2 * pw + 21 + 3 * 5 + 1]
+    for r, c in enumerate(cols[:16]):
+        W[r, c] = 1.0
+    # output layer passes hidden unit r to head r (ReLU keeps the non-negative ones only)
+    Wo = prm[16 * E + 16:16 * E + 16 + probe.n_heads * 16].reshape(probe.n_heads, 16)
+    for r in range(probe.n_heads):
+        Wo[r, r] = 1.0
+    z = orc.forward(probe, tab, prm, x0, x1)
+    xc0 = np.clip(x0, 0, 1); xc1 = np.clip(x1, 0, 1)
+    ref = [xc0[:, 0], xc0[:, 1], xc0[:, 2], np.sin(xc0[:, 0]), np.sin(xc0[:, 1]), np.sin(xc0[:, 2]),
+           np.cos(xc0[:, 0]), np.cos(xc0[:, 1]), np.cos(xc0[:, 2]), np.cos(4 * xc0[:, 0]), np.cos(4 * xc0[:, 1]),
+           np.cos(4 * xc0[:, 2])]
+    for r in range(min(probe.n_heads, len(ref))):
+        assert np.abs(z[:, r] - np.maximum(ref[r], 0.0)).max() < 1e-14, r
+
+
 def test_points_are_clamped_to_the_unit_cube(orc):
     m = _small_model()
     rng = np.random.default_rng(2)
@@ -319,9 +353,12 @@ def test_uncertainty_weights_are_stationary_at_log_loss(orc):
 @pytest.mark.parametrize("n_materials,dist_head,fixed,per_sample", [(1, S.DIST_LOG_RELU, False, 0),
                                                                    (4, S.DIST_LOG_RELU, False, 0),
                                                                    (4, S.DIST_SIGMOID, True, 0),
-                                                                   (4, S.DIST_LOG_RELU, False, 1)])
+                                                                   (4, S.DIST_LOG_RELU, False, 1),
+                                                                   (4, S.DIST_LOG_RELU, False, 2)])
 def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head, fixed, per_sample):
-    m = _small_model(n_materials=n_materials, dist_head=dist_head, per_sample_tables=per_sample)
+    """per_sample 2: the concatenated [gamma, phi] encoding (one table set)."""
+    m = _small_model(n_materials=n_materials, dist_head=dist_head, per_sample_tables=int(per_sample == 1),
+                     concat_encoding=int(per_sample == 2))
     tab, prm, x0, x1, hit, t, nr, al, mt = _batch(m, 20, 62 + n_materials)
     s = np.array([0.1, -0.2, 0.3, 0.0, 0.5])
     L, gt, gp, gs, gx0, gx1 = orc.loss_grad(m, tab, prm, s, x0, x1, hit, t, nr, al, mt, want_x=True,
@@ -330,8 +367,10 @@ def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head
     def total(tab_=tab, prm_=prm, s_=s, x0_=x0, x1_=x1):
         return orc.loss_grad(m, tab_, prm_, s_, x0_, x1_, hit, t, nr, al, mt, fixed_weights=fixed)[0][5]
 
-    def check(fd, an):
-        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * scale) + 1e-10
+    def check(fd, an, h=1e-6):
+        # rounding floor of a central difference: a few ulps of the total over the step
+        floor = 4 * np.finfo(float).eps * abs(L[5]) / h
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * scale) + 1e-10 + floor
 
     rng = np.random.default_rng(70)
     scale = np.abs(gp).max()
@@ -339,7 +378,7 @@ def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head
         h = 1e-6 * max(1.0, abs(prm[idx]))
         p1 = prm.copy(); p1[idx] += h
         p2 = prm.copy(); p2[idx] -= h
-        check((total(prm_=p1) - total(prm_=p2)) / (2 * h), gp[idx])
+        check((total(prm_=p1) - total(prm_=p2)) / (2 * h), gp[idx], h)
     flat = tab.reshape(-1)
     scale = np.abs(gt).max()
     for idx in rng.choice(np.nonzero(gt.reshape(-1))[0], 8, replace=False):
@@ -347,7 +386,7 @@ def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head
         t1 = flat.copy(); t1[idx] += h
         t2 = flat.copy(); t2[idx] -= h
         check((total(tab_=t1.reshape(tab.shape)) - total(tab_=t2.reshape(tab.shape))) / (2 * h),
-              gt.reshape(-1)[idx])
+              gt.reshape(-1)[idx], h)
     scale = max(np.abs(gs).max(), 1.0)
     for k in range(5):
         s1 = s.copy(); s1[k] += 1e-6
