@@ -68,7 +68,8 @@ typedef struct { int32_t kind; float strength; } nif_pose;
  *   tables: [sets][levels][2^log2_table][feat_dim], sets = 1 + 2 pe_freqs with per_sample_tables
  *           else 1
  *   mlp   : per layer W[out][in] row-major then b[out]; layer widths
- *           E = 2 (1 + 2 pe_freqs) levels feat_dim, hidden_width x hidden_layers, 8 + n_materials
+ *           E = 2 (1 + 2 pe_freqs) levels feat_dim (see concat_encoding for the other form),
+ *           hidden_width x hidden_layers, 8 + n_materials
  *   s     : [5] log-variances of the tasks (hit, distance, normal, albedo, material)
  */
 enum { NIF_TABLE_F32 = 0, NIF_TABLE_F16 = 1 };
@@ -95,6 +96,11 @@ typedef struct {
     int32_t dist_head;       /* NIF_DIST_LOG_RELU (the method) or NIF_DIST_SIGMOID (ablation) */
     int32_t per_sample_tables; /* 0: one table set serves every PE sample (Eq. (1) as read here);
                                   1: PE sample s reads its own set s; tables [sets][L][T][feat_dim] */
+    int32_t concat_encoding; /* 0: psi = phi(gamma(x)) (Eq. (1) as read here); 1: the other reading,
+                                the grid on x itself and the raw gamma values appended:
+                                [phi(x0), phi(x1), gamma(x0), gamma(x1)], gamma value 3 s + a =
+                                sample s (x, sin 2^k x, cos 2^k x) of axis a of the clamped point;
+                                E = 2 (levels feat_dim + 3 (1 + 2 pe_freqs)) */
 } nif_model_desc;
 
 /* Allocates parameters (FP32 masters and working copies), gradients and Adam state. */
@@ -245,7 +251,8 @@ int nif_autotune_query(const nif_model* model, const nif_grid* grid, const nif_r
                        nif_stream stream);
 
 /* ---------------------------------------------------------------- network on points
- * psi encoding of n rest-space points (SoA [3][n]) -> out[n][(1+2F) L feat_dim], FP32. */
+ * Grid encoding of n rest-space points (SoA [3][n]) -> out[n][(1+2F) L feat_dim], FP32: psi;
+ * with concat_encoding, phi of the points themselves, out[n][L feat_dim]. */
 int nif_encode(const nif_model* model, const float* x_dev, int64_t n, float* out_dev, nif_stream stream);
 /* Heads of B point pairs: heads_dev[B][8 + n_materials] = MLP(psi(x0) ++ psi(x1)). */
 int nif_forward(const nif_model* model, const float* x0_dev, const float* x1_dev, int64_t B,

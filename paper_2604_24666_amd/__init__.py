@@ -41,7 +41,7 @@ class ModelDesc(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("table_dtype", C.c_int32), ("res", C.c_int32 * 32), ("pe_freqs", C.c_int32),
                 ("hidden_width", C.c_int32), ("hidden_layers", C.c_int32), ("n_materials", C.c_int32),
-                ("dist_head", C.c_int32), ("per_sample_tables", C.c_int32)]
+                ("dist_head", C.c_int32), ("per_sample_tables", C.c_int32), ("concat_encoding", C.c_int32)]
 
 
 class Pose(C.Structure):
@@ -301,7 +301,7 @@ def nif_train_step(model, batch: Batch, B: int, cfg: TrainCfg, losses, stream=No
 # ------------------------------------------------------------------ convenience objects
 
 def model_desc(levels, log2_table, feat_dim, table_dtype, res, pe_freqs, hidden_width, hidden_layers,
-               n_materials, dist_head=0, per_sample_tables=0) -> ModelDesc:
+               n_materials, dist_head=0, per_sample_tables=0, concat_encoding=0) -> ModelDesc:
     d = ModelDesc()
     d.levels, d.log2_table, d.feat_dim, d.table_dtype = levels, log2_table, feat_dim, table_dtype
     for i, r in enumerate(res):
@@ -309,6 +309,7 @@ def model_desc(levels, log2_table, feat_dim, table_dtype, res, pe_freqs, hidden_
     d.pe_freqs, d.hidden_width, d.hidden_layers, d.n_materials = pe_freqs, hidden_width, hidden_layers, n_materials
     d.dist_head = dist_head
     d.per_sample_tables = per_sample_tables
+    d.concat_encoding = concat_encoding
     return d
 
 
@@ -319,10 +320,12 @@ class Model:
         self.spec = m
         self.desc = model_desc(m.levels, m.log2_table, m.feat_dim, m.table_dtype, m.res, m.pe_freqs,
                                m.hidden_width, m.hidden_layers, m.n_materials, getattr(m, "dist_head", 0),
-                               getattr(m, "per_sample_tables", 0))
+                               getattr(m, "per_sample_tables", 0), getattr(m, "concat_encoding", 0))
         self.n_table, self.n_mlp = nif_model_sizes(self.desc)
         self.H = 8 + m.n_materials
-        self.E = 2 * (1 + 2 * m.pe_freqs) * m.levels * m.feat_dim
+        concat = getattr(m, "concat_encoding", 0)
+        self.S_grid = 1 if concat else 1 + 2 * m.pe_freqs
+        self.E = 2 * (self.S_grid * m.levels * m.feat_dim + (3 * (1 + 2 * m.pe_freqs) if concat else 0))
         self.device = device
         self.h = nif_model_create(self.desc)
 
@@ -356,8 +359,7 @@ class Model:
 
     def encode(self, x):
         n = x.shape[1]
-        out = torch.empty((n, (1 + 2 * self.spec.pe_freqs) * self.spec.levels * self.spec.feat_dim),
-                          device=self.device)
+        out = torch.empty((n, self.S_grid * self.spec.levels * self.spec.feat_dim), device=self.device)
         nif_encode(self.h, x, n, out)
         return out
 

@@ -64,18 +64,23 @@ static int validate_desc(const nif_model_desc* d) {
     REQUIRE(d->dist_head == NIF_DIST_LOG_RELU || d->dist_head == NIF_DIST_SIGMOID,
             "dist_head must be NIF_DIST_LOG_RELU or NIF_DIST_SIGMOID");
     REQUIRE(d->per_sample_tables == 0 || d->per_sample_tables == 1, "per_sample_tables must be 0 or 1");
+    REQUIRE(d->concat_encoding == 0 || d->concat_encoding == 1, "concat_encoding must be 0 or 1");
+    REQUIRE((d->per_sample_tables ? (int64_t)(d->concat_encoding ? 1 : 1 + 2 * d->pe_freqs) : 1) * d->levels
+                    * ((int64_t)1 << d->log2_table) < ((int64_t)1 << 32),
+            "the tables must hold fewer than 2^32 entries");
     return NIF_OK;
 }
 
 int nif_model_sizes(const nif_model_desc* d, int64_t* n_table, int64_t* n_mlp) {
     int rc = validate_desc(d);
     if (rc) return rc;
-    const int64_t E = 2LL * (1 + 2 * d->pe_freqs) * d->levels * d->feat_dim;
+    const int64_t Sg = d->concat_encoding ? 1 : 1 + 2 * d->pe_freqs;
+    const int64_t E = 2LL * (Sg * d->levels * d->feat_dim + (d->concat_encoding ? 3 * (1 + 2 * d->pe_freqs) : 0));
     const int64_t H = 8 + d->n_materials;
     int64_t n = 0, prev = E;
     for (int i = 0; i < d->hidden_layers; ++i) { n += (int64_t)d->hidden_width * prev + d->hidden_width; prev = d->hidden_width; }
     n += H * prev + H;
-    if (n_table) *n_table = (int64_t)(d->per_sample_tables ? 1 + 2 * d->pe_freqs : 1) * d->levels *
+    if (n_table) *n_table = (int64_t)(d->per_sample_tables ? Sg : 1) * d->levels *
                             ((int64_t)1 << d->log2_table) * d->feat_dim;
     if (n_mlp) *n_mlp = n;
     return NIF_OK;

@@ -26,7 +26,8 @@ struct nif_grid {
 
 struct nif_model {
     nif_model_desc desc{};
-    int32_t S = 0;           // PE samples per point
+    int32_t S = 0;           // PE samples per point that go through the grid
+    int32_t GW = 0;          // raw gamma values per point appended (concatenated encoding)
     int32_t E = 0;           // encoding width (both points)
     int32_t H = 0;           // head count (8 + materials)
     int64_t n_table = 0, n_mlp = 0;

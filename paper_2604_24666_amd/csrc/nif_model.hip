@@ -123,8 +123,9 @@ static int dalloc(T** p, int64_t n, const char* what) {
 
 int model_alloc(nif_model* m) {
     const nif_model_desc& d = m->desc;
-    m->S = 1 + 2 * d.pe_freqs;
-    m->E = 2 * m->S * d.levels * d.feat_dim;
+    m->S = d.concat_encoding ? 1 : 1 + 2 * d.pe_freqs;
+    m->GW = d.concat_encoding ? 3 * (1 + 2 * d.pe_freqs) : 0;
+    m->E = 2 * (m->S * d.levels * d.feat_dim + m->GW);
     m->H = 8 + d.n_materials;
     m->n_table = (int64_t)(d.per_sample_tables ? m->S : 1) * d.levels * ((int64_t)1 << d.log2_table) * d.feat_dim;
     m->dims.clear();

@@ -48,10 +48,10 @@ struct EncParams {
     int64_t set_stride;     // entries per table set: L T with one set per PE sample, else 0
 };
 
-// First entry of the table set that PE sample s reads.
-__device__ __forceinline__ size_t set_offset(const EncParams& ep, int s) { return (size_t)s * (size_t)ep.set_stride; }
+// First entry of the table set that PE sample s reads (the tables hold fewer than 2^32 entries).
+__device__ __forceinline__ uint32_t set_offset(const EncParams& ep, int s) { return (uint32_t)s * (uint32_t)ep.set_stride; }
 // Table set entry offset of PE combination c (point-major: c = p S + s).
-__device__ __forceinline__ size_t combo_set_offset(const EncParams& ep, int c, int S) {
+__device__ __forceinline__ uint32_t combo_set_offset(const EncParams& ep, int c, int S) {
     return set_offset(ep, c >= S ? c - S : c);
 }
 
@@ -64,6 +64,8 @@ struct NetParams {
     int32_t E;                   // encoding width (both points)
     int32_t H;                   // real head count
     int32_t dist_head;           // NIF_DIST_LOG_RELU or NIF_DIST_SIGMOID
+    int32_t gamma_F;             // concatenated encoding: PE frequencies of the appended gamma (-1: none)
+    int32_t E_phi;               // encoding columns of the grid part (the gamma part follows)
 };
 
 __device__ __forceinline__ uint16_t f2bf(float x) {
@@ -122,7 +124,7 @@ __device__ __forceinline__ float2 table_entry(const void* tab, size_t e) {
 // All 8 NL corner gathers are issued before any is used, so they are in flight together.
 template <int NL, bool F16>
 __device__ __forceinline__ void grid_lookup_n(const EncParams& ep, int l0, int dl, double sx, double sy, double sz,
-                                              float2 out[NL], size_t set_off = 0) {
+                                              float2 out[NL], uint32_t set_off = 0) {
     const uint32_t mask = (1u << ep.log2T) - 1u;
     size_t idx[NL][8];
     float wx[NL], wy[NL], wz[NL];
@@ -136,7 +138,7 @@ __device__ __forceinline__ void grid_lookup_n(const EncParams& ep, int l0, int d
         grid_axis(sx, N, ix, wx[k]);
         grid_axis(sy, N, iy, wy[k]);
         grid_axis(sz, N, iz, wz[k]);
-        const size_t base = set_off + ((size_t)l << ep.log2T);
+        const size_t base = (size_t)(set_off + ((uint32_t)l << ep.log2T));
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             idx[k][c] = base + grid_index(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1), n1, dense, mask);
@@ -311,7 +313,7 @@ __device__ __forceinline__ void fix_axis(uint32_t f, uint32_t N, uint32_t& i0, f
 // position: feat[2k + f] = feature f of level l0 + k.
 template <int LB, bool F16>
 __device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const uint32_t f[3], float feat[2 * LB],
-                                              size_t set_off = 0) {
+                                              uint32_t set_off = 0) {
     using E = typename TabTypes<F16>::E;
     using Pr = typename TabTypes<F16>::Pr;
     const E* tab = reinterpret_cast<const E*>(ep.tab);
@@ -331,7 +333,7 @@ __device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const
         fix_axis(f[2], N, iz, wz[k]);
         ixs[k] = ix;
         swp[k] = 0u;
-        const E* tl = tab + set_off + ((size_t)l << ep.log2T);
+        const E* tl = tab + (set_off + ((uint32_t)l << ep.log2T));
         if ((ep.dense_mask >> l) & 1u) {
             const uint32_t n1 = N + 1u;
 #pragma unroll
@@ -427,7 +429,7 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
         const int c_raw = q * U + u;
         const bool live = c_raw < n_comb;
         const int c = live ? c_raw : 0;
-        const size_t soff = combo_set_offset(np.enc, c, S);
+        const uint32_t soff = combo_set_offset(np.enc, c, S);
         uint32_t smp[CB][3];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -596,14 +598,84 @@ __device__ __forceinline__ void mlp_tail(const NetParams& np, floatx4 (&acc)[HW 
     }
 }
 
-// Whole network on segments [seg_base, seg_base + 16*CB); acts / enc_out as above.
+// Raw gamma value v of a segment (concatenated encoding): point v / GW, then sample s and axis a
+// of value 3 s + a: x, sin 2^k x or cos 2^k x of the clamped coordinate.
+__device__ __forceinline__ float gamma_value(const float* seg, int v, int GW) {
+    const int p = v >= GW ? 1 : 0, r = v - p * GW, s = r / 3, a = r - 3 * s;
+    const float x = fminf(fmaxf(seg[4 * p + a], 0.f), 1.f);
+    if (s == 0) return x;
+    const float f = (float)(1 << ((s - 1) >> 1));
+    return (s - 1) & 1 ? cosf(f * x) : sinf(f * x);
+}
+
+// First-layer contribution of the appended gamma values (columns E_phi .. E_phi + 2 GW) of
+// segments [seg_base, seg_base + 16 CB): lane (q, j) supplies value k of segment j for the
+// MFMA k-index it owns; enc_out (nullable) also receives the values.
 template <int HW, int CB, int PREC>
+__device__ __forceinline__ void layer1_gamma(const NetParams& np, const float* s_seg, int seg_base,
+                                             floatx4 (&acc)[HW / 16][CB], float* enc_out, int64_t seg_g0,
+                                             int64_t n_valid) {
+    constexpr int OB = HW / 16;
+    constexpr int KL = PREC == P_FP32 ? 1 : 4;    // k values per lane per MFMA
+    const int lane = lane_id();
+    const int q = lane >> 4, j = lane & 15;
+    const int GW = 3 * (1 + 2 * np.gamma_F), NV = 2 * GW;
+    for (int v0 = 0; v0 < NV; v0 += 4 * KL) {
+        float g[CB][KL];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const float* my = s_seg + (seg_base + cb * 16 + j) * kSegStride;
+#pragma unroll
+            for (int i = 0; i < KL; ++i) {
+                const int v = v0 + q * KL + i;
+                g[cb][i] = v < NV ? gamma_value(my, v, GW) : 0.f;
+            }
+            if (enc_out) {
+                const int64_t seg = seg_g0 + cb * 16 + j;
+                if (seg < n_valid)
+#pragma unroll
+                    for (int i = 0; i < KL; ++i) {
+                        const int v = v0 + q * KL + i;
+                        if (v < NV) enc_out[seg * np.E + np.E_phi + v] = g[cb][i];
+                    }
+            }
+        }
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) {
+            const size_t row = (size_t)(ob * 16 + j) * np.E + np.E_phi;
+            if constexpr (PREC == P_FP32) {
+                const int v = v0 + q;
+                const float w = v < NV ? reinterpret_cast<const float*>(np.W[0])[row + v] : 0.f;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(w, g[cb][0], acc[ob][cb]);
+            } else {
+                const uint16_t* wr = reinterpret_cast<const uint16_t*>(np.W[0]) + row;
+                shortx4 wa;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int v = v0 + q * 4 + i;
+                    wa[i] = v < NV ? (short)wr[v] : (short)0;
+                }
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const shortx4 gb = pack4<PREC>(g[cb][0], g[cb][1], g[cb][2], g[cb][3]);
+                    acc[ob][cb] = mfma16<PREC>(wa, gb, acc[ob][cb]);
+                }
+            }
+        }
+    }
+}
+
+// Whole network on segments [seg_base, seg_base + 16*CB); acts / enc_out as above.  GAMMA:
+// the concatenated encoding (compiled separately, so the other kernels carry none of its code).
+template <int HW, int CB, int PREC, bool GAMMA = false>
 __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg, int seg_base, float* s_z,
                                          float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid,
                                          float* enc_out = nullptr) {
     floatx4 acc[HW / 16][CB];
     layer1_bias<HW, CB>(np, acc);
     layer1_levels<HW, CB, PREC, 4>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
+    if constexpr (GAMMA) layer1_gamma<HW, CB, PREC>(np, s_seg, seg_base, acc, enc_out, seg_g0, n_valid);
     mlp_tail<HW, CB, PREC>(np, acc, seg_base, s_z, acts, act_stride_layer, seg_g0, n_valid);
 }
 

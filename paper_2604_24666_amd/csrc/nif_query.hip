@@ -246,7 +246,7 @@ __device__ __forceinline__ void unpark_trav(const Parked& pk, Trav& T) {
 
 // RPW rays per wave (64, or 16 for launches too small to hide the latency of a network round:
 // then a round is one pass of 16 segments instead of four, and four times as many waves run).
-template <int HW, int PREC, int RPW>
+template <int HW, int PREC, int RPW, bool GAMMA = false>
 __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats,
                                               int pose_times) {
@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
         }
         wave_lds_sync();
 #pragma unroll
-        for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
+        for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
         wave_lds_sync();
     }
     if (stats) wave_add_stats(stats, n_done, n_eval, bad);
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
 // Heads of point pairs.  Each wave evaluates tiles of 64 pairs; acts (nullable) receives the
 // hidden activations [layer][B][HW] and enc (nullable) the encoding [B][E], for the training
 // backward.
-template <int HW, int PREC>
+template <int HW, int PREC, bool GAMMA = false>
 __global__ void __launch_bounds__(256) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
                                                  int64_t B, float* __restrict__ heads, float* __restrict__ acts,
                                                  float* __restrict__ enc) {
@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(256) k_forward(NetParams np, const float* __re
         wave_lds_sync();
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps)
-            net_pass<HW, CB, PREC>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * 64 + ps * 16 * CB, B, enc);
+            net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * 64 + ps * 16 * CB, B, enc);
         wave_lds_sync();
         if (seg < B)
             for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
@@ -513,7 +513,9 @@ NetParams make_net_params(const nif_model* m, int32_t precision) {
     np.enc.f16 = d.table_dtype == NIF_TABLE_F16;
     np.enc.L = d.levels;
     np.enc.log2T = d.log2_table;
-    np.enc.F = d.pe_freqs;
+    np.enc.F = d.concat_encoding ? 0 : d.pe_freqs;      // the grid sees x only in the concatenated form
+    np.gamma_F = d.concat_encoding ? d.pe_freqs : -1;
+    np.E_phi = 2 * m->S * d.levels * d.feat_dim;
     np.enc.dense_mask = 0;
     np.enc.set_stride = d.per_sample_tables ? ((int64_t)d.levels << d.log2_table) : 0;
     for (int l = 0; l < d.levels; ++l) {
@@ -573,10 +575,14 @@ static void launch_query(const NetParams& np, const GridArgs& G, const RayArgs& 
     if (rpw == 0) rpw = R.n < kSmallLaunchRaysPerCU * device_cus() ? 16 : 64;
     const int64_t waves = (R.n + rpw - 1) / rpw;
     const int64_t blocks = std::max<int64_t>(std::min<int64_t>(waves, (int64_t)device_cus() * g_query_blocks_per_cu), 1);
-    if (rpw == 16)
+    if (np.gamma_F >= 0) {
+        const int64_t b64 = std::max<int64_t>(std::min<int64_t>((R.n + 63) / 64, (int64_t)device_cus() * g_query_blocks_per_cu), 1);
+        hipLaunchKernelGGL((k_query<HW, PREC, 64, true>), dim3((unsigned)b64), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
+    } else if (rpw == 16) {
         hipLaunchKernelGGL((k_query<HW, PREC, 16>), dim3((unsigned)blocks), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
-    else
+    } else {
         hipLaunchKernelGGL((k_query<HW, PREC, 64>), dim3((unsigned)blocks), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
+    }
 }
 
 template <int PREC>
@@ -679,7 +685,10 @@ static void launch_forward(const NetParams& np, const float* x0, const float* x1
                            float* enc, hipStream_t st) {
     const int64_t tiles = (B + 63) / 64;
     const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cus() * 8);
-    hipLaunchKernelGGL((k_forward<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts, enc);
+    if (np.gamma_F >= 0)
+        hipLaunchKernelGGL((k_forward<HW, PREC, true>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts, enc);
+    else
+        hipLaunchKernelGGL((k_forward<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts, enc);
 }
 
 template <int PREC>

@@ -35,6 +35,39 @@ constexpr int kGrowInterval = 1000;
 constexpr int64_t kEncBwdChunk = 1 << 16;  // samples per count/fill/reduce round
 constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
 
+// Concatenated encoding: d x of the appended gamma values, d enc_v = (W0^T delta_0)_v times
+// d gamma_v / d x_a of the clamped coordinate (zero outside the cube), added to dx0 / dx1.
+__global__ void __launch_bounds__(256) k_gamma_dx(const float* __restrict__ W0t, const float* __restrict__ delta0,
+                                                  int HW, int E_phi, int GW, const float* __restrict__ x0,
+                                                  const float* __restrict__ x1, int64_t B, float* __restrict__ dx0,
+                                                  float* __restrict__ dx1) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += (int64_t)gridDim.x * blockDim.x) {
+        const float* d = delta0 + i * HW;
+        for (int p = 0; p < 2; ++p) {
+            const float* xs = p ? x1 : x0;
+            float* dx = p ? dx1 : dx0;
+            float acc[3] = {0.f, 0.f, 0.f};
+            for (int r = 0; r < GW; ++r) {
+                const int s = r / 3, a = r - 3 * s;
+                const float* w = W0t + (size_t)(E_phi + p * GW + r) * HW;
+                float de = 0.f;
+                for (int o = 0; o < HW; ++o) de = fmaf(w[o], d[o], de);
+                const float x = fminf(fmaxf(xs[a * B + i], 0.f), 1.f);
+                float dg = 1.f;
+                if (s > 0) {
+                    const float f = (float)(1 << ((s - 1) >> 1));
+                    dg = (s - 1) & 1 ? -f * sinf(f * x) : f * cosf(f * x);
+                }
+                acc[a] = fmaf(de, dg, acc[a]);
+            }
+            for (int a = 0; a < 3; ++a) {
+                const float xv = xs[a * B + i];
+                if (xv >= 0.f && xv <= 1.f) dx[a * B + i] += acc[a];
+            }
+        }
+    }
+}
+
 // Arguments of the weight-gradient kernels (k_dw_part, k_dw_sum).
 struct DwArgs {
     const float* d; int dstride; int M_pad; int M_real;
@@ -1153,6 +1186,11 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, st, ep, total, parts);
         const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
         hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, st, ep, total, parts);
+    }
+    if (dx0 && m->GW > 0) {                  // concatenated encoding: d x through the raw gamma values
+        const int E_phi = 2 * m->S * m->desc.levels * m->desc.feat_dim;
+        hipLaunchKernelGGL(k_gamma_dx, dim3(grid_for(B)), dim3(256), 0, st, m->mlp_pad_f32 + m->wt_off[0], m->delta,
+                           hw, E_phi, m->GW, x0, x1, B, dx0, dx1);
     }
     return check_hip(hipGetLastError(), "backward launch");
 }

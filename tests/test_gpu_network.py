@@ -23,6 +23,9 @@ MODELS = {
     "small16": dataclasses.replace(S.workload("torus16").model, hidden_width=16, hidden_layers=1, n_materials=3),
     "w32": dataclasses.replace(S.workload("spheres64").model, hidden_width=32, hidden_layers=2, pe_freqs=2),
     "torus16_per_sample": dataclasses.replace(S.workload("torus16").model, per_sample_tables=1),
+    "torus16_concat": dataclasses.replace(S.workload("torus16").model, concat_encoding=1),
+    "w32_concat": dataclasses.replace(S.workload("spheres64").model, hidden_width=32, hidden_layers=2,
+                                      concat_encoding=1),
     "w32_per_sample": dataclasses.replace(S.workload("spheres64").model, hidden_width=32, hidden_layers=2,
                                           pe_freqs=2, log2_table=16, per_sample_tables=1),
 }
@@ -39,7 +42,7 @@ def _points(n, seed):
     return x0, x1
 
 
-@pytest.mark.parametrize("name", ["torus16", "spheres64", "torus16_per_sample", "w32_per_sample"])
+@pytest.mark.parametrize("name", ["torus16", "spheres64", "torus16_per_sample", "w32_per_sample", "torus16_concat"])
 def test_encoding_matches_oracle(orc, P, name):
     m = MODELS[name]
     say(f"encode {name}")
@@ -94,7 +97,7 @@ def test_fp32_heads_at_the_training_batch_size_sampled(orc, P):
 
 
 @pytest.mark.parametrize("prec,p99", [(1, 3e-2), (2, 4e-3)])
-@pytest.mark.parametrize("name", ["spheres64_p", "spheres64"])
+@pytest.mark.parametrize("name", ["spheres64_p", "spheres64", "w32_concat"])
 def test_low_precision_heads_error_per_head(orc, P, name, prec, p99):
     m = MODELS[name]
     say(f"forward prec={prec} {name}")

@@ -98,7 +98,7 @@ def test_query_torus16_fp32(orc, P, kind, s):
 
 ABLATIONS = {"sigmoid_head": dict(dist_head=S.DIST_SIGMOID), "no_pe": dict(pe_freqs=0),
              "no_pe_sigmoid_head": dict(pe_freqs=0, dist_head=S.DIST_SIGMOID),
-             "per_sample_tables": dict(per_sample_tables=1)}
+             "per_sample_tables": dict(per_sample_tables=1), "concat_encoding": dict(concat_encoding=1)}
 
 
 @pytest.mark.parametrize("variant", list(ABLATIONS))

@@ -50,6 +50,7 @@ def _grad_close(got, ref, name, big_frac=1e-3, el_tol=1e-4):
 MODELS = {
     "torus16": dataclasses.replace(S.workload("torus16").model, hidden_width=32),
     "torus16_per_sample": dataclasses.replace(S.workload("torus16").model, hidden_width=32, per_sample_tables=1),
+    "torus16_concat": dataclasses.replace(S.workload("torus16").model, hidden_width=32, concat_encoding=1),
     "spheres64": S.workload("spheres64").model,
     "blobs128": S.workload("blobs128").model,
 }
@@ -133,6 +134,7 @@ ABLATIONS = {
     "no_pe": (dict(pe_freqs=0), False),
     "no_pe_sigmoid_head_fixed_weights": (dict(pe_freqs=0, dist_head=S.DIST_SIGMOID), True),
     "per_sample_tables": (dict(per_sample_tables=1), False),
+    "concat_encoding": (dict(concat_encoding=1), False),
 }
 
 
@@ -144,6 +146,10 @@ def test_train_step_ablation_switches_match_oracle(orc, P, variant):
     m = dataclasses.replace(MODELS["torus16"], **kw)
     say(f"train step fp32 torus16 ablation {variant}")
     tab, prm, seen = model_params(m, 9, scale_tables=300.0)
+    # distance bias 1: the log-distance gradient 2 r / (d + eps) would otherwise amplify the
+    # FP32 rounding of the forward by up to 1 / eps wherever the predicted d is near 0 (the raw
+    # gamma inputs of the concatenated encoding spread the first-layer outputs by O(1))
+    prm[m.n_mlp_params - m.n_heads + 1] = 1.0
     B = 2048 + 13
     batch = _batch(m, B, 10)
     x0, x1, hit, t, nr, al, mt = batch
