@@ -66,6 +66,10 @@ struct nif_model {
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
     uint16_t* bwd_key = nullptr;        // table-gradient additions: entry within the bucket
     float2* bwd_val = nullptr;          //                            value per feature
+    uint32_t* ord_u32 = nullptr;        // batch ordering: keys and indices, 2 x 2 x max_batch
+    float* ord_f32 = nullptr;           //   the ordered batch (15 max_batch words)
+    void* ord_temp = nullptr;           //   radix-sort scratch
+    size_t ord_temp_bytes = 0;
     float* dw_part = nullptr;           // weight-gradient partial sums per K slice
     int64_t dw_part_n = 0;              //   capacity in floats
     double* dacc = nullptr;             // [16] loss sums, loss scale, Adam bias corrections
@@ -118,5 +122,9 @@ int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, c
 int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg,
                       float* losses, hipStream_t st);
 int model_reserve(nif_model* m, int64_t B);
+
+// nif_order.hip
+size_t order_temp_bytes(int64_t B);
+int order_batch(nif_model* m, const nif_batch* b, int64_t B, nif_batch* sorted, hipStream_t st);
 
 }  // namespace nif

@@ -141,6 +141,16 @@ int model_reserve(nif_model* m, int64_t B) {
             need = std::max(need, dw_part_floats(dw_shape(out ? 16 : (int)hw, m->dims[i], B, cus)));
         }
         if (m->dw_part) { (void)hipFree(m->dw_part); m->dw_part = nullptr; }
+        for (void** p : {(void**)&m->ord_u32, (void**)&m->ord_f32, (void**)&m->ord_temp})
+            if (*p) { (void)hipFree(*p); *p = nullptr; }
+        m->ord_temp_bytes = order_temp_bytes(B);
+        if (m->ord_temp_bytes == 0 ||
+            hipMalloc((void**)&m->ord_u32, sizeof(uint32_t) * 4 * (size_t)B) != hipSuccess ||
+            hipMalloc((void**)&m->ord_f32, sizeof(float) * 15 * (size_t)B) != hipSuccess ||
+            hipMalloc(&m->ord_temp, m->ord_temp_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(NIF_E_OOM, "batch-ordering scratch allocation failed");
+        }
         if (hipMalloc((void**)&m->dw_part, sizeof(float) * (size_t)need) != hipSuccess) {
             (void)hipGetLastError();
             return fail(NIF_E_OOM, "weight-gradient scratch allocation failed");
@@ -1206,8 +1216,18 @@ int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, c
     return backward_core(m, x0, x1, B, dx0, dx1, precision, st);
 }
 
-int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg, float* losses,
+// Batches at least this large are put in spatial order before the step (nif_order.hip).
+constexpr int64_t kOrderMinBatch = 1 << 14;
+
+int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_train_cfg* cfg, float* losses,
                       hipStream_t st) {
+    nif_batch ordered;
+    const nif_batch* b = b_in;
+    if (B >= kOrderMinBatch) {
+        const int rc = order_batch(m, b_in, B, &ordered, st);
+        if (rc) return rc;
+        b = &ordered;
+    }
     const int prec = cfg->precision;
     const float scale_init = cfg->loss_scale_init > 0.f ? cfg->loss_scale_init : (prec == NIF_PREC_FP16 ? 32768.f : 1.f);
     hipLaunchKernelGGL(k_train_begin, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, scale_init);
