@@ -121,7 +121,9 @@ int nif_model_get_grads(const nif_model* model, float* g_tables_dev, float* g_ml
                         nif_stream stream);
 int nif_model_zero_grads(nif_model* model, nif_stream stream);
 /* Allocates the training scratch for batches of up to max_batch samples (activations,
-   deltas); nif_backward and nif_train_step fail with NIF_E_STATE above it. */
+   deltas, the stored encoding, table-gradient additions, weight-gradient partials and the
+   spatially ordered copy of a batch); nif_backward and nif_train_step fail with NIF_E_STATE
+   above it. */
 int nif_model_reserve(nif_model* model, int64_t max_batch);
 
 /* ---------------------------------------------------------------- scene preparation
