@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 KQUERY_SOURCES = ["csrc/nif_query.hip", "csrc/nif_net.hpp", "csrc/nif_trace.hpp", "csrc/nif_device.hpp",
                   "csrc/nif_internal.hpp", "build.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "07225ae642504d172bee8dd4b13b8801b599994db96136b1bf2da77b38bc77eb",
-    "fetch_kib": 1.11824e8, "write_kib": 1.96452e6,         # per k_query<64, FP32, 64> launch, default workload
+    "sources_sha256": "61e0c6c93f2b6ff1a547b42981b7859f3c869e898cf60ea97779132fc1839351",
+    "fetch_kib": 1.12178e8, "write_kib": 1.96396e6,         # per k_query<64, FP32, 64> launch, default workload
     "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
 }
 
@@ -89,7 +89,7 @@ def setup(workload: str, precision: int):
                 kinds=kinds, strengths=strengths, precision=precision)
 
 
-def cpu_baseline(ctx, sample_stride: int = 16):
+def cpu_baseline(ctx, sample_stride: int = 4):
     """The FP64 oracle's query on a strided subset of pose 0's camera rays, timed on the host."""
     import nif_synth as S
     import oracle
@@ -107,7 +107,7 @@ def cpu_baseline(ctx, sample_stride: int = 16):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": o.shape[1] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
             "sample": f"{o.shape[1]} rays (every {sample_stride}th pixel of pose 0, "
-                      f"{['identity', 'twist', 'bend', 'taper'][int(ctx['kinds'][0])]} s={float(ctx['strengths'][0])}), "
+                      f"{['identity', 'twist', 'bend', 'taper', 'twist-bend'][int(ctx['kinds'][0])]} s={float(ctx['strengths'][0])}), "
                       f"FP64 oracle, {dt:.1f} s"}
 
 
