@@ -93,3 +93,17 @@ def test_bad_query_arguments_are_rejected_on_the_host(P):
     assert L.nif_query(None, g, C.byref(rays), 0, C.byref(hits), 0, 7, None, None) == 1      # bad precision
     assert L.nif_query(None, g, C.byref(rays), 0, C.byref(hits), 0x40, 0, None, None) == 1   # unknown flag
     assert L.nif_query(None, g, C.byref(rays), 0, C.byref(hits), 0, 0, None, None) == 1      # null model
+
+
+def test_launch_shape_setters_and_autotuner_validate_on_the_host(P):
+    L = P.lib()
+    assert L.nif_set_query_blocks_per_cu(0) == 1 and L.nif_set_query_blocks_per_cu(33) == 1
+    assert L.nif_set_query_rays_per_wave(32) == 1 and L.nif_set_query_rays_per_wave(-1) == 1
+    assert L.nif_set_query_rays_per_wave(0) == 0 and L.nif_set_query_blocks_per_cu(12) == 0
+    best = (C.c_int32 * 2)()
+    rays = P.Rays()
+    hits = P.Hits()
+    g = C.c_void_p(1)
+    assert L.nif_autotune_query(None, g, C.byref(rays), 4, C.byref(hits), 0, 2, best, None, None) == 1   # null model
+    assert L.nif_autotune_query(g, None, C.byref(rays), 4, C.byref(hits), 0, 2, best, None, None) == 1   # null grid
+    assert L.nif_last_error()
