@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 KQUERY_SOURCES = ["csrc/nif_query.hip", "csrc/nif_net.hpp", "csrc/nif_trace.hpp", "csrc/nif_device.hpp",
                   "csrc/nif_internal.hpp", "build.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "61e0c6c93f2b6ff1a547b42981b7859f3c869e898cf60ea97779132fc1839351",
-    "fetch_kib": 1.12178e8, "write_kib": 1.96396e6,         # per k_query<64, FP32, 64> launch, default workload
+    "sources_sha256": "ffa2aed23baf13a44b793e852fa49315eb682f9bfffa57f9c9c0ba571db98863",
+    "fetch_kib": 1.12175e8, "write_kib": 1.96578e6,         # per k_query<64, FP32, 64> launch, default workload
     "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
 }
 

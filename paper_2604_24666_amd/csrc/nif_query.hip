@@ -458,12 +458,14 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
 
 // Heads of point pairs.  Each wave evaluates tiles of 64 pairs; acts (nullable) receives the
 // hidden activations [layer][B][HW] and enc (nullable) the encoding [B][E], for the training
-// backward.
+// backward.  At width 128 each pass takes 16 of the tile's 64 points, which keeps the
+// accumulators small enough for two waves per SIMD; with spatially ordered batches that
+// latency hiding outweighs streaming the first-layer weights once per pass.
 template <int HW, int PREC, bool GAMMA = false>
-__global__ void __launch_bounds__(256) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
+__global__ void __launch_bounds__(256, 2) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
                                                  int64_t B, float* __restrict__ heads, float* __restrict__ acts,
                                                  float* __restrict__ enc) {
-    constexpr int CB = HW >= 128 ? 2 : 4;
+    constexpr int CB = HW >= 128 ? 1 : 4;
     constexpr int PASSES = 4 / CB;
     __shared__ float s_seg_all[4][64 * kSegStride];
     __shared__ float s_z_all[4][64 * kZStride];
