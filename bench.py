@@ -30,12 +30,15 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes that k_query moves per launch on the default workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE; KiB summed over the launch) scaled by what the same counters read for a
 # plain 1 GiB device copy (bench.py --calibrate-copy).  They hold only for the kernel sources they
-# were taken on (SHA-256 of KQUERY_SOURCES); otherwise the traffic is reported as null.
-KQUERY_SOURCES = ["csrc/nif_query.hip", "csrc/nif_net.hpp", "csrc/nif_trace.hpp", "csrc/nif_device.hpp",
-                  "csrc/nif_internal.hpp", "build.py"]
+# were taken on and the ray generator of the workload (SHA-256 of KQUERY_SOURCES); otherwise the
+# traffic is reported as null.
+KQUERY_SOURCES = ["paper_2604_24666_amd/csrc/nif_query.hip", "paper_2604_24666_amd/csrc/nif_net.hpp",
+                  "paper_2604_24666_amd/csrc/nif_trace.hpp", "paper_2604_24666_amd/csrc/nif_device.hpp",
+                  "paper_2604_24666_amd/csrc/nif_internal.hpp", "paper_2604_24666_amd/build.py",
+                  "nif_synth/__init__.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "ffa2aed23baf13a44b793e852fa49315eb682f9bfffa57f9c9c0ba571db98863",
-    "fetch_kib": 1.12175e8, "write_kib": 1.96578e6,         # per k_query<64, FP32, 64> launch, default workload
+    "sources_sha256": "0f07b9f794652294f213fcd22de62016a2a4add14e1c20cbf2db142a53f58ea5",
+    "fetch_kib": 1.04845e8, "write_kib": 1.9385e6,         # per k_query<64, FP32, 64> launch, default workload
     "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
 }
 
@@ -44,7 +47,7 @@ def kquery_sources_sha() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in KQUERY_SOURCES:
-        with open(os.path.join(ROOT, "paper_2604_24666_amd", f), "rb") as fh:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -79,7 +82,7 @@ def setup(workload: str, precision: int):
     o_all = torch.empty((3, n), device="cuda")
     d_all = torch.empty((3, n), device="cuda")
     for p in range(len(kinds)):
-        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p])
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], tile=w.cam_tile)
         o_all[:, p * n_pose:(p + 1) * n_pose] = torch.as_tensor(o).cuda()
         d_all[:, p * n_pose:(p + 1) * n_pose] = torch.as_tensor(d).cuda()
     off = torch.as_tensor(np.arange(len(kinds) + 1, dtype=np.int64) * n_pose).cuda()
@@ -171,7 +174,7 @@ def precision_leg(steps=5):
     o_all = torch.empty((3, 2 * n_pose), device="cuda")
     d_all = torch.empty((3, 2 * n_pose), device="cuda")
     for p in range(2):
-        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p])
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], tile=w.cam_tile)
         o_all[:, p * n_pose:(p + 1) * n_pose] = torch.as_tensor(o).cuda()
         d_all[:, p * n_pose:(p + 1) * n_pose] = torch.as_tensor(d).cuda()
     off = torch.tensor([0, n_pose, 2 * n_pose], dtype=torch.int64, device="cuda")
@@ -190,7 +193,7 @@ def precision_leg(steps=5):
         else:
             res[name]["vs_fp32"] = head_errors(got, ref)
         log(f"precision leg {name}: {ms:.2f} ms {res[name].get('vs_fp32', '')}")
-    return {"workload": "spheres64_p: 2 poses (twist, bend s=1) x 1024^2 pinhole rays, 16-level 2^19 FP16 grid, "
+    return {"workload": "spheres64_p: 2 poses (twist, bend s=1) x 1024^2 pinhole rays in 8x8 tiles, 16-level 2^19 FP16 grid, "
                         "MLP 832-128x4-12 (Xavier init)", **res,
             "note": "vs_fp32 compares with the FP32 path on the same rays (which the parity tests hold to the "
                     "FP64 oracle); per-head errors against the oracle itself: tests/test_gpu_network.py"}
@@ -689,7 +692,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": ["f32", "bf16", "f16"][args.precision], "data": "synthetic",
         "config": {"workload": f"{args.workload}: 8 spheres at 64^3, 24 poses (twist/bend/taper x 8 strengths), "
-                               f"24 x 1024^2 pinhole rays, 16-level 2^19 FP16 hash grid, F=6, MLP 832-64x3-12",
+                               f"24 x 1024^2 pinhole rays in 8x8 screen tiles, 16-level 2^19 FP16 hash grid, F=6, MLP 832-64x3-12",
                    "rays_per_step": n, "poses": len(ctx["kinds"]), "grid_rebuilt_each_step": not args.no_rebuild},
         "launch_shape": {"blocks_per_cu": shape[0], "rays_per_wave": shape[1], "chosen_by": "nif_autotune_query"},
         "query_kernel_ms": float(q_ms.mean()), "grid_rebuild_ms": float(b_ms.mean()),

@@ -100,6 +100,7 @@ class Workload:
     n_rays: int = 0                      # per pose for "camera" (res*res) or total for "random"
     cam_res: int = 0
     cam_az_deg: List[float] = field(default_factory=list)
+    cam_tile: int = 0                    # camera rays issued in cam_tile^2 screen tiles (0: rows)
     precision: int = PREC_FP32
 
 
@@ -119,9 +120,9 @@ def workload(name: str) -> Workload:
 
     torus16      -- 16^3 torus, one twist (0.6 rad per unit z), 4,096 random rays, FP32.
     spheres64    -- 8 random spheres at 64^3; twist/bend/taper x 8 strengths = 24 poses,
-                    1024x1024 pinhole rays each, FP32 inference, MLP 3x64.
-    spheres64_p  -- the same scene, 2 poses (twist, bend at full strength) x 1024^2 rays,
-                    MLP 4x128 for the FP32 / BF16 / FP16 comparison.
+                    1024x1024 pinhole rays each in 8x8 screen tiles, FP32 inference, MLP 3x64.
+    spheres64_p  -- the same scene, 2 poses (twist, bend at full strength) x 1024^2 rays
+                    in 8x8 tiles, MLP 4x128 for the FP32 / BF16 / FP16 comparison.
     blobs128     -- 32-Gaussian blob field at 128^3 for the training step, MLP 4x128.
     blobs128_b   -- the blob scene with 16 poses of uneven ray counts (batched query).
     """
@@ -135,11 +136,11 @@ def workload(name: str) -> Workload:
         return Workload(name, SCENE_SPHERES, 64, _C1_MODEL, seed=1001,
                         pose_kinds=kinds, pose_strengths=strengths, rays="camera",
                         cam_res=1024, n_rays=1024 * 1024,
-                        cam_az_deg=[15.0 * p for p in range(24)])
+                        cam_az_deg=[15.0 * p for p in range(24)], cam_tile=8)
     if name == "spheres64_p":
         return Workload(name, SCENE_SPHERES, 64, _C2_MODEL, seed=1001,
                         pose_kinds=[TWIST, BEND], pose_strengths=[1.0, 1.0], rays="camera",
-                        cam_res=1024, n_rays=1024 * 1024, cam_az_deg=[0.0, 90.0],
+                        cam_res=1024, n_rays=1024 * 1024, cam_az_deg=[0.0, 90.0], cam_tile=8,
                         precision=PREC_BF16)
     if name == "blobs128":
         return Workload(name, SCENE_BLOBS, 128, replace(_C2_MODEL), seed=1003,
@@ -224,11 +225,14 @@ def rays_inside(n: int, seed: int, lo: float = 0.0, hi: float = 1.0):
 
 
 def rays_camera(res: int, az_deg: float, elev_deg: float = 20.0, dist: float = 2.0,
-                vfov_deg: float = 45.0, sub: int = 1, sub_index: int = 0):
+                vfov_deg: float = 45.0, sub: int = 1, sub_index: int = 0, tile: int = 0):
     """Pinhole primary rays through pixel centres, eye at distance `dist` from the cube
     centre at the given azimuth/elevation, looking at the centre with +z up.
 
-    `sub` > 1 keeps every sub-th pixel (a strided subset, used to bound CPU work)."""
+    Rays come in row-major pixel order, or with `tile` > 0 (dividing `res`) in tile x tile
+    screen tiles, the tiles row-major and the pixels of a tile row-major, as a tiled renderer
+    issues them (with tile = 8 one 64-ray wave of the query covers one tile).
+    `sub` > 1 keeps every sub-th ray of that order (a strided subset, used to bound CPU work)."""
     az, el = math.radians(az_deg), math.radians(elev_deg)
     eye = np.array([0.5 + dist * math.cos(el) * math.cos(az),
                     0.5 + dist * math.cos(el) * math.sin(az),
@@ -237,7 +241,13 @@ def rays_camera(res: int, az_deg: float, elev_deg: float = 20.0, dist: float = 2
     right = _unit(np.cross(fwd, np.array([0.0, 0.0, 1.0])))
     up = np.cross(right, fwd)
     h = math.tan(math.radians(vfov_deg) / 2.0)
-    pix = np.arange(res * res, dtype=np.int64)[sub_index::sub]
+    pix = np.arange(res * res, dtype=np.int64)
+    if tile > 0:
+        assert res % tile == 0, "tile must divide res"
+        i = pix
+        t, r = i // (tile * tile), i % (tile * tile)
+        pix = ((t // (res // tile)) * tile + r // tile) * res + (t % (res // tile)) * tile + r % tile
+    pix = pix[sub_index::sub]
     px, py = (pix % res).astype(np.float64), (pix // res).astype(np.float64)
     sx = ((px + 0.5) / res * 2.0 - 1.0) * h
     sy = (1.0 - (py + 0.5) / res * 2.0) * h

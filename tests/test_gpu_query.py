@@ -255,7 +255,7 @@ def test_query_spheres64_full_workload_sampled(orc, P):
     o_all = torch.empty((3, 24 * n_pose), device="cuda")
     d_all = torch.empty((3, 24 * n_pose), device="cuda")
     for p in range(24):
-        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p])
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], tile=w.cam_tile)
         o_all[:, p * n_pose:(p + 1) * n_pose] = dev_f32(o)
         d_all[:, p * n_pose:(p + 1) * n_pose] = dev_f32(d)
     stats = torch.zeros(4, dtype=torch.int64, device="cuda")
@@ -272,7 +272,7 @@ def test_query_spheres64_full_workload_sampled(orc, P):
         # mostly rays that touch the geometry, plus a few that do not
         touch = np.nonzero(out["n_queried"][p * n_pose:(p + 1) * n_pose].cpu().numpy() > 0)[0]
         idx = np.sort(np.concatenate([rng.choice(touch, 300, replace=False), rng.integers(0, n_pose, 50)]))
-        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p])
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], tile=w.cam_tile)
         got = {k: v[p * n_pose:(p + 1) * n_pose][torch.as_tensor(idx).cuda()] for k, v in out.items()}
         say(f"  pose {p} kind {kinds[p]} s {strengths[p]}")
         n_ok, _ = _compare(orc, P, m, seen, prm, w.N, occ_ref, int(kinds[p]), float(strengths[p]),
