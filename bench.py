@@ -37,9 +37,9 @@ KQUERY_SOURCES = ["paper_2604_24666_amd/csrc/nif_query.hip", "paper_2604_24666_a
                   "paper_2604_24666_amd/csrc/nif_internal.hpp", "paper_2604_24666_amd/build.py",
                   "nif_synth/__init__.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "0f07b9f794652294f213fcd22de62016a2a4add14e1c20cbf2db142a53f58ea5",
-    "fetch_kib": 1.04845e8, "write_kib": 1.9385e6,         # per k_query<64, FP32, 64> launch, default workload
-    "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
+    "sources_sha256": "e36ad0daaf3e892dbcaafa489f2a3b38e71d33d9683eb5a26e3c616cef8a1234",
+    "fetch_kib": 1.04806e8, "write_kib": 1.94331e6,         # per k_query<64, FP32, 64> launch, default workload
+    "fetch_scale": 1048576 / 524304, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,304 / writes 1,048,576 KiB
 }
 
 
@@ -251,20 +251,30 @@ def train_leg(steps=5, B=1 << 18):
     batch = P.Batch(x0.data_ptr(), x1.data_ptr(), hit.data_ptr(), t.data_ptr(), nrm.data_ptr(), alb.data_ptr(),
                     mat.data_ptr())
     res = {}
-    for prec, name in ((1, "bf16"), (0, "fp32")):
-        model = P.Model(m)
-        model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))
-        P.nif_model_reserve(model.h, B)
-        cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, prec, 0.0)
-        losses = torch.zeros(16, device="cuda")
-        ms = timed(lambda: P.nif_train_step(model.h, batch, B, cfg, losses), steps, 2)
-        res[name] = {"samples_per_s": B / (ms * 1e-3), "ms_per_step": ms, "loss": float(losses[5])}
-        log(f"train leg {name}: {ms:.2f} ms per step of {B}")
-        del model
+    for store in (0, 1):
+        for prec, name in ((1, "bf16"), (0, "fp32")):
+            model = P.Model(m)
+            model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))
+            P.nif_model_reserve(model.h, B)
+            if store:
+                P.nif_model_reserve_encoding(model.h)
+            cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, prec, 0.0, 0, store)
+            losses = torch.zeros(16, device="cuda")
+            ms = timed(lambda: P.nif_train_step(model.h, batch, B, cfg, losses), steps, 2)
+            r = {"samples_per_s": B / (ms * 1e-3), "ms_per_step": ms, "loss": float(losses[5])}
+            if store:
+                res.setdefault("stored_encoding", {})[name] = r
+            else:
+                res[name] = r
+            log(f"train leg {name}{' stored encoding' if store else ''}: {ms:.2f} ms per step of {B}")
+            del model
     return {"workload": "blobs128: 32-Gaussian blob field at 128^3, B = 2^18 segments traced on the GPU from random "
                         "rays through 8 random twist/bend poses, labelled on the GPU from the analytic scene, "
                         "MLP 832-128x4-12, 16-level 2^19 FP16 grid, Adam", "hit_ratio": hit_ratio,
-            "label_ms": label_ms, **res}
+            "label_ms": label_ms,
+            "encoding_policy": "bf16 / fp32: the backward recomputes the encoding (chunks of 2^16 samples); "
+                               "stored_encoding: the forward keeps the [B][832] FP32 encoding for the backward",
+            **res}
 
 
 def _segment_dataset(P, grid, o, d, off, scene_kind, sp, max_seg):

@@ -121,10 +121,14 @@ int nif_model_get_grads(const nif_model* model, float* g_tables_dev, float* g_ml
                         nif_stream stream);
 int nif_model_zero_grads(nif_model* model, nif_stream stream);
 /* Allocates the training scratch for batches of up to max_batch samples (activations,
-   deltas, the stored encoding, table-gradient additions, weight-gradient partials and the
-   spatially ordered copy of a batch); nif_backward and nif_train_step fail with NIF_E_STATE
-   above it. */
+   deltas, a [min(max_batch, 2^16)][E] encoding scratch for the backward's recomputation,
+   table-gradient additions, weight-gradient partials and the spatially ordered copy of a
+   batch); nif_backward and nif_train_step fail with NIF_E_STATE above it.  A later call
+   with a larger max_batch frees and re-allocates everything, the stored encoding included. */
 int nif_model_reserve(nif_model* model, int64_t max_batch);
+/* Allocates the [max_batch][E] FP32 stored encoding that nif_train_step uses when
+   nif_train_cfg.store_encoding = 1 (NIF_E_STATE before nif_model_reserve; idempotent). */
+int nif_model_reserve_encoding(nif_model* model);
 
 /* ---------------------------------------------------------------- scene preparation
  * Rest-space voxelization (Methodology: the geometry is voxelized in rest space).  Cell
@@ -262,7 +266,9 @@ int nif_forward(const nif_model* model, const float* x0_dev, const float* x1_dev
 /* Backward of nif_forward given d heads [B][8 + n_materials]: adds dL/dtables, dL/dmlp to
  * the model's gradient accumulators (zeroed first unless accumulate != 0) and writes
  * dL/dx0, dL/dx1 (SoA, nullable).  Hand-written: MLP backward, hash-grid scatter-add with
- * the trilinear weights (FP32 atomics), PE chain rule; the encoding is recomputed. */
+ * the trilinear weights (additions grouped by table slice and summed in 64-bit fixed
+ * point), PE chain rule.  Nothing is kept from nif_forward: the hidden activations are
+ * recomputed, and the encoding is recomputed per chunk of 2^16 samples. */
 int nif_backward(nif_model* model, const float* x0_dev, const float* x1_dev, int64_t B,
                  const float* d_heads_dev, float* d_x0_dev, float* d_x1_dev, int32_t accumulate,
                  int32_t precision, nif_stream stream);
@@ -292,9 +298,29 @@ typedef struct {
     float loss_scale_init;      /* 0 = 1 for FP32/BF16, 32768 for FP16 */
     int32_t fixed_task_weights; /* 1 = ablation without uncertainty weighting: total = sum of
                                    the five task losses, s neither used nor updated */
+    int32_t store_encoding;     /* 0: the forward keeps no encoding; the backward recomputes it
+                                   (gathers again) per chunk of 2^16 samples for the first
+                                   layer's weight gradient, in a [2^16][E] FP32 scratch.
+                                   1: the forward stores the [B][E] FP32 encoding for the
+                                   backward (one gather pass less per step; max_batch E 4 bytes
+                                   more device memory, from nif_model_reserve_encoding; without
+                                   it the step fails with NIF_E_STATE).  The hidden activations
+                                   are stored in both cases. */
 } nif_train_cfg;
 int nif_train_step(nif_model* model, const nif_batch* batch, int64_t B, const nif_train_cfg* cfg,
                    float* losses_dev, nif_stream stream);
+
+/* The training step's loss on its own ("Uncertainty-Weighted Multi-Task Loss"), for callers
+ * that run the network themselves (the Python autograd wrapper): heads_dev [B][8 + n_materials]
+ * are raw MLP outputs, labels as in nif_batch (x0 / x1 read only by the sigmoid distance head),
+ * s_dev[5] the task log-variances.  Writes losses_dev[6] = {L_hit, L_dist, L_nrm, L_alb,
+ * L_mat, total}, d_heads_dev [B][8 + n_materials] = d total / d heads (nullable) and
+ * d_s_dev[5] = d total / d s (nullable; zero with fixed_task_weights, as in nif_train_cfg).
+ * Uses the model's description and a few words of accumulator it owns (not those of the
+ * training step); no allocation, no synchronisation. */
+int nif_loss(nif_model* model, const float* heads_dev, int64_t B, const nif_batch* labels, const float* s_dev,
+             int32_t fixed_task_weights, float* losses_dev, float* d_heads_dev, float* d_s_dev,
+             nif_stream stream);
 
 #ifdef __cplusplus
 }

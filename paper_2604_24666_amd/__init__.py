@@ -20,9 +20,10 @@ import torch
 __all__ = ["NifError", "lib", "ModelDesc", "Pose", "Rays", "Hits", "Segments", "Batch", "TrainCfg",
            "nif_model_create", "nif_model_destroy", "nif_model_sizes", "nif_model_set_params",
            "nif_model_get_params", "nif_model_get_grads", "nif_model_zero_grads", "nif_model_reserve",
+           "nif_model_reserve_encoding",
            "nif_voxelize", "nif_label", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
-           "nif_encode", "nif_forward", "nif_backward", "nif_train_step",
-           "Model", "Grid", "NifField", "label"]
+           "nif_encode", "nif_forward", "nif_backward", "nif_train_step", "nif_loss",
+           "Model", "Grid", "NifField", "NifMultiTaskLoss", "label"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnif.so")
@@ -74,7 +75,7 @@ class Batch(C.Structure):
 class TrainCfg(C.Structure):
     _fields_ = [("lr_table", C.c_float), ("lr_mlp", C.c_float), ("lr_s", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("precision", C.c_int32),
-                ("loss_scale_init", C.c_float), ("fixed_task_weights", C.c_int32)]
+                ("loss_scale_init", C.c_float), ("fixed_task_weights", C.c_int32), ("store_encoding", C.c_int32)]
 
 
 _lib = None
@@ -97,6 +98,7 @@ def lib():
             "nif_model_get_params": ([P, P, P, P, P], C.c_int),
             "nif_model_get_grads": ([P, P, P, P, P], C.c_int),
             "nif_model_zero_grads": ([P, P], C.c_int), "nif_model_reserve": ([P, I64], C.c_int),
+            "nif_model_reserve_encoding": ([P], C.c_int),
             "nif_voxelize": ([I32, P, I32, I32, P, P], C.c_int),
             "nif_label": ([I32, P, I32, I32, P, P, C.c_int64, P, P, P, P, P, P], C.c_int),
             "nif_build_grid": ([P, I32, P, I32, I32, P, P], C.c_int), "nif_grid_destroy": ([P], C.c_int),
@@ -110,6 +112,7 @@ def lib():
             "nif_forward": ([P, P, P, I64, P, I32, P], C.c_int),
             "nif_backward": ([P, P, P, I64, P, P, P, I32, I32, P], C.c_int),
             "nif_train_step": ([P, P, I64, P, P, P], C.c_int),
+            "nif_loss": ([P, P, I64, P, P, I32, P, P, P, P], C.c_int),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -177,6 +180,11 @@ def nif_model_zero_grads(h, stream=None):
 
 def nif_model_reserve(h, max_batch: int):
     _check(lib().nif_model_reserve(h, C.c_int64(max_batch)))
+
+
+def nif_model_reserve_encoding(h):
+    """Stored-encoding buffer for training steps with store_encoding = 1."""
+    _check(lib().nif_model_reserve_encoding(h))
 
 
 def nif_voxelize(scene_kind: int, params, N: int, occ, stream=None):
@@ -296,6 +304,11 @@ def nif_backward(model, x0, x1, B: int, d_heads, d_x0=None, d_x1=None, accumulat
 
 def nif_train_step(model, batch: Batch, B: int, cfg: TrainCfg, losses, stream=None):
     _check(lib().nif_train_step(model, C.byref(batch), B, C.byref(cfg), _ptr(losses), _stream(stream)))
+
+
+def nif_loss(model, heads, B: int, labels: Batch, s, fixed: bool, losses, d_heads=None, d_s=None, stream=None):
+    _check(lib().nif_loss(model, _ptr(heads), B, C.byref(labels), _ptr(s), int(fixed), _ptr(losses), _ptr(d_heads),
+                          _ptr(d_s), _stream(stream)))
 
 
 # ------------------------------------------------------------------ convenience objects
@@ -436,6 +449,34 @@ def alloc_hits(n, dev):
 def hits_struct(out) -> Hits:
     names = [f[0] for f in Hits._fields_]
     return Hits(*[out[k].data_ptr() if out.get(k) is not None else None for k in names])
+
+
+class NifMultiTaskLoss(torch.autograd.Function):
+    """Uncertainty-weighted multi-task loss with a hand-written backward (libnif kernels).
+
+    forward(heads [B][H], s [5], model, labels, fixed=False) -> total loss (0-d tensor);
+    labels = (x0, x1, hit, t, n, a, m) as in a training batch (x0 / x1 SoA [3][B], used by the
+    sigmoid distance head only; n, a SoA [3][B]).  Only the total is returned (nif_loss also
+    gives the five task losses).  backward returns d total / d heads and d total / d s."""
+
+    @staticmethod
+    def forward(ctx, heads, s, model, labels, fixed=False):
+        heads = heads.contiguous()
+        s = s.contiguous()
+        B = heads.shape[0]
+        keep = [t.contiguous() for t in labels]
+        b = Batch(*[t.data_ptr() for t in keep])
+        losses = torch.empty(6, device=heads.device)
+        d_heads = torch.empty_like(heads)
+        d_s = torch.empty(5, device=heads.device)
+        nif_loss(model.h, heads, B, b, s, fixed, losses, d_heads, d_s)
+        ctx.save_for_backward(d_heads, d_s)
+        return losses[5].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        d_heads, d_s = ctx.saved_tensors
+        return d_heads * g, d_s * g, None, None, None
 
 
 class NifField(torch.autograd.Function):

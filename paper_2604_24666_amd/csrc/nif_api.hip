@@ -169,6 +169,11 @@ int nif_model_reserve(nif_model* m, int64_t max_batch) {
     return nif::model_reserve(m, max_batch);
 }
 
+int nif_model_reserve_encoding(nif_model* m) {
+    REQUIRE(m, "model is null");
+    return nif::model_reserve_encoding(m);
+}
+
 int nif_voxelize(int32_t kind, const double* params, int32_t n_params, int32_t N, uint8_t* occ, nif_stream stream) {
     REQUIRE(kind >= 0 && kind <= 2, "scene_kind must be 0 (torus), 1 (spheres) or 2 (blobs)");
     REQUIRE(params && n_params >= 1, "params must not be empty");
@@ -351,6 +356,18 @@ int nif_backward(nif_model* m, const float* x0, const float* x1, int64_t B, cons
     return nif::backward_launch(m, x0, x1, B, dh, m->H, dx0, dx1, precision, S(stream));
 }
 
+int nif_loss(nif_model* m, const float* heads, int64_t B, const nif_batch* labels, const float* s,
+             int32_t fixed_task_weights, float* losses, float* d_heads, float* d_s, nif_stream stream) {
+    REQUIRE(m, "model is null");
+    REQUIRE(heads && labels && s && losses, "heads, labels, s and losses must not be null");
+    REQUIRE(B >= 1, "B must be >= 1");
+    REQUIRE(labels->hit && labels->t && labels->n && labels->a && labels->m, "label arrays must not be null");
+    REQUIRE(fixed_task_weights == 0 || fixed_task_weights == 1, "fixed_task_weights must be 0 or 1");
+    REQUIRE(m->desc.dist_head != NIF_DIST_SIGMOID || (labels->x0 && labels->x1),
+            "the sigmoid distance head needs the segment end points x0, x1");
+    return nif::loss_launch(m, heads, B, labels, s, fixed_task_weights, losses, d_heads, d_s, S(stream));
+}
+
 int nif_train_step(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg, float* losses, nif_stream stream) {
     REQUIRE(m, "model is null");
     REQUIRE(b && cfg && losses, "batch, cfg and losses must not be null");
@@ -359,6 +376,7 @@ int nif_train_step(nif_model* m, const nif_batch* b, int64_t B, const nif_train_
     REQUIRE(cfg->precision >= 0 && cfg->precision <= 2, "precision must be NIF_PREC_FP32, _BF16 or _FP16");
     REQUIRE(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps > 0.f, "bad Adam hyper-parameters");
     REQUIRE(cfg->fixed_task_weights == 0 || cfg->fixed_task_weights == 1, "fixed_task_weights must be 0 or 1");
+    REQUIRE(cfg->store_encoding == 0 || cfg->store_encoding == 1, "store_encoding must be 0 or 1");
     if (!m->params_set) return fail(NIF_E_STATE, "model parameters were never set");
     if (B > m->max_batch) return fail(NIF_E_STATE, "batch larger than reserved with nif_model_reserve");
     return nif::train_step_launch(m, b, B, cfg, losses, S(stream));

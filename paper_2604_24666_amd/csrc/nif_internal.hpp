@@ -60,7 +60,9 @@ struct nif_model {
     float* dz = nullptr;                // [max_batch][16] d loss / d heads (loss-scaled, padded)
     float* acts = nullptr;              // [hidden_layers][max_batch][hidden_width] post-ReLU
     float* delta = nullptr;             // [hidden_layers][max_batch][hidden_width] d loss / d pre-activation
-    float* enc = nullptr;               // [max_batch][E] encoding of the training forward
+    float* enc = nullptr;               // [bwd_chunk][E] encoding recomputed for the first layer's dW
+    float* enc_all = nullptr;           // [max_batch][E] stored encoding (store_encoding steps only;
+                                        //   allocated by nif_model_reserve_encoding)
     int64_t bwd_chunk = 0;              // samples per encoding-backward round
     int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
@@ -111,6 +113,10 @@ int label_launch(int kind, const double* params_host, int32_t n_params, int forc
                  hipStream_t st);
 int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads,
                    int32_t precision, float* acts, float* enc, hipStream_t st);
+// Encoding only of n pairs whose SoA rows have stride ld: enc[n][E], the values the forward
+// of the same precision feeds its first layer.
+int encode_pairs_launch(const nif_model* m, const float* x0, const float* x1, int64_t n, int64_t ld,
+                        int32_t precision, float* enc, hipStream_t st);
 
 // nif_train.hip
 int model_alloc(nif_model* m);
@@ -122,6 +128,9 @@ int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, c
 int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg,
                       float* losses, hipStream_t st);
 int model_reserve(nif_model* m, int64_t B);
+int model_reserve_encoding(nif_model* m);
+int loss_launch(nif_model* m, const float* heads, int64_t B, const nif_batch* b, const float* s, int32_t fixed,
+                float* losses, float* d_heads, float* d_s, hipStream_t st);
 
 // nif_order.hip
 size_t order_temp_bytes(int64_t B);

@@ -456,41 +456,62 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
     }
 }
 
+// Encoding of segments [seg_base, seg_base + 16*CB) into enc_out only (no MLP past the
+// first layer's accumulation, whose result is dropped).
+template <int HW, int CB, int PREC, bool GAMMA>
+__device__ __forceinline__ void enc_pass(const NetParams& np, const float* s_seg, int seg_base, int64_t seg_g0,
+                                         int64_t n_valid, float* enc_out) {
+    floatx4 acc[HW / 16][CB];
+    layer1_bias<HW, CB>(np, acc);
+    layer1_levels<HW, CB, PREC, 4>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
+    if constexpr (GAMMA) layer1_gamma<HW, CB, PREC>(np, s_seg, seg_base, acc, enc_out, seg_g0, n_valid);
+}
+
 // Heads of point pairs.  Each wave evaluates tiles of 64 pairs; acts (nullable) receives the
 // hidden activations [layer][B][HW] and enc (nullable) the encoding [B][E], for the training
-// backward.  At width 128 each pass takes 16 of the tile's 64 points, which keeps the
-// accumulators small enough for two waves per SIMD; with spatially ordered batches that
-// latency hiding outweighs streaming the first-layer weights once per pass.
-template <int HW, int PREC, bool GAMMA = false>
+// backward.  x0 / x1 are SoA with row stride ld >= B.  ENC_ONLY: only the encoding is written
+// (the backward's recomputation, per chunk of samples; heads and acts unused), in tiles of 16
+// pairs so that a chunk still spreads over many waves.  At width 128 each pass takes 16 of
+// the tile's 64 points, which keeps the accumulators small enough for two waves per SIMD; with
+// spatially ordered batches that latency hiding outweighs streaming the first-layer weights
+// once per pass.
+template <int HW, int PREC, bool GAMMA = false, bool ENC_ONLY = false>
 __global__ void __launch_bounds__(256, 2) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
-                                                 int64_t B, float* __restrict__ heads, float* __restrict__ acts,
-                                                 float* __restrict__ enc) {
-    constexpr int CB = HW >= 128 ? 1 : 4;
-    constexpr int PASSES = 4 / CB;
+                                                 int64_t B, int64_t ld, float* __restrict__ heads,
+                                                 float* __restrict__ acts, float* __restrict__ enc) {
+    constexpr int TILE = ENC_ONLY ? 16 : 64;
+    constexpr int CB = ENC_ONLY || HW >= 128 ? 1 : 4;
+    constexpr int PASSES = TILE / 16 / CB;
     __shared__ float s_seg_all[4][64 * kSegStride];
     __shared__ float s_z_all[4][64 * kZStride];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     float* s_seg = s_seg_all[w];
     float* s_z = s_z_all[w];
-    const int64_t n_tiles = (B + 63) / 64;
+    const int64_t n_tiles = (B + TILE - 1) / TILE;
     const int64_t wave_g = (int64_t)blockIdx.x * 4 + w, n_waves = (int64_t)gridDim.x * 4;
     for (int64_t tile = wave_g; tile < n_tiles; tile += n_waves) {
-        const int64_t seg = tile * 64 + lane;
+        const int64_t seg = tile * TILE + lane;
         float* my = s_seg + lane * kSegStride;
-        if (seg < B) {
-            my[0] = x0[seg]; my[1] = x0[B + seg]; my[2] = x0[2 * B + seg];
-            my[4] = x1[seg]; my[5] = x1[B + seg]; my[6] = x1[2 * B + seg];
+        if (lane < TILE && seg < B) {
+            my[0] = x0[seg]; my[1] = x0[ld + seg]; my[2] = x0[2 * ld + seg];
+            my[4] = x1[seg]; my[5] = x1[ld + seg]; my[6] = x1[2 * ld + seg];
         } else {
             my[0] = my[1] = my[2] = my[4] = my[5] = my[6] = 0.5f;
         }
         wave_lds_sync();
+        if constexpr (ENC_ONLY) {
 #pragma unroll
-        for (int ps = 0; ps < PASSES; ++ps)
-            net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * 64 + ps * 16 * CB, B, enc);
-        wave_lds_sync();
-        if (seg < B)
-            for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
+            for (int ps = 0; ps < PASSES; ++ps)
+                enc_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, tile * TILE + ps * 16 * CB, B, enc);
+        } else {
+#pragma unroll
+            for (int ps = 0; ps < PASSES; ++ps)
+                net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * TILE + ps * 16 * CB, B, enc);
+            wave_lds_sync();
+            if (seg < B)
+                for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
+        }
         wave_lds_sync();
     }
 }
@@ -683,40 +704,54 @@ int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hip
 }
 
 template <int HW, int PREC>
-static void launch_forward(const NetParams& np, const float* x0, const float* x1, int64_t B, float* heads, float* acts,
-                           float* enc, hipStream_t st) {
-    const int64_t tiles = (B + 63) / 64;
+static void launch_forward(const NetParams& np, const float* x0, const float* x1, int64_t B, int64_t ld, float* heads,
+                           float* acts, float* enc, hipStream_t st) {
+    const bool gamma = np.gamma_F >= 0, enc_only = heads == nullptr;
+    const int64_t tiles = enc_only ? (B + 15) / 16 : (B + 63) / 64;
     const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cus() * 8);
-    if (np.gamma_F >= 0)
-        hipLaunchKernelGGL((k_forward<HW, PREC, true>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts, enc);
-    else
-        hipLaunchKernelGGL((k_forward<HW, PREC>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, np, x0, x1, B, heads, acts, enc);
+    const dim3 g((unsigned)std::max<int64_t>(blocks, 1)), b(256);
+    if (gamma && enc_only) hipLaunchKernelGGL((k_forward<HW, PREC, true, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+    else if (gamma) hipLaunchKernelGGL((k_forward<HW, PREC, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+    else if (enc_only) hipLaunchKernelGGL((k_forward<HW, PREC, false, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+    else hipLaunchKernelGGL((k_forward<HW, PREC>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
 }
 
 template <int PREC>
-static int dispatch_forward(int hw, const NetParams& np, const float* x0, const float* x1, int64_t B, float* heads,
-                            float* acts, float* enc, hipStream_t st) {
+static int dispatch_forward(int hw, const NetParams& np, const float* x0, const float* x1, int64_t B, int64_t ld,
+                            float* heads, float* acts, float* enc, hipStream_t st) {
     switch (hw) {
-        case 16: launch_forward<16, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
-        case 32: launch_forward<32, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
-        case 64: launch_forward<64, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
-        case 128: launch_forward<128, PREC>(np, x0, x1, B, heads, acts, enc, st); break;
+        case 16: launch_forward<16, PREC>(np, x0, x1, B, ld, heads, acts, enc, st); break;
+        case 32: launch_forward<32, PREC>(np, x0, x1, B, ld, heads, acts, enc, st); break;
+        case 64: launch_forward<64, PREC>(np, x0, x1, B, ld, heads, acts, enc, st); break;
+        case 128: launch_forward<128, PREC>(np, x0, x1, B, ld, heads, acts, enc, st); break;
         default: return fail(NIF_E_UNSUPPORTED, "hidden_width must be 16, 32, 64 or 128");
     }
     return NIF_OK;
 }
 
-int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads, int32_t precision,
-                   float* acts, float* enc, hipStream_t st) {
+static int forward_any(const nif_model* m, const float* x0, const float* x1, int64_t B, int64_t ld, float* heads,
+                       int32_t precision, float* acts, float* enc, hipStream_t st) {
     if (B == 0) return NIF_OK;
     const NetParams np = make_net_params(m, precision);
     const int hw = m->desc.hidden_width;
     int rc;
-    if (precision == NIF_PREC_FP32) rc = dispatch_forward<P_FP32>(hw, np, x0, x1, B, heads, acts, enc, st);
-    else if (precision == NIF_PREC_BF16) rc = dispatch_forward<P_BF16>(hw, np, x0, x1, B, heads, acts, enc, st);
-    else rc = dispatch_forward<P_FP16>(hw, np, x0, x1, B, heads, acts, enc, st);
+    if (precision == NIF_PREC_FP32) rc = dispatch_forward<P_FP32>(hw, np, x0, x1, B, ld, heads, acts, enc, st);
+    else if (precision == NIF_PREC_BF16) rc = dispatch_forward<P_BF16>(hw, np, x0, x1, B, ld, heads, acts, enc, st);
+    else rc = dispatch_forward<P_FP16>(hw, np, x0, x1, B, ld, heads, acts, enc, st);
     if (rc) return rc;
     return check_hip(hipGetLastError(), "k_forward launch");
+}
+
+int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads, int32_t precision,
+                   float* acts, float* enc, hipStream_t st) {
+    if (heads == nullptr) return fail(NIF_E_INVALID_ARG, "forward needs a heads buffer");
+    return forward_any(m, x0, x1, B, B, heads, precision, acts, enc, st);
+}
+
+int encode_pairs_launch(const nif_model* m, const float* x0, const float* x1, int64_t n, int64_t ld, int32_t precision,
+                        float* enc, hipStream_t st) {
+    if (enc == nullptr || ld < n) return fail(NIF_E_INVALID_ARG, "pair encoding needs an output and ld >= n");
+    return forward_any(m, x0, x1, n, ld, nullptr, precision, nullptr, enc, st);
 }
 
 }  // namespace nif

@@ -98,7 +98,7 @@ static int64_t dw_part_floats(const DwArgs& A) { return A.n_slots * A.M_pad * ((
 
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
-    for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta, &m->enc})
+    for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta, &m->enc, &m->enc_all})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
     for (void** p : {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
@@ -125,7 +125,7 @@ int model_reserve(nif_model* m, int64_t B) {
     }
     const int64_t hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
     const struct { float** p; int64_t n; } a[] = {{&m->zbuf, B * m->H}, {&m->dz, B * 16}, {&m->acts, B * hw * nh},
-                                                  {&m->delta, B * hw * nh}, {&m->enc, B * m->E}};
+                                                  {&m->delta, B * hw * nh}, {&m->enc, m->bwd_chunk * m->E}};
     for (auto& x : a)
         if (hipMalloc((void**)x.p, sizeof(float) * (size_t)std::max<int64_t>(x.n, 1)) != hipSuccess) {
             (void)hipGetLastError();
@@ -158,6 +158,17 @@ int model_reserve(nif_model* m, int64_t B) {
         m->dw_part_n = need;
     }
     m->max_batch = B;
+    return NIF_OK;
+}
+
+int model_reserve_encoding(nif_model* m) {
+    if (m->max_batch <= 0) return fail(NIF_E_STATE, "nif_model_reserve must come first");
+    if (m->enc_all) return NIF_OK;
+    if (hipMalloc((void**)&m->enc_all, sizeof(float) * (size_t)m->max_batch * m->E) != hipSuccess) {
+        (void)hipGetLastError();
+        m->enc_all = nullptr;
+        return fail(NIF_E_OOM, "stored-encoding allocation failed");
+    }
     return NIF_OK;
 }
 
@@ -199,7 +210,7 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H
                                               const float* __restrict__ ln, const float* __restrict__ la,
                                               const int32_t* __restrict__ lm, const float* __restrict__ s,
                                               const int64_t* __restrict__ tcount, double* __restrict__ dacc,
-                                              float* __restrict__ dz, const float* __restrict__ x0,
+                                              float* __restrict__ dz, int dz_ld, const float* __restrict__ x0,
                                               const float* __restrict__ x1, int dist_head, int fixed) {
     const int M = H - 8;
     const double P = (double)tcount[TC_NPOS];
@@ -267,9 +278,15 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H
                     if (c2 < M) g[8 + c2] = w4 * (expf(zi[8 + c2] - lse) - (c2 == mi ? 1.f : 0.f)) * invP;
             }
         }
-        float4* dst = reinterpret_cast<float4*>(dz + i * 16);
+        if (dz_ld == 16) {
+            float4* dst = reinterpret_cast<float4*>(dz + i * 16);
 #pragma unroll
-        for (int h = 0; h < 4; ++h) dst[h] = make_float4(scale * g[4 * h], scale * g[4 * h + 1], scale * g[4 * h + 2], scale * g[4 * h + 3]);
+            for (int h = 0; h < 4; ++h) dst[h] = make_float4(scale * g[4 * h], scale * g[4 * h + 1], scale * g[4 * h + 2], scale * g[4 * h + 3]);
+        } else if (dz) {
+#pragma unroll
+            for (int h = 0; h < 16; ++h)
+                if (h < H) dz[i * dz_ld + h] = scale * g[h];
+        }
     }
     __shared__ double red[4][5];
 #pragma unroll
@@ -973,6 +990,40 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     }
 }
 
+// ------------------------------------------------------------------ the loss on its own
+// nif_loss uses the upper halves of the model's accumulators (sums at dacc[9..13], scale 1 at
+// dacc[15], positives at tcount[8]), so a training step's loss scale and counters are untouched.
+constexpr int kLossDacc = 9, kLossTcount = 8;
+
+__global__ void k_loss_begin(double* dacc, int64_t* tcount) {
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 5; ++k) dacc[DA_SUM + k] = 0.0;
+    dacc[DA_SCALE_USED] = 1.0;
+    tcount[TC_NPOS] = 0;
+}
+
+// Task losses and total (Eq. of the uncertainty-weighted loss) and d total / d s.
+__global__ void k_loss_out(const double* dacc, const int64_t* tcount, const float* s, int64_t B, int fixed,
+                           float* losses, float* g_s) {
+    if (threadIdx.x != 0) return;
+    const double P = (double)tcount[TC_NPOS];
+    double total = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        const double Lk = k == 0 ? dacc[DA_SUM] / (double)B : (P > 0 ? dacc[DA_SUM + k] / P : 0.0);
+        const double w = (k == 0 || k == 4 ? 1.0 : 0.5) * exp(-(double)s[k]);
+        losses[k] = (float)Lk;
+        if (fixed) {
+            total += Lk;
+            if (g_s) g_s[k] = 0.f;
+        } else {
+            total += w * Lk + 0.5 * s[k];
+            if (g_s) g_s[k] = (float)(-w * Lk + 0.5);
+        }
+    }
+    losses[5] = (float)total;
+}
+
+
 // ------------------------------------------------------------------ step bookkeeping
 
 __global__ void k_check_finite(const float* __restrict__ a, int64_t n, int64_t* tcount) {
@@ -1109,8 +1160,35 @@ static int dispatch_mlp_bwd(int hw, const BwdParams& bp, const float* dz, const 
 }
 
 // Backward from dz (already in m->dz) to the gradient accumulators; activations in m->acts.
+// One layer's weight gradient over rows [0, B) of d (stride dstride) and h (stride hstride),
+// added to gW / gb: K-sliced MFMA partials, then a sum per output.
+static int weight_grad(nif_model* m, int layer, const float* d, int dstride, int M_pad, const float* h, int64_t B,
+                       int cus, hipStream_t st) {
+    DwArgs A = dw_shape(M_pad, m->dims[layer], B, cus);
+    A.d = d;
+    A.dstride = dstride;
+    A.M_real = m->dims[layer + 1];
+    A.h = h;
+    A.hstride = m->dims[layer];
+    A.part = m->dw_part;
+    if (dw_part_floats(A) > m->dw_part_n) return fail(NIF_E_STATE, "weight-gradient scratch too small");
+    const dim3 grid((unsigned)((B + A.Kc - 1) / A.Kc), (unsigned)(A.ks > 1 ? 1 : (A.n_cb + 3) / 4));
+    switch (A.M_pad / 16) {
+        case 1: hipLaunchKernelGGL(k_dw_part<1>, grid, dim3(256), 0, st, A); break;
+        case 2: hipLaunchKernelGGL(k_dw_part<2>, grid, dim3(256), 0, st, A); break;
+        case 4: hipLaunchKernelGGL(k_dw_part<4>, grid, dim3(256), 0, st, A); break;
+        default: hipLaunchKernelGGL(k_dw_part<8>, grid, dim3(256), 0, st, A); break;
+    }
+    const int64_t n_out = (int64_t)A.M_real * A.N + A.M_real;
+    hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((n_out + 63) / 64)), dim3(256), 0, st, A,
+                       m->g_mlp + m->w_off[layer], A.N, m->g_mlp + m->b_off[layer]);
+    return NIF_OK;
+}
+
+// Backward from m->dz.  enc_stored: the forward's encoding [B][E], or null to recompute it
+// per chunk of bwd_chunk samples for the first layer's weight gradient.
 static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t B, float* dx0, float* dx1,
-                         int32_t precision, hipStream_t st) {
+                         int32_t precision, const float* enc_stored, hipStream_t st) {
     const int hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
     BwdParams bp;
     memset(&bp, 0, sizeof(bp));
@@ -1125,30 +1203,25 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     else if (precision == NIF_PREC_BF16) rc = dispatch_mlp_bwd<P_BF16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     else rc = dispatch_mlp_bwd<P_FP16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     if (rc) return rc;
-    // weight gradients of every layer (layer 0 from the stored encoding)
+    // weight gradients of every layer (layer 0 from the stored or the recomputed encoding)
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     for (int i = 0; i < m->n_layers; ++i) {
         const bool out = i == m->n_layers - 1;
-        DwArgs A = dw_shape(out ? 16 : hw, m->dims[i], B, cus);
-        A.d = out ? m->dz : m->delta + (size_t)i * B * hw;
-        A.dstride = out ? 16 : hw;
-        A.M_real = m->dims[i + 1];
-        A.h = i == 0 ? m->enc : m->acts + (size_t)(i - 1) * B * hw;
-        A.hstride = m->dims[i];
-        A.part = m->dw_part;
-        if (dw_part_floats(A) > m->dw_part_n) return fail(NIF_E_STATE, "weight-gradient scratch too small");
-        const dim3 grid((unsigned)((B + A.Kc - 1) / A.Kc), (unsigned)(A.ks > 1 ? 1 : (A.n_cb + 3) / 4));
-        switch (A.M_pad / 16) {
-            case 1: hipLaunchKernelGGL(k_dw_part<1>, grid, dim3(256), 0, st, A); break;
-            case 2: hipLaunchKernelGGL(k_dw_part<2>, grid, dim3(256), 0, st, A); break;
-            case 4: hipLaunchKernelGGL(k_dw_part<4>, grid, dim3(256), 0, st, A); break;
-            default: hipLaunchKernelGGL(k_dw_part<8>, grid, dim3(256), 0, st, A); break;
+        const float* d = out ? m->dz : m->delta + (size_t)i * B * hw;
+        const int ds = out ? 16 : hw;
+        if (i > 0) {
+            if ((rc = weight_grad(m, i, d, ds, ds, m->acts + (size_t)(i - 1) * B * hw, B, cus, st))) return rc;
+        } else if (enc_stored) {
+            if ((rc = weight_grad(m, 0, d, ds, ds, enc_stored, B, cus, st))) return rc;
+        } else {
+            for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
+                const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
+                if ((rc = encode_pairs_launch(m, x0 + c0, x1 + c0, n, B, precision, m->enc, st))) return rc;
+                if ((rc = weight_grad(m, 0, d + (size_t)c0 * ds, ds, ds, m->enc, n, cus, st))) return rc;
+            }
         }
-        const int64_t n_out = (int64_t)A.M_real * A.N + A.M_real;
-        hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((n_out + 63) / 64)), dim3(256), 0, st, A,
-                           m->g_mlp + m->w_off[i], A.N, m->g_mlp + m->b_off[i]);
     }
     // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
     EncBwdParams ep;
@@ -1208,12 +1281,24 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
 int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh, int32_t, float* dx0,
                     float* dx1, int32_t precision, hipStream_t st) {
     if (B == 0) return NIF_OK;
-    int rc = forward_launch(m, x0, x1, B, m->zbuf, precision, m->acts, m->enc, st);
+    int rc = forward_launch(m, x0, x1, B, m->zbuf, precision, m->acts, nullptr, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_pad_dz, dim3(grid_for(B * 16)), dim3(256), 0, st, dh, m->H, B, m->dz);
     if (dx0) hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * B)), dim3(256), 0, st, dx0, 3 * B);
     if (dx1) hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(3 * B)), dim3(256), 0, st, dx1, 3 * B);
-    return backward_core(m, x0, x1, B, dx0, dx1, precision, st);
+    return backward_core(m, x0, x1, B, dx0, dx1, precision, nullptr, st);
+}
+
+int loss_launch(nif_model* m, const float* heads, int64_t B, const nif_batch* b, const float* s, int32_t fixed,
+                float* losses, float* d_heads, float* d_s, hipStream_t st) {
+    double* dacc = m->dacc + kLossDacc;
+    int64_t* tcount = m->tcount + kLossTcount;
+    hipLaunchKernelGGL(k_loss_begin, dim3(1), dim3(64), 0, st, dacc, tcount);
+    hipLaunchKernelGGL(k_count_pos, dim3(grid_for(B)), dim3(256), 0, st, b->hit, B, tcount);
+    hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, heads, m->H, B, b->hit, b->t, b->n, b->a, b->m,
+                       s, tcount, dacc, d_heads, m->H, b->x0, b->x1, m->desc.dist_head, fixed);
+    hipLaunchKernelGGL(k_loss_out, dim3(1), dim3(64), 0, st, dacc, tcount, s, B, fixed, losses, d_s);
+    return check_hip(hipGetLastError(), "loss launch");
 }
 
 // Batches at least this large are put in spatial order before the step (nif_order.hip).
@@ -1234,11 +1319,14 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
     hipLaunchKernelGGL(k_count_pos, dim3(grid_for(B)), dim3(256), 0, st, b->hit, B, m->tcount);
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table);
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp);
-    int rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, m->enc, st);
-    if (rc) return rc;
+    int rc;
+    if (cfg->store_encoding && !m->enc_all)
+        return fail(NIF_E_STATE, "store_encoding needs nif_model_reserve_encoding first");
+    float* enc_keep = cfg->store_encoding ? m->enc_all : nullptr;
+    if ((rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, enc_keep, st))) return rc;
     hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, m->zbuf, m->H, B, b->hit, b->t, b->n, b->a, b->m,
-                       m->s, m->tcount, m->dacc, m->dz, b->x0, b->x1, m->desc.dist_head, cfg->fixed_task_weights);
-    if ((rc = backward_core(m, b->x0, b->x1, B, nullptr, nullptr, prec, st))) return rc;
+                       m->s, m->tcount, m->dacc, m->dz, 16, b->x0, b->x1, m->desc.dist_head, cfg->fixed_task_weights);
+    if ((rc = backward_core(m, b->x0, b->x1, B, nullptr, nullptr, prec, enc_keep, st))) return rc;
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table, m->tcount);
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp, m->tcount);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, m->s, m->g_s, losses, B,

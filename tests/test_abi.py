@@ -107,3 +107,58 @@ def test_launch_shape_setters_and_autotuner_validate_on_the_host(P):
     assert L.nif_autotune_query(None, g, C.byref(rays), 4, C.byref(hits), 0, 2, best, None, None) == 1   # null model
     assert L.nif_autotune_query(g, None, C.byref(rays), 4, C.byref(hits), 0, 2, best, None, None) == 1   # null grid
     assert L.nif_last_error()
+
+
+def test_train_step_configuration_is_validated_on_the_host(P):
+    L = P.lib()
+    fake = C.c_void_p(1)
+    batch = P.Batch(*([1] * 7))
+    good = dict(lr_table=1e-2, lr_mlp=1e-3, lr_s=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, precision=0,
+                loss_scale_init=0.0, fixed_task_weights=0, store_encoding=0)
+    for k, v in [("store_encoding", 2), ("store_encoding", -1), ("fixed_task_weights", 3), ("precision", 3),
+                 ("beta1", 1.0), ("eps", 0.0)]:
+        cfg = P.TrainCfg(**{**good, k: v})
+        assert L.nif_train_step(fake, C.byref(batch), 4, C.byref(cfg), fake, None) == 1, k
+    assert L.nif_train_step(fake, C.byref(batch), 0, C.byref(P.TrainCfg(**good)), fake, None) == 1   # empty batch
+    assert L.nif_model_reserve_encoding(None) == 1
+
+
+def test_binding_structures_match_the_header_layout(P, tmp_path):
+    """Every struct the Python binding passes through the C ABI has the header's size and
+    field offsets (a C program compiled from include/nif.h prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"nif_model_desc": P.ModelDesc, "nif_pose": P.Pose, "nif_rays": P.Rays, "nif_segments": P.Segments,
+             "nif_hits": P.Hits, "nif_batch": P.Batch, "nif_train_cfg": P.TrainCfg}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nif.h"', 'int main(void) {']
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    for cname, py in pairs.items():
+        assert int(got[f"{cname} size"]) == C.sizeof(py), cname
+        for f in py._fields_:
+            assert int(got[f"{cname} {f[0]}"]) == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_loss_arguments_are_validated_on_the_host(P):
+    L = P.lib()
+    fake = C.c_void_p(1)
+    labels = P.Batch(*([1] * 7))
+    assert L.nif_loss(None, fake, 4, C.byref(labels), fake, 0, fake, None, None, None) == 1   # null model
+    assert L.nif_loss(fake, None, 4, C.byref(labels), fake, 0, fake, None, None, None) == 1   # null heads
+    assert L.nif_loss(fake, fake, 0, C.byref(labels), fake, 0, fake, None, None, None) == 1   # empty batch
+    assert L.nif_loss(fake, fake, 4, C.byref(labels), fake, 2, fake, None, None, None) == 1   # bad switch
+    assert L.nif_loss(fake, fake, 4, C.byref(labels), None, 0, fake, None, None, None) == 1   # null s
+    no_t = P.Batch(1, 1, 1, None, 1, 1, 1)
+    assert L.nif_loss(fake, fake, 4, C.byref(no_t), fake, 0, fake, None, None, None) == 1     # missing labels

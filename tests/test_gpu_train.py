@@ -81,23 +81,26 @@ def test_backward_matches_oracle_gradient(orc, P, name):
     _grad_close(dx1.cpu().numpy().T, gx1, "d x1")
 
 
-def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3), fixed=False):
+def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3), fixed=False, store=False):
     import torch
     x0, x1, hit, t, nr, al, mt = batch
     keep = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
             torch.as_tensor(mt).cuda()]
     b = P.Batch(*[k.data_ptr() for k in keep])
-    cfg = P.TrainCfg(lr[0], lr[1], lr[2], 0.9, 0.999, 1e-8, prec, 0.0, int(fixed))
+    if store:
+        P.nif_model_reserve_encoding(model.h)
+    cfg = P.TrainCfg(lr[0], lr[1], lr[2], 0.9, 0.999, 1e-8, prec, 0.0, int(fixed), int(store))
     losses = torch.zeros(16, device="cuda")
     P.nif_train_step(model.h, b, B, cfg, losses)
     torch.cuda.synchronize()
     return losses.cpu().numpy()
 
 
+@pytest.mark.parametrize("store", [False, True], ids=["recomputed_encoding", "stored_encoding"])
 @pytest.mark.parametrize("name", ["torus16", "blobs128"])
-def test_train_step_matches_oracle(orc, P, name):
+def test_train_step_matches_oracle(orc, P, name, store):
     m = MODELS[name]
-    say(f"train step fp32 {name}")
+    say(f"train step fp32 {name} store_encoding={int(store)}")
     tab, prm, seen = model_params(m, 7, scale_tables=300.0)
     B = 2048 + 11
     batch = _batch(m, B, 8)
@@ -107,7 +110,7 @@ def test_train_step_matches_oracle(orc, P, name):
     model = P.Model(m)
     model.set_params(tab, prm)
     P.nif_model_reserve(model.h, B)
-    losses = _train_step(P, model, batch, B)
+    losses = _train_step(P, model, batch, B, store=store)
     say(f"  losses gpu {np.round(losses[:6], 6)}  oracle {np.round(L, 6)}")
     assert np.all(np.abs(losses[:6] - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
     assert losses[12] == 0 and losses[13] == hit.sum()
@@ -197,6 +200,106 @@ def test_training_reduces_the_loss(orc, P, prec):
         last = losses[5]
     say(f"  total loss {first:.4f} -> {last:.4f}  loss scale {losses[11]}")
     assert last < first
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stored_and_recomputed_encoding_give_the_same_step(P, prec):
+    """The two encoding policies of the training step at a batch of several recomputation
+    chunks (2^16 + 4321 samples, spatially ordered): same losses and task-weight gradients;
+    table gradients equal up to FP32 rounding (that path never reads the encoding, but its
+    register-merged runs and multi-part slices are summed in an order set by atomics); MLP
+    gradients equal up to the summation order of the first layer's chunks."""
+    import torch
+    m = MODELS["blobs128"]
+    tab, prm, _ = model_params(m, 21, scale_tables=300.0)
+    B = (1 << 16) + 4321
+    batch = _batch(m, B, 22)
+    out = []
+    for store in (False, True):
+        say(f"train step policy store_encoding={int(store)} prec={prec} B={B}")
+        model = P.Model(m)
+        model.set_params(tab, prm)
+        P.nif_model_reserve(model.h, B)
+        losses = _train_step(P, model, batch, B, prec, store=store)
+        g_t, g_p, g_s = [g.cpu().numpy().astype(np.float64) for g in model.get_grads()]
+        out.append((losses, g_t, g_p, g_s))
+        del model
+    (l0, t0, p0, s0), (l1, t1, p1, s1) = out
+    np.testing.assert_array_equal(l0[:6], l1[:6])
+    np.testing.assert_array_equal(s0, s1)
+    for name, a, b in (("tables", t0, t1), ("mlp", p0, p1)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+        say(f"  {name} gradient relative difference {rel:.2e}, max {np.abs(a - b).max():.2e}")
+        assert np.linalg.norm(a) > 0 and rel <= 1e-6, name
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max(), name
+
+
+def test_stored_encoding_step_needs_its_reservation(P):
+    m = MODELS["torus16"]
+    model = P.Model(m)
+    tab, prm, _ = model_params(m, 3)
+    model.set_params(tab, prm)
+    P.nif_model_reserve(model.h, 64)
+    import torch
+    batch = _batch(m, 64, 1)
+    x0, x1, hit, t, nr, al, mt = batch
+    keep = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
+            torch.as_tensor(mt).cuda()]
+    b = P.Batch(*[k.data_ptr() for k in keep])
+    cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, 0, 0.0, 0, 1)
+    with pytest.raises(P.NifError):
+        P.nif_train_step(model.h, b, 64, cfg, torch.zeros(16, device="cuda"))
+
+
+LOSS_CASES = {
+    "torus16": ("torus16", {}, False, False),
+    "blobs128": ("blobs128", {}, False, False),
+    "blobs128_fixed_weights": ("blobs128", {}, True, False),
+    "blobs128_sigmoid_head": ("blobs128", dict(dist_head=S.DIST_SIGMOID), False, False),
+    "blobs128_no_hits": ("blobs128", {}, False, True),
+}
+
+
+@pytest.mark.parametrize("case", list(LOSS_CASES))
+def test_multitask_loss_matches_oracle(orc, P, case):
+    """nif_loss and its autograd wrapper on heads the oracle computed: the five task losses and
+    the total to 1e-5, d total / d heads (through NifMultiTaskLoss.backward) and d total / d s
+    to the gradient bar; with no positive label the masked terms are zero."""
+    import torch
+    name, kw, fixed, no_hits = LOSS_CASES[case]
+    m = dataclasses.replace(MODELS[name], **kw)
+    say(f"loss {case}")
+    tab, prm, seen = model_params(m, 31, scale_tables=300.0)
+    B = 1000 + 23
+    x0, x1, hit, t, nr, al, mt = _batch(m, B, 32)
+    if no_hits:
+        hit = np.zeros_like(hit)
+    s = np.array([0.2, -0.1, 0.3, 0.1, -0.2])
+    z = orc.forward(m, seen, prm.astype(np.float64), x0.T, x1.T)
+    L, _, _, gs, _, _, dz = orc.loss_grad(m, seen, prm.astype(np.float64), s, x0.T, x1.T, hit, t, nr.T, al.T, mt,
+                                          want_dz=True, fixed_weights=fixed)
+    model = P.Model(m)
+    labels = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
+              torch.as_tensor(mt).cuda()]
+    heads = dev_f32(z).requires_grad_(True)
+    s_dev = dev_f32(s).requires_grad_(True)
+    total = P.NifMultiTaskLoss.apply(heads, s_dev, model, labels, fixed)
+    (2.0 * total).backward()
+    losses = torch.zeros(6, device="cuda")
+    P.nif_loss(model.h, heads.detach(), B, P.Batch(*[k.data_ptr() for k in labels]), s_dev.detach(), fixed, losses)
+    torch.cuda.synchronize()
+    got = losses.cpu().numpy().astype(np.float64)
+    say(f"  losses gpu {np.round(got, 6)}  oracle {np.round(L, 6)}")
+    assert np.all(np.abs(got - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
+    assert abs(total.detach().item() - L[5]) <= 1e-5 * max(abs(L[5]), 1e-3)
+    if no_hits:
+        assert np.all(got[1:5] == 0.0)
+        assert np.all(heads.grad.cpu().numpy()[:, 1:] == 0.0)
+    _grad_close(heads.grad.cpu().numpy() / 2.0, dz, "d heads")
+    g_s = s_dev.grad.cpu().numpy().astype(np.float64) / 2.0
+    assert np.abs(g_s - gs).max() <= 1e-5 * max(np.abs(gs).max(), 1e-3)
+    if fixed:
+        assert np.all(g_s == 0.0)
 
 
 def test_train_step_rejects_oversized_batches(P):
