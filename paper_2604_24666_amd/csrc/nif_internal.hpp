@@ -54,6 +54,9 @@ struct nif_model {
     float *g_tables = nullptr, *g_mlp = nullptr, *g_s = nullptr;
     float *m_tables = nullptr, *v_tables = nullptr, *m_mlp = nullptr, *v_mlp = nullptr;
     float *m_s = nullptr, *v_s = nullptr;
+    // the backward runs the table-gradient chain on `side` beside the weight gradients
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // training scratch (sized for max_batch samples; grown only by nif_model_reserve)
     int64_t max_batch = 0;
     float* zbuf = nullptr;              // [max_batch][H] heads of the training forward

@@ -173,10 +173,18 @@ int model_alloc(nif_model* m) {
     if ((rc = dalloc(&m->counters, 8, "counters"))) return rc;
     if ((rc = dalloc(&m->dacc, 16, "train accumulators"))) return rc;
     if ((rc = dalloc(&m->tcount, 16, "train counters"))) return rc;
+    // side stream of the backward (default priority) and its fork / join events
+    if (hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(NIF_E_DEVICE, "stream / event creation failed");
+    }
     return NIF_OK;
 }
 
 void model_free(nif_model* m) {
+    if (m->side) (void)hipStreamSynchronize(m->side);     // the backward's side work reads these buffers
     void* ps[] = {m->tables, m->tables_h, m->mlp, m->mlp_pad_f32, m->mlp_pad_bf16, m->mlp_pad_f16, m->s,
                   m->g_tables, m->g_mlp, m->g_s, m->m_tables, m->v_tables, m->m_mlp, m->v_mlp,
                   m->m_s, m->v_s, m->counters, m->dacc, m->tcount, m->zbuf, m->dz, m->acts, m->delta,
@@ -184,6 +192,9 @@ void model_free(nif_model* m) {
                   m->dw_part, m->ord_u32, m->ord_f32, m->ord_temp};
     for (void* p : ps)
         if (p) (void)hipFree(p);
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+    if (m->side) (void)hipStreamDestroy(m->side);
 }
 
 }  // namespace nif

@@ -1203,26 +1203,13 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     else if (precision == NIF_PREC_BF16) rc = dispatch_mlp_bwd<P_BF16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     else rc = dispatch_mlp_bwd<P_FP16>(hw, bp, m->dz, m->acts, m->delta, B, st);
     if (rc) return rc;
-    // weight gradients of every layer (layer 0 from the stored or the recomputed encoding)
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;
-    for (int i = 0; i < m->n_layers; ++i) {
-        const bool out = i == m->n_layers - 1;
-        const float* d = out ? m->dz : m->delta + (size_t)i * B * hw;
-        const int ds = out ? 16 : hw;
-        if (i > 0) {
-            if ((rc = weight_grad(m, i, d, ds, ds, m->acts + (size_t)(i - 1) * B * hw, B, cus, st))) return rc;
-        } else if (enc_stored) {
-            if ((rc = weight_grad(m, 0, d, ds, ds, enc_stored, B, cus, st))) return rc;
-        } else {
-            for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
-                const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
-                if ((rc = encode_pairs_launch(m, x0 + c0, x1 + c0, n, B, precision, m->enc, st))) return rc;
-                if ((rc = weight_grad(m, 0, d + (size_t)c0 * ds, ds, ds, m->enc, n, cus, st))) return rc;
-            }
-        }
-    }
+    // Fork: the table-gradient chain (reads delta[0], x0, x1; writes the table gradient and, by
+    // atomics, dx0 / dx1) runs on the model's side stream while this stream forms the weight
+    // gradients (reads the deltas, activations and the encoding; writes the MLP gradient); the
+    // two touch disjoint scratch.
+    hipStream_t sd = m->side;
+    if ((rc = check_hip(hipEventRecord(m->ev_fork, st), "backward fork"))) return rc;
+    if ((rc = check_hip(hipStreamWaitEvent(sd, m->ev_fork, 0), "backward fork"))) return rc;
     // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
     EncBwdParams ep;
     memset(&ep, 0, sizeof(ep));
@@ -1256,20 +1243,46 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
         const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
         const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL * n_sets;
-        hipLaunchKernelGGL(k_enc_bwd_count, fg, dim3(256), lds_f, st, ep);
-        hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sums, n_chunks, total);
-        hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, st, ep.cnt, n_cnt, sums);
+        hipLaunchKernelGGL(k_enc_bwd_count, fg, dim3(256), lds_f, sd, ep);
+        hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, total);
+        hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
         switch (hw) {
-            case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, st, ep); break;
-            case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, st, ep); break;
-            case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, fg, dim3(256), lds_f, st, ep); break;
-            default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, fg, dim3(256), lds_f, st, ep); break;
+            case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, sd, ep); break;
+            case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, sd, ep); break;
+            case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, fg, dim3(256), lds_f, sd, ep); break;
+            default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, fg, dim3(256), lds_f, sd, ep); break;
         }
-        hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, st, ep, total, parts);
+        hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, total, parts);
         const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
-        hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, st, ep, total, parts);
+        hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, total, parts);
     }
+    if ((rc = check_hip(hipEventRecord(m->ev_join, sd), "backward join"))) return rc;
+    // weight gradients of every layer (layer 0 from the stored or the recomputed encoding)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    for (int i = 0; i < m->n_layers; ++i) {
+        const bool out = i == m->n_layers - 1;
+        const float* d = out ? m->dz : m->delta + (size_t)i * B * hw;
+        const int ds = out ? 16 : hw;
+        if (rc) break;
+        if (i > 0) {
+            rc = weight_grad(m, i, d, ds, ds, m->acts + (size_t)(i - 1) * B * hw, B, cus, st);
+        } else if (enc_stored) {
+            rc = weight_grad(m, 0, d, ds, ds, enc_stored, B, cus, st);
+        } else {
+            for (int64_t c0 = 0; c0 < B && !rc; c0 += m->bwd_chunk) {
+                const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
+                if (!(rc = encode_pairs_launch(m, x0 + c0, x1 + c0, n, B, precision, m->enc, st)))
+                    rc = weight_grad(m, 0, d + (size_t)c0 * ds, ds, ds, m->enc, n, cus, st);
+            }
+        }
+    }
+    // join before anything that reads the table gradient or dx
+    const int rc_join = check_hip(hipStreamWaitEvent(st, m->ev_join, 0), "backward join");
+    if (rc) return rc;
+    if (rc_join) return rc_join;
     if (dx0 && m->GW > 0) {                  // concatenated encoding: d x through the raw gamma values
         const int E_phi = 2 * m->S * m->desc.levels * m->desc.feat_dim;
         hipLaunchKernelGGL(k_gamma_dx, dim3(grid_for(B)), dim3(256), 0, st, m->mlp_pad_f32 + m->wt_off[0], m->delta,
