@@ -37,9 +37,9 @@ KQUERY_SOURCES = ["paper_2604_24666_amd/csrc/nif_query.hip", "paper_2604_24666_a
                   "paper_2604_24666_amd/csrc/nif_internal.hpp", "paper_2604_24666_amd/build.py",
                   "nif_synth/__init__.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "e36ad0daaf3e892dbcaafa489f2a3b38e71d33d9683eb5a26e3c616cef8a1234",
-    "fetch_kib": 1.04806e8, "write_kib": 1.94331e6,         # per k_query<64, FP32, 64> launch, default workload
-    "fetch_scale": 1048576 / 524304, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,304 / writes 1,048,576 KiB
+    "sources_sha256": "afe426992ae7a23cb02cec386ab7dffd9b7fa50f4a96d7cf0042e5e0d409baab",
+    "fetch_kib": 1.04834e8, "write_kib": 1.94483e6,         # per k_query<64, FP32, 64> launch, default workload
+    "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
 }
 
 
