@@ -14,8 +14,8 @@
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is enqueued on it
  *    and the call returns without synchronising, except where stated.  nif_backward and
  *    nif_train_step also run the table-gradient part of the backward on a stream the model
- *    owns, forked from `stream` and joined back to it with events before the call returns
- *    (under graph capture it becomes a parallel branch of the captured graph).
+ *    owns, forked from `stream` and joined back to it with events before the call returns.
+ *    These two calls are not tested under graph capture.
  *  - Opaque handles (nif_model, nif_grid) own their device memory, which is allocated at
  *    create/build time only.  nif_query, nif_trace, nif_forward, nif_encode, nif_backward
  *    and nif_train_step never allocate device memory.  A handle must not be used by two
