@@ -8,7 +8,7 @@ animation would.  Default workload: 8 random spheres voxelized at 64^3, 24 poses
 (twist/bend/taper x 8 strengths), 1024x1024 pinhole rays per pose, 16-level 2^19 FP16 hash
 grid, 6 PE frequencies, MLP 832->64x3->12, FP32.
 
-Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this build runs on one
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: the library runs on one
 GPU.
 """
 from __future__ import annotations
@@ -628,7 +628,7 @@ def main():
                     help="extra measurements: precision,train,batched,ablation,render (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design note in DESIGN.md",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

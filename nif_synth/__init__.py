@@ -7,7 +7,7 @@ so both the CPU oracle and the GPU library can consume its output without sharin
 any computation.
 
 The paper's own test objects (bunny, cat, dragon) are not available; the synthetic
-scenes below stand in for them (see the workload table in the design doc).
+scenes below stand in for them.
 """
 from __future__ import annotations
 

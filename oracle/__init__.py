@@ -13,7 +13,6 @@ Each function follows a passage of the paper (cited in the C sources):
   query                        front-to-back first hit with segmented distance
   loss_grad, adam              uncertainty-weighted multi-task loss, analytic gradient, Adam
 
-Parity status of every function is listed in the design doc.
 """
 from __future__ import annotations
 
