@@ -116,6 +116,10 @@ int label_launch(int kind, const double* params_host, int32_t n_params, int forc
                  hipStream_t st);
 int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads,
                    int32_t precision, float* acts, float* enc, hipStream_t st);
+// Forward of n pairs whose SoA rows have stride ld (heads [n][H], acts [layers][n][HW] and enc
+// [n][E] local to the n rows).
+int forward_rows_launch(const nif_model* m, const float* x0, const float* x1, int64_t n, int64_t ld, float* heads,
+                        int32_t precision, float* acts, float* enc, hipStream_t st);
 // Encoding only of n pairs whose SoA rows have stride ld: enc[n][E], the values the forward
 // of the same precision feeds its first layer.
 int encode_pairs_launch(const nif_model* m, const float* x0, const float* x1, int64_t n, int64_t ld,

@@ -475,12 +475,11 @@ __device__ __forceinline__ void enc_pass(const NetParams& np, const float* s_seg
 // the tile's 64 points, which keeps the accumulators small enough for two waves per SIMD; with
 // spatially ordered batches that latency hiding outweighs streaming the first-layer weights
 // once per pass.
-template <int HW, int PREC, bool GAMMA = false, bool ENC_ONLY = false>
+template <int HW, int PREC, bool GAMMA = false, bool ENC_ONLY = false, int TILE = ENC_ONLY ? 16 : 64>
 __global__ void __launch_bounds__(256, 2) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
                                                  int64_t B, int64_t ld, float* __restrict__ heads,
                                                  float* __restrict__ acts, float* __restrict__ enc) {
-    constexpr int TILE = ENC_ONLY ? 16 : 64;
-    constexpr int CB = ENC_ONLY || HW >= 128 ? 1 : 4;
+    constexpr int CB = TILE == 16 || HW >= 128 ? 1 : 4;
     constexpr int PASSES = TILE / 16 / CB;
     __shared__ float s_seg_all[4][64 * kSegStride];
     __shared__ float s_z_all[4][64 * kZStride];
@@ -509,7 +508,7 @@ __global__ void __launch_bounds__(256, 2) k_forward(NetParams np, const float* _
             for (int ps = 0; ps < PASSES; ++ps)
                 net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * TILE + ps * 16 * CB, B, enc);
             wave_lds_sync();
-            if (seg < B)
+            if (lane < TILE && seg < B)
                 for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
         }
         wave_lds_sync();
@@ -706,13 +705,16 @@ int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hip
 template <int HW, int PREC>
 static void launch_forward(const NetParams& np, const float* x0, const float* x1, int64_t B, int64_t ld, float* heads,
                            float* acts, float* enc, hipStream_t st) {
-    const bool gamma = np.gamma_F >= 0, enc_only = heads == nullptr;
-    const int64_t tiles = enc_only ? (B + 15) / 16 : (B + 63) / 64;
+    // small launches (up to 2^17 pairs) take 16 pairs per wave so that they still fill the chip
+    const bool gamma = np.gamma_F >= 0, enc_only = heads == nullptr, small = B <= (1 << 17);
+    const int64_t tiles = enc_only || small ? (B + 15) / 16 : (B + 63) / 64;
     const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cus() * 8);
     const dim3 g((unsigned)std::max<int64_t>(blocks, 1)), b(256);
     if (gamma && enc_only) hipLaunchKernelGGL((k_forward<HW, PREC, true, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+    else if (gamma && small) hipLaunchKernelGGL((k_forward<HW, PREC, true, false, 16>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
     else if (gamma) hipLaunchKernelGGL((k_forward<HW, PREC, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
     else if (enc_only) hipLaunchKernelGGL((k_forward<HW, PREC, false, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+    else if (small) hipLaunchKernelGGL((k_forward<HW, PREC, false, false, 16>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
     else hipLaunchKernelGGL((k_forward<HW, PREC>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
 }
 
@@ -746,6 +748,12 @@ int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t
                    float* acts, float* enc, hipStream_t st) {
     if (heads == nullptr) return fail(NIF_E_INVALID_ARG, "forward needs a heads buffer");
     return forward_any(m, x0, x1, B, B, heads, precision, acts, enc, st);
+}
+
+int forward_rows_launch(const nif_model* m, const float* x0, const float* x1, int64_t n, int64_t ld, float* heads,
+                        int32_t precision, float* acts, float* enc, hipStream_t st) {
+    if (heads == nullptr || ld < n) return fail(NIF_E_INVALID_ARG, "forward needs a heads buffer and ld >= n");
+    return forward_any(m, x0, x1, n, ld, heads, precision, acts, enc, st);
 }
 
 int encode_pairs_launch(const nif_model* m, const float* x0, const float* x1, int64_t n, int64_t ld, int32_t precision,

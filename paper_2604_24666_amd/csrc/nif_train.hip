@@ -96,6 +96,14 @@ static DwArgs dw_shape(int M_pad, int N, int64_t B, int cus) {
 
 static int64_t dw_part_floats(const DwArgs& A) { return A.n_slots * A.M_pad * ((int64_t)A.N + 1); }
 
+// Partial-slot floats any batch size can need for one layer: dw_shape never uses more K chunks
+// than its first estimate ceil(2 cus / column groups).
+static int64_t dw_part_floats_max(int M_pad, int N, int cus) {
+    const int n_cb = (N + 63) / 64, ks = n_cb >= 4 ? 1 : 4 / n_cb, n_cg = (n_cb + 3) / 4;
+    const int64_t nch = std::max<int64_t>(1, (2LL * cus + n_cg - 1) / n_cg);
+    return nch * ks * M_pad * ((int64_t)N + 1);
+}
+
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
     for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta, &m->enc, &m->enc_all})
@@ -138,7 +146,7 @@ int model_reserve(nif_model* m, int64_t B) {
         int64_t need = 0;
         for (int i = 0; i < m->n_layers; ++i) {
             const bool out = i == m->n_layers - 1;
-            need = std::max(need, dw_part_floats(dw_shape(out ? 16 : (int)hw, m->dims[i], B, cus)));
+            need = std::max(need, dw_part_floats_max(out ? 16 : (int)hw, m->dims[i], cus));
         }
         if (m->dw_part) { (void)hipFree(m->dw_part); m->dw_part = nullptr; }
         for (void** p : {(void**)&m->ord_u32, (void**)&m->ord_f32, (void**)&m->ord_temp})
@@ -205,7 +213,9 @@ __global__ void k_pad_dz(const float* __restrict__ dh, int H, int64_t B, float* 
 __device__ __forceinline__ float sigm(float v) { return 1.f / (1.f + expf(-v)); }
 
 // Per-sample loss terms and d loss / d heads (times the loss scale), padded to 16 columns.
-__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H, int64_t B,
+// Rows [0, n) of a batch of Btot samples (means over Btot and over its positives); label and
+// point pointers start at the chunk, SoA arrays with stride ld.
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H, int64_t n, int64_t ld, int64_t Btot,
                                               const uint8_t* __restrict__ lhit, const float* __restrict__ lt,
                                               const float* __restrict__ ln, const float* __restrict__ la,
                                               const int32_t* __restrict__ lm, const float* __restrict__ s,
@@ -218,9 +228,10 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ z, int H
     float w0 = expf(-s[0]), w1 = 0.5f * expf(-s[1]), w2 = 0.5f * expf(-s[2]), w3 = 0.5f * expf(-s[3]),
           w4 = expf(-s[4]);
     if (fixed) w0 = w1 = w2 = w3 = w4 = 1.f;
-    const float invB = (float)(1.0 / (double)B), invP = P > 0 ? (float)(1.0 / P) : 0.f;
+    const float invB = (float)(1.0 / (double)Btot), invP = P > 0 ? (float)(1.0 / P) : 0.f;
+    const int64_t B = ld;                      // stride of the SoA label / point arrays
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float* zi = z + i * H;
         float g[16];
 #pragma unroll
@@ -567,7 +578,8 @@ __global__ void __launch_bounds__(256) k_dw_sum(DwArgs A, float* __restrict__ gW
 struct EncBwdParams {
     EncParams enc;
     const float* W0t;    // FP32 [E][HW]: W0 transposed
-    const float* delta0; // [B][HW]
+    const float* delta0; // [rows][HW]; row of sample seg = seg - drow0
+    int64_t drow0;
     const float* x0;     // SoA [3][B]
     const float* x1;
     int32_t HW, E, S;
@@ -715,7 +727,7 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
 #pragma unroll
         for (int t = 0; t < KQ; t += 4) {
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid) v = *reinterpret_cast<const float4*>(P.delta0 + seg * HW + q * KQ + t);
+            if (valid) v = *reinterpret_cast<const float4*>(P.delta0 + (seg - P.drow0) * HW + q * KQ + t);
             bd[t] = v.x; bd[t + 1] = v.y; bd[t + 2] = v.z; bd[t + 3] = v.w;
         }
         float dxa[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
@@ -1185,6 +1197,63 @@ static int weight_grad(nif_model* m, int layer, const float* d, int dstride, int
     return NIF_OK;
 }
 
+// Table-gradient parameters of a batch (points SoA with stride B, delta rows from drow0).
+static EncBwdParams table_grad_params(nif_model* m, const float* x0, const float* x1, int64_t B, float* dx0, float* dx1) {
+    EncBwdParams ep;
+    memset(&ep, 0, sizeof(ep));
+    ep.enc = make_net_params(m, NIF_PREC_FP32).enc;
+    ep.W0t = m->mlp_pad_f32 + m->wt_off[0];
+    ep.delta0 = m->delta;
+    ep.drow0 = 0;
+    ep.x0 = x0; ep.x1 = x1;
+    ep.HW = m->desc.hidden_width; ep.E = m->E; ep.S = m->S;
+    ep.g_tables = m->g_tables;
+    ep.dx0 = dx0; ep.dx1 = dx1;
+    ep.B = B;
+    const int log2T = m->desc.log2_table;
+    ep.SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
+    ep.NBL = 1 << (log2T - ep.SB);
+    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
+    ep.n_buckets = m->desc.levels * n_sets * ep.NBL;
+    ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
+    ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
+    ep.vmax = nullptr;
+    return ep;
+}
+
+// One round of the table gradient: samples [c0, c0 + n), n <= bwd_chunk: count / scan / fill /
+// parts / reduce on stream sd (the round's scratch is shared, so rounds run in stream order).
+static void table_grad_round(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
+    const int hw = m->desc.hidden_width;
+    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
+    const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
+    ep.c0 = c0;
+    ep.n = n;
+    const int64_t n_tiles = (ep.n + 15) / 16;
+    ep.n_blk = (int32_t)((n_tiles + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock);
+    const int64_t n_cnt = (int64_t)ep.n_buckets * ep.n_blk;
+    const int n_chunks = (int)((n_cnt + 4095) / 4096);
+    int32_t* sums = m->bwd_scan;
+    int32_t* total = m->bwd_scan + n_chunks;
+    int32_t* parts = total + 1;
+    ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
+    const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
+    const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL * n_sets;
+    hipLaunchKernelGGL(k_enc_bwd_count, fg, dim3(256), lds_f, sd, ep);
+    hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
+    switch (hw) {
+        case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, sd, ep); break;
+        case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, sd, ep); break;
+        case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, fg, dim3(256), lds_f, sd, ep); break;
+        default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, fg, dim3(256), lds_f, sd, ep); break;
+    }
+    hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, total, parts);
+    const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
+    hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, total, parts);
+}
+
 // Backward from m->dz.  enc_stored: the forward's encoding [B][E], or null to recompute it
 // per chunk of bwd_chunk samples for the first layer's weight gradient.
 static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t B, float* dx0, float* dx1,
@@ -1211,52 +1280,8 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     if ((rc = check_hip(hipEventRecord(m->ev_fork, st), "backward fork"))) return rc;
     if ((rc = check_hip(hipStreamWaitEvent(sd, m->ev_fork, 0), "backward fork"))) return rc;
     // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
-    EncBwdParams ep;
-    memset(&ep, 0, sizeof(ep));
-    ep.enc = make_net_params(m, NIF_PREC_FP32).enc;
-    ep.W0t = m->mlp_pad_f32 + m->wt_off[0];
-    ep.delta0 = m->delta;
-    ep.x0 = x0; ep.x1 = x1;
-    ep.HW = hw; ep.E = m->E; ep.S = m->S;
-    ep.g_tables = m->g_tables;
-    ep.dx0 = dx0; ep.dx1 = dx1;
-    ep.B = B;
-    const int log2T = m->desc.log2_table;
-    ep.SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
-    ep.NBL = 1 << (log2T - ep.SB);
-    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
-    ep.n_buckets = m->desc.levels * n_sets * ep.NBL;
-    ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
-    ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
-    ep.vmax = nullptr;
-    const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
-    for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) {
-        ep.c0 = c0;
-        ep.n = std::min<int64_t>(m->bwd_chunk, B - c0);
-        const int64_t n_tiles = (ep.n + 15) / 16;
-        ep.n_blk = (int32_t)((n_tiles + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock);
-        const int64_t n_cnt = (int64_t)ep.n_buckets * ep.n_blk;
-        const int n_chunks = (int)((n_cnt + 4095) / 4096);
-        int32_t* sums = m->bwd_scan;
-        int32_t* total = m->bwd_scan + n_chunks;
-        int32_t* parts = total + 1;
-        ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
-        const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
-        const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL * n_sets;
-        hipLaunchKernelGGL(k_enc_bwd_count, fg, dim3(256), lds_f, sd, ep);
-        hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, total);
-        hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
-        switch (hw) {
-            case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, sd, ep); break;
-            case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, sd, ep); break;
-            case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, fg, dim3(256), lds_f, sd, ep); break;
-            default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, fg, dim3(256), lds_f, sd, ep); break;
-        }
-        hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, total, parts);
-        const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
-        hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, total, parts);
-    }
+    const EncBwdParams ep = table_grad_params(m, x0, x1, B, dx0, dx1);
+    for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) table_grad_round(m, ep, c0, std::min<int64_t>(m->bwd_chunk, B - c0), sd);
     if ((rc = check_hip(hipEventRecord(m->ev_join, sd), "backward join"))) return rc;
     // weight gradients of every layer (layer 0 from the stored or the recomputed encoding)
     int dev = 0, cus = 256;
@@ -1308,8 +1333,8 @@ int loss_launch(nif_model* m, const float* heads, int64_t B, const nif_batch* b,
     int64_t* tcount = m->tcount + kLossTcount;
     hipLaunchKernelGGL(k_loss_begin, dim3(1), dim3(64), 0, st, dacc, tcount);
     hipLaunchKernelGGL(k_count_pos, dim3(grid_for(B)), dim3(256), 0, st, b->hit, B, tcount);
-    hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, heads, m->H, B, b->hit, b->t, b->n, b->a, b->m,
-                       s, tcount, dacc, d_heads, m->H, b->x0, b->x1, m->desc.dist_head, fixed);
+    hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, heads, m->H, B, B, B, b->hit, b->t, b->n, b->a,
+                       b->m, s, tcount, dacc, d_heads, m->H, b->x0, b->x1, m->desc.dist_head, fixed);
     hipLaunchKernelGGL(k_loss_out, dim3(1), dim3(64), 0, st, dacc, tcount, s, B, fixed, losses, d_s);
     return check_hip(hipGetLastError(), "loss launch");
 }
@@ -1328,18 +1353,74 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
     }
     const int prec = cfg->precision;
     const float scale_init = cfg->loss_scale_init > 0.f ? cfg->loss_scale_init : (prec == NIF_PREC_FP16 ? 32768.f : 1.f);
+    if (cfg->store_encoding && !m->enc_all)
+        return fail(NIF_E_STATE, "store_encoding needs nif_model_reserve_encoding first");
     hipLaunchKernelGGL(k_train_begin, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, scale_init);
     hipLaunchKernelGGL(k_count_pos, dim3(grid_for(B)), dim3(256), 0, st, b->hit, B, m->tcount);
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table);
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp);
-    int rc;
-    if (cfg->store_encoding && !m->enc_all)
-        return fail(NIF_E_STATE, "store_encoding needs nif_model_reserve_encoding first");
-    float* enc_keep = cfg->store_encoding ? m->enc_all : nullptr;
-    if ((rc = forward_launch(m, b->x0, b->x1, B, m->zbuf, prec, m->acts, enc_keep, st))) return rc;
-    hipLaunchKernelGGL(k_loss, dim3(grid_for(B)), dim3(256), 0, st, m->zbuf, m->H, B, b->hit, b->t, b->n, b->a, b->m,
-                       m->s, m->tcount, m->dacc, m->dz, 16, b->x0, b->x1, m->desc.dist_head, cfg->fixed_task_weights);
-    if ((rc = backward_core(m, b->x0, b->x1, B, nullptr, nullptr, prec, enc_keep, st))) return rc;
+    // The step runs per chunk of bwd_chunk samples: forward, loss rows (the means use the whole
+    // batch's size and positive count, known before), MLP backward; then the chunk's table
+    // gradient goes to the side stream while this stream forms its weight gradients (the first
+    // layer's from the encoding, recomputed unless stored) and moves on to the next chunk.
+    // Chunk c keeps its heads, d heads, activations and deltas in rows of its own block of the
+    // batch-sized buffers, so the side stream can still read chunk c's deltas meanwhile.
+    const int hw = m->desc.hidden_width, nh = m->desc.hidden_layers, H = m->H;
+    BwdParams bp;
+    memset(&bp, 0, sizeof(bp));
+    bp.n_hidden = nh;
+    for (int i = 1; i < m->n_layers; ++i) {
+        if (prec == NIF_PREC_FP32) bp.Wt[i] = m->mlp_pad_f32 + m->wt_off[i];
+        else if (prec == NIF_PREC_BF16) bp.Wt[i] = m->mlp_pad_bf16 + m->wt_off[i];
+        else bp.Wt[i] = m->mlp_pad_f16 + m->wt_off[i];
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    EncBwdParams ep = table_grad_params(m, b->x0, b->x1, B, nullptr, nullptr);
+    hipStream_t sd = m->side;
+    int rc = NIF_OK;
+    bool forked = false;
+    for (int64_t c0 = 0; c0 < B && !rc; c0 += m->bwd_chunk) {
+        const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
+        float* acts_c = m->acts + (size_t)c0 * nh * hw;      // [hidden layers][n][hw]
+        float* delta_c = m->delta + (size_t)c0 * nh * hw;
+        float* z_c = m->zbuf + (size_t)c0 * H;
+        float* dz_c = m->dz + (size_t)c0 * 16;
+        float* enc_c = cfg->store_encoding ? m->enc_all + (size_t)c0 * m->E : nullptr;
+        if ((rc = forward_rows_launch(m, b->x0 + c0, b->x1 + c0, n, B, z_c, prec, acts_c, enc_c, st))) break;
+        hipLaunchKernelGGL(k_loss, dim3(grid_for(n)), dim3(256), 0, st, z_c, H, n, B, B, b->hit + c0, b->t + c0,
+                           b->n + c0, b->a + c0, b->m + c0, m->s, m->tcount, m->dacc, dz_c, 16, b->x0 + c0, b->x1 + c0,
+                           m->desc.dist_head, cfg->fixed_task_weights);
+        if (prec == NIF_PREC_FP32) rc = dispatch_mlp_bwd<P_FP32>(hw, bp, dz_c, acts_c, delta_c, n, st);
+        else if (prec == NIF_PREC_BF16) rc = dispatch_mlp_bwd<P_BF16>(hw, bp, dz_c, acts_c, delta_c, n, st);
+        else rc = dispatch_mlp_bwd<P_FP16>(hw, bp, dz_c, acts_c, delta_c, n, st);
+        if (rc) break;
+        if ((rc = check_hip(hipEventRecord(m->ev_fork, st), "train fork"))) break;
+        if ((rc = check_hip(hipStreamWaitEvent(sd, m->ev_fork, 0), "train fork"))) break;
+        forked = true;
+        ep.delta0 = delta_c;                    // layer 0 of the chunk's block
+        ep.drow0 = c0;
+        table_grad_round(m, ep, c0, n, sd);
+        for (int i = 0; i < m->n_layers && !rc; ++i) {
+            const bool out = i == m->n_layers - 1;
+            const float* d = out ? dz_c : delta_c + (size_t)i * n * hw;
+            const int ds = out ? 16 : hw;
+            if (i > 0) {
+                rc = weight_grad(m, i, d, ds, ds, acts_c + (size_t)(i - 1) * n * hw, n, cus, st);
+            } else if (enc_c) {
+                rc = weight_grad(m, 0, d, ds, ds, enc_c, n, cus, st);
+            } else if (!(rc = encode_pairs_launch(m, b->x0 + c0, b->x1 + c0, n, B, prec, m->enc, st))) {
+                rc = weight_grad(m, 0, d, ds, ds, m->enc, n, cus, st);
+            }
+        }
+    }
+    if (forked) {                               // join before the gradients are read
+        const int rj = check_hip(hipEventRecord(m->ev_join, sd), "train join");
+        const int rw = rj ? rj : check_hip(hipStreamWaitEvent(st, m->ev_join, 0), "train join");
+        if (!rc) rc = rw;
+    }
+    if (rc) return rc;
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table, m->tcount);
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp, m->tcount);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, m->s, m->g_s, losses, B,
