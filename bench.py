@@ -37,8 +37,8 @@ KQUERY_SOURCES = ["paper_2604_24666_amd/csrc/nif_query.hip", "paper_2604_24666_a
                   "paper_2604_24666_amd/csrc/nif_internal.hpp", "paper_2604_24666_amd/build.py",
                   "nif_synth/__init__.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "afe426992ae7a23cb02cec386ab7dffd9b7fa50f4a96d7cf0042e5e0d409baab",
-    "fetch_kib": 1.04834e8, "write_kib": 1.94483e6,         # per k_query<64, FP32, 64> launch, default workload
+    "sources_sha256": "b286b7fce0494ffa057e3eef33670a4f50461d815f806bc014d2e0e13db76b4a",
+    "fetch_kib": 1.04882e8, "write_kib": 1.94201e6,         # per k_query<64, FP32, 64> launch, default workload
     "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
 }
 
