@@ -234,6 +234,52 @@ def test_stored_and_recomputed_encoding_give_the_same_step(P, prec):
         assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max(), name
 
 
+@pytest.mark.parametrize("store", [False, True], ids=["recomputed_encoding", "stored_encoding"])
+def test_pipelined_step_at_full_batch_matches_the_separate_calls(P, store):
+    """At the benchmark's training batch (2^18 samples: spatially ordered, four pipelined
+    chunks, the table gradient on the side stream) the step's losses and gradients equal those
+    of nif_forward -> nif_loss -> nif_backward on the same batch (calls held to the oracle by
+    the tests above), within FP32 summation-order error."""
+    import torch
+    m = MODELS["blobs128"]
+    tab, prm, _ = model_params(m, 41, scale_tables=300.0)
+    B = 1 << 18
+    x0, x1, hit, t, nr, al, mt = _batch(m, B, 42)
+    labels = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
+              torch.as_tensor(mt).cuda()]
+    lb = P.Batch(*[k.data_ptr() for k in labels])
+    say(f"pipelined step B={B} store_encoding={int(store)}")
+    ref = P.Model(m)
+    ref.set_params(tab, prm)
+    P.nif_model_reserve(ref.h, B)
+    heads = ref.forward(labels[0], labels[1])
+    losses_ref = torch.zeros(6, device="cuda")
+    d_heads = torch.empty_like(heads)
+    d_s = torch.empty(5, device="cuda")
+    P.nif_loss(ref.h, heads, B, lb, torch.zeros(5, device="cuda"), False, losses_ref, d_heads, d_s)
+    P.nif_backward(ref.h, labels[0], labels[1], B, d_heads, None, None, False, P.PREC_FP32)
+    r_t, r_p, _ = [g.cpu().numpy().astype(np.float64) for g in ref.get_grads()]
+    del ref
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    P.nif_model_reserve(model.h, B)
+    if store:
+        P.nif_model_reserve_encoding(model.h)
+    cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, P.PREC_FP32, 0.0, 0, int(store))
+    losses = torch.zeros(16, device="cuda")
+    P.nif_train_step(model.h, lb, B, cfg, losses)
+    g_t, g_p, g_s = [g.cpu().numpy().astype(np.float64) for g in model.get_grads()]
+    torch.cuda.synchronize()
+    got, want = losses.cpu().numpy()[:6].astype(np.float64), losses_ref.cpu().numpy().astype(np.float64)
+    say(f"  losses step {np.round(got, 6)}  separate {np.round(want, 6)}")
+    assert np.all(np.abs(got - want) <= 1e-5 * np.maximum(np.abs(want), 1e-3))
+    assert np.abs(g_s - d_s.cpu().numpy()).max() <= 1e-5 * max(np.abs(d_s.cpu().numpy()).max(), 1e-3)
+    for name, a, b in (("tables", g_t, r_t), ("mlp", g_p, r_p)):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        say(f"  {name} gradient relative difference {rel:.2e}")
+        assert np.linalg.norm(b) > 0 and rel <= 1e-5, name
+
+
 def test_stored_encoding_step_needs_its_reservation(P):
     m = MODELS["torus16"]
     model = P.Model(m)
