@@ -1381,6 +1381,30 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
     hipStream_t sd = m->side;
     int rc = NIF_OK;
     bool forked = false;
+    // weight gradients of the chunk at rows [c0, c0 + n)
+    auto chunk_weight_grads = [&](int64_t c0, int64_t n) {
+        float* acts_c = m->acts + (size_t)c0 * nh * hw;
+        float* delta_c = m->delta + (size_t)c0 * nh * hw;
+        float* dz_c = m->dz + (size_t)c0 * 16;
+        float* enc_c = cfg->store_encoding ? m->enc_all + (size_t)c0 * m->E : nullptr;
+        int r = NIF_OK;
+        for (int i = 0; i < m->n_layers && !r; ++i) {
+            const bool out = i == m->n_layers - 1;
+            const float* d = out ? dz_c : delta_c + (size_t)i * n * hw;
+            const int ds = out ? 16 : hw;
+            if (i > 0) {
+                r = weight_grad(m, i, d, ds, ds, acts_c + (size_t)(i - 1) * n * hw, n, cus, st);
+            } else if (enc_c) {
+                r = weight_grad(m, 0, d, ds, ds, enc_c, n, cus, st);
+            } else if (!(r = encode_pairs_launch(m, b->x0 + c0, b->x1 + c0, n, B, prec, m->enc, st))) {
+                r = weight_grad(m, 0, d, ds, ds, m->enc, n, cus, st);
+            }
+        }
+        return r;
+    };
+    // The weight gradients of chunk c are issued after chunk c + 1's MLP backward, so the next
+    // table-gradient round (the longer branch) can start as early as possible.
+    int64_t prev_c0 = -1, prev_n = 0;
     for (int64_t c0 = 0; c0 < B && !rc; c0 += m->bwd_chunk) {
         const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
         float* acts_c = m->acts + (size_t)c0 * nh * hw;      // [hidden layers][n][hw]
@@ -1402,19 +1426,11 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
         ep.delta0 = delta_c;                    // layer 0 of the chunk's block
         ep.drow0 = c0;
         table_grad_round(m, ep, c0, n, sd);
-        for (int i = 0; i < m->n_layers && !rc; ++i) {
-            const bool out = i == m->n_layers - 1;
-            const float* d = out ? dz_c : delta_c + (size_t)i * n * hw;
-            const int ds = out ? 16 : hw;
-            if (i > 0) {
-                rc = weight_grad(m, i, d, ds, ds, acts_c + (size_t)(i - 1) * n * hw, n, cus, st);
-            } else if (enc_c) {
-                rc = weight_grad(m, 0, d, ds, ds, enc_c, n, cus, st);
-            } else if (!(rc = encode_pairs_launch(m, b->x0 + c0, b->x1 + c0, n, B, prec, m->enc, st))) {
-                rc = weight_grad(m, 0, d, ds, ds, m->enc, n, cus, st);
-            }
-        }
+        if (prev_c0 >= 0 && (rc = chunk_weight_grads(prev_c0, prev_n))) break;
+        prev_c0 = c0;
+        prev_n = n;
     }
+    if (!rc && prev_c0 >= 0) rc = chunk_weight_grads(prev_c0, prev_n);
     if (forked) {                               // join before the gradients are read
         const int rj = check_hip(hipEventRecord(m->ev_join, sd), "train join");
         const int rw = rj ? rj : check_hip(hipStreamWaitEvent(st, m->ev_join, 0), "train join");
