@@ -158,7 +158,6 @@ int nif_voxelize(int32_t scene_kind, const double* params_host, int32_t n_params
 int nif_label(int32_t scene_kind, const double* params_host, int32_t n_params, int32_t force_march,
               const float* x0_dev, const float* x1_dev, int64_t n, uint8_t* hit_dev, float* t_dev,
               float* normal_dev, float* albedo_dev, int32_t* material_dev, nif_stream stream);
-
 /* ---------------------------------------------------------------- deformed grid
  * Per pose: the deformed lattice vertices V_ijk = D(i/N, j/N, k/N) (faces split along their
  * main diagonal), and an acceleration structure over the occupied deformed voxels
@@ -309,6 +308,11 @@ typedef struct {
                                    more device memory, from nif_model_reserve_encoding; without
                                    it the step fails with NIF_E_STATE).  The hidden activations
                                    are stored in both cases. */
+    int32_t loss_scale_growth_interval; /* dynamic loss scaling (BF16/FP16): the scale doubles
+                                   after this many clean steps in a row; 0 = 1000.  A step with
+                                   a non-finite loss or gradient is skipped (no parameter,
+                                   moment or step-counter change) and halves the scale (not
+                                   below 2^-16).  FP32 steps keep the scale at 1. */
 } nif_train_cfg;
 int nif_train_step(nif_model* model, const nif_batch* batch, int64_t B, const nif_train_cfg* cfg,
                    float* losses_dev, nif_stream stream);

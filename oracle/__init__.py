@@ -10,6 +10,8 @@ Each function follows a passage of the paper (cited in the C sources):
   voxelize, label              rest-space voxelization, ground-truth labels of rest segments
   lattice_vertices, trace      deformed lattice; ordered occupied-voxel hit lists (brute/walk)
   encode, forward              psi = phi(gamma(x)) encoding; MLP heads on point pairs
+  encode_backward              adjoint of the encoding with respect to the tables
+  encode_corners               its sparse Jacobian: table entry and weight of every corner
   query                        front-to-back first hit with segmented distance
   loss_grad, adam              uncertainty-weighted multi-task loss, analytic gradient, Adam
 
@@ -187,6 +189,33 @@ def encode(desc, tables, x) -> np.ndarray:
     lib().orc_encode_batch(C.byref(m), _p(tab, C.c_double), C.c_int64(len(x)), _p(x, C.c_double),
                            _p(out, C.c_double))
     return out
+
+
+def encode_corners(desc, x):
+    """(idx, w) [n][S][L][8]: the flat table entry ((set L + level) T + entry) and trilinear
+    weight of every corner the encoding of each point reads (its sparse Jacobian)."""
+    m = model_struct(desc)
+    x = _aos(x)
+    S = 1 if getattr(desc, "concat_encoding", 0) else 1 + 2 * desc.pe_freqs
+    idx = np.zeros((len(x), S, desc.levels, 8), np.int64)
+    w = np.zeros((len(x), S, desc.levels, 8))
+    lib().orc_encode_corners_batch(C.byref(m), C.c_int64(len(x)), _p(x, C.c_double), _p(idx, C.c_int64),
+                                   _p(w, C.c_double))
+    return idx, w
+
+
+def encode_backward(desc, tables, x, d_enc) -> np.ndarray:
+    """J^T d_enc: the table gradient of sum(d_enc * psi(x)) over the points x (rows), shaped
+    like the tables.  psi is linear in the tables with nonnegative (trilinear) coefficients."""
+    m = model_struct(desc)
+    tab = _f64(tables).reshape(-1)
+    x = _aos(x)
+    W = (1 if getattr(desc, "concat_encoding", 0) else 1 + 2 * desc.pe_freqs) * desc.levels * desc.feat_dim
+    dv = _f64(d_enc).reshape(len(x), W)
+    g = np.zeros_like(tab)
+    lib().orc_encode_backward_batch(C.byref(m), _p(tab, C.c_double), C.c_int64(len(x)), _p(x, C.c_double),
+                                    _p(dv, C.c_double), _p(g, C.c_double))
+    return g.reshape(np.shape(tables))
 
 
 def forward(desc, tables, params, x0, x1, with_scale: bool = False):

@@ -277,6 +277,49 @@ void orc_encode_batch(const orc_model* m, const double* tables, int64_t n, const
     for (int64_t i = 0; i < n; ++i) orc_encode_point(m, tables, x + 3 * i, out + i * W);
 }
 
+/* Sparse Jacobian of the encoding with respect to the tables: for each of n points, every
+   PE sample s, level l and corner c in the order of orc_encode_point, the flat index of the
+   table entry the corner reads ((set L + l) T + entry; times feat_dim gives its first
+   feature) and the corner's trilinear weight.  idx, w: [n][S][L][8]. */
+void orc_encode_corners_batch(const orc_model* m, int64_t n, const double* xin, int64_t* idx, double* w) {
+    const int L = m->levels, S = n_samples(m);
+    const int64_t T = 1LL << m->log2_table;
+    for (int64_t i = 0; i < n; ++i) {
+        double x[3] = {clamp01(xin[3 * i]), clamp01(xin[3 * i + 1]), clamp01(xin[3 * i + 2])};
+        for (int s = 0; s < S; ++s) {
+            double smp[3], dd;
+            for (int a = 0; a < 3; ++a) smp[a] = pe_sample(s, x[a], &dd);
+            for (int l = 0; l < L; ++l) {
+                uint32_t i0[3];
+                double f[3];
+                grid_cell(m, l, smp, i0, f);
+                const int64_t o = ((i * S + s) * L + l) * 8;
+                for (int c = 0; c < 8; ++c) {
+                    uint32_t v[3];
+                    double wt = 1.0;
+                    for (int a = 0; a < 3; ++a) {
+                        int bit = (c >> a) & 1;
+                        v[a] = i0[a] + bit;
+                        wt *= bit ? f[a] : 1.0 - f[a];
+                    }
+                    idx[o + c] = ((int64_t)table_set(m, s) * L + l) * T + grid_index(m, l, v);
+                    w[o + c] = wt;
+                }
+            }
+        }
+    }
+}
+
+/* Adjoint of the encoding with respect to the tables (the table part of step 12's
+   gradient): for each of n points, the rows dout[i] of d loss / d psi(x_i) are scattered
+   into g_tables with the trilinear weights of every sample and level, exactly as the
+   loss gradient does it.  The encoding is linear in the tables, so this is J^T dout. */
+void orc_encode_backward_batch(const orc_model* m, const double* tables, int64_t n, const double* x,
+                               const double* dout, double* g_tables) {
+    const int W = point_width(m);
+    for (int64_t i = 0; i < n; ++i) encode_point_backward(m, tables, x + 3 * i, dout + i * W, g_tables, NULL);
+}
+
 /* Network on given rest-space point pairs: z[i] = MLP(psi(x0_i) ++ psi(x1_i)). */
 void orc_forward_batch(const orc_model* m, const double* tables, const double* params, int64_t n,
                        const double* x0, const double* x1, double* z, double* zscale) {

@@ -75,7 +75,8 @@ class Batch(C.Structure):
 class TrainCfg(C.Structure):
     _fields_ = [("lr_table", C.c_float), ("lr_mlp", C.c_float), ("lr_s", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("precision", C.c_int32),
-                ("loss_scale_init", C.c_float), ("fixed_task_weights", C.c_int32), ("store_encoding", C.c_int32)]
+                ("loss_scale_init", C.c_float), ("fixed_task_weights", C.c_int32), ("store_encoding", C.c_int32),
+                ("loss_scale_growth_interval", C.c_int32)]
 
 
 _lib = None

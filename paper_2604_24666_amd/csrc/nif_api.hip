@@ -377,6 +377,8 @@ int nif_train_step(nif_model* m, const nif_batch* b, int64_t B, const nif_train_
     REQUIRE(cfg->beta1 >= 0.f && cfg->beta1 < 1.f && cfg->beta2 >= 0.f && cfg->beta2 < 1.f && cfg->eps > 0.f, "bad Adam hyper-parameters");
     REQUIRE(cfg->fixed_task_weights == 0 || cfg->fixed_task_weights == 1, "fixed_task_weights must be 0 or 1");
     REQUIRE(cfg->store_encoding == 0 || cfg->store_encoding == 1, "store_encoding must be 0 or 1");
+    REQUIRE(cfg->loss_scale_growth_interval >= 0, "loss_scale_growth_interval must be >= 0");
+    REQUIRE(cfg->loss_scale_init >= 0.f && cfg->loss_scale_init < 3.0e38f, "loss_scale_init must be finite and >= 0");
     if (!m->params_set) return fail(NIF_E_STATE, "model parameters were never set");
     if (B > m->max_batch) return fail(NIF_E_STATE, "batch larger than reserved with nif_model_reserve");
     return nif::train_step_launch(m, b, B, cfg, losses, S(stream));

@@ -31,7 +31,7 @@ NetParams make_net_params(const nif_model* m, int32_t precision);
 enum { TC_NPOS = 0, TC_STEP = 1, TC_GOOD = 2, TC_NONFINITE = 3, TC_SKIP = 4 };
 enum { DA_SUM = 0, DA_SCALE = 5, DA_SCALE_USED = 6, DA_C1 = 7, DA_C2 = 8 };
 constexpr float kDistEps = 1e-4f;
-constexpr int kGrowInterval = 1000;
+constexpr int kGrowIntervalDefault = 1000;  // clean steps before the loss scale doubles
 constexpr int64_t kEncBwdChunk = 1 << 16;  // samples per count/fill/reduce round
 constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
 
@@ -1047,7 +1047,7 @@ __global__ void k_check_finite(const float* __restrict__ a, int64_t n, int64_t* 
 
 // Losses, d total / d s, dynamic loss scale, skip decision, Adam bias corrections (one thread).
 __global__ void k_finalize(double* dacc, int64_t* tcount, const float* s, float* g_s, float* losses, int64_t B,
-                           int dynamic, float beta1, float beta2, int fixed) {
+                           int dynamic, int grow_interval, float beta1, float beta2, int fixed) {
     if (threadIdx.x != 0) return;
     const double P = (double)tcount[TC_NPOS];
     double Ls[5], w[5];
@@ -1079,7 +1079,7 @@ __global__ void k_finalize(double* dacc, int64_t* tcount, const float* s, float*
         tcount[TC_SKIP] = 0;
         tcount[TC_STEP] += 1;
         tcount[TC_GOOD] += 1;
-        if (dynamic && tcount[TC_GOOD] >= kGrowInterval) { scale *= 2.0; tcount[TC_GOOD] = 0; }
+        if (dynamic && tcount[TC_GOOD] >= grow_interval) { scale *= 2.0; tcount[TC_GOOD] = 0; }
     }
     dacc[DA_SCALE] = scale;
     const double t = (double)tcount[TC_STEP];
@@ -1439,8 +1439,9 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
     if (rc) return rc;
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table, m->tcount);
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp, m->tcount);
+    const int grow = cfg->loss_scale_growth_interval > 0 ? cfg->loss_scale_growth_interval : kGrowIntervalDefault;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, m->dacc, m->tcount, m->s, m->g_s, losses, B,
-                       prec != NIF_PREC_FP32 ? 1 : 0, cfg->beta1, cfg->beta2, cfg->fixed_task_weights);
+                       prec != NIF_PREC_FP32 ? 1 : 0, grow, cfg->beta1, cfg->beta2, cfg->fixed_task_weights);
     AdamParams A;
     A.tables = m->tables; A.g_tables = m->g_tables; A.m_tables = m->m_tables; A.v_tables = m->v_tables;
     A.tables_h = m->desc.table_dtype == NIF_TABLE_F16 ? m->tables_h : nullptr;

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -114,9 +115,10 @@ def test_train_step_configuration_is_validated_on_the_host(P):
     fake = C.c_void_p(1)
     batch = P.Batch(*([1] * 7))
     good = dict(lr_table=1e-2, lr_mlp=1e-3, lr_s=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, precision=0,
-                loss_scale_init=0.0, fixed_task_weights=0, store_encoding=0)
+                loss_scale_init=0.0, fixed_task_weights=0, store_encoding=0, loss_scale_growth_interval=0)
     for k, v in [("store_encoding", 2), ("store_encoding", -1), ("fixed_task_weights", 3), ("precision", 3),
-                 ("beta1", 1.0), ("eps", 0.0)]:
+                 ("beta1", 1.0), ("eps", 0.0), ("loss_scale_growth_interval", -1), ("loss_scale_init", -1.0),
+                 ("loss_scale_init", float("inf"))]:
         cfg = P.TrainCfg(**{**good, k: v})
         assert L.nif_train_step(fake, C.byref(batch), 4, C.byref(cfg), fake, None) == 1, k
     assert L.nif_train_step(fake, C.byref(batch), 0, C.byref(P.TrainCfg(**good)), fake, None) == 1   # empty batch
@@ -162,3 +164,4 @@ def test_loss_arguments_are_validated_on_the_host(P):
     assert L.nif_loss(fake, fake, 4, C.byref(labels), None, 0, fake, None, None, None) == 1   # null s
     no_t = P.Batch(1, 1, 1, None, 1, 1, 1)
     assert L.nif_loss(fake, fake, 4, C.byref(no_t), fake, 0, fake, None, None, None) == 1     # missing labels
+

@@ -4,8 +4,10 @@ weight values (FP16 tables and BF16/FP16 weights widened exactly).
 
 Bars (derivation in DESIGN.md):
   encoding      |gpu - ref| <= 2e-6 * max|table|  (weights rounded to FP32, 8-term sums)
-  FP32 heads    |gpu - ref| / max(|ref|, RMS of the head) <= 1e-5
-  BF16 / FP16   per-head error reported; p99 of the same relative error <= 3e-2 / 4e-3."""
+  FP32 heads    |gpu - ref| / max(|ref|, 1e-3 RMS of the head) <= 1e-5, or (outputs near 0)
+                within 7 sigma of the first-order rounding-error model of tests/_bounds.py
+  BF16 / FP16   per-head error reported here; held element-wise to the rounding-error model in
+                test_gpu_precision."""
 import dataclasses
 
 import numpy as np
@@ -57,6 +59,24 @@ def test_encoding_matches_oracle(orc, P, name):
     assert err <= 2e-6 * np.abs(seen).max()
 
 
+def _fp32_close(orc, m, seen, prm, x0, x1, got, ref, rms, label):
+    """FP32 heads: |gpu - ref| <= 1e-5 max(|ref|, 1e-3 RMS of the head); an output closer to 0
+    than that floor may instead lie within 7 sigma of the first-order rounding-error model of
+    the FP32 arithmetic (tests/_bounds.py)."""
+    err = np.abs(got - ref)
+    ok = err <= 1e-5 * np.maximum(np.abs(ref), 1e-3 * rms)
+    e = err / np.maximum(np.abs(ref), 1e-3 * rms)
+    n_model = 0
+    if not ok.all():
+        import _bounds as BD
+        fw = BD.forward(orc, m, seen, prm.astype(np.float64), x0.T.astype(np.float64), x1.T.astype(np.float64), 0)
+        within = err <= BD.LAMBDA * fw["sz"]
+        n_model = int((~ok & within).sum())
+        ok |= within
+    say(f"  {label}  max rel err {e.max():.3e}  beyond 1e-5 but within the rounding model: {n_model}")
+    assert ok.all(), f"{int((~ok).sum())} heads beyond both bars"
+
+
 @pytest.mark.parametrize("name", list(MODELS))
 def test_fp32_heads_match_oracle(orc, P, name):
     m = MODELS[name]
@@ -71,9 +91,7 @@ def test_fp32_heads_match_oracle(orc, P, name):
         ref = orc.forward(m, seen, prm.astype(np.float64), x0.T.astype(np.float64), x1.T.astype(np.float64))
         if rms is None:
             rms = np.sqrt(np.mean(ref ** 2, axis=0, keepdims=True))
-        e = np.abs(got - ref) / np.maximum(np.abs(ref), rms)
-        say(f"  B={B}  max rel err {e.max():.3e}")
-        assert e.max() <= 1e-5
+        _fp32_close(orc, m, seen, prm, x0, x1, got, ref, rms, f"B={B}")
 
 
 def test_fp32_heads_at_the_training_batch_size_sampled(orc, P):
@@ -91,14 +109,16 @@ def test_fp32_heads_at_the_training_batch_size_sampled(orc, P):
     ref = orc.forward(m, seen, prm.astype(np.float64), x0[:, idx].T.astype(np.float64),
                       x1[:, idx].T.astype(np.float64))
     rms = np.sqrt(np.mean(ref ** 2, axis=0, keepdims=True))
-    e = np.abs(got[idx] - ref) / np.maximum(np.abs(ref), rms)
-    say(f"forward fp32 blobs128 B={B} sampled: max rel err {e.max():.3e}")
-    assert e.max() <= 1e-5
+    say(f"forward fp32 blobs128 B={B} sampled")
+    _fp32_close(orc, m, seen, prm, x0[:, idx], x1[:, idx], got[idx], ref, rms, "sampled")
 
 
-@pytest.mark.parametrize("prec,p99", [(1, 3e-2), (2, 4e-3)])
-@pytest.mark.parametrize("name", ["spheres64_p", "spheres64", "w32_concat"])
-def test_low_precision_heads_error_per_head(orc, P, name, prec, p99):
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("name", ["spheres64_p", "spheres64", "w32_concat", "torus16"])
+def test_low_precision_heads_error_per_head(orc, P, name, prec):
+    """BF16 / FP16 heads against the oracle on the same rounded weights: per-head relative error
+    reported, every head within 7 sigma of the first-order rounding-error model."""
+    import _bounds as BD
     m = MODELS[name]
     say(f"forward prec={prec} {name}")
     tab, prm, seen = model_params(m, 31, scale_tables=1e3)
@@ -106,12 +126,14 @@ def test_low_precision_heads_error_per_head(orc, P, name, prec, p99):
     model.set_params(tab, prm)
     x0, x1 = _points(4096, 32)
     got = model.forward(dev_f32(x0), dev_f32(x1), prec).cpu().numpy().astype(np.float64)
-    ref = orc.forward(m, seen, quantized_mlp(prm, prec), x0.T.astype(np.float64), x1.T.astype(np.float64))
+    q = quantized_mlp(prm, prec)
+    ref = orc.forward(m, seen, q, x0.T.astype(np.float64), x1.T.astype(np.float64))
     e = rel_err(got, ref)
     heads = {"hit": [0], "dist": [1], "normal": [2, 3, 4], "albedo": [5, 6, 7], "material": list(range(8, m.n_heads))}
     for h, cols in heads.items():
         say(f"  {h:8s} p50 {np.quantile(e[:, cols], 0.5):.2e}  p99 {np.quantile(e[:, cols], 0.99):.2e}")
-    assert np.quantile(e, 0.99) <= p99
+    fw = BD.forward(orc, m, seen, q, x0.T.astype(np.float64), x1.T.astype(np.float64), prec)
+    BD.check(got, ref, fw["sz"], "heads", say)
 
 
 def test_fp32_heads_of_the_workload_models_are_not_trivial(orc, P):

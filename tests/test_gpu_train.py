@@ -1,9 +1,9 @@
 """GPU parity of the hand-written backward and of the training step against the FP64 oracle.
 
 Bar: gradients within 1e-4 relative, norm-wise per tensor, and element-wise wherever
-|g| > 1e-3 max|g| given the same d loss / d heads; for a whole step (d loss / d heads formed
-by the GPU in FP32) norm-wise 1e-4 and element-wise 1e-3 from 1e-2 max|g|; losses within 1e-5
-relative; the first Adam update equals -lr g / (|g| + eps) element-wise."""
+|g| > 1e-3 max|g|, both given the oracle's d loss / d heads and for a whole step (d loss /
+d heads formed by the GPU from its own FP32 forward; the distance head's bias away from 0);
+losses within 1e-5 relative; the first Adam update equals -lr g / (|g| + eps) element-wise."""
 import ctypes as C
 import dataclasses
 
@@ -37,14 +37,26 @@ def _batch(m, B, seed):
     return x0, x1, hit, t, nr, al, mt
 
 
-def _grad_close(got, ref, name, big_frac=1e-3, el_tol=1e-4):
+def _grad_close(got, ref, name, big_frac=1e-3, el_tol=1e-4, sigma=None, lam=7.0):
+    """Norm-wise 1e-4 and element-wise el_tol where |g| > big_frac max|g|; with sigma (the
+    first-order rounding-error model of tests/_bounds.py), an element beyond el_tol passes if
+    it lies within lam sigma (gradients that cancel over the batch: small against the sum of
+    their terms, which sets their rounding error)."""
     got = np.asarray(got, dtype=np.float64).reshape(-1)
     ref = np.asarray(ref, dtype=np.float64).reshape(-1)
     nrm = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
     big = np.abs(ref) > big_frac * np.abs(ref).max()
-    el = (np.abs(got - ref)[big] / np.abs(ref)[big]).max(initial=0)
-    say(f"  {name:8s} norm-wise {nrm:.2e}  element-wise (|g| > {big_frac:g} max) {el:.2e}  n={int(big.sum())}")
-    assert nrm <= 1e-4 and el <= el_tol, name
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    bad = big & (rel > el_tol)
+    n_model = 0
+    if sigma is not None:
+        within = np.abs(got - ref) <= lam * np.asarray(sigma).reshape(-1)
+        n_model = int((bad & within).sum())
+        bad &= ~within
+    el = rel[big].max(initial=0)
+    say(f"  {name:8s} norm-wise {nrm:.2e}  element-wise (|g| > {big_frac:g} max) {el:.2e}  n={int(big.sum())}"
+        + (f"  beyond {el_tol:g} but within the rounding model: {n_model}" if sigma is not None else ""))
+    assert nrm <= 1e-4 and not bad.any(), name
 
 
 MODELS = {
@@ -81,6 +93,20 @@ def test_backward_matches_oracle_gradient(orc, P, name):
     _grad_close(dx1.cpu().numpy().T, gx1, "d x1")
 
 
+def _step_model(orc, m, seen, prm, batch, s, fixed=False):
+    """sigma of the FP32 whole step's table and MLP gradients under the first-order
+    rounding-error model (the step forms d heads from its own forward)."""
+    import _bounds as BD
+    x0, x1, hit, t, nr, al, mt = batch
+    X0, X1, q = x0.T.astype(np.float64), x1.T.astype(np.float64), prm.astype(np.float64)
+    dz = orc.loss_grad(m, seen, q, s, X0, X1, hit, t, nr.T, al.T, mt, want_dz=True, fixed_weights=fixed)[6]
+    fw = BD.forward(orc, m, seen, q, X0, X1, 0)
+    Cdz = BD.loss_dz_cov(m, fw, dz, hit, t.astype(np.float64), nr.T.astype(np.float64), al.T.astype(np.float64), s,
+                         fixed=fixed, x0=X0, x1=X1)
+    bw = BD.backward(orc, m, seen, q, fw, X0, X1, dz, Cdz, 0)
+    return bw["tables"][1], bw["mlp"]
+
+
 def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3), fixed=False, store=False):
     import torch
     x0, x1, hit, t, nr, al, mt = batch
@@ -102,6 +128,10 @@ def test_train_step_matches_oracle(orc, P, name, store):
     m = MODELS[name]
     say(f"train step fp32 {name} store_encoding={int(store)}")
     tab, prm, seen = model_params(m, 7, scale_tables=300.0)
+    # distance head live at half a voxel: with its bias at 0 the predicted distances sit near
+    # 0, where the log-distance gradient 2 r / (d + eps) amplifies the forward's FP32 error by
+    # up to 1 / eps
+    prm[m.n_mlp_params - m.n_heads + 1] = 0.5 / 128
     B = 2048 + 11
     batch = _batch(m, B, 8)
     x0, x1, hit, t, nr, al, mt = batch
@@ -115,12 +145,9 @@ def test_train_step_matches_oracle(orc, P, name, store):
     assert np.all(np.abs(losses[:6] - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
     assert losses[12] == 0 and losses[13] == hit.sum()
     g_t, g_p, g_s = model.get_grads()
-    # here d loss / d heads is formed from the GPU's own FP32 forward: the log-distance term
-    # 2 r / (d + eps) amplifies the forward's error by up to ~1 / (d + eps) where the predicted
-    # distance d is near eps, so per-element gradients of the whole step are held to 1e-3
-    # (from 1e-2 max|g|); the strict element-wise 1e-4 applies given the same d loss / d heads
-    _grad_close(g_t.cpu().numpy(), gt, "tables", big_frac=1e-2, el_tol=1e-3)
-    _grad_close(g_p.cpu().numpy(), gp, "mlp", big_frac=1e-2, el_tol=1e-3)
+    st, sp = _step_model(orc, m, seen, prm, batch, s0)
+    _grad_close(g_t.cpu().numpy(), gt, "tables", sigma=st)
+    _grad_close(g_p.cpu().numpy(), gp, "mlp", sigma=sp)
     assert np.abs(g_s.cpu().numpy() - gs).max() <= 1e-5 * np.abs(gs).max()
     # first Adam step: theta - lr g / (|g| + eps), element-wise where the gradient is not tiny
     t1, p1, s1 = [v.cpu().numpy().astype(np.float64) for v in model.get_params()]
@@ -167,8 +194,9 @@ def test_train_step_ablation_switches_match_oracle(orc, P, variant):
     say(f"  losses gpu {np.round(losses[:6], 6)}  oracle {np.round(L, 6)}")
     assert np.all(np.abs(losses[:6] - L) <= 1e-5 * np.maximum(np.abs(L), 1e-3))
     g_t, g_p, g_s = model.get_grads()
-    _grad_close(g_t.cpu().numpy(), gt, "tables", big_frac=1e-2, el_tol=1e-3)
-    _grad_close(g_p.cpu().numpy(), gp, "mlp", big_frac=1e-2, el_tol=1e-3)
+    st, sp = _step_model(orc, m, seen, prm, batch, s0, fixed=fixed)
+    _grad_close(g_t.cpu().numpy(), gt, "tables", sigma=st)
+    _grad_close(g_p.cpu().numpy(), gp, "mlp", sigma=sp)
     t1, p1, s1 = [v.cpu().numpy().astype(np.float64) for v in model.get_params()]
     if fixed:
         assert np.all(g_s.cpu().numpy() == 0) and np.all(s1 == s0.astype(np.float32))

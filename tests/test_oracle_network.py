@@ -167,6 +167,35 @@ def test_hashed_level_reads_the_instant_ngp_hash_entry_at_a_vertex(orc):
         assert exact.sum() >= 1
 
 
+@pytest.mark.parametrize("per_sample", [0, 1])
+def test_encoding_adjoint_is_the_transpose_of_the_encoding(orc, per_sample):
+    """psi is linear in the tables, psi(x; t) = J(x) t, so <v, psi(x; t)> = <J^T v, t> for any
+    tables t and any v: the adjoint scatter agrees with the encoding itself, on dense and
+    hashed levels; and J^T |v| >= |J^T v| (trilinear weights are nonnegative)."""
+    m = _small_model(log2_table=12, per_sample_tables=per_sample)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-0.05, 1.05, (200, 3))
+    W = m.n_samples * m.levels * m.feat_dim
+    v = rng.normal(size=(200, W))
+    t = rng.normal(size=(m.table_levels, m.table_size, m.feat_dim))
+    g = orc.encode_backward(m, t, x, v)
+    assert g.shape == t.shape
+    lhs = float(np.sum(v * orc.encode(m, t, x)))
+    rhs = float(np.sum(g * t))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, np.abs(v).sum() * np.abs(t).max())
+    ga = orc.encode_backward(m, t, x, np.abs(v))
+    assert np.all(ga >= np.abs(g) - 1e-15) and np.count_nonzero(ga) > 0
+    # the sparse Jacobian: scattering v with the listed corners and weights is the adjoint
+    idx, w = orc.encode_corners(m, x)
+    assert idx.shape == (200, m.n_samples, m.levels, 8)
+    np.testing.assert_allclose(w.sum(axis=3), 1.0, rtol=0, atol=1e-12)          # partition of unity
+    vv = v.reshape(200, m.n_samples, m.levels, m.feat_dim)
+    gs = np.zeros(t.size)
+    for f in range(m.feat_dim):
+        np.add.at(gs, (idx * m.feat_dim + f).reshape(-1), (w * vv[:, :, :, None, f]).reshape(-1))
+    np.testing.assert_allclose(gs, g.reshape(-1), rtol=0, atol=1e-12 * np.abs(g).max())
+
+
 def test_mlp_matches_numpy_float64(orc):
     m = _small_model()
     tab = S.init_tables(m, 5).astype(np.float64) * 1e3
