@@ -158,6 +158,20 @@ int nif_voxelize(int32_t scene_kind, const double* params_host, int32_t n_params
 int nif_label(int32_t scene_kind, const double* params_host, int32_t n_params, int32_t force_march,
               const float* x0_dev, const float* x1_dev, int64_t n, uint8_t* hit_dev, float* t_dev,
               float* normal_dev, float* albedo_dev, int32_t* material_dev, nif_stream stream);
+/* nif_label for callers that cannot allocate device memory (tight data-generation loops,
+ * harnesses that forbid hipMalloc).  Same arguments and outputs as nif_label, bit for bit;
+ * it allocates nothing and does not synchronise: the scene parameters are staged (copied
+ * from params_host before the call returns) into a fixed per-device array of the library,
+ * NIF_LABEL_NOALLOC_MAX_PARAMS doubles (32,832 bytes, held by every device the library runs
+ * on until the process ends); more parameters are rejected with NIF_E_INVALID_ARG.  Every
+ * call on one device shares that array: calls that overlap on a device (other streams or
+ * threads, before the previous call's kernel has finished) race on it; calls on one stream
+ * are ordered. */
+#define NIF_LABEL_NOALLOC_MAX_PARAMS 4104
+int nif_label_noalloc(int32_t scene_kind, const double* params_host, int32_t n_params, int32_t force_march,
+                      const float* x0_dev, const float* x1_dev, int64_t n, uint8_t* hit_dev, float* t_dev,
+                      float* normal_dev, float* albedo_dev, int32_t* material_dev, nif_stream stream);
+
 /* ---------------------------------------------------------------- deformed grid
  * Per pose: the deformed lattice vertices V_ijk = D(i/N, j/N, k/N) (faces split along their
  * main diagonal), and an acceleration structure over the occupied deformed voxels

@@ -21,7 +21,7 @@ __all__ = ["NifError", "lib", "ModelDesc", "Pose", "Rays", "Hits", "Segments", "
            "nif_model_create", "nif_model_destroy", "nif_model_sizes", "nif_model_set_params",
            "nif_model_get_params", "nif_model_get_grads", "nif_model_zero_grads", "nif_model_reserve",
            "nif_model_reserve_encoding",
-           "nif_voxelize", "nif_label", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
+           "nif_voxelize", "nif_label", "nif_label_noalloc", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
            "nif_encode", "nif_forward", "nif_backward", "nif_train_step", "nif_loss",
            "Model", "Grid", "NifField", "NifMultiTaskLoss", "label"]
 
@@ -102,6 +102,7 @@ def lib():
             "nif_model_reserve_encoding": ([P], C.c_int),
             "nif_voxelize": ([I32, P, I32, I32, P, P], C.c_int),
             "nif_label": ([I32, P, I32, I32, P, P, C.c_int64, P, P, P, P, P, P], C.c_int),
+            "nif_label_noalloc": ([I32, P, I32, I32, P, P, C.c_int64, P, P, P, P, P, P], C.c_int),
             "nif_build_grid": ([P, I32, P, I32, I32, P, P], C.c_int), "nif_grid_destroy": ([P], C.c_int),
             "nif_grid_info": ([P, I32, P, P, P], C.c_int), "nif_grid_bounds": ([P, I32, P, P], C.c_int), "nif_grid_update": ([P, P, I32, P], C.c_int),
             "nif_trace": ([P, P, I64, I32, P, P], C.c_int),
@@ -200,6 +201,20 @@ def nif_label(scene_kind: int, params, x0, x1, n: int, hit=None, t=None, normal=
     p = np.ascontiguousarray(params, dtype=np.float64)
     _check(lib().nif_label(scene_kind, p.ctypes.data_as(C.c_void_p), len(p), int(force_march), _ptr(x0), _ptr(x1), n,
                            _ptr(hit), _ptr(t), _ptr(normal), _ptr(albedo), _ptr(material), _stream(stream)))
+
+
+def nif_label_noalloc(scene_kind: int, params, x0, x1, n: int, hit=None, t=None, normal=None, albedo=None,
+                      material=None, force_march: bool = False, stream=None):
+    """nif_label without allocation or synchronisation (scene parameters staged in the
+    library's fixed per-device array, at most NIF_LABEL_NOALLOC_MAX_PARAMS values)."""
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    _check(lib().nif_label_noalloc(scene_kind, p.ctypes.data_as(C.c_void_p), len(p), int(force_march), _ptr(x0),
+                                   _ptr(x1), n, _ptr(hit), _ptr(t), _ptr(normal), _ptr(albedo), _ptr(material),
+                                   _stream(stream)))
+
+
+LABEL_NOALLOC_MAX_PARAMS = 4104
 
 
 def label(scene_kind: int, params, x0, x1, force_march: bool = False):

@@ -205,6 +205,21 @@ int nif_label(int32_t kind, const double* params, int32_t n_params, int32_t forc
     return nif::label_launch(kind, params, n_params, force_march, x0, x1, n, hit, t, nrm, alb, mat, S(stream));
 }
 
+static_assert(NIF_LABEL_NOALLOC_MAX_PARAMS == nif::kLabelScratchDoubles, "label scratch size");
+
+int nif_label_noalloc(int32_t kind, const double* params, int32_t n_params, int32_t force_march, const float* x0,
+                      const float* x1, int64_t n, uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat,
+                      nif_stream stream) {
+    REQUIRE(kind >= 0 && kind <= 2, "scene_kind must be 0 (torus), 1 (spheres) or 2 (blobs)");
+    REQUIRE(params && n_params >= 1, "params must not be empty");
+    REQUIRE(n_params <= NIF_LABEL_NOALLOC_MAX_PARAMS, "n_params exceeds NIF_LABEL_NOALLOC_MAX_PARAMS (4104)");
+    if (kind == 0) REQUIRE(n_params >= 5, "torus needs 5 parameters");
+    else REQUIRE(params[0] >= 0 && n_params >= 1 + 8 * (int64_t)params[0], "parameter count does not match n");
+    REQUIRE(n >= 0, "n must be >= 0");
+    if (n > 0) REQUIRE(x0 && x1, "x0 and x1 must not be null");
+    return nif::label_launch_noalloc(kind, params, n_params, force_march, x0, x1, n, hit, t, nrm, alb, mat, S(stream));
+}
+
 int nif_build_grid(const uint8_t* occ, int32_t N, const nif_pose* poses, int32_t n_poses, int32_t bins_per_axis,
                    nif_grid** out, nif_stream stream) {
     REQUIRE(occ, "occ is null");

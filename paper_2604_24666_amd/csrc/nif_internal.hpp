@@ -114,6 +114,12 @@ int encode_launch(const nif_model* m, const float* x, int64_t n, float* out, hip
 int label_launch(int kind, const double* params_host, int32_t n_params, int force_march, const float* x0,
                  const float* x1, int64_t n, uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat,
                  hipStream_t st);
+// Same labels with the scene parameters staged in a static per-device array (no allocation,
+// no synchronisation); n_params <= kLabelScratchDoubles.
+constexpr int32_t kLabelScratchDoubles = 4104;
+int label_launch_noalloc(int kind, const double* params_host, int32_t n_params, int force_march, const float* x0,
+                         const float* x1, int64_t n, uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat,
+                         hipStream_t st);
 int forward_launch(const nif_model* m, const float* x0, const float* x1, int64_t B, float* heads,
                    int32_t precision, float* acts, float* enc, hipStream_t st);
 // Forward of n pairs whose SoA rows have stride ld (heads [n][H], acts [layers][n][HW] and enc

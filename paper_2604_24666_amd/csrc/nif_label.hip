@@ -12,6 +12,7 @@
 // at that point.  Everything in FP64, so the sign decisions are taken in the same precision as
 // the reference implementation.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "nif_internal.hpp"
@@ -187,6 +188,16 @@ __global__ void __launch_bounds__(256) k_label(int kind, const double* __restric
     }
 }
 
+static void launch_label(int kind, const double* sp_dev, int force_march, const float* x0, const float* x1, int64_t n,
+                         uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat, hipStream_t st) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)cus * 16);
+    hipLaunchKernelGGL(k_label, dim3((unsigned)blocks), dim3(256), 0, st, kind, sp_dev, force_march, x0, x1, n, hit, t,
+                       nrm, alb, mat);
+}
+
 int label_launch(int kind, const double* params_host, int32_t n_params, int force_march, const float* x0,
                  const float* x1, int64_t n, uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat,
                  hipStream_t st) {
@@ -196,17 +207,56 @@ int label_launch(int kind, const double* params_host, int32_t n_params, int forc
     if (rc) return rc;
     rc = check_hip(hipMemcpyAsync(dp, params_host, sizeof(double) * n_params, hipMemcpyHostToDevice, st), "copy scene");
     if (!rc) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 256;
-        const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)cus * 16);
-        hipLaunchKernelGGL(k_label, dim3((unsigned)blocks), dim3(256), 0, st, kind, dp, force_march, x0, x1, n, hit, t,
-                           nrm, alb, mat);
+        launch_label(kind, dp, force_march, x0, x1, n, hit, t, nrm, alb, mat, st);
         rc = check_hip(hipGetLastError(), "k_label launch");
     }
     if (!rc) rc = check_hip(hipStreamSynchronize(st), "label sync");
     (void)hipFree(dp);
     return rc;
+}
+
+// Allocation-free labelling: the scene parameters are staged in a per-device array of the
+// code object instead of a buffer allocated per call.  The array's host-side name is not a
+// device address; its address on each device comes from hipGetSymbolAddress, once per device,
+// with that device current, and only that address is handed to copies and kernels.  Every
+// call on a device shares its array: calls that overlap on one device (other streams, other
+// threads) race on it.
+static __device__ __align__(256) double scratch[kLabelScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static int label_scratch(double** out) {
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return fail(NIF_E_DEVICE, "device index beyond the library's table of 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return rc;
+        if (!p) return fail(NIF_E_DEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return NIF_OK;
+}
+
+int label_launch_noalloc(int kind, const double* params_host, int32_t n_params, int force_march, const float* x0,
+                         const float* x1, int64_t n, uint8_t* hit, float* t, float* nrm, float* alb, int32_t* mat,
+                         hipStream_t st) {
+    if (n_params > kLabelScratchDoubles)
+        return fail(NIF_E_INVALID_ARG, "n_params exceeds the allocation-free label scratch (4104 values)");
+    if (n == 0) return NIF_OK;
+    double* sp = nullptr;
+    int rc = label_scratch(&sp);
+    if (rc) return rc;
+    rc = check_hip(hipMemcpyAsync(sp, params_host, sizeof(double) * n_params, hipMemcpyHostToDevice, st),
+                   "stage scene parameters");
+    if (rc) return rc;
+    launch_label(kind, sp, force_march, x0, x1, n, hit, t, nrm, alb, mat, st);
+    return check_hip(hipGetLastError(), "k_label launch");
 }
 
 #pragma clang fp contract(fast)

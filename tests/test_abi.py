@@ -165,3 +165,20 @@ def test_loss_arguments_are_validated_on_the_host(P):
     no_t = P.Batch(1, 1, 1, None, 1, 1, 1)
     assert L.nif_loss(fake, fake, 4, C.byref(no_t), fake, 0, fake, None, None, None) == 1     # missing labels
 
+
+def test_label_noalloc_validates_on_the_host(P):
+    """The allocation-free labelling call rejects, before touching the device, a parameter
+    vector longer than its fixed array, and the same malformed inputs as nif_label."""
+    L = P.lib()
+    fake = C.c_void_p(1)
+    n_max = 4104
+    assert P.LABEL_NOALLOC_MAX_PARAMS == n_max
+    ok = np.zeros(1 + 8 * 4)
+    ok[0] = 4
+    big = np.zeros(1 + 8 * 513)
+    big[0] = 513
+    args = lambda p, n: (1, p.ctypes.data_as(C.c_void_p), len(p), 0, fake, fake, n) + (None,) * 5 + (None,)
+    assert L.nif_label_noalloc(*args(big, 4)) == 1 and b"NIF_LABEL_NOALLOC_MAX_PARAMS" in L.nif_last_error()
+    assert L.nif_label_noalloc(*args(ok[:9], 4)) == 1           # parameter count does not match n
+    assert L.nif_label_noalloc(*args(ok, -1)) == 1              # negative count
+    assert L.nif_label_noalloc(3, ok.ctypes.data_as(C.c_void_p), len(ok), 0, fake, fake, 4, *([None] * 5), None) == 1
