@@ -7,6 +7,7 @@ It shares no code with the GPU library: the C sources here are compiled with gcc
 
 Each function follows a passage of the paper (cited in the C sources):
   deform / deform_inv          parameterized deformation and its analytic inverse
+  scene_f, scene_grad, scene_attr  the synthetic scenes' implicit function, gradient, attributes
   voxelize, label              rest-space voxelization, ground-truth labels of rest segments
   lattice_vertices, trace      deformed lattice; ordered occupied-voxel hit lists (brute/walk)
   encode, forward              psi = phi(gamma(x)) encoding; MLP heads on point pairs
@@ -128,6 +129,25 @@ def scene_f(kind: int, sp, p) -> np.ndarray:
     lib().orc_scene_f_batch(C.c_int32(kind), _p(sp, C.c_double), C.c_int64(len(p)),
                             _p(p, C.c_double), _p(out, C.c_double))
     return out
+
+
+def scene_grad(kind: int, sp, p) -> np.ndarray:
+    """grad f of the scene's implicit function at points p (rows)."""
+    sp = _f64(sp); p = _aos(p).reshape(-1, 3)
+    g = np.empty_like(p)
+    lib().orc_scene_grad_batch(C.c_int32(kind), _p(sp, C.c_double), C.c_int64(len(p)), _p(p, C.c_double),
+                               _p(g, C.c_double))
+    return g
+
+
+def scene_attr(kind: int, sp, p):
+    """(albedo [n][3], material [n]) of the scene at points p (rows)."""
+    sp = _f64(sp); p = _aos(p).reshape(-1, 3)
+    al = np.empty_like(p)
+    mt = np.empty(len(p), np.int32)
+    lib().orc_scene_attr_batch(C.c_int32(kind), _p(sp, C.c_double), C.c_int64(len(p)), _p(p, C.c_double),
+                               _p(al, C.c_double), _p(mt, C.c_int32))
+    return al, mt
 
 
 def voxelize(kind: int, sp, N: int) -> np.ndarray:

@@ -250,6 +250,15 @@ void orc_scene_f_batch(int32_t kind, const double* sp, int64_t n, const double* 
     for (int64_t i = 0; i < n; ++i) out[i] = orc_scene_f(kind, sp, p + 3 * i);
 }
 
+void orc_scene_grad_batch(int32_t kind, const double* sp, int64_t n, const double* p, double* g) {
+    for (int64_t i = 0; i < n; ++i) orc_scene_grad(kind, sp, p + 3 * i, g + 3 * i);
+}
+
+void orc_scene_attr_batch(int32_t kind, const double* sp, int64_t n, const double* p, double* albedo,
+                          int32_t* material) {
+    for (int64_t i = 0; i < n; ++i) orc_scene_attr(kind, sp, p + 3 * i, albedo + 3 * i, material + i);
+}
+
 void orc_label_batch(int32_t kind, const double* sp, int32_t force_march, int64_t n,
                      const double* x0, const double* x1, uint8_t* hit, double* t, double* nrm,
                      double* alb, int32_t* mat) {

@@ -236,6 +236,89 @@ def test_blob_labels_lie_on_the_surface(orc):
     assert np.all((alb[sel] >= 0.1) & (alb[sel] <= 0.9))
 
 
+@pytest.mark.parametrize("workload", ["torus16", "spheres64", "blobs128"])
+def test_scene_gradient_is_the_central_difference_of_f_and_points_outward(orc, workload):
+    """grad f (which every label normal comes from) against FP64 central differences of f, and
+    the label normals point outward: f grows along them across the surface."""
+    w = S.workload(workload)
+    sp = S.scene_params(w.scene_kind, w.seed)
+    rng = np.random.default_rng(21)
+    p = rng.uniform(0.15, 0.85, (3000, 3))
+    f0 = orc.scene_f(w.scene_kind, sp, p)
+    if w.scene_kind == S.SCENE_SPHERES:          # away from the switch between nearest spheres
+        c = np.stack([sp[1 + 8 * i:4 + 8 * i] for i in range(int(sp[0]))])
+        dist = np.linalg.norm(p[:, None, :] - c[None], axis=2) - sp[1 + 8 * np.arange(int(sp[0])) + 3][None]
+        two = np.sort(dist, axis=1)[:, :2]
+        p = p[two[:, 1] - two[:, 0] > 1e-3]
+    g = orc.scene_grad(w.scene_kind, sp, p)
+    h = 1e-6
+    fd = np.stack([(orc.scene_f(w.scene_kind, sp, p + h * e) - orc.scene_f(w.scene_kind, sp, p - h * e)) / (2 * h)
+                   for e in np.eye(3)], axis=1)
+    scale = np.maximum(np.linalg.norm(g, axis=1), 1e-3)
+    assert np.abs(g - fd).max(axis=1).max() / 1.0 <= 1e-6 * max(1.0, np.abs(fd).max())
+    assert np.all(np.abs(g - fd).max(axis=1) <= 1e-6 * scale + 1e-9)
+    x0, x1 = _segments(4000, 22, lo=0.1, hi=0.9)
+    hit, t, nrm, _, _ = orc.label(w.scene_kind, sp, x0, x1)
+    u = (x1 - x0) / np.linalg.norm(x1 - x0, axis=1, keepdims=True)
+    sel = (hit == 1) & (t > 0)
+    assert sel.sum() > 50
+    q = x0[sel] + t[sel, None] * u[sel]
+    n = nrm[sel]
+    np.testing.assert_allclose(np.linalg.norm(n, axis=1), 1.0, atol=1e-12)
+    gq = orc.scene_grad(w.scene_kind, sp, q)
+    np.testing.assert_allclose(n, gq / np.linalg.norm(gq, axis=1, keepdims=True), atol=1e-12)
+    assert np.all(orc.scene_f(w.scene_kind, sp, q + 1e-6 * n) > 0)
+    assert np.all(orc.scene_f(w.scene_kind, sp, q - 1e-6 * n) < 0)
+
+
+def test_torus_attributes_closed_form_spot_values(orc):
+    """Torus albedo: channel c peaks at 0.9 where 2 p_c + c/3 = 1/4 (mod 1) and has period 1/2 in
+    p_c; material flips at x = 1/2."""
+    w = S.workload("torus16")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    # channel 0 at p_x = 1/8, channel 1 at p_y = 11/24, channel 2 at p_z = 7/24: sine = 1
+    p = np.array([[1 / 8, 11 / 24, 7 / 24], [1 / 8 + 0.5, 11 / 24 - 0.25, 7 / 24 + 0.5]])
+    al, _ = orc.scene_attr(w.scene_kind, sp, p)
+    np.testing.assert_allclose(al[0], [0.9, 0.9, 0.9], atol=1e-12)
+    np.testing.assert_allclose(al[1], [0.9, 0.1, 0.9], atol=1e-12)       # p_y shifted a quarter: trough
+    p = np.array([[3 / 8, 0.2, 0.3], [0.25, 0.2, 0.3]])                  # channel 0: 2 p = 3/4 -> -1; 1/2 -> 0
+    al, _ = orc.scene_attr(w.scene_kind, sp, p)
+    np.testing.assert_allclose(al[:, 0], [0.1, 0.5], atol=1e-12)
+    _, mt = orc.scene_attr(w.scene_kind, sp, np.array([[0.5, 0.3, 0.3], [0.5 - 1e-12, 0.3, 0.3], [0.9, 0.1, 0.1]]))
+    assert list(mt) == [1, 0, 1]
+
+
+def test_sphere_attributes_are_those_of_the_nearest_sphere(orc):
+    w = S.workload("spheres64")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    n = int(sp[0])
+    rec = sp[1:1 + 8 * n].reshape(n, 8)
+    p = np.random.default_rng(23).uniform(0.0, 1.0, (2000, 3))
+    al, mt = orc.scene_attr(w.scene_kind, sp, p)
+    near = np.argmin(np.linalg.norm(p[:, None, :] - rec[None, :, :3], axis=2) - rec[None, :, 3], axis=1)
+    np.testing.assert_array_equal(al, rec[near, 4:7])
+    np.testing.assert_array_equal(mt, rec[near, 7].astype(np.int32))
+
+
+def test_blob_attributes_single_blob_and_symmetric_pair(orc):
+    """One blob: its own colour and material everywhere.  Two equal blobs: at the midpoint the
+    colour is the mean of both (equal contributions, dyadic positions) and the material the
+    first's (ties go to the lower index); next to one
+    blob and far from the other, that blob's colour."""
+    one = np.array([1, 0.5, 0.5, 0.5, 0.05, 0.2, 0.4, 0.6, 3.0])
+    p = np.random.default_rng(24).uniform(0.3, 0.7, (50, 3))
+    al, mt = orc.scene_attr(S.SCENE_BLOBS, one, p)
+    np.testing.assert_allclose(al, np.tile([0.2, 0.4, 0.6], (50, 1)), atol=1e-15)
+    assert np.all(mt == 3)
+    two = np.array([2, 0.25, 0.5, 0.5, 0.05, 0.1, 0.2, 0.3, 1.0, 0.75, 0.5, 0.5, 0.05, 0.5, 0.6, 0.9, 2.0])
+    al, mt = orc.scene_attr(S.SCENE_BLOBS, two, np.array([[0.5, 0.5, 0.5], [0.27, 0.5, 0.5], [0.73, 0.51, 0.5]]))
+    np.testing.assert_allclose(al[0], [0.3, 0.4, 0.6], atol=1e-12)
+    assert mt[0] == 1
+    np.testing.assert_allclose(al[1], [0.1, 0.2, 0.3], atol=1e-12)
+    np.testing.assert_allclose(al[2], [0.5, 0.6, 0.9], atol=1e-12)
+    assert list(mt[1:]) == [1, 2]
+
+
 # ------------------------------------------------------------------ lattice and hit lists
 
 def _amanatides_woo(N, occ3, o, d):
@@ -271,6 +354,82 @@ def _amanatides_woo(N, occ3, o, d):
         cell[a] += step[a]
         tmax[a] += tdel[a]
     return out
+
+
+def _line_segment_distance(o, d, a, e):
+    """Distance from each line o + t d (rows, d unit; t over all reals) to each segment
+    a + s e, s in [0, 1]: [rays][segments]."""
+    w0 = o[:, None, :] - a[None, :, :]
+    b = d @ e.T
+    c = np.sum(e * e, axis=1)[None, :]
+    dd = np.einsum("ri,rsi->rs", d, w0)
+    ee = np.einsum("si,rsi->rs", e, w0)
+    den = c - b * b
+    s = np.clip(np.where(den > 1e-300, (ee - b * dd) / np.where(den > 1e-300, den, 1.0), 0.0), 0.0, 1.0)
+    t = s * b - dd
+    diff = w0 + t[..., None] * d[:, None, :] - s[..., None] * e[None, :, :]
+    return np.linalg.norm(diff, axis=2)
+
+
+def test_grazing_flags_equal_an_independent_identity_check(orc):
+    """At the identity pose the lattice is the regular grid, so the grazing criteria have plain
+    forms: the line within 1e-6 of an edge of an occupied voxel (which also covers crossings
+    near an outer edge of a face of one), or an origin within 1e-6 of a face of the voxel the ray
+    starts in (no ray here is near-parallel to a face).  Random rays, rays through
+    edges and vertices of occupied voxels, origins on faces, and offsets of 3e-7 (grazing) and 3e-6
+    (not); rays within a factor 2 of the threshold are left out."""
+    N = 6
+    rng = np.random.default_rng(31)
+    occ = (rng.uniform(size=N ** 3) < 0.5).astype(np.uint8)
+    V = orc.lattice_vertices(S.IDENTITY, 0.0, N)
+    occ_ids = np.flatnonzero(occ)
+    ijk = np.stack([occ_ids % N, (occ_ids // N) % N, occ_ids // (N * N)], axis=1)
+
+    def unit(v):
+        return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+    o_r, d_r = S.rays_random(300, 32)
+    o_r, d_r = o_r.T.astype(np.float64), d_r.T.astype(np.float64)
+    # lines through points of occupied voxels' edges, and offset from them by 3e-7 / 3e-6
+    k = rng.integers(0, len(ijk), 300)
+    ax = rng.integers(0, 3, 300)
+    pe = (ijk[k] + (np.eye(3)[ax] * rng.uniform(0.1, 0.9, 300)[:, None])) / N
+    de = unit(rng.normal(size=(300, 3)))
+    off = unit(np.cross(de, rng.normal(size=(300, 3)))) * np.repeat([0.0, 3e-7, 3e-6], 100)[:, None]
+    o_e = pe + off - 2.0 * de
+    # origins on faces inside the lattice (a random axis coordinate snapped to the grid)
+    o_f = rng.uniform(0.05, 0.95, (100, 3))
+    a_f = rng.integers(0, 3, 100)
+    o_f[np.arange(100), a_f] = np.round(o_f[np.arange(100), a_f] * N) / N
+    d_f = unit(rng.normal(size=(100, 3)))
+    o = np.concatenate([o_r, o_e, o_f])
+    d = np.concatenate([d_r, de, d_f])
+    flags = orc.trace(N, occ, V, o, d, brute=True)[4]
+    # independent: edges of occupied voxels (12 per voxel, shared ones repeated)
+    starts, dirs = [], []
+    for m in range(8):
+        for a in range(3):
+            if m & (1 << a):
+                continue
+            corner = np.array([m & 1, (m >> 1) & 1, (m >> 2) & 1])
+            starts.append((ijk + corner) / N)
+            dirs.append(np.tile(np.eye(3)[a] / N, (len(ijk), 1)))
+    dist_edge = _line_segment_distance(o, d, np.concatenate(starts), np.concatenate(dirs)).min(axis=1)
+    # no ray here is within 1e-6 of parallel to a face, so the n . d criterion cannot fire
+    assert np.abs(d).min() >= 1e-6
+    # origin near a face of the voxel the ray is in just after t = 0 (if it starts in the lattice)
+    ahead = o + 1e-9 * d
+    inside = np.all((ahead > 0) & (ahead < 1), axis=1)
+    cell = np.floor(ahead * N)
+    frac = o * N - cell
+    dist_face = np.where(inside, np.minimum(frac, 1 - frac).min(axis=1) / N, np.inf)
+    crit = np.minimum(dist_edge, dist_face)
+    clear = (crit < 0.5e-6) | (crit > 2e-6)
+    want = crit < 1e-6
+    got = flags != 0
+    assert want[clear].sum() > 100 and (~want[clear]).sum() > 300
+    bad = np.flatnonzero(clear & (want != got))
+    assert len(bad) == 0, [(int(i), float(dist_edge[i]), float(dist_face[i]), int(flags[i])) for i in bad[:5]]
 
 
 def test_identity_pose_hit_lists_equal_textbook_dda(orc):
