@@ -544,22 +544,8 @@ def batched_leg(replays=50, warmup=5):
     grid = P.Grid(occ, w.N, kinds, strengths)
     counts = S.uneven_counts(n_p, w.seed)
     n = int(counts.sum())
-    o_all = torch.empty((3, n), device="cuda")
-    d_all = torch.empty((3, n), device="cuda")
-    rng = np.random.default_rng(w.seed)
-    start = 0
-    for p in range(n_p):
-        c = int(counts[p])
-        half = c // 2
-        res_ = int(np.ceil(np.sqrt(half)))
-        o, d = S.rays_camera(res_, float(rng.uniform(0, 360)))
-        o_all[:, start:start + half] = torch.as_tensor(o[:, :half]).cuda()
-        d_all[:, start:start + half] = torch.as_tensor(d[:, :half]).cuda()
-        lo, hi = grid.bounds(p)
-        o2, d2 = S.rays_inside(c - half, w.seed + p, lo, hi)
-        o_all[:, start + half:start + c] = torch.as_tensor(o2).cuda()
-        d_all[:, start + half:start + c] = torch.as_tensor(d2).cuda()
-        start += c
+    o, d = S.batched_rays(counts, w.seed, [grid.bounds(p) for p in range(n_p)])
+    o_all, d_all = torch.as_tensor(o).cuda(), torch.as_tensor(d).cuda()
     off = torch.as_tensor(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).cuda()
     model = P.Model(m)
     model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))

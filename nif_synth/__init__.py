@@ -262,6 +262,25 @@ def uneven_counts(n_poses: int, seed: int, lo: int = 65536, hi: int = 1048576):
     return rng.integers(lo, hi + 1, size=n_poses).astype(np.int64)
 
 
+def batched_rays(counts, seed: int, boxes):
+    """The batched query's rays: per pose p, counts[p] rays, the first half pinhole primary rays
+    (a square camera of at least that many pixels at a random azimuth, its first pixels), the
+    rest secondary rays with origins uniform in boxes[p] = (lo[3], hi[3]) (the pose's occupied
+    deformed box) and directions uniform on S^2.  SoA float32 (o[3][n], d[3][n])."""
+    rng = np.random.default_rng(seed)
+    os_, ds_ = [], []
+    for p, c in enumerate(counts):
+        c = int(c)
+        half = c // 2
+        res_ = int(np.ceil(np.sqrt(half)))
+        o, d = rays_camera(res_, float(rng.uniform(0, 360)))
+        lo, hi = boxes[p]
+        o2, d2 = rays_inside(c - half, seed + p, lo, hi)
+        os_ += [o[:, :half], o2]
+        ds_ += [d[:, :half], d2]
+    return (np.ascontiguousarray(np.concatenate(os_, axis=1)), np.ascontiguousarray(np.concatenate(ds_, axis=1)))
+
+
 # ----------------------------------------------------------------------------- weights
 
 def init_tables(m: ModelDesc, seed: int) -> np.ndarray:

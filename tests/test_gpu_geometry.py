@@ -35,12 +35,18 @@ def _compare_trace(orc, P, N, occ, kind, s, o, d, max_seg=96, brute=True):
     grid = P.Grid(torch.as_tensor(occ).cuda(), N, [kind], [s])
     out = grid.trace(dev_f32(o), dev_f32(d), offsets([o.shape[1]]), max_seg=max_seg)
     torch.cuda.synchronize()
-    cnt = out["count"].cpu().numpy()
-    cell = out["cell"].cpu().numpy()
-    tin = out["t_in"].cpu().numpy().astype(np.float64)
-    tout = out["t_out"].cpu().numpy().astype(np.float64)
-    x0 = out["x0"].cpu().numpy().astype(np.float64)
-    x1 = out["x1"].cpu().numpy().astype(np.float64)
+    return _check_segments(orc, N, occ, kind, s, o, d, {k: v.cpu().numpy() for k, v in out.items()}, max_seg, brute)
+
+
+def _check_segments(orc, N, occ, kind, s, o, d, out, max_seg, brute):
+    """Hit lists of rays o, d (SoA) traced on the GPU under one pose (out: numpy arrays of the
+    rays, x0 / x1 as [3][rays][max_seg]) against the oracle's."""
+    cnt = out["count"]
+    cell = out["cell"]
+    tin = out["t_in"].astype(np.float64)
+    tout = out["t_out"].astype(np.float64)
+    x0 = out["x0"].astype(np.float64)
+    x1 = out["x1"].astype(np.float64)
     V = orc.lattice_vertices(kind, float(np.float32(s)), N)
     rc, rtin, rtout, rcnt, fl, cin, cout = orc.trace(N, occ, V, o, d, brute=brute, max_out=max_seg,
                                                      with_cos=True)
@@ -71,7 +77,7 @@ def _compare_trace(orc, P, N, occ, kind, s, o, d, max_seg=96, brute=True):
     return n_seg
 
 
-@pytest.mark.parametrize("name,N", [("torus16", 16), ("spheres64", 64), ("blobs128", 40)])
+@pytest.mark.parametrize("name,N", [("torus16", 16), ("spheres64", 64), ("blobs128", 40), ("blobs128", 128)])
 def test_voxelization_matches_oracle(orc, P, name, N):
     import torch
     w = S.workload(name)
@@ -119,6 +125,39 @@ def test_hit_lists_spheres64_sampled(orc, P, kind, s):
     say(f"trace spheres64 kind={kind} s={s} rays={o.shape[1]}")
     n_seg = _compare_trace(orc, P, w.N, occ, kind, s, o, d, brute=False)
     assert n_seg > 1000
+
+
+def test_hit_lists_blobs128_multi_pose_sampled(orc, P):
+    """The training and batched-query scene (32 blobs at 128^3) under four poses of different
+    kinds in one multi-pose launch: camera and secondary rays of every pose, bit-exact hit
+    lists on non-grazing rays and the FP32 bounds on entry/exit and rest points."""
+    import torch
+    w = S.workload("blobs128")
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    kinds, strengths = [S.TWIST, S.BEND, S.TAPER, S.TWIST_BEND], [1.0, 0.8, 0.6, 0.5]
+    os_, ds_ = [], []
+    for p in range(4):
+        o, d = S.rays_camera(64, 40.0 + 90.0 * p, sub=7)
+        oi, di = S.rays_inside(200, 80 + p, lo=0.25, hi=0.75)
+        os_.append(np.concatenate([o, oi], axis=1))
+        ds_.append(np.concatenate([d, di], axis=1))
+    counts = [x.shape[1] for x in os_]
+    o_all, d_all = np.concatenate(os_, axis=1), np.concatenate(ds_, axis=1)
+    max_seg = 256
+    say(f"trace blobs128 N=128, 4 poses in one launch, rays {counts}")
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    out = grid.trace(dev_f32(o_all), dev_f32(d_all), offsets(counts), max_seg=max_seg)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    start, n_seg = 0, 0
+    for p in range(4):
+        c = counts[p]
+        part = {k: (v[:, start:start + c] if k in ("x0", "x1") else v[start:start + c]) for k, v in out.items()}
+        say(f"  pose {p}: kind {kinds[p]} s {strengths[p]}")
+        n_seg += _check_segments(orc, w.N, occ, kinds[p], strengths[p], os_[p], ds_[p], part, max_seg, brute=False)
+        start += c
+    assert n_seg > 5000
 
 
 def test_multi_pose_grid_and_empty_and_degenerate_inputs(orc, P):

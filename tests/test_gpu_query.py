@@ -352,3 +352,172 @@ def test_grid_bounds_hold_the_deformed_occupied_voxels(orc, P):
         assert np.all(lo <= corners.min(0) + 1e-6) and np.all(hi >= corners.max(0) - 1e-6)
         # padded by 1e-5 on each side; FP32 lattice vs the FP64 one differ by ~1e-7
         assert np.all(lo >= corners.min(0) - 2e-5) and np.all(hi <= corners.max(0) + 2e-5 + 1e-6 * ext)
+
+
+def test_query_blobs128_multi_pose_fp32_sampled(orc, P):
+    """The 128^3 blob scene with the 832-128x4-12 network (FP32) under three poses in one
+    launch: camera and secondary rays of each pose against the oracle's query."""
+    import torch
+    w = S.workload("blobs128")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    kinds, strengths = [S.TWIST, S.BEND, S.TAPER], [0.9, 0.7, 1.0]
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    os_, ds_ = [], []
+    for p in range(3):
+        o, d = S.rays_camera(64, 25.0 + 120.0 * p, sub=9)
+        oi, di = S.rays_inside(250, 90 + p, lo=0.25, hi=0.75)
+        os_.append(np.concatenate([o, oi], axis=1))
+        ds_.append(np.concatenate([d, di], axis=1))
+    counts = [x.shape[1] for x in os_]
+    say(f"query blobs128 fp32, 3 poses in one launch, rays {counts}")
+    got = _np(grid.query(model, dev_f32(np.concatenate(os_, axis=1)), dev_f32(np.concatenate(ds_, axis=1)),
+                         offsets(counts)))
+    start, total_ok, total_hit = 0, 0, 0
+    for p in range(3):
+        sl = slice(start, start + counts[p])
+        say(f"  pose {p}: kind {kinds[p]} s {strengths[p]}")
+        n_ok, n_hit = _compare(orc, P, m, seen, prm, w.N, occ, kinds[p], strengths[p], os_[p], ds_[p], got, sl=sl)
+        total_ok += n_ok
+        total_hit += n_hit
+        start += counts[p]
+    assert total_ok > 1200 and total_hit > 200
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
+def test_query_batched_workload_poses_sampled(orc, P, prec):
+    """The batched workload's launch as the benchmark issues it (16 poses of the blob scene,
+    8 M rays in uneven counts, half pinhole and half secondary), sampled rays of two poses (one
+    twist or bend, one taper where present) against the oracle; at BF16 the decisions and heads
+    are held to the rounding-error model (test_query_low_precision_end_to_end)."""
+    import torch
+    w = S.workload("blobs128_b")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ_ref = orc.voxelize(w.scene_kind, sp, w.N)
+    n_p = 16
+    kinds, strengths = S.random_poses(n_p, w.seed, kinds=(S.TWIST, S.BEND, S.TAPER))
+    grid = P.Grid(torch.as_tensor(occ_ref).cuda(), w.N, kinds, strengths)
+    counts = S.uneven_counts(n_p, w.seed)
+    o, d = S.batched_rays(counts, w.seed, [grid.bounds(p) for p in range(n_p)])
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    say(f"batched workload prec={prec}: {int(counts.sum())} rays, 16 poses")
+    out = grid.query(model, dev_f32(o), dev_f32(d), offsets(counts), precision=prec)
+    torch.cuda.synchronize()
+    start = np.concatenate([[0], np.cumsum(counts)])
+    picks = [int(np.flatnonzero(kinds != S.TAPER)[0]), int(np.flatnonzero(kinds == S.TAPER)[0])]
+    rng = np.random.default_rng(7)
+    total = 0
+    for p in picks:
+        c = int(counts[p])
+        idx = np.sort(np.concatenate([rng.choice(c // 2, 200, replace=False), c // 2 + rng.choice(c - c // 2, 200, replace=False)]))
+        sel = start[p] + idx
+        got = _np({k: v[torch.as_tensor(sel).cuda()] for k, v in out.items()})
+        say(f"  pose {p}: kind {kinds[p]} s {strengths[p]:.3f}, rays {c}")
+        if prec == 0:
+            n_ok, _ = _compare(orc, P, m, seen, prm, w.N, occ_ref, int(kinds[p]), float(strengths[p]),
+                               o[:, sel], d[:, sel], got)
+        else:
+            n_ok = _compare_low(orc, m, seen, prm, w.N, occ_ref, int(kinds[p]), float(strengths[p]), o[:, sel],
+                                d[:, sel], got, prec)
+        total += n_ok
+    assert total > 500
+
+
+def _segment_points(kind, s, o, d, t0, t1, orc):
+    o64, d64 = o.T.astype(np.float64), d.T.astype(np.float64)
+    return (orc.deform_inv(kind, s, o64 + t0[:, None] * d64), orc.deform_inv(kind, s, o64 + t1[:, None] * d64))
+
+
+def _compare_low(orc, m, seen, prm, N, occ, kind, s, o, d, g, prec):
+    """End-to-end BF16 / FP16 query against the oracle on the same rounded weights.  Decisions
+    (hit, voxel, segments evaluated) must agree on rays that are not grazing and whose smallest
+    |hit logit| / (|b| + sum |w||h|) over the evaluated segments exceeds 7 times the largest
+    sigma / scale the rounding-error model gives for the hit logit (twice that for safety);
+    on hits, t, normal, albedo within 7 sigma of the model (plus the FP32 end-to-end bounds of
+    the geometry) and the material wherever its two top logits are 7 sigma apart."""
+    import _bounds as BD
+    from _helpers import quantized_mlp
+    q = quantized_mlp(prm, prec)
+    s64 = float(np.float32(s))
+    ref = orc.query(m, seen, q, N, occ, kind, s64, o, d)
+    graz = _grazing(orc, N, occ, kind, s64, o, d)
+    h = ref["hit"] == 1
+    si = ref["seginfo"]
+    x0, x1 = _segment_points(kind, s64, o[:, h], d[:, h], si[h, 0], si[h, 1], orc)
+    fw = BD.forward(orc, m, seen, q, x0, x1, prec)
+    W, b = BD.layers(m, q)[-1]
+    scale0 = np.abs(fw["acts"][-1]) @ np.abs(W[0]) + abs(b[0])
+    kappa = max(2.0 * BD.LAMBDA * float((fw["sz"][:, 0] / scale0).max()), 1e-4)
+    amb = ref["margin"] <= kappa
+    ok = ~graz & ~amb
+    say(f"    rays {len(ok)}  grazing {int(graz.sum())}  ambiguous (margin <= {kappa:.2e}) {int((amb & ~graz).sum())}"
+        f"  hits {int(ref['hit'][ok].sum())}")
+    assert np.array_equal(g["hit"][ok], ref["hit"][ok])
+    assert np.array_equal(g["cell"][ok], ref["cell"][ok]) and np.array_equal(g["n_queried"][ok], ref["n_queried"][ok])
+    hh = ok[h]                                   # hit rays (in the order of fw's rows) that are compared
+    z, sz = fw["z"][hh], fw["sz"][hh]
+    lam = BD.LAMBDA
+    t0, t1, lr = si[h][hh, 0], si[h][hh, 1], si[h][hh, 2]
+    f = np.clip(np.maximum(z[:, 1], 0.0) / lr, 0.0, 1.0)
+    inner = (f > 0) & (f < 1)
+    tb = np.where(inner, (t1 - t0) * lam * sz[:, 1] / lr, (t1 - t0) * np.clip(lam * sz[:, 1] / lr, 0, 1)) + 2e-4
+    idx = np.flatnonzero(ok & h)
+    et = np.abs(g["t"][idx] - ref["t"][idx])
+    nrm = np.stack([g["nx"], g["ny"], g["nz"]], 1)[idx]
+    vl = np.linalg.norm(z[:, 2:5], axis=1)
+    sv = lam * np.linalg.norm(sz[:, 2:5], axis=1)
+    vrms = np.sqrt(np.mean(vl ** 2)) if len(vl) else 1.0
+    # the model's share, and the FP32 end-to-end share of the geometry (1e-2 at the RMS |z_n|)
+    nb = np.minimum(2.0, sv / np.maximum(vl - sv, 1e-30) + 1e-2 * np.maximum(1.0, vrms / np.maximum(vl, 1e-30)))
+    en = np.abs(nrm - ref["normal"][idx]).max(1)
+    alb = np.stack([g["ar"], g["ag"], g["ab"]], 1)[idx]
+    ea = np.abs(alb - ref["albedo"][idx]).max(1)
+    ab = 0.25 * lam * sz[:, 5:8].max(1) + 5e-4
+    say(f"    t err p99 {np.quantile(et, .99) if len(et) else 0:.2e}  normal p99 {np.quantile(en, .99) if len(en) else 0:.2e}"
+        f"  albedo p99 {np.quantile(ea, .99) if len(ea) else 0:.2e}")
+    assert np.all(et <= tb) and np.all(en <= nb) and np.all(ea <= ab)
+    zm = z[:, 8:]
+    top2 = np.sort(zm, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > lam * (sz[:, 8:].max(1) * 2)
+    assert np.array_equal(g["material"][idx][clear], ref["material"][idx][clear])
+    return int(ok.sum())
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_query_low_precision_end_to_end(orc, P, prec):
+    """The precision comparison's workload (the sphere scene, twist and bend at full strength,
+    MLP 832-128x4-12) end to end at BF16 / FP16 on sampled camera rays of both poses."""
+    import torch
+    w = S.workload("spheres64_p")
+    m = w.model
+    sp = S.scene_params(w.scene_kind, w.seed)
+    occ = orc.voxelize(w.scene_kind, sp, w.N)
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    kinds, strengths = S.poses(w)
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    os_, ds_ = [], []
+    for p in range(2):
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], tile=w.cam_tile, sub=997)
+        os_.append(o)
+        ds_.append(d)
+    counts = [x.shape[1] for x in os_]
+    say(f"query spheres64_p prec={prec}, rays {counts}")
+    got = _np(grid.query(model, dev_f32(np.concatenate(os_, axis=1)), dev_f32(np.concatenate(ds_, axis=1)),
+                         offsets(counts), precision=prec))
+    start, total = 0, 0
+    for p in range(2):
+        sl = slice(start, start + counts[p])
+        say(f"  pose {p}: kind {kinds[p]} s {strengths[p]}")
+        total += _compare_low(orc, m, seen, prm, w.N, occ, int(kinds[p]), float(strengths[p]), os_[p], ds_[p],
+                              {k: v[sl] for k, v in got.items()}, prec)
+        start += counts[p]
+    assert total > 1500
