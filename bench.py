@@ -25,6 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 GATHER_BYTES_PER_EVAL = 13312   # 2 points x 13 PE samples x 16 levels x 8 corners x 4 B (FP16 pair)
+GATHER_BYTES_PER_EVAL_C0 = 13312  # torus workload: 2 x 13 x 8 levels x 8 corners x 8 B (FP32 pair)
+# training step per sample: forward gathers 13,312 B + the backward's recomputed gathers 13,312 B
+# + the FP32 table-gradient payload (2 points x 13 samples x 16 levels x 8 corners x 8 B) 26,624 B
+# + dense Adam over all parameters (~570 MB per step at B = 2^18) 2,176 B
+TRAIN_BYTES_PER_SAMPLE = 13312 + 13312 + 26624 + 2176
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes that k_query moves per launch on the default workload, from two rocprofv3 --pmc runs
@@ -92,8 +97,9 @@ def setup(workload: str, precision: int):
                 kinds=kinds, strengths=strengths, precision=precision)
 
 
-def cpu_baseline(ctx, sample_stride: int = 4):
-    """The FP64 oracle's query on a strided subset of pose 0's camera rays, timed on the host."""
+def cpu_baseline(ctx, sample_stride: int = 12, one_core_stride: int = 160):
+    """The FP64 oracle's query on strided subsets of the camera rays of three poses (a twist, a
+    bend and a taper), timed on the host with all cores, and on one core on a smaller subset."""
     import nif_synth as S
     import oracle
 
@@ -102,16 +108,32 @@ def cpu_baseline(ctx, sample_stride: int = 4):
     tab = S.init_tables(m, w.seed + 100)
     tab64 = oracle.round_f16(tab) if m.table_dtype == S.TABLE_F16 else tab.astype(np.float64)
     prm = S.init_mlp(m, w.seed + 100).astype(np.float64)
-    o, d = S.rays_camera(w.cam_res, w.cam_az_deg[0], sub=sample_stride)
-    oracle.query(m, tab64, prm, w.N, occ, int(ctx["kinds"][0]), float(ctx["strengths"][0]), o[:, :256], d[:, :256])
-    t0 = time.perf_counter()
-    oracle.query(m, tab64, prm, w.N, occ, int(ctx["kinds"][0]), float(ctx["strengths"][0]), o, d)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": o.shape[1] / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
-            "sample": f"{o.shape[1]} rays (every {sample_stride}th pixel of pose 0, "
-                      f"{['identity', 'twist', 'bend', 'taper', 'twist-bend'][int(ctx['kinds'][0])]} s={float(ctx['strengths'][0])}), "
-                      f"FP64 oracle, {dt:.1f} s"}
+    kinds, strengths = ctx["kinds"], ctx["strengths"]
+    picks = [int(np.flatnonzero((kinds == k) & (strengths == 0.5))[0]) for k in (S.TWIST, S.BEND, S.TAPER)]
+    names = ["identity", "twist", "bend", "taper", "twist-bend"]
+
+    def run(stride):
+        n, dt = 0, 0.0
+        for p in picks:
+            o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], sub=stride, sub_index=p % stride)
+            t0 = time.perf_counter()
+            oracle.query(m, tab64, prm, w.N, occ, int(kinds[p]), float(strengths[p]), o, d)
+            dt += time.perf_counter() - t0
+            n += o.shape[1]
+        return n, dt
+
+    all_cores = oracle.set_threads(0)
+    o, d = S.rays_camera(w.cam_res, w.cam_az_deg[0], sub=4096)
+    oracle.query(m, tab64, prm, w.N, occ, int(kinds[0]), float(strengths[0]), o, d)        # warm-up
+    n, dt = run(sample_stride)
+    oracle.set_threads(1)
+    n1, dt1 = run(one_core_stride)
+    oracle.set_threads(all_cores)
+    poses = ", ".join(f"{names[int(kinds[p])]} s={float(strengths[p])}" for p in picks)
+    return {"value": n / dt, "unit": "rays/s", "cores": all_cores, "kind": "oracle",
+            "sample": f"{n} rays (every {sample_stride}th pixel of 3 poses: {poses}), FP64 oracle, {dt:.1f} s",
+            "one_core": {"value": n1 / dt1, "unit": "rays/s", "cores": 1,
+                         "sample": f"{n1} rays (every {one_core_stride}th pixel of the same poses), {dt1:.1f} s"}}
 
 
 def tuned_query_shape(key: str, model, grid, rays, n: int, hits, precision: int = 0, cache_path=None):
@@ -155,8 +177,115 @@ def timed(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def precision_leg(steps=5):
-    """4x128 MLP on 2 poses x 1024^2 rays: query rays/s with the MLP in FP32, BF16 and FP16."""
+def torus_leg(replays=200, warmup=20):
+    """The plain method at the smallest size: 4,096 random rays into the 16^3 torus under one
+    twist, MLP 416-64x2-9 FP32 (Xavier, tables U(+-1e-4)), forward only; one launch replayed
+    from a captured graph (a launch this small is bound by its latency)."""
+    import torch
+
+    import nif_synth as S
+    import paper_2604_24666_amd as P
+
+    w = S.workload("torus16")
+    m = w.model
+    sp = S.scene_of(w)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    model = P.Model(m)
+    model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))
+    grid = P.Grid(occ, w.N, w.pose_kinds, w.pose_strengths)
+    o, d = [torch.as_tensor(a).cuda() for a in S.rays_random(w.n_rays, w.seed)]
+    off = torch.tensor([0, w.n_rays], dtype=torch.int64, device="cuda")
+    rays = P.make_rays(o, d, off)
+    out = P.alloc_hits(w.n_rays, "cuda")
+    hits = P.hits_struct(out)
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    s_cap = torch.cuda.Stream()
+    call = lambda: P.nif_query(model.h, grid.h, rays, w.n_rays, hits, 0, P.PREC_FP32, stats, stream=s_cap)
+    with torch.cuda.stream(s_cap):
+        call()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s_cap):
+        call()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = int(stats.cpu()[1])
+    ms = []
+    for _ in range(replays):
+        with torch.cuda.stream(s_cap):
+            a.record(s_cap)
+            g.replay()
+            b.record(s_cap)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    evals = (int(stats.cpu()[1]) - e0) / replays
+    med = float(np.median(ms))
+    achieved = evals * GATHER_BYTES_PER_EVAL_C0 / (float(np.mean(ms)) * 1e-3) / 1e9
+    log(f"torus leg: {med:.4f} ms per launch, {evals:.0f} network evaluations")
+    del g
+    return {"workload": "torus16: 16^3 torus (R 0.35, r 0.12), twist 0.6 z, 4,096 random rays, 8-level 2^14 FP32 grid, "
+                        "F = 6, MLP 416-64x2-9 FP32; one launch replayed from a captured graph, median of "
+                        f"{replays} after {warmup} warm-up",
+            "rays_per_s": w.n_rays / (med * 1e-3), "ms_per_launch_median": med, "network_evals_per_launch": evals,
+            "hit_rate": float(out["hit"].float().mean().item()),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_query",
+                         "algorithmic_bytes": f"{GATHER_BYTES_PER_EVAL_C0} B of hash-corner gathers per network evaluation"}}
+
+
+def trained_model(P, S, w, steps, B=1 << 16, n_rays=1 << 20, seed_offset=300):
+    """A model of workload w's architecture trained by this library's own FP32 training step:
+    `steps` Adam steps on batches of B labelled segments of random rays through the rest pose
+    and 31 random twist/bend/taper poses of w's scene (distance head's bias at half a voxel).
+    Returns (model, seconds, final losses)."""
+    import torch
+    sp = S.scene_of(w)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    o, d = [torch.as_tensor(a).cuda() for a in S.rays_random(n_rays, w.seed + seed_offset)]
+    kd, sd = S.random_poses(31, w.seed + seed_offset + 1, kinds=(S.TWIST, S.BEND, S.TAPER))
+    kd = np.concatenate([[S.IDENTITY], kd]).astype(np.int32)
+    sd = np.concatenate([[0.0], sd]).astype(np.float32)
+    g = P.Grid(occ, w.N, kd, sd)
+    ds = _segment_dataset(P, g, o, d, torch.as_tensor(np.linspace(0, n_rays, 33).astype(np.int64)).cuda(),
+                          w.scene_kind, sp, 16)
+    del g, o, d
+    model, secs, losses = _train_model(P, w.model, ds, steps, B, False, w.seed + seed_offset + 2,
+                                       f"{w.name} model", dist_bias=0.5 / w.N)
+    return model, secs, losses
+
+
+def oracle_errors(P, model, m, w, kinds, strengths, occ_np, o, d, got):
+    """Per-head errors of query outputs `got` (numpy, rays o, d of one pose) against the FP64
+    oracle run on the model's FP32 master weights and the tables as the GPU reads them."""
+    import torch
+
+    import nif_synth as S
+    import oracle
+    t, prm, _ = [v.cpu().numpy() for v in model.get_params()]
+    torch.cuda.synchronize()
+    tab = t.reshape(m.table_levels, m.table_size, m.feat_dim)
+    tab64 = oracle.round_f16(tab) if m.table_dtype == S.TABLE_F16 else tab.astype(np.float64)
+    ref = oracle.query(m, tab64, prm.astype(np.float64), w.N, occ_np, kinds, strengths, o, d)
+    both = (got["hit"] == 1) & (ref["hit"] == 1)
+    q = lambda e: [float(np.quantile(e, 0.5)), float(np.quantile(e, 0.99))] if len(e) else [0.0, 0.0]
+    rel_t = np.abs(got["t"][both] - ref["t"][both]) / np.maximum(np.abs(ref["t"][both]), 1e-6)
+    ng = np.stack([got["nx"], got["ny"], got["nz"]], 1)[both]
+    ang = np.degrees(np.arccos(np.clip(np.sum(ng * ref["normal"][both], 1), -1.0, 1.0)))
+    alb = np.abs(np.stack([got["ar"], got["ag"], got["ab"]], 1)[both] - ref["albedo"][both]).sum(1)
+    return {"hit_accuracy": float(np.mean(got["hit"] == ref["hit"])),
+            "material_accuracy": float(np.mean(got["material"][both] == ref["material"][both])) if both.any() else 1.0,
+            "distance_rel_p50_p99": q(rel_t), "normal_deg_p50_p99": q(ang), "albedo_l1_p50_p99": q(alb),
+            "rays": int(len(o[0])), "hits_compared": int(both.sum())}
+
+
+def precision_leg(steps=5, train_steps=1500, sample=512):
+    """4x128 MLP on 2 poses x 1024^2 rays: query rays/s with the MLP in FP32, BF16 and FP16, on a
+    model trained by this library (FP32); per-head errors of each precision against the FP64
+    oracle on every `sample`-th ray of both poses."""
     import torch
 
     import nif_synth as S
@@ -167,14 +296,15 @@ def precision_leg(steps=5):
     sp = S.scene_params(w.scene_kind, w.seed)
     occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
     P.nif_voxelize(w.scene_kind, sp, w.N, occ)
-    model = P.Model(m)
-    model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))
+    model, train_s, train_losses = trained_model(P, S, w, train_steps)
     kinds, strengths = S.poses(w)
     n_pose = w.cam_res ** 2
     o_all = torch.empty((3, 2 * n_pose), device="cuda")
     d_all = torch.empty((3, 2 * n_pose), device="cuda")
+    cams = []
     for p in range(2):
         o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], tile=w.cam_tile)
+        cams.append((o, d))
         o_all[:, p * n_pose:(p + 1) * n_pose] = torch.as_tensor(o).cuda()
         d_all[:, p * n_pose:(p + 1) * n_pose] = torch.as_tensor(d).cuda()
     off = torch.tensor([0, n_pose, 2 * n_pose], dtype=torch.int64, device="cuda")
@@ -182,6 +312,7 @@ def precision_leg(steps=5):
     rays = P.make_rays(o_all, d_all, off)
     out = P.alloc_hits(2 * n_pose, "cuda")
     hits = P.hits_struct(out)
+    occ_np = occ.cpu().numpy()
     res = {}
     ref = None
     for prec, name in ((0, "fp32"), (1, "bf16"), (2, "fp16")):
@@ -192,11 +323,19 @@ def precision_leg(steps=5):
             ref = got
         else:
             res[name]["vs_fp32"] = head_errors(got, ref)
-        log(f"precision leg {name}: {ms:.2f} ms {res[name].get('vs_fp32', '')}")
+        per_pose = []
+        for p in range(2):
+            sl = np.arange(p * n_pose, (p + 1) * n_pose)[::sample]
+            o, d = cams[p][0][:, ::sample], cams[p][1][:, ::sample]
+            g = {k: v[sl].astype(np.float64) if v.dtype.kind == "f" else v[sl] for k, v in got.items()}
+            per_pose.append(oracle_errors(P, model, m, w, int(kinds[p]), float(strengths[p]), occ_np, o, d, g))
+        res[name]["vs_oracle"] = {"pose_twist": per_pose[0], "pose_bend": per_pose[1]}
+        log(f"precision leg {name}: {ms:.2f} ms; vs oracle {res[name]['vs_oracle']}")
     return {"workload": "spheres64_p: 2 poses (twist, bend s=1) x 1024^2 pinhole rays in 8x8 tiles, 16-level 2^19 FP16 grid, "
-                        "MLP 832-128x4-12 (Xavier init)", **res,
-            "note": "vs_fp32 compares with the FP32 path on the same rays (which the parity tests hold to the "
-                    "FP64 oracle); per-head errors against the oracle itself: tests/test_gpu_network.py"}
+                        f"MLP 832-128x4-12 trained by this library ({train_steps} FP32 Adam steps of 2^16 labelled "
+                        f"segments, {train_s:.1f} s, final losses {[round(x, 4) for x in train_losses]})", **res,
+            "note": f"vs_oracle: every {sample}th ray of each pose against the FP64 oracle on the FP32 master weights "
+                    "(the BF16/FP16 error includes the rounding of the weights); vs_fp32: the FP32 path on all rays"}
 
 
 def head_errors(got, ref):
@@ -261,7 +400,13 @@ def train_leg(steps=5, B=1 << 18):
             cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, prec, 0.0, 0, store)
             losses = torch.zeros(16, device="cuda")
             ms = timed(lambda: P.nif_train_step(model.h, batch, B, cfg, losses), steps, 2)
-            r = {"samples_per_s": B / (ms * 1e-3), "ms_per_step": ms, "loss": float(losses[5])}
+            achieved = TRAIN_BYTES_PER_SAMPLE * B / (ms * 1e-3) / 1e9
+            r = {"samples_per_s": B / (ms * 1e-3), "ms_per_step": ms, "loss": float(losses[5]),
+                 "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                              "kernel": "training step (all kernels of one step)",
+                              "algorithmic_bytes": f"{TRAIN_BYTES_PER_SAMPLE} B per sample (gathers, recomputed "
+                                                   "gathers, FP32 table-gradient payload, dense Adam)"}}
             if store:
                 res.setdefault("stored_encoding", {})[name] = r
             else:
@@ -333,14 +478,17 @@ def _errors(P, model, grid, o, d, off, gt):
             "rays_compared": int(both.sum())}
 
 
-def _train_model(P, m, ds, steps, B, fixed, seed, tag):
-    """Adam on minibatches of B segments drawn uniformly from the labelled set ds."""
+def _train_model(P, m, ds, steps, B, fixed, seed, tag, dist_bias=0.0):
+    """Adam on minibatches of B segments drawn uniformly from the labelled set ds; the distance
+    head's bias starts at dist_bias (so that a ReLU distance head is live from the first step)."""
     import torch
 
     import nif_synth as S
     n_seg = ds["x0"].shape[1]
     model = P.Model(m)
-    model.set_params(S.init_tables(m, seed), S.init_mlp(m, seed))
+    prm = S.init_mlp(m, seed)
+    prm[m.n_mlp_params - m.n_heads + 1] = dist_bias
+    model.set_params(S.init_tables(m, seed), prm)
     P.nif_model_reserve(model.h, B)
     cfg = P.TrainCfg(1e-2, 1e-3, 1e-3, 0.9, 0.999, 1e-8, P.PREC_FP32, 0.0, int(fixed))
     losses = torch.zeros(16, device="cuda")
@@ -408,11 +556,12 @@ def ablation_leg(steps=2000, B=1 << 16):
         o_e, d_e = eo.repeat(1, reps).contiguous(), ed.repeat(1, reps).contiguous()
         off = torch.as_tensor(np.arange(reps + 1, dtype=np.int64) * ne).cuda()
         evals[name] = (g, o_e, d_e, off, _ground_truth(P, g, o_e, d_e, off, w.scene_kind, sp))
-    variants = (("LSNIF", baseline, True, "rest"), ("Deformed", baseline, True, "poses"),
-                ("Proposed", base, False, "poses"))
+    bias = 0.5 / w.N           # half a voxel: the ReLU distance head is live from the first step
+    variants = (("LSNIF", baseline, True, "rest", 0.0), ("Deformed", baseline, True, "poses", 0.0),
+                ("Proposed", base, False, "poses", bias), ("Proposed (distance bias 0)", base, False, "poses", 0.0))
     res = {}
-    for vname, m, fixed, dname in variants:
-        model, train_s, losses = _train_model(P, m, data[dname], steps, B, fixed, w.seed + 200, vname)
+    for vname, m, fixed, dname, db in variants:
+        model, train_s, losses = _train_model(P, m, data[dname], steps, B, fixed, w.seed + 200, vname, dist_bias=db)
         r = {"train_s": train_s, "final_losses": losses}
         for ename, (g, o_e, d_e, off, gt) in evals.items():
             r[ename] = _errors(P, model, g, o_e, d_e, off, gt)
@@ -420,7 +569,8 @@ def ablation_leg(steps=2000, B=1 << 16):
         res[vname] = r
         del model
     return {"workload": f"spheres64 scene (8 spheres, 64^3), 16-level 2^19 FP16 grid, MLP 64x3; {steps} Adam steps of "
-                        f"B = {B} segments drawn from 2^20 random rays through the rest pose (LSNIF) or through the "
+                        f"B = {B} segments (the proposed head's distance bias at half a voxel, and at 0) "
+                        f"drawn from 2^20 random rays through the rest pose (LSNIF) or through the "
                         f"rest pose and 31 random twist/bend/taper poses (Deformed, Proposed); evaluated on 4 x 256^2 "
                         f"pinhole rays at the rest pose and at 4 unseen poses against labelled ground truth",
             **res}
@@ -452,7 +602,7 @@ def render_leg(steps=1500, B=1 << 16, res=1024, reps=5):
     ds = _segment_dataset(P, g, o, d, torch.as_tensor(np.linspace(0, nr, 33).astype(np.int64)).cuda(),
                           w.scene_kind, sp, 16)
     del g, o, d
-    model, train_s, _ = _train_model(P, m, ds, steps, B, False, w.seed + 400, "render model")
+    model, train_s, _ = _train_model(P, m, ds, steps, B, False, w.seed + 400, "render model", dist_bias=0.5 / w.N)
     del ds
     # one frame under an unseen twist
     grid = P.Grid(occ, w.N, [S.TWIST], [0.8])
@@ -525,7 +675,7 @@ def render_leg(steps=1500, B=1 << 16, res=1024, reps=5):
             "mean_shade": float(shade.mean())}
 
 
-def batched_leg(replays=50, warmup=5):
+def batched_leg(replays=50, warmup=5, train_steps=1000):
     """16 poses of uneven ray counts (half pinhole, half secondary) in one persistent launch,
     replayed from a captured graph: aggregate rays/s (median launch) and per-pose completion
     latency p50/p99 over all replays (device wall-clock stamps)."""
@@ -536,7 +686,7 @@ def batched_leg(replays=50, warmup=5):
 
     w = S.workload("blobs128_b")
     m = w.model
-    sp = S.scene_params(w.scene_kind, w.seed)
+    sp = S.scene_of(w)
     occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
     P.nif_voxelize(w.scene_kind, sp, w.N, occ)
     n_p = 16
@@ -547,8 +697,7 @@ def batched_leg(replays=50, warmup=5):
     o, d = S.batched_rays(counts, w.seed, [grid.bounds(p) for p in range(n_p)])
     o_all, d_all = torch.as_tensor(o).cuda(), torch.as_tensor(d).cuda()
     off = torch.as_tensor(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).cuda()
-    model = P.Model(m)
-    model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))
+    model, train_s, train_losses = trained_model(P, S, S.workload("blobs128"), train_steps)
     rays = P.make_rays(o_all, d_all, off)
     out = P.alloc_hits(n, "cuda")
     hits = P.hits_struct(out)
@@ -569,24 +718,34 @@ def batched_leg(replays=50, warmup=5):
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         launch_ms, lat = [], []
+        evals = 0
         for i in range(warmup + replays):
             with torch.cuda.stream(s_cap):
                 a.record(s_cap)
                 g.replay()
                 b.record(s_cap)
             torch.cuda.synchronize()
+            st = stats.cpu().numpy()
             if i < warmup:
+                evals = int(st[1])
                 continue
             launch_ms.append(a.elapsed_time(b))
-            st = stats.cpu().numpy()
             assert np.array_equal(st[5 + n_p:5 + 2 * n_p], counts), "rays finished per pose"
             lat.append((st[5:5 + n_p] - st[4]).astype(np.float64) / khz)     # ticks -> ms
         lat = np.concatenate(lat)
         ms = float(np.median(launch_ms))
+        evals_per_launch = (int(stats.cpu().numpy()[1]) - evals) / replays
+        achieved = evals_per_launch * GATHER_BYTES_PER_EVAL / (float(np.mean(launch_ms)) * 1e-3) / 1e9
         res[name] = {"rays_per_s": n / (ms * 1e-3), "ms_per_launch_median": ms,
                      "pose_latency_ms_p50": float(np.quantile(lat, 0.5)),
                      "pose_latency_ms_p99": float(np.quantile(lat, 0.99)),
                      "hit_rate": float(out["hit"].float().mean().item()),
+                     "network_evals_per_launch": evals_per_launch,
+                     "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                  "kernel": "k_query (one persistent launch over the 16 poses)",
+                                  "algorithmic_bytes": f"{GATHER_BYTES_PER_EVAL} B of hash-corner gathers per "
+                                                       "network evaluation"},
                      "launch_shape": {"blocks_per_cu": shape[0], "rays_per_wave": shape[1]}}
         log(f"batched leg {name}: {ms:.2f} ms per launch, pose latency p50 {res[name]['pose_latency_ms_p50']:.2f} "
             f"p99 {res[name]['pose_latency_ms_p99']:.2f} ms")
@@ -595,7 +754,8 @@ def batched_leg(replays=50, warmup=5):
                         f"[{int(counts.min())}, {int(counts.max())}], half pinhole (random azimuth), half secondary "
                         f"(origin uniform in the pose's occupied deformed box, direction uniform on S^2); one "
                         f"persistent launch replayed from a captured graph, median of {replays} after {warmup} "
-                        f"warm-up; untrained MLP 832-128x4-12",
+                        f"warm-up; MLP 832-128x4-12 trained by this library on the scene ({train_steps} FP32 Adam "
+                        f"steps, {train_s:.1f} s, final losses {[round(x, 4) for x in train_losses]})",
             "rays": n, **res}
 
 
@@ -610,8 +770,8 @@ def main():
     ap.add_argument("--no-rebuild", action="store_true", help="time the query only (grids built once)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (scale for HBM byte counters)")
-    ap.add_argument("--legs", default="precision,train,batched",
-                    help="extra measurements: precision,train,batched,ablation,render (empty for none)")
+    ap.add_argument("--legs", default="torus,precision,train,batched",
+                    help="extra measurements: torus,precision,train,batched,ablation,render (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
@@ -707,6 +867,8 @@ def main():
     torch.cuda.empty_cache()
     P.nif_set_query_blocks_per_cu(12)           # the legs below use the default launch shape
     P.nif_set_query_rays_per_wave(0)            # unless they tune their own
+    if "torus" in legs:
+        res["torus16"] = torus_leg()
     if "precision" in legs:
         res["precision_compare"] = precision_leg()
     if "train" in legs:

@@ -102,6 +102,7 @@ class Workload:
     cam_az_deg: List[float] = field(default_factory=list)
     cam_tile: int = 0                    # camera rays issued in cam_tile^2 screen tiles (0: rows)
     precision: int = PREC_FP32
+    scene_seed: int = -1                 # seed of the scene when it differs from `seed` (-1: seed)
 
 
 # Torus workload (4,096 random rays, twist, 16^3 grid, 8-level 2^14 FP32 tables).
@@ -124,7 +125,7 @@ def workload(name: str) -> Workload:
     spheres64_p  -- the same scene, 2 poses (twist, bend at full strength) x 1024^2 rays
                     in 8x8 tiles, MLP 4x128 for the FP32 / BF16 / FP16 comparison.
     blobs128     -- 32-Gaussian blob field at 128^3 for the training step, MLP 4x128.
-    blobs128_b   -- the blob scene with 16 poses of uneven ray counts (batched query).
+    blobs128_b   -- the blobs128 scene with 16 poses of uneven ray counts (batched query).
     """
     strengths8 = [(i + 1) / 8.0 for i in range(8)]
     if name == "torus16":
@@ -147,11 +148,16 @@ def workload(name: str) -> Workload:
                         rays="random", precision=PREC_BF16)
     if name == "blobs128_b":
         return Workload(name, SCENE_BLOBS, 128, replace(_C2_MODEL), seed=1004,
-                        rays="mixed", precision=PREC_BF16)
+                        rays="mixed", precision=PREC_BF16, scene_seed=1003)
     raise KeyError(name)
 
 
 # ----------------------------------------------------------------------------- scenes
+
+def scene_of(w: Workload) -> np.ndarray:
+    """The scene parameters of a workload."""
+    return scene_params(w.scene_kind, w.seed if w.scene_seed < 0 else w.scene_seed)
+
 
 def scene_params(kind: int, seed: int) -> np.ndarray:
     """Flat float64 parameter vector of a scene (layout documented per kind).

@@ -51,6 +51,11 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (n <= 0 keeps the default); returns the count used."""
+    return int(lib().orc_set_threads(C.c_int32(n)))
+
+
 class Model(C.Structure):
     _fields_ = [("levels", C.c_int32), ("log2_table", C.c_int32), ("feat_dim", C.c_int32),
                 ("pe_freqs", C.c_int32), ("res", C.c_int32 * 32), ("n_layers", C.c_int32),

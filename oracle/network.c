@@ -34,6 +34,7 @@
  *    formulas; these are the plainest forms consistent with that description.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 #include "oracle.h"
@@ -234,6 +235,12 @@ static void features(const orc_model* m, const double* tables, const double x0[3
 }
 
 /* ------------------------------------------------------------------ batch entry points */
+
+/* Threads of the OpenMP loops below (n <= 0: the runtime's default); returns the count in use. */
+int32_t orc_set_threads(int32_t n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 void orc_deform_batch(int32_t kind, double s, int64_t n, const double* p, double* q, int32_t inverse) {
     for (int64_t i = 0; i < n; ++i) {

@@ -397,7 +397,7 @@ def test_query_batched_workload_poses_sampled(orc, P, prec):
     import torch
     w = S.workload("blobs128_b")
     m = w.model
-    sp = S.scene_params(w.scene_kind, w.seed)
+    sp = S.scene_of(w)
     occ_ref = orc.voxelize(w.scene_kind, sp, w.N)
     n_p = 16
     kinds, strengths = S.random_poses(n_p, w.seed, kinds=(S.TWIST, S.BEND, S.TAPER))
