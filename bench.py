@@ -759,6 +759,23 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
             "rays": n, **res}
 
 
+def run_legs(legs):
+    res = {}
+    if "torus" in legs:
+        res["torus16"] = torus_leg()
+    if "precision" in legs:
+        res["precision_compare"] = precision_leg()
+    if "train" in legs:
+        res["train"] = train_leg()
+    if "batched" in legs:
+        res["batched"] = batched_leg()
+    if "ablation" in legs:
+        res["ablation"] = ablation_leg()
+    if "render" in legs:
+        res["render"] = render_leg()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -768,6 +785,8 @@ def main():
     ap.add_argument("--precision", type=int, default=0, help="0 FP32, 1 BF16, 2 FP16 MLP")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rebuild", action="store_true", help="time the query only (grids built once)")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="profiling runs: skip the headline query and the CPU baseline, print the legs' JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (scale for HBM byte counters)")
     ap.add_argument("--legs", default="torus,precision,train,batched",
@@ -792,6 +811,10 @@ def main():
     import paper_2604_24666_amd as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.legs_only:
+        res = run_legs([x for x in args.legs.split(",") if x])
+        print(json.dumps(res), flush=True)
+        return
     log("setup ...")
     ctx = setup(args.workload, args.precision)
     grid, model, out, n = ctx["grid"], ctx["model"], ctx["out"], ctx["n"]
@@ -867,18 +890,7 @@ def main():
     torch.cuda.empty_cache()
     P.nif_set_query_blocks_per_cu(12)           # the legs below use the default launch shape
     P.nif_set_query_rays_per_wave(0)            # unless they tune their own
-    if "torus" in legs:
-        res["torus16"] = torus_leg()
-    if "precision" in legs:
-        res["precision_compare"] = precision_leg()
-    if "train" in legs:
-        res["train"] = train_leg()
-    if "batched" in legs:
-        res["batched"] = batched_leg()
-    if "ablation" in legs:
-        res["ablation"] = ablation_leg()
-    if "render" in legs:
-        res["render"] = render_leg()
+    res.update(run_legs(legs))
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)

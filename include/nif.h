@@ -15,7 +15,8 @@
  *    and the call returns without synchronising, except where stated.  nif_backward and
  *    nif_train_step also run the table-gradient part of the backward on a stream the model
  *    owns, forked from `stream` and joined back to it with events before the call returns.
- *    These two calls are not tested under graph capture.
+ *    Both may be captured into a HIP graph (the fork and join become graph edges); they
+ *    clear their accumulators with kernels, not memset nodes.
  *  - Opaque handles (nif_model, nif_grid) own their device memory, which is allocated at
  *    create/build time only.  nif_query, nif_trace, nif_forward, nif_encode, nif_backward
  *    and nif_train_step never allocate device memory.  A handle must not be used by two
@@ -87,9 +88,10 @@ enum { NIF_PREC_FP32 = 0, NIF_PREC_BF16 = 1, NIF_PREC_FP16 = 2 };
 enum { NIF_DIST_LOG_RELU = 0, NIF_DIST_SIGMOID = 1 };
 
 typedef struct {
-    int32_t levels;          /* L: 8 or 16 */
+    int32_t levels;          /* L: 4, 8, 12 or 16 with feat_dim 2; even, 2..16 with feat_dim 3 */
     int32_t log2_table;      /* T = 2^log2_table entries per level, 4..24 */
-    int32_t feat_dim;        /* features per level; 2 */
+    int32_t feat_dim;        /* features per level: 2, or 3 (the paper's comparison of deformation
+                                results: two levels, base resolution 64, three features) */
     int32_t table_dtype;     /* NIF_TABLE_F32 or NIF_TABLE_F16 (working copy; master is FP32) */
     int32_t res[32];         /* per-level grid resolution N_l >= 1 */
     int32_t pe_freqs;        /* F >= 0: PE samples per point = 1 + 2F */
@@ -103,7 +105,7 @@ typedef struct {
                                 the grid on x itself and the raw gamma values appended:
                                 [phi(x0), phi(x1), gamma(x0), gamma(x1)], gamma value 3 s + a =
                                 sample s (x, sin 2^k x, cos 2^k x) of axis a of the clamped point;
-                                E = 2 (levels feat_dim + 3 (1 + 2 pe_freqs)) */
+                                E = 2 (levels feat_dim + 3 (1 + 2 pe_freqs)); feat_dim 2 only */
 } nif_model_desc;
 
 /* Allocates parameters (FP32 masters and working copies), gradients and Adam state. */

@@ -114,6 +114,11 @@ _C1_MODEL = ModelDesc(levels=16, log2_table=19, feat_dim=2, table_dtype=TABLE_F1
                       res=level_resolutions(16, 16, 2048), pe_freqs=6,
                       hidden_width=64, hidden_layers=3, n_materials=4)
 _C2_MODEL = replace(_C1_MODEL, hidden_width=128, hidden_layers=4)
+# The configuration of the paper's comparison of deformation results: a two-level grid with
+# base resolution 64 and three features per entry, three PE bands (the second level's
+# resolution, the table size and the MLP are not stated: 128, 2^19 FP16, 3 x 64).
+_PAPER_MODEL = ModelDesc(levels=2, log2_table=19, feat_dim=3, table_dtype=TABLE_F16, res=[64, 128], pe_freqs=3,
+                         hidden_width=64, hidden_layers=3, n_materials=4)
 
 
 def workload(name: str) -> Workload:
@@ -126,6 +131,9 @@ def workload(name: str) -> Workload:
                     in 8x8 tiles, MLP 4x128 for the FP32 / BF16 / FP16 comparison.
     blobs128     -- 32-Gaussian blob field at 128^3 for the training step, MLP 4x128.
     blobs128_b   -- the blobs128 scene with 16 poses of uneven ray counts (batched query).
+    spheres32_paper -- the paper's deformation-comparison configuration: the sphere scene at
+                    32^3 voxels, a 2-level grid (64, 128) with 3 features per entry, F = 3;
+                    twist, bend and taper at full strength, 512x512 pinhole rays per pose.
     """
     strengths8 = [(i + 1) / 8.0 for i in range(8)]
     if name == "torus16":
@@ -149,6 +157,10 @@ def workload(name: str) -> Workload:
     if name == "blobs128_b":
         return Workload(name, SCENE_BLOBS, 128, replace(_C2_MODEL), seed=1004,
                         rays="mixed", precision=PREC_BF16, scene_seed=1003)
+    if name == "spheres32_paper":
+        return Workload(name, SCENE_SPHERES, 32, _PAPER_MODEL, seed=1005, scene_seed=1001,
+                        pose_kinds=[TWIST, BEND, TAPER], pose_strengths=[1.0, 1.0, 1.0], rays="camera",
+                        cam_res=512, n_rays=512 * 512, cam_az_deg=[0.0, 120.0, 240.0])
     raise KeyError(name)
 
 

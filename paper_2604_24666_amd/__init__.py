@@ -345,7 +345,7 @@ def model_desc(levels, log2_table, feat_dim, table_dtype, res, pe_freqs, hidden_
 class Model:
     """Owns a nif_model handle.  `m` is any object with the ModelDesc attributes."""
 
-    def __init__(self, m, device="cuda"):
+    def __init__(self, m, device="cuda", max_batch: int = 0):
         self.spec = m
         self.desc = model_desc(m.levels, m.log2_table, m.feat_dim, m.table_dtype, m.res, m.pe_freqs,
                                m.hidden_width, m.hidden_layers, m.n_materials, getattr(m, "dist_head", 0),
@@ -357,6 +357,14 @@ class Model:
         self.E = 2 * (self.S_grid * m.levels * m.feat_dim + (3 * (1 + 2 * m.pe_freqs) if concat else 0))
         self.device = device
         self.h = nif_model_create(self.desc)
+        self.max_batch = 0
+        if max_batch > 0:
+            self.reserve(max_batch)
+
+    def reserve(self, max_batch: int):
+        """Training / backward scratch for batches of up to max_batch samples (allocates)."""
+        nif_model_reserve(self.h, max_batch)
+        self.max_batch = max(self.max_batch, int(max_batch))
 
     def set_params(self, tables, mlp, s=None):
         t = torch.as_tensor(tables, dtype=torch.float32).reshape(-1).contiguous().to(self.device)
@@ -499,8 +507,10 @@ class NifField(torch.autograd.Function):
     """Heads of point pairs with a hand-written backward (libnif kernels both ways).
 
     forward(x0, x1, model, precision) -> heads [B][H]; backward accumulates the parameter
-    gradients into the model's accumulators (read them with Model.get_grads) and returns
-    d x0, d x1 through the hash grid and the positional encoding."""
+    gradients into the model's accumulators (read them with Model.get_grads; zero them with
+    nif_model_zero_grads) and returns d x0, d x1 through the hash grid and the positional
+    encoding.  The model must be reserved for B samples beforehand (Model(..., max_batch=B)):
+    the backward itself allocates nothing."""
 
     @staticmethod
     def forward(ctx, x0, x1, model, precision=PREC_FP32):
@@ -513,9 +523,11 @@ class NifField(torch.autograd.Function):
         x0, x1 = ctx.saved_tensors
         m = ctx.model
         B = x0.shape[1]
+        if B > m.max_batch:
+            raise NifError(f"NifField backward of {B} samples: reserve the model for them first "
+                           f"(Model(..., max_batch=B) or Model.reserve(B); reserved {m.max_batch})")
         dx0 = torch.empty_like(x0)
         dx1 = torch.empty_like(x1)
-        nif_model_reserve(m.h, B)
         nif_backward(m.h, x0.contiguous(), x1.contiguous(), B, d_heads.contiguous(), dx0, dx1, True,
                      ctx.precision)
         return dx0, dx1, None, None

@@ -51,9 +51,12 @@ int nif_version(void) { return 1; }
 
 static int validate_desc(const nif_model_desc* d) {
     REQUIRE(d, "desc is null");
-    REQUIRE(d->levels == 8 || d->levels == 16, "levels must be 8 or 16");
+    REQUIRE(d->feat_dim == 2 || d->feat_dim == 3, "feat_dim must be 2 or 3");
+    if (d->feat_dim == 2) REQUIRE(d->levels == 4 || d->levels == 8 || d->levels == 12 || d->levels == 16,
+                                  "with feat_dim 2, levels must be 4, 8, 12 or 16");
+    else REQUIRE(d->levels >= 2 && d->levels <= 16 && d->levels % 2 == 0, "with feat_dim 3, levels must be even in [2, 16]");
+    REQUIRE(d->feat_dim == 2 || d->concat_encoding == 0, "the concatenated encoding needs feat_dim 2");
     REQUIRE(d->log2_table >= 4 && d->log2_table <= 24, "log2_table must be in [4, 24]");
-    REQUIRE(d->feat_dim == 2, "feat_dim must be 2");
     REQUIRE(d->table_dtype == NIF_TABLE_F32 || d->table_dtype == NIF_TABLE_F16, "table_dtype must be NIF_TABLE_F32 or NIF_TABLE_F16");
     for (int l = 0; l < d->levels; ++l) REQUIRE(d->res[l] >= 1 && d->res[l] <= (1 << 20), "res[l] must be in [1, 2^20]");
     REQUIRE(d->pe_freqs >= 0 && d->pe_freqs <= 12, "pe_freqs must be in [0, 12]");

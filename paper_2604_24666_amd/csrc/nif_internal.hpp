@@ -70,7 +70,7 @@ struct nif_model {
     int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
     uint16_t* bwd_key = nullptr;        // table-gradient additions: entry within the bucket
-    float2* bwd_val = nullptr;          //                            value per feature
+    float* bwd_val = nullptr;           //                            value per feature (Fd each)
     uint32_t* ord_u32 = nullptr;        // batch ordering: keys and indices, 2 x 2 x max_batch
     float* ord_f32 = nullptr;           //   the ordered batch (15 max_batch words)
     void* ord_temp = nullptr;           //   radix-sort scratch

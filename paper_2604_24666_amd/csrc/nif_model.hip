@@ -53,12 +53,15 @@ __global__ void k_sync_mlp(LayerMap lm, const float* __restrict__ src, float* __
 
 // First-layer weights in the order the fused kernels read them, so that each of a wave's
 // weight loads is one contiguous block (8 or 4 whole cache lines) instead of 64 scattered rows.
-// Lane (q, j) of MFMA block ob, at the u-th PE combination of its quarter (c = qU + u) and
-// level batch lb (levels 4lb .. 4lb+3), reads W0[ob 16 + j][c 2L + 8 lb + 4h + k] as element
-// k of half h; combinations past 2S are zero.
-__global__ void k_sync_w0l(const float* __restrict__ w0, int E, int HW, int U, int L, int n_comb,
+// A level batch is LB levels (4 with two features per entry, 2 with three), whose LB Fd
+// features fill t < LB Fd of a lane's 8 k-values.  Lane (q, j) of MFMA block ob, at the u-th
+// PE combination of its quarter (c = qU + u) and level batch lb, reads
+// W0[ob 16 + j][(c L + LB lb) Fd + t], t = 4h + k, as element k of half h; the padding
+// (t >= LB Fd) and combinations past 2S are zero.
+__global__ void k_sync_w0l(const float* __restrict__ w0, int E, int HW, int U, int L, int Fd, int n_comb,
                            float* __restrict__ f32, uint16_t* __restrict__ bf16, __half* __restrict__ f16, int64_t n) {
-    const int NLB = L >> 2;
+    const int LB = Fd == 2 ? 4 : 2;
+    const int NLB = L / LB;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i;
         const int k = (int)(r & 3); r >>= 2;
@@ -69,7 +72,8 @@ __global__ void k_sync_w0l(const float* __restrict__ w0, int E, int HW, int U, i
         const int ob = (int)r;
         const int q = lane >> 4, j = lane & 15;
         const int c = q * U + u;
-        const float v = c < n_comb ? w0[(int64_t)(ob * 16 + j) * E + c * 2 * L + 8 * lb + 4 * h + k] : 0.f;
+        const int t = 4 * h + k;
+        const float v = c < n_comb && t < LB * Fd ? w0[(int64_t)(ob * 16 + j) * E + ((int64_t)c * L + LB * lb) * Fd + t] : 0.f;
         f32[i] = v;
         bf16[i] = f2bf(v);
         f16[i] = __float2half_rn(v);
@@ -78,8 +82,8 @@ __global__ void k_sync_w0l(const float* __restrict__ w0, int E, int HW, int U, i
 
 static int sync_w0l(nif_model* m, hipStream_t st) {
     const int L = m->desc.levels, HW = m->desc.hidden_width, n_comb = 2 * m->S, U = (n_comb + 3) >> 2;
-    hipLaunchKernelGGL(k_sync_w0l, dim3(256), dim3(256), 0, st, m->mlp_pad_f32 + m->wp_off[0], m->E, HW, U, L, n_comb,
-                       m->w0l_f32, m->w0l_bf16, m->w0l_f16, m->n_w0l);
+    hipLaunchKernelGGL(k_sync_w0l, dim3(256), dim3(256), 0, st, m->mlp_pad_f32 + m->wp_off[0], m->E, HW, U, L,
+                       m->desc.feat_dim, n_comb, m->w0l_f32, m->w0l_bf16, m->w0l_f16, m->n_w0l);
     return check_hip(hipGetLastError(), "k_sync_w0l");
 }
 
@@ -149,7 +153,7 @@ int model_alloc(nif_model* m) {
     }
     m->n_mlp = off;
     m->n_mlp_pad = offp;
-    m->n_w0l = (int64_t)(d.hidden_width / 16) * ((2 * m->S + 3) / 4) * (d.levels / 4) * 2 * 64 * 4;
+    m->n_w0l = (int64_t)(d.hidden_width / 16) * ((2 * m->S + 3) / 4) * (d.levels / (d.feat_dim == 2 ? 4 : 2)) * 2 * 64 * 4;
     int rc;
     if ((rc = dalloc(&m->tables, m->n_table, "tables"))) return rc;
     if (d.table_dtype == NIF_TABLE_F16 && (rc = dalloc(&m->tables_h, m->n_table, "fp16 tables"))) return rc;

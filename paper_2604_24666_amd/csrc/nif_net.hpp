@@ -40,9 +40,10 @@ constexpr int kZStride = 17;     // LDS floats per segment of head outputs (16 +
 constexpr int kQueryCB = NIF_QUERY_CB;      // 16-segment column blocks per MLP pass in the fused query
 
 struct EncParams {
-    const void* tab;        // [sets][L][T][2] FP32 or FP16
+    const void* tab;        // [sets][L][T][Fd] FP32 or FP16
     int32_t f16;
     int32_t L, log2T, F;
+    int32_t Fd;             // features per entry: 2 or 3
     int32_t res[16];
     uint32_t dense_mask;    // bit l: level l indexed densely
     int64_t set_stride;     // entries per table set: L T with one set per PE sample, else 0
@@ -114,60 +115,33 @@ __device__ __forceinline__ uint32_t grid_index(uint32_t vx, uint32_t vy, uint32_
     return dense ? hd : hh;
 }
 
+// Trilinearly interpolated features of level l at one sample (any Fd; one load per feature):
+// out[f], f < Fd.  The plain form, for the encoding on its own.
 template <bool F16>
-__device__ __forceinline__ float2 table_entry(const void* tab, size_t e) {
-    if constexpr (F16) return __half22float2(reinterpret_cast<const __half2*>(tab)[e]);
-    else return reinterpret_cast<const float2*>(tab)[e];
-}
-
-// Trilinearly interpolated 2-feature entries of NL levels (l0, l0 + dl, ...) at one sample.
-// All 8 NL corner gathers are issued before any is used, so they are in flight together.
-template <int NL, bool F16>
-__device__ __forceinline__ void grid_lookup_n(const EncParams& ep, int l0, int dl, double sx, double sy, double sz,
-                                              float2 out[NL], uint32_t set_off = 0) {
+__device__ __forceinline__ void grid_lookup_any(const EncParams& ep, int l, double sx, double sy, double sz,
+                                                uint32_t set_off, float* out) {
     const uint32_t mask = (1u << ep.log2T) - 1u;
-    size_t idx[NL][8];
-    float wx[NL], wy[NL], wz[NL];
+    const int N = ep.res[l];
+    const bool dense = (ep.dense_mask >> l) & 1u;
+    const uint32_t n1 = (uint32_t)N + 1u;
+    uint32_t ix, iy, iz;
+    float wx, wy, wz;
+    grid_axis(sx, N, ix, wx);
+    grid_axis(sy, N, iy, wy);
+    grid_axis(sz, N, iz, wz);
+    const size_t base = (size_t)(set_off + ((uint32_t)l << ep.log2T));
+    for (int f = 0; f < ep.Fd; ++f) out[f] = 0.f;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int l = l0 + k * dl;
-        const int N = ep.res[l];
-        const bool dense = (ep.dense_mask >> l) & 1u;
-        const uint32_t n1 = (uint32_t)N + 1u;
-        uint32_t ix, iy, iz;
-        grid_axis(sx, N, ix, wx[k]);
-        grid_axis(sy, N, iy, wy[k]);
-        grid_axis(sz, N, iz, wz[k]);
-        const size_t base = (size_t)(set_off + ((uint32_t)l << ep.log2T));
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            idx[k][c] = base + grid_index(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1), n1, dense, mask);
-    }
-    float2 v[NL][8];
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) v[k][c] = table_entry<F16>(ep.tab, idx[k][c]);
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float wt = ((c & 1) ? wx[k] : 1.f - wx[k]) * (((c >> 1) & 1) ? wy[k] : 1.f - wy[k]) *
-                             (((c >> 2) & 1) ? wz[k] : 1.f - wz[k]);
-            acc.x = fmaf(wt, v[k][c].x, acc.x);
-            acc.y = fmaf(wt, v[k][c].y, acc.y);
+    for (int c = 0; c < 8; ++c) {
+        const size_t e = (base + grid_index(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1), n1, dense, mask)) *
+                         (size_t)ep.Fd;
+        const float wt = ((c & 1) ? wx : 1.f - wx) * (((c >> 1) & 1) ? wy : 1.f - wy) * (((c >> 2) & 1) ? wz : 1.f - wz);
+        for (int f = 0; f < ep.Fd; ++f) {
+            const float v = F16 ? __half2float(reinterpret_cast<const __half*>(ep.tab)[e + f])
+                                : reinterpret_cast<const float*>(ep.tab)[e + f];
+            out[f] = fmaf(wt, v, out[f]);
         }
-        out[k] = acc;
     }
-}
-
-// One level (used where a single lookup is wanted).
-__device__ __forceinline__ float2 grid_lookup(const EncParams& ep, int l, double sx, double sy, double sz) {
-    float2 r[1];
-    if (ep.f16) grid_lookup_n<1, true>(ep, l, 1, sx, sy, sz, r);
-    else grid_lookup_n<1, false>(ep, l, 1, sx, sy, sz, r);
-    return r[0];
 }
 
 // ------------------------------------------------------------------ wave-uniform level lookups
@@ -230,29 +204,6 @@ __device__ __forceinline__ void pe_walk(const float* sp, int c, int S, PEWalk& w
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = 0.5 * (((s & 1) ? w.sn[a] : w.cs[a]) + 1.0);
-}
-
-// Features of lane quarter q for one sample: levels [q LQ, (q+1) LQ), 2 features each.
-template <int LQ, bool F16>
-__device__ __forceinline__ void quarter_features(const EncParams& ep, int q, const double smp[3], float feat[8]) {
-    float2 r[LQ];
-    grid_lookup_n<LQ, F16>(ep, q * LQ, 1, smp[0], smp[1], smp[2], r);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        feat[2 * k] = k < LQ ? r[k < LQ ? k : 0].x : 0.f;
-        feat[2 * k + 1] = k < LQ ? r[k < LQ ? k : 0].y : 0.f;
-    }
-}
-
-__device__ __forceinline__ void lane_features(const EncParams& ep, int q, const double smp[3], float feat[8]) {
-    // uniform branches: one straight-line gather sequence per (levels, table type)
-    if (ep.L == 16) {
-        if (ep.f16) quarter_features<4, true>(ep, q, smp, feat);
-        else quarter_features<4, false>(ep, q, smp, feat);
-    } else {
-        if (ep.f16) quarter_features<2, true>(ep, q, smp, feat);
-        else quarter_features<2, false>(ep, q, smp, feat);
-    }
 }
 
 // Positional-encoding state of one point coordinate triple across the samples.
@@ -385,6 +336,59 @@ __device__ __forceinline__ void lookup_levels(const EncParams& ep, int l0, const
     }
 }
 
+// Three-feature entries (12 or 6 bytes, no aligned pairs): every corner is its own load, all
+// 8 LB of them issued before any is used.  feat[3k + f] = feature f of level l0 + k.
+template <int LB, bool F16>
+__device__ __forceinline__ void lookup_levels3(const EncParams& ep, int l0, const uint32_t f[3], float feat[3 * LB],
+                                               uint32_t set_off = 0) {
+    const uint32_t mask = (1u << ep.log2T) - 1u;
+    uint32_t idx[LB][8];
+    float wx[LB], wy[LB], wz[LB];
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+        const int l = l0 + k;
+        const uint32_t N = (uint32_t)ep.res[l];
+        uint32_t ix, iy, iz;
+        fix_axis(f[0], N, ix, wx[k]);
+        fix_axis(f[1], N, iy, wy[k]);
+        fix_axis(f[2], N, iz, wz[k]);
+        const bool dense = (ep.dense_mask >> l) & 1u;
+        const uint32_t base = set_off + ((uint32_t)l << ep.log2T);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            idx[k][c] = base + grid_index(ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1), N + 1u, dense, mask);
+    }
+    float v[LB][8][3];
+#pragma unroll
+    for (int k = 0; k < LB; ++k)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const size_t e = (size_t)idx[k][c] * 3;
+            if constexpr (F16) {
+                const __half* t = reinterpret_cast<const __half*>(ep.tab) + e;
+                v[k][c][0] = __half2float(t[0]); v[k][c][1] = __half2float(t[1]); v[k][c][2] = __half2float(t[2]);
+            } else {
+                const float* t = reinterpret_cast<const float*>(ep.tab) + e;
+                v[k][c][0] = t[0]; v[k][c][1] = t[1]; v[k][c][2] = t[2];
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < LB; ++k) {
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float wt = ((c & 1) ? wx[k] : 1.f - wx[k]) * (((c >> 1) & 1) ? wy[k] : 1.f - wy[k]) *
+                             (((c >> 2) & 1) ? wz[k] : 1.f - wz[k]);
+            a0 = fmaf(wt, v[k][c][0], a0);
+            a1 = fmaf(wt, v[k][c][1], a1);
+            a2 = fmaf(wt, v[k][c][2], a2);
+        }
+        feat[3 * k] = a0;
+        feat[3 * k + 1] = a1;
+        feat[3 * k + 2] = a2;
+    }
+}
+
 // ------------------------------------------------------------------ one MLP pass
 // The wave evaluates segments [seg_base, seg_base + 16*CB) whose rest-space points sit in
 // s_seg (kSegStride floats each).  acc[ob][cb] holds the 16x16 MFMA tile of output rows
@@ -405,16 +409,20 @@ __device__ __forceinline__ void layer1_bias(const NetParams& np, floatx4 (&acc)[
 // Layer 1 restricted to levels [lb, le) (a multiple of LB each), added to acc.  Lane (q, j)
 // takes the PE combinations c = qU .. qU + U - 1 (point-major, 2S in all, U = ceil(2S / 4))
 // of segment j in order, so its samples follow the double-angle recurrence; the wave walks
-// the levels in batches of LB, all lanes on the same level.  MFMA k-index = (combination of the
-// lane's quarter, level, feature), so each lane loads the matching weights W0[row][c 2L + 2l + f].
+// the levels in batches of LB, all lanes on the same level.  A batch gives each lane 8 MFMA
+// k-values: the LB FD features of (its combination, level batch) in encoding order, zero-padded
+// (FD = 2: 4 levels, 8 features; FD = 3: 2 levels, 6 features and 2 zeros); the lane loads the
+// matching lane-ordered weights (zero at the padding).
 // enc_out (nullable): the features are also stored to enc_out[seg_g0 + seg][E].
-template <int HW, int CB, int PREC, int LB>
+template <int HW, int CB, int PREC, int FD>
 __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* s_seg, int seg_base, int lb, int le,
                                               floatx4 (&acc)[HW / 16][CB], float* enc_out, int64_t seg_g0,
                                               int64_t n_valid) {
-    static_assert(LB == 4, "level batch of the lane-ordered first-layer weights");
+    static_assert(FD == 2 || FD == 3, "2 or 3 features per entry");
+    constexpr int LB = FD == 2 ? 4 : 2;      // levels per batch
+    constexpr int NR = LB * FD;              // real features per lane per batch
+    constexpr int NF = 8;                    // MFMA k-values per lane per batch
     constexpr int OB = HW / 16;
-    constexpr int NF = 2 * LB;               // features per lane per batch
     const int lane = lane_id();
     const int q = lane >> 4, j = lane & 15;
     const int L = np.enc.L;
@@ -445,34 +453,46 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
             float feat[CB][NF];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                if (np.enc.f16) {
-                    lookup_levels<LB, true>(np.enc, l0, smp[cb], feat[cb], soff);
-                } else {     // FP32 entries are twice the size: two levels at a time
+                if constexpr (FD == 2) {
+                    if (np.enc.f16) {
+                        lookup_levels<LB, true>(np.enc, l0, smp[cb], feat[cb], soff);
+                    } else {     // FP32 entries are twice the size: two levels at a time
 #pragma unroll
-                    for (int h = 0; h < LB; h += 2) lookup_levels<2, false>(np.enc, l0 + h, smp[cb], feat[cb] + 2 * h, soff);
+                        for (int h = 0; h < LB; h += 2) lookup_levels<2, false>(np.enc, l0 + h, smp[cb], feat[cb] + 2 * h, soff);
+                    }
+                } else {
+                    if (np.enc.f16) lookup_levels3<LB, true>(np.enc, l0, smp[cb], feat[cb], soff);
+                    else lookup_levels3<LB, false>(np.enc, l0, smp[cb], feat[cb], soff);
+#pragma unroll
+                    for (int t = NR; t < NF; ++t) feat[cb][t] = 0.f;
                 }
                 if (!live) {
 #pragma unroll
                     for (int t = 0; t < NF; ++t) feat[cb][t] = 0.f;
                 }
             }
-            const int e0 = c * 2 * L + 2 * l0;
+            const int e0 = (c * L + l0) * FD;
             if (enc_out) {
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
                     const int64_t seg = seg_g0 + cb * 16 + j;
                     if (live && seg < n_valid) {
-                        float4* dst = reinterpret_cast<float4*>(enc_out + seg * E + e0);
+                        if constexpr (FD == 2) {
+                            float4* dst = reinterpret_cast<float4*>(enc_out + seg * E + e0);
 #pragma unroll
-                        for (int h = 0; h < NF / 4; ++h)
-                            dst[h] = make_float4(feat[cb][4 * h], feat[cb][4 * h + 1], feat[cb][4 * h + 2], feat[cb][4 * h + 3]);
+                            for (int h = 0; h < NF / 4; ++h)
+                                dst[h] = make_float4(feat[cb][4 * h], feat[cb][4 * h + 1], feat[cb][4 * h + 2], feat[cb][4 * h + 3]);
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < NR; ++t) enc_out[seg * E + e0 + t] = feat[cb][t];
+                        }
                     }
                 }
             }
 #pragma unroll
             for (int ob = 0; ob < OB; ++ob) {
                 // lane-ordered weights: half h of this lane's 8 at wl + (h 64 + lane) 4
-                const size_t wl = (((size_t)ob * U + u) * (L >> 2) + (l0 >> 2)) * 512;
+                const size_t wl = (((size_t)ob * U + u) * (L / LB) + l0 / LB) * 512;
                 if constexpr (PREC == P_FP32) {
                     const float* w = reinterpret_cast<const float*>(np.W0L) + wl + lane * 4;
                     float wf[NF];
@@ -482,7 +502,7 @@ __device__ __forceinline__ void layer1_levels(const NetParams& np, const float* 
                         wf[4 * h] = wv.x; wf[4 * h + 1] = wv.y; wf[4 * h + 2] = wv.z; wf[4 * h + 3] = wv.w;
                     }
 #pragma unroll
-                    for (int t = 0; t < NF; ++t)
+                    for (int t = 0; t < NR; ++t)
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) acc[ob][cb] = mfma32(wf[t], feat[cb][t], acc[ob][cb]);
                 } else {
@@ -539,6 +559,15 @@ __device__ __forceinline__ void mlp_tail(const NetParams& np, floatx4 (&acc)[HW 
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) nxt[ob][cb] = floatx4{bb.x, bb.y, bb.z, bb.w};
             }
+            // the layer's input as B operands, converted once for all output blocks
+            shortx4 hp[OB][CB];
+            if constexpr (PREC != P_FP32) {
+#pragma unroll
+                for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        hp[ob][cb] = pack4<PREC>(acc[ob][cb][0], acc[ob][cb][1], acc[ob][cb][2], acc[ob][cb][3]);
+            }
 #pragma unroll
             for (int oo = 0; oo < OB; ++oo)
 #pragma unroll
@@ -555,10 +584,7 @@ __device__ __forceinline__ void mlp_tail(const NetParams& np, floatx4 (&acc)[HW 
                         const shortx4 wa = *reinterpret_cast<const shortx4*>(
                             reinterpret_cast<const uint16_t*>(np.W[layer]) + (size_t)(oo * 16 + j) * HW + ob * 16 + 4 * q);
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) {
-                            const shortx4 hb = pack4<PREC>(acc[ob][cb][0], acc[ob][cb][1], acc[ob][cb][2], acc[ob][cb][3]);
-                            nxt[oo][cb] = mfma16<PREC>(wa, hb, nxt[oo][cb]);
-                        }
+                        for (int cb = 0; cb < CB; ++cb) nxt[oo][cb] = mfma16<PREC>(wa, hp[ob][cb], nxt[oo][cb]);
                     }
                 }
 #pragma unroll
@@ -667,14 +693,15 @@ __device__ __forceinline__ void layer1_gamma(const NetParams& np, const float* s
 }
 
 // Whole network on segments [seg_base, seg_base + 16*CB); acts / enc_out as above.  GAMMA:
-// the concatenated encoding (compiled separately, so the other kernels carry none of its code).
-template <int HW, int CB, int PREC, bool GAMMA = false>
+// the concatenated encoding, FD: features per table entry (each compiled separately, so the
+// other kernels carry none of their code).
+template <int HW, int CB, int PREC, bool GAMMA = false, int FD = 2>
 __device__ __forceinline__ void net_pass(const NetParams& np, const float* s_seg, int seg_base, float* s_z,
                                          float* acts, int64_t act_stride_layer, int64_t seg_g0, int64_t n_valid,
                                          float* enc_out = nullptr) {
     floatx4 acc[HW / 16][CB];
     layer1_bias<HW, CB>(np, acc);
-    layer1_levels<HW, CB, PREC, 4>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
+    layer1_levels<HW, CB, PREC, FD>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
     if constexpr (GAMMA) layer1_gamma<HW, CB, PREC>(np, s_seg, seg_base, acc, enc_out, seg_g0, n_valid);
     mlp_tail<HW, CB, PREC>(np, acc, seg_base, s_z, acts, act_stride_layer, seg_g0, n_valid);
 }

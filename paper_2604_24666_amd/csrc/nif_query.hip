@@ -246,7 +246,7 @@ __device__ __forceinline__ void unpark_trav(const Parked& pk, Trav& T) {
 
 // RPW rays per wave (64, or 16 for launches too small to hide the latency of a network round:
 // then a round is one pass of 16 segments instead of four, and four times as many waves run).
-template <int HW, int PREC, int RPW, bool GAMMA = false>
+template <int HW, int PREC, int RPW, bool GAMMA = false, int FD = 2>
 __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np, GridArgs G, RayArgs R, nif_hits out,
                                               int64_t* __restrict__ counters, int64_t* __restrict__ stats,
                                               int pose_times) {
@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
         }
         wave_lds_sync();
 #pragma unroll
-        for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
+        for (int ps = 0; ps < PASSES; ++ps) net_pass<HW, CB, PREC, GAMMA, FD>(np, s_seg, ps * 16 * CB, s_z, nullptr, 0, 0, 0);
         wave_lds_sync();
     }
     if (stats) wave_add_stats(stats, n_done, n_eval, bad);
@@ -431,26 +431,21 @@ __global__ void __launch_bounds__(256) k_proxy(GridArgs G, RayArgs R, nif_hits o
 
 // ------------------------------------------------------------------ network on given points
 
-// Full encoding of n points (lane per point): out[i][(s L + l) 2 + f].
+// Full encoding of n points (lane per point): out[i][(s L + l) Fd + f].
 __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __restrict__ x, int64_t n,
                                                 float* __restrict__ out) {
     const int S = 1 + 2 * ep.F;
-    const int W = S * ep.L * 2;
+    const int W = S * ep.L * ep.Fd;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         PEState pe;
         pe_begin(pe, x[i], x[n + i], x[2 * n + i]);
         for (int s = 0; s < S; ++s) {
             double smp[3];
             pe_sample(pe, s, smp);
-            for (int l0 = 0; l0 < ep.L; l0 += 4) {
-                float2 f[4];
-                if (ep.f16) grid_lookup_n<4, true>(ep, l0, 1, smp[0], smp[1], smp[2], f, set_offset(ep, s));
-                else grid_lookup_n<4, false>(ep, l0, 1, smp[0], smp[1], smp[2], f, set_offset(ep, s));
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    out[i * W + (s * ep.L + l0 + k) * 2] = f[k].x;
-                    out[i * W + (s * ep.L + l0 + k) * 2 + 1] = f[k].y;
-                }
+            for (int l = 0; l < ep.L; ++l) {
+                float* o = out + i * W + (s * ep.L + l) * ep.Fd;
+                if (ep.f16) grid_lookup_any<true>(ep, l, smp[0], smp[1], smp[2], set_offset(ep, s), o);
+                else grid_lookup_any<false>(ep, l, smp[0], smp[1], smp[2], set_offset(ep, s), o);
             }
         }
     }
@@ -458,12 +453,12 @@ __global__ void __launch_bounds__(256) k_encode(EncParams ep, const float* __res
 
 // Encoding of segments [seg_base, seg_base + 16*CB) into enc_out only (no MLP past the
 // first layer's accumulation, whose result is dropped).
-template <int HW, int CB, int PREC, bool GAMMA>
+template <int HW, int CB, int PREC, bool GAMMA, int FD>
 __device__ __forceinline__ void enc_pass(const NetParams& np, const float* s_seg, int seg_base, int64_t seg_g0,
                                          int64_t n_valid, float* enc_out) {
     floatx4 acc[HW / 16][CB];
     layer1_bias<HW, CB>(np, acc);
-    layer1_levels<HW, CB, PREC, 4>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
+    layer1_levels<HW, CB, PREC, FD>(np, s_seg, seg_base, 0, np.enc.L, acc, enc_out, seg_g0, n_valid);
     if constexpr (GAMMA) layer1_gamma<HW, CB, PREC>(np, s_seg, seg_base, acc, enc_out, seg_g0, n_valid);
 }
 
@@ -475,7 +470,7 @@ __device__ __forceinline__ void enc_pass(const NetParams& np, const float* s_seg
 // the tile's 64 points, which keeps the accumulators small enough for two waves per SIMD; with
 // spatially ordered batches that latency hiding outweighs streaming the first-layer weights
 // once per pass.
-template <int HW, int PREC, bool GAMMA = false, bool ENC_ONLY = false, int TILE = ENC_ONLY ? 16 : 64>
+template <int HW, int PREC, bool GAMMA = false, bool ENC_ONLY = false, int TILE = ENC_ONLY ? 16 : 64, int FD = 2>
 __global__ void __launch_bounds__(256, 2) k_forward(NetParams np, const float* __restrict__ x0, const float* __restrict__ x1,
                                                  int64_t B, int64_t ld, float* __restrict__ heads,
                                                  float* __restrict__ acts, float* __restrict__ enc) {
@@ -502,11 +497,11 @@ __global__ void __launch_bounds__(256, 2) k_forward(NetParams np, const float* _
         if constexpr (ENC_ONLY) {
 #pragma unroll
             for (int ps = 0; ps < PASSES; ++ps)
-                enc_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, tile * TILE + ps * 16 * CB, B, enc);
+                enc_pass<HW, CB, PREC, GAMMA, FD>(np, s_seg, ps * 16 * CB, tile * TILE + ps * 16 * CB, B, enc);
         } else {
 #pragma unroll
             for (int ps = 0; ps < PASSES; ++ps)
-                net_pass<HW, CB, PREC, GAMMA>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * TILE + ps * 16 * CB, B, enc);
+                net_pass<HW, CB, PREC, GAMMA, FD>(np, s_seg, ps * 16 * CB, s_z, acts, B * HW, tile * TILE + ps * 16 * CB, B, enc);
             wave_lds_sync();
             if (lane < TILE && seg < B)
                 for (int h = 0; h < np.H; ++h) heads[seg * np.H + h] = s_z[lane * kZStride + h];
@@ -534,6 +529,7 @@ NetParams make_net_params(const nif_model* m, int32_t precision) {
     np.enc.tab = d.table_dtype == NIF_TABLE_F16 ? (const void*)m->tables_h : (const void*)m->tables;
     np.enc.f16 = d.table_dtype == NIF_TABLE_F16;
     np.enc.L = d.levels;
+    np.enc.Fd = d.feat_dim;
     np.enc.log2T = d.log2_table;
     np.enc.F = d.concat_encoding ? 0 : d.pe_freqs;      // the grid sees x only in the concatenated form
     np.gamma_F = d.concat_encoding ? d.pe_freqs : -1;
@@ -597,9 +593,12 @@ static void launch_query(const NetParams& np, const GridArgs& G, const RayArgs& 
     if (rpw == 0) rpw = R.n < kSmallLaunchRaysPerCU * device_cus() ? 16 : 64;
     const int64_t waves = (R.n + rpw - 1) / rpw;
     const int64_t blocks = std::max<int64_t>(std::min<int64_t>(waves, (int64_t)device_cus() * g_query_blocks_per_cu), 1);
-    if (np.gamma_F >= 0) {
+    if (np.gamma_F >= 0 || np.enc.Fd == 3) {     // the method variants: one launch shape
         const int64_t b64 = std::max<int64_t>(std::min<int64_t>((R.n + 63) / 64, (int64_t)device_cus() * g_query_blocks_per_cu), 1);
-        hipLaunchKernelGGL((k_query<HW, PREC, 64, true>), dim3((unsigned)b64), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
+        if (np.enc.Fd == 3)
+            hipLaunchKernelGGL((k_query<HW, PREC, 64, false, 3>), dim3((unsigned)b64), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
+        else
+            hipLaunchKernelGGL((k_query<HW, PREC, 64, true>), dim3((unsigned)b64), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
     } else if (rpw == 16) {
         hipLaunchKernelGGL((k_query<HW, PREC, 16>), dim3((unsigned)blocks), dim3(64), 0, st, np, G, R, out, ctr, stats, pt);
     } else {
@@ -707,9 +706,14 @@ static void launch_forward(const NetParams& np, const float* x0, const float* x1
                            float* acts, float* enc, hipStream_t st) {
     // small launches (up to 2^17 pairs) take 16 pairs per wave so that they still fill the chip
     const bool gamma = np.gamma_F >= 0, enc_only = heads == nullptr, small = B <= (1 << 17);
-    const int64_t tiles = enc_only || small ? (B + 15) / 16 : (B + 63) / 64;
+    const int64_t tiles = enc_only || small || np.enc.Fd == 3 ? (B + 15) / 16 : (B + 63) / 64;
     const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, (int64_t)device_cus() * 8);
     const dim3 g((unsigned)std::max<int64_t>(blocks, 1)), b(256);
+    if (np.enc.Fd == 3) {            // three-feature entries: 16 pairs per wave throughout
+        if (enc_only) hipLaunchKernelGGL((k_forward<HW, PREC, false, true, 16, 3>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+        else hipLaunchKernelGGL((k_forward<HW, PREC, false, false, 16, 3>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
+        return;
+    }
     if (gamma && enc_only) hipLaunchKernelGGL((k_forward<HW, PREC, true, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
     else if (gamma && small) hipLaunchKernelGGL((k_forward<HW, PREC, true, false, 16>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);
     else if (gamma) hipLaunchKernelGGL((k_forward<HW, PREC, true>), g, b, 0, st, np, x0, x1, B, ld, heads, acts, enc);

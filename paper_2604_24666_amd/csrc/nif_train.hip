@@ -78,7 +78,10 @@ struct DwArgs {
     int64_t n_slots;
 };
 
-// Launch shape of one layer's weight gradient: about two blocks per compute unit.
+constexpr int64_t kDwMinK = 512;
+
+// Launch shape of one layer's weight gradient: about two blocks per compute unit, each over at
+// least kDwMinK samples.
 static DwArgs dw_shape(int M_pad, int N, int64_t B, int cus) {
     DwArgs A;
     memset(&A, 0, sizeof(A));
@@ -88,7 +91,9 @@ static DwArgs dw_shape(int M_pad, int N, int64_t B, int cus) {
     const int n_cg = (A.n_cb + 3) / 4;
     const int64_t target = 2LL * cus;
     int64_t nch = std::max<int64_t>(1, (target + n_cg - 1) / n_cg);
-    A.Kc = std::max<int64_t>(16, (((B + nch - 1) / nch) + 15) / 16 * 16);
+    // at least kDwMinK samples per K chunk: fewer partial slots for k_dw_sum to add up, and
+    // each wave's MFMA loop long enough to cover its operand loads
+    A.Kc = std::max<int64_t>(kDwMinK, (((B + nch - 1) / nch) + 15) / 16 * 16);
     nch = (B + A.Kc - 1) / A.Kc;
     A.n_slots = nch * A.ks;
     return A;
@@ -122,7 +127,7 @@ int model_reserve(nif_model* m, int64_t B) {
         const int64_t n_cnt = n_buckets * n_blk;
         const size_t sz[4] = {sizeof(int32_t) * (size_t)n_cnt,
                               sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 3 + n_buckets),
-                              sizeof(uint16_t) * (size_t)n_add, sizeof(float2) * (size_t)n_add};
+                              sizeof(uint16_t) * (size_t)n_add, sizeof(float) * (size_t)m->desc.feat_dim * (size_t)n_add};
         void** ptr[4] = {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val};
         for (int i = 0; i < 4; ++i)
             if (hipMalloc(ptr[i], sz[i]) != hipSuccess) {
@@ -347,6 +352,11 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
                 if (seg < B) v = *reinterpret_cast<const float4*>(dz + seg * 16 + 4 * q);
                 dout[cb] = floatx4{v.x, v.y, v.z, v.w};
             }
+            shortx4 pout[CB];
+            if constexpr (PREC != P_FP32) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) pout[cb] = pack4<PREC>(dout[cb][0], dout[cb][1], dout[cb][2], dout[cb][3]);
+            }
 #pragma unroll
             for (int ib = 0; ib < OB; ++ib)
 #pragma unroll
@@ -361,7 +371,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
                     } else {
                         const shortx4 wa = *reinterpret_cast<const shortx4*>(
                             reinterpret_cast<const uint16_t*>(bp.Wt[bp.n_hidden]) + (size_t)(ib * 16 + j) * 16 + 4 * q);
-                        acc = mfma16<PREC>(wa, pack4<PREC>(dout[cb][0], dout[cb][1], dout[cb][2], dout[cb][3]), acc);
+                        acc = mfma16<PREC>(wa, pout[cb], acc);
                     }
                     dh[ib][cb] = acc;
                 }
@@ -392,6 +402,15 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
             for (int ib = 0; ib < OB; ++ib)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) dn[ib][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // the deltas as B operands, converted once for all output blocks
+            shortx4 pk[OB][CB];
+            if constexpr (PREC != P_FP32) {
+#pragma unroll
+                for (int ob = 0; ob < OB; ++ob)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        pk[ob][cb] = pack4<PREC>(dh[ob][cb][0], dh[ob][cb][1], dh[ob][cb][2], dh[ob][cb][3]);
+            }
 #pragma unroll
             for (int ib = 0; ib < OB; ++ib)
 #pragma unroll
@@ -408,8 +427,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
                         const shortx4 wa = *reinterpret_cast<const shortx4*>(
                             reinterpret_cast<const uint16_t*>(bp.Wt[k]) + (size_t)(ib * 16 + j) * HW + ob * 16 + 4 * q);
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb)
-                            dn[ib][cb] = mfma16<PREC>(wa, pack4<PREC>(dh[ob][cb][0], dh[ob][cb][1], dh[ob][cb][2], dh[ob][cb][3]), dn[ib][cb]);
+                        for (int cb = 0; cb < CB; ++cb) dn[ib][cb] = mfma16<PREC>(wa, pk[ob][cb], dn[ib][cb]);
                     }
                 }
 #pragma unroll
@@ -430,7 +448,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdParams bp, const float* __re
 // columns; when the layer has fewer than 4 column tiles, the spare waves take further
 // slices of the chunk.  Partials (and the bias sums of column group 0) go to a scratch slot
 // per (chunk, slice); k_dw_sum adds the slots into the gradient, without atomics.
-template <int MT>
+template <int MT, int PREC>
 __global__ void __launch_bounds__(256) k_dw_part(DwArgs A) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
     const int cb = A.ks > 1 ? w % A.n_cb : (int)blockIdx.y * 4 + w;      // column tile
@@ -449,40 +467,65 @@ __global__ void __launch_bounds__(256) k_dw_part(DwArgs A) {
 #pragma unroll
     for (int a = 0; a < MT; ++a) bs[a] = 0.f;
     const bool ncol_ok = n0 + 4 * j + 3 < A.N;
-    for (int64_t kb = k0; kb < k1; kb += 4) {
-        const int64_t k = kb + q;
-        float av[MT], bv[4];
-        if (k < k1) {
-            const float* dr = A.d + k * A.dstride + MT * j;
-            if constexpr (MT >= 4) {
+    // FP32: one 16x16x4 MFMA per 4 samples, lane quarter q holding sample q of each group.
+    // BF16/FP16: operands rounded from the stored FP32 deltas and activations, one 16x16x16
+    // MFMA per 16 samples, lane quarter q holding samples 4q .. 4q + 3 (same row and column
+    // mapping).
+    constexpr int R = PREC == P_FP32 ? 1 : 4;
+    constexpr int STEP = 4 * R;
+    float av[R][MT], bv[R][4];
+    auto load = [&](int64_t kb, float (&a)[R][MT], float (&b)[R][4]) {
 #pragma unroll
-                for (int t = 0; t < MT; t += 4) {
-                    const float4 v = *reinterpret_cast<const float4*>(dr + t);
-                    av[t] = v.x; av[t + 1] = v.y; av[t + 2] = v.z; av[t + 3] = v.w;
+        for (int r = 0; r < R; ++r) {
+            const int64_t k = kb + R * q + r;
+            if (k < k1) {
+                const float* dr = A.d + k * A.dstride + MT * j;
+                if constexpr (MT >= 4) {
+#pragma unroll
+                    for (int t = 0; t < MT; t += 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(dr + t);
+                        a[r][t] = v.x; a[r][t + 1] = v.y; a[r][t + 2] = v.z; a[r][t + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < MT; ++t) a[r][t] = dr[t];
+                }
+                const float* hr = A.h + k * A.hstride + n0 + 4 * j;
+                if (ncol_ok) {
+                    const float4 v = *reinterpret_cast<const float4*>(hr);
+                    b[r][0] = v.x; b[r][1] = v.y; b[r][2] = v.z; b[r][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) b[r][t] = n0 + 4 * j + t < A.N ? hr[t] : 0.f;
                 }
             } else {
 #pragma unroll
-                for (int t = 0; t < MT; ++t) av[t] = dr[t];
-            }
-            const float* hr = A.h + k * A.hstride + n0 + 4 * j;
-            if (ncol_ok) {
-                const float4 v = *reinterpret_cast<const float4*>(hr);
-                bv[0] = v.x; bv[1] = v.y; bv[2] = v.z; bv[3] = v.w;
-            } else {
+                for (int t = 0; t < MT; ++t) a[r][t] = 0.f;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bv[t] = n0 + 4 * j + t < A.N ? hr[t] : 0.f;
+                for (int t = 0; t < 4; ++t) b[r][t] = 0.f;
+            }
+        }
+    };
+    for (int64_t kb = k0; kb < k1; kb += STEP) {
+        load(kb, av, bv);
+        if constexpr (PREC == P_FP32) {
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                bs[a] += av[0][a];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(av[0][a], bv[0][c], acc[a][c]);
             }
         } else {
+            shortx4 bp[4];
 #pragma unroll
-            for (int t = 0; t < MT; ++t) av[t] = 0.f;
+            for (int c = 0; c < 4; ++c) bp[c] = pack4<PREC>(bv[0][c], bv[1][c], bv[2][c], bv[3][c]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) bv[t] = 0.f;
-        }
+            for (int a = 0; a < MT; ++a) {
+                bs[a] += (av[0][a] + av[1][a]) + (av[2][a] + av[3][a]);
+                const shortx4 ap = pack4<PREC>(av[0][a], av[1][a], av[2][a], av[3][a]);
 #pragma unroll
-        for (int a = 0; a < MT; ++a) {
-            bs[a] += av[a];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(av[a], bv[c], acc[a][c]);
+                for (int c = 0; c < 4; ++c) acc[a][c] = mfma16<PREC>(ap, bp[c], acc[a][c]);
+            }
         }
     }
     const int64_t slot = (int64_t)blockIdx.x * A.ks + sub;
@@ -515,9 +558,11 @@ __global__ void __launch_bounds__(256) k_dw_part(DwArgs A) {
 }
 
 // gW[m][n] += sum over slots of part[slot][m][n] (m < M_real), gb[m] likewise.  Block: 64
-// consecutive outputs x 4 groups of slots (the groups' sums meet in LDS).
-__global__ void __launch_bounds__(256) k_dw_sum(DwArgs A, float* __restrict__ gW, int ldw, float* __restrict__ gb) {
-    __shared__ float red[4][64];
+// consecutive outputs x kDwSumGroups groups of slots (the groups' sums meet in LDS), so each
+// thread's chain of dependent loads is n_slots / kDwSumGroups long.
+constexpr int kDwSumGroups = 16;
+__global__ void __launch_bounds__(64 * kDwSumGroups) k_dw_sum(DwArgs A, float* __restrict__ gW, int ldw, float* __restrict__ gb) {
+    __shared__ float red[kDwSumGroups][64];
     const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t n_out = (int64_t)A.M_real * A.N;
     const int64_t i = (int64_t)blockIdx.x * 64 + o;
@@ -531,23 +576,26 @@ __global__ void __launch_bounds__(256) k_dw_sum(DwArgs A, float* __restrict__ gW
         p = A.part + A.n_slots * A.M_pad * A.N + (i - n_out);
         stride = A.M_pad;
     }
+    constexpr int G = kDwSumGroups;
     float s = 0.f;
     if (live) {
         int64_t t = g;
         float s1 = 0.f, s2 = 0.f, s3 = 0.f;
-        for (; t + 12 < A.n_slots; t += 16) {
+        for (; t + 3 * G < A.n_slots; t += 4 * G) {
             s += p[t * stride];
-            s1 += p[(t + 4) * stride];
-            s2 += p[(t + 8) * stride];
-            s3 += p[(t + 12) * stride];
+            s1 += p[(t + G) * stride];
+            s2 += p[(t + 2 * G) * stride];
+            s3 += p[(t + 3 * G) * stride];
         }
-        for (; t < A.n_slots; t += 4) s += p[t * stride];
+        for (; t < A.n_slots; t += G) s += p[t * stride];
         s += s1 + s2 + s3;
     }
     red[g][o] = s;
     __syncthreads();
     if (g == 0 && live) {
-        const float v = red[0][o] + red[1][o] + red[2][o] + red[3][o];
+        float v = 0.f;
+#pragma unroll
+        for (int k = 0; k < G; ++k) v += red[k][o];
         if (is_w) gW[(i / A.N) * ldw + i % A.N] += v;
         else gb[i - n_out] += v;
     }
@@ -595,7 +643,7 @@ struct EncBwdParams {
     int32_t n_blk;       // blocks of the chunk grid
     int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
     uint16_t* key;       // additions: entry within the bucket
-    float2* val;         // additions: value per feature
+    float* val;          // additions: Fd values each
     int64_t cap;         // capacity of key / val
     uint32_t* vmax;      // bits of the largest |value| of the chunk's additions (+inf if not finite)
 };
@@ -653,10 +701,15 @@ __device__ __forceinline__ bool tile_sample(const EncBwdParams& P, int64_t tile,
     return valid;
 }
 
-// Buckets of one level pair: table set s (one per PE sample with per-sample tables, else one),
-// level lp + k, slice: local index (s 2 + k) NBL + slice, global ((s L + lp + k) NBL + slice).
-__device__ __forceinline__ int64_t pair_bucket_global(const EncBwdParams& P, int lp, int i) {
-    const int s = i / (2 * P.NBL), r = i % (2 * P.NBL);
+// Levels per block row of the count and fill passes: two with two features per entry (the
+// four (level, feature) rows of a PE combination), one with three.
+template <int FD> constexpr int kLevelGroup = FD == 2 ? 2 : 1;
+
+// Buckets of one level group: table set s (one per PE sample with per-sample tables, else one),
+// level lp + k, slice: local index (s LG + k) NBL + slice, global ((s L + lp + k) NBL + slice).
+template <int LG>
+__device__ __forceinline__ int64_t group_bucket_global(const EncBwdParams& P, int lp, int i) {
+    const int s = i / (LG * P.NBL), r = i % (LG * P.NBL);
     return ((int64_t)s * P.enc.L + lp + r / P.NBL) * P.NBL + r % P.NBL;
 }
 __device__ __forceinline__ int n_table_sets(const EncBwdParams& P) { return P.enc.set_stride ? P.S : 1; }
@@ -665,13 +718,15 @@ __device__ __forceinline__ int combo_set(const EncBwdParams& P, int c) {
     return P.enc.set_stride ? (c >= P.S ? c - P.S : c) : 0;
 }
 
-// Block (x, y): the samples of tile group x, levels 2y and 2y + 1 (as the fill below).
+// Block (x, y): the samples of tile group x, the levels of level group y (as the fill below).
+template <int FD>
 __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
-    extern __shared__ int32_t s_h[];    // [sets][2][NBL]
+    constexpr int LG = kLevelGroup<FD>;
+    extern __shared__ int32_t s_h[];    // [sets][LG][NBL]
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
     const int n_comb = 2 * P.S;
-    const int lp = (int)blockIdx.y * 2;
-    const int nloc = 2 * P.NBL * n_table_sets(P);
+    const int lp = (int)blockIdx.y * LG;
+    const int nloc = LG * P.NBL * n_table_sets(P);
     for (int i = tid; i < nloc; i += 256) s_h[i] = 0;
     if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *P.vmax = 0u;
     __syncthreads();
@@ -687,8 +742,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
             double smp[3];
             float dsdx[3], inside[3];
             pe_combo_grad(xs, live ? c : 0, P.S, smp, dsdx, inside);
-            const int sb = combo_set(P, live ? c : 0) * 2;
-            for (int k = 0; k < 2; ++k) {
+            const int sb = combo_set(P, live ? c : 0) * LG;
+            for (int k = 0; k < LG; ++k) {
                 uint32_t idx[8];
                 float wt[3];
                 level_corners(P.enc, lp + k, smp, idx, wt);
@@ -699,22 +754,23 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
         }
     }
     __syncthreads();
-    for (int i = tid; i < nloc; i += 256) P.cnt[pair_bucket_global(P, lp, i) * P.n_blk + blockIdx.x] = s_h[i];
+    for (int i = tid; i < nloc; i += 256) P.cnt[group_bucket_global<LG>(P, lp, i) * P.n_blk + blockIdx.x] = s_h[i];
 }
 
-// Block (x, y): the samples of tile group x, levels 2y and 2y + 1 only, so that a block
-// writes into the 2 NBL buckets of one level pair: the lines it leaves partly written at any
-// time stay few enough to complete in L2 before eviction.
-template <int HW>
+// Block (x, y): the samples of tile group x, the LG levels of level group y only, so that a
+// block writes into the LG NBL buckets of those levels: the lines it leaves partly written at
+// any time stay few enough to complete in L2 before eviction.
+template <int HW, int FD>
 __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     constexpr int KQ = HW / 4;                 // MFMA k-steps: lane quarter q covers [q KQ, (q+1) KQ)
-    extern __shared__ int32_t s_cur[];         // [sets][2][NBL]: this block's next output slot per bucket
+    constexpr int LG = kLevelGroup<FD>;
+    extern __shared__ int32_t s_cur[];         // [sets][LG][NBL]: this block's next output slot per bucket
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
     const int L = P.enc.L, n_comb = 2 * P.S;
-    const int lp = (int)blockIdx.y * 2;        // first level of this block's pair
+    const int lp = (int)blockIdx.y * LG;       // first level of this block's group
     const uint32_t kmask = (1u << P.SB) - 1u;
-    const int nloc = 2 * P.NBL * n_table_sets(P);
-    for (int i = tid; i < nloc; i += 256) s_cur[i] = P.cnt[pair_bucket_global(P, lp, i) * P.n_blk + blockIdx.x];
+    const int nloc = LG * P.NBL * n_table_sets(P);
+    for (int i = tid; i < nloc; i += 256) s_cur[i] = P.cnt[group_bucket_global<LG>(P, lp, i) * P.n_blk + blockIdx.x];
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
     const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
@@ -739,13 +795,14 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
             float dsdx[3], inside[3];
             pe_combo_grad(xs, live ? c : 0, P.S, smp, dsdx, inside);
             float dpos[3] = {0.f, 0.f, 0.f};
-            // A operand row of lane (q, j): combination 4u + j/4, feature j%4 of the level pair
+            // A operand row of lane (q, j): combination 4u + j/4, (level, feature) j%4 of the level
+            // group in encoding order (with three features, index 3 is a zero row)
             const int ca = 4 * u + (j >> 2);
-            const bool a_live = ca < n_comb;
+            const bool a_live = ca < n_comb && (j & 3) < LG * FD;
             {
                 const int l0 = lp;
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                const float* wrow = P.W0t + (size_t)(a_live ? ca * 2 * L + 2 * l0 + (j & 3) : 0) * HW + q * KQ;
+                const float* wrow = P.W0t + (size_t)(a_live ? (ca * L + l0) * FD + (j & 3) : 0) * HW + q * KQ;
 #pragma unroll
                 for (int t = 0; t < KQ; t += 4) {
                     float4 av = *reinterpret_cast<const float4*>(wrow + t);
@@ -755,34 +812,51 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
                     acc = mfma32(av.z, bd[t + 2], acc);
                     acc = mfma32(av.w, bd[t + 3], acc);
                 }
-                // acc[2k + f] = d enc of (combination c, level l0 + k, feature f), sample j
+                // acc[FD k + f] = d enc of (combination c, level l0 + k, feature f), sample j
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
+                for (int k = 0; k < LG; ++k) {
                     const int l = l0 + k;
                     uint32_t idx[8];
                     float wt[3];
                     level_corners(P.enc, l, smp, idx, wt);
                     if (!live) continue;
-                    const float g0 = acc[2 * k], g1 = acc[2 * k + 1];
+                    float gf[FD];
+#pragma unroll
+                    for (int f = 0; f < FD; ++f) gf[f] = acc[FD * k + f];
                     float dl[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                     for (int cc = 0; cc < 8; ++cc) {
                         const float cw = corner_weight(wt, cc);
-                        const int32_t slot = atomicAdd(&s_cur[(combo_set(P, c) * 2 + l - lp) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
+                        const int32_t slot = atomicAdd(&s_cur[(combo_set(P, c) * LG + l - lp) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
                         if (slot < P.cap) {      // always true: the count pass saw the same additions
-                            const float v0 = cw * g0, v1 = cw * g1;
+                            float v[FD];
+                            bool fin = true;
+                            float a = 0.f;
+#pragma unroll
+                            for (int f = 0; f < FD; ++f) {
+                                v[f] = cw * gf[f];
+                                fin = fin && isfinite(v[f]);
+                                a = fmaxf(a, fabsf(v[f]));
+                            }
                             P.key[slot] = (uint16_t)(idx[cc] & kmask);
-                            P.val[slot] = make_float2(v0, v1);
-                            const float a = fmaxf(fabsf(v0), fabsf(v1));
-                            vmx = (isfinite(v0) && isfinite(v1)) ? fmaxf(vmx, a) : INFINITY;
+                            if constexpr (FD == 2) {
+                                reinterpret_cast<float2*>(P.val)[slot] = make_float2(v[0], v[1]);
+                            } else {
+#pragma unroll
+                                for (int f = 0; f < FD; ++f) P.val[(size_t)slot * FD + f] = v[f];
+                            }
+                            vmx = fin ? fmaxf(vmx, a) : INFINITY;
                         }
                         if (P.dx0) {
-                            const size_t te = (size_t)combo_set(P, c) * (size_t)P.enc.set_stride +
-                                              ((size_t)l << P.enc.log2T) + idx[cc];
-                            float2 tv;
-                            if (P.enc.f16) tv = __half22float2(reinterpret_cast<const __half2*>(P.enc.tab)[te]);
-                            else tv = reinterpret_cast<const float2*>(P.enc.tab)[te];
-                            const float gd = g0 * tv.x + g1 * tv.y;
+                            const size_t te = ((size_t)combo_set(P, c) * (size_t)P.enc.set_stride +
+                                               ((size_t)l << P.enc.log2T) + idx[cc]) * FD;
+                            float gd = 0.f;
+#pragma unroll
+                            for (int f = 0; f < FD; ++f) {
+                                const float tv = P.enc.f16 ? __half2float(reinterpret_cast<const __half*>(P.enc.tab)[te + f])
+                                                           : reinterpret_cast<const float*>(P.enc.tab)[te + f];
+                                gd = fmaf(gf[f], tv, gd);
+                            }
                             const float fx = (cc & 1) ? wt[0] : 1.f - wt[0];
                             const float fy = ((cc >> 1) & 1) ? wt[1] : 1.f - wt[1];
                             const float fz = ((cc >> 2) & 1) ? wt[2] : 1.f - wt[2];
@@ -910,16 +984,21 @@ __global__ void __launch_bounds__(1024) k_enc_bwd_parts(EncBwdParams P, const in
     if (threadIdx.x == 0) parts[P.n_buckets] = carry;
 }
 
-// Block (i, w): part i of the work list, window w (4096 entries) of its bucket.  A bucket cut
-// into one part is added to the table gradient directly; parts of a bucket cut into several
-// add their nonzero window entries with atomics.
+// Entries per reduction window: the window's FD 64-bit sums fill 64 or 48 KiB of LDS.
+template <int FD> constexpr int kLog2Window = FD == 2 ? 12 : 11;
+
+// Block (i, w): part i of the work list, window w (2^kLog2Window entries) of its bucket.  A
+// bucket cut into one part is added to the table gradient directly; parts of a bucket cut into
+// several add their nonzero window entries with atomics.
 // The window is summed in 64-bit fixed point with integer LDS atomics (several times the rate
 // of floating-point LDS atomics): with |value| < 2^e over the chunk and at most N additions,
 // the scale 2^s, s = 62 - e - ceil(log2 N), keeps every partial sum below 2^62 while the unit
 // is 2^-34 of the largest addition; the sum is exact in that unit and independent of order.
+template <int FD>
 __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const int32_t* __restrict__ total,
                                                         const int32_t* __restrict__ parts) {
-    __shared__ unsigned long long s_acc[2 * 4096];
+    constexpr int LW = kLog2Window<FD>, WN = 1 << LW;
+    __shared__ unsigned long long s_acc[FD * WN];
     const int i = blockIdx.x, w = blockIdx.y;
     if (i >= parts[P.n_buckets]) return;
     int lo = 0, hi = P.n_buckets - 1;                    // bucket b: parts[b] <= i < parts[b + 1]
@@ -929,8 +1008,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     }
     const int b = lo;
     const int n_parts = parts[b + 1] - parts[b], part = i - parts[b];
-    const int wn = P.SB < 12 ? (1 << P.SB) : 4096;   // entries per window
-    for (int k = threadIdx.x; k < 2 * wn; k += 256) s_acc[k] = 0ull;
+    const int wn = P.SB < LW ? (1 << P.SB) : WN;     // entries per window
+    for (int k = threadIdx.x; k < FD * wn; k += 256) s_acc[k] = 0ull;
     const float vmax = __uint_as_float(*P.vmax);
     const bool finite = isfinite(vmax);
     int ev = 0;
@@ -957,47 +1036,49 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
             kw[0] = k0.x; kw[1] = k0.y; kw[2] = k0.z; kw[3] = k0.w;
             kw[4] = k1.x; kw[5] = k1.y; kw[6] = k1.z; kw[7] = k1.w;
         }
-        float vv[32];
+        float vv[16 * FD];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const float4 t = *reinterpret_cast<const float4*>(P.val + base + 2 * r);
+        for (int r = 0; r < 4 * FD; ++r) {
+            const float4 t = *reinterpret_cast<const float4*>(P.val + base * FD + 4 * r);
             vv[4 * r] = t.x; vv[4 * r + 1] = t.y; vv[4 * r + 2] = t.z; vv[4 * r + 3] = t.w;
         }
         uint32_t cur = 0xffffffffu;
-        float rx = 0.f, ry = 0.f;
+        float rs[FD];
+#pragma unroll
+        for (int f = 0; f < FD; ++f) rs[f] = 0.f;
+        auto flush = [&]() {
+            if ((int)(cur >> LW) == w) {
+                const int e = (int)(cur & (WN - 1));
+#pragma unroll
+                for (int f = 0; f < FD; ++f)
+                    atomicAdd(&s_acc[FD * e + f], (unsigned long long)llrint(ldexp((double)rs[f], sc)));
+            }
+        };
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t k = base + r;
             const uint32_t key = (k >= start && k < end) ? ((kw[r >> 1] >> (16 * (r & 1))) & 0xffffu) : 0xffffffffu;
             if (key != cur) {
-                if ((int)(cur >> 12) == w) {
-                    const int e = (int)(cur & 4095u);
-                    atomicAdd(&s_acc[2 * e], (unsigned long long)llrint(ldexp((double)rx, sc)));
-                    atomicAdd(&s_acc[2 * e + 1], (unsigned long long)llrint(ldexp((double)ry, sc)));
-                }
+                flush();
                 cur = key;
-                rx = vv[2 * r];
-                ry = vv[2 * r + 1];
+#pragma unroll
+                for (int f = 0; f < FD; ++f) rs[f] = vv[FD * r + f];
             } else {
-                rx += vv[2 * r];
-                ry += vv[2 * r + 1];
+#pragma unroll
+                for (int f = 0; f < FD; ++f) rs[f] += vv[FD * r + f];
             }
         }
-        if ((int)(cur >> 12) == w) {
-            const int e = (int)(cur & 4095u);
-            atomicAdd(&s_acc[2 * e], (unsigned long long)llrint(ldexp((double)rx, sc)));
-            atomicAdd(&s_acc[2 * e + 1], (unsigned long long)llrint(ldexp((double)ry, sc)));
-        }
+        flush();
     }
     __syncthreads();
     const int l = b / P.NBL, slice = b % P.NBL;
-    float* g = P.g_tables + (((size_t)l << P.enc.log2T) + ((size_t)slice << P.SB) + (size_t)w * 4096) * 2;
+    float* g = P.g_tables + (((size_t)l << P.enc.log2T) + ((size_t)slice << P.SB) + ((size_t)w << LW)) * FD;
     // a non-finite addition poisons the window, so the step's finiteness check skips the update
     auto value = [&](int k) { return finite ? (float)ldexp((double)(long long)s_acc[k], -sc) : NAN; };
     if (n_parts == 1) {
-        for (int k = threadIdx.x; k < 2 * wn; k += 256) g[k] += value(k);
+        for (int k = threadIdx.x; k < FD * wn; k += 256) g[k] += value(k);
     } else {
-        for (int k = threadIdx.x; k < 2 * wn; k += 256)
+        for (int k = threadIdx.x; k < FD * wn; k += 256)
             if (s_acc[k] != 0ull || !finite) unsafeAtomicAdd(&g[k], value(k));
     }
 }
@@ -1174,8 +1255,20 @@ static int dispatch_mlp_bwd(int hw, const BwdParams& bp, const float* dz, const 
 // Backward from dz (already in m->dz) to the gradient accumulators; activations in m->acts.
 // One layer's weight gradient over rows [0, B) of d (stride dstride) and h (stride hstride),
 // added to gW / gb: K-sliced MFMA partials, then a sum per output.
+template <int PREC>
+static void launch_dw_part(const DwArgs& A, dim3 grid, hipStream_t st) {
+    switch (A.M_pad / 16) {
+        case 1: hipLaunchKernelGGL((k_dw_part<1, PREC>), grid, dim3(256), 0, st, A); break;
+        case 2: hipLaunchKernelGGL((k_dw_part<2, PREC>), grid, dim3(256), 0, st, A); break;
+        case 4: hipLaunchKernelGGL((k_dw_part<4, PREC>), grid, dim3(256), 0, st, A); break;
+        default: hipLaunchKernelGGL((k_dw_part<8, PREC>), grid, dim3(256), 0, st, A); break;
+    }
+}
+
+// Weight gradient of one layer; with BF16/FP16 MLP arithmetic its operands are rounded to that
+// precision as in the forward and the MLP backward (FP32 accumulation either way).
 static int weight_grad(nif_model* m, int layer, const float* d, int dstride, int M_pad, const float* h, int64_t B,
-                       int cus, hipStream_t st) {
+                       int cus, int32_t precision, hipStream_t st) {
     DwArgs A = dw_shape(M_pad, m->dims[layer], B, cus);
     A.d = d;
     A.dstride = dstride;
@@ -1185,14 +1278,11 @@ static int weight_grad(nif_model* m, int layer, const float* d, int dstride, int
     A.part = m->dw_part;
     if (dw_part_floats(A) > m->dw_part_n) return fail(NIF_E_STATE, "weight-gradient scratch too small");
     const dim3 grid((unsigned)((B + A.Kc - 1) / A.Kc), (unsigned)(A.ks > 1 ? 1 : (A.n_cb + 3) / 4));
-    switch (A.M_pad / 16) {
-        case 1: hipLaunchKernelGGL(k_dw_part<1>, grid, dim3(256), 0, st, A); break;
-        case 2: hipLaunchKernelGGL(k_dw_part<2>, grid, dim3(256), 0, st, A); break;
-        case 4: hipLaunchKernelGGL(k_dw_part<4>, grid, dim3(256), 0, st, A); break;
-        default: hipLaunchKernelGGL(k_dw_part<8>, grid, dim3(256), 0, st, A); break;
-    }
+    if (precision == NIF_PREC_BF16) launch_dw_part<P_BF16>(A, grid, st);
+    else if (precision == NIF_PREC_FP16) launch_dw_part<P_FP16>(A, grid, st);
+    else launch_dw_part<P_FP32>(A, grid, st);
     const int64_t n_out = (int64_t)A.M_real * A.N + A.M_real;
-    hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((n_out + 63) / 64)), dim3(256), 0, st, A,
+    hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((n_out + 63) / 64)), dim3(64 * kDwSumGroups), 0, st, A,
                        m->g_mlp + m->w_off[layer], A.N, m->g_mlp + m->b_off[layer]);
     return NIF_OK;
 }
@@ -1223,10 +1313,12 @@ static EncBwdParams table_grad_params(nif_model* m, const float* x0, const float
 
 // One round of the table gradient: samples [c0, c0 + n), n <= bwd_chunk: count / scan / fill /
 // parts / reduce on stream sd (the round's scratch is shared, so rounds run in stream order).
-static void table_grad_round(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
+template <int FD>
+static void table_grad_round_fd(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
+    constexpr int LG = kLevelGroup<FD>, LW = kLog2Window<FD>;
     const int hw = m->desc.hidden_width;
     const int n_sets = m->desc.per_sample_tables ? m->S : 1;
-    const unsigned n_win = ep.SB > 12 ? 1u << (ep.SB - 12) : 1u;
+    const unsigned n_win = ep.SB > LW ? 1u << (ep.SB - LW) : 1u;
     ep.c0 = c0;
     ep.n = n;
     const int64_t n_tiles = (ep.n + 15) / 16;
@@ -1237,21 +1329,26 @@ static void table_grad_round(nif_model* m, EncBwdParams ep, int64_t c0, int64_t 
     int32_t* total = m->bwd_scan + n_chunks;
     int32_t* parts = total + 1;
     ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
-    const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / 2));
-    const size_t lds_f = sizeof(int32_t) * 2 * (size_t)ep.NBL * n_sets;
-    hipLaunchKernelGGL(k_enc_bwd_count, fg, dim3(256), lds_f, sd, ep);
+    const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / LG));
+    const size_t lds_f = sizeof(int32_t) * LG * (size_t)ep.NBL * n_sets;
+    hipLaunchKernelGGL(k_enc_bwd_count<FD>, fg, dim3(256), lds_f, sd, ep);
     hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, total);
     hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
     switch (hw) {
-        case 16: hipLaunchKernelGGL(k_enc_bwd_fill<16>, fg, dim3(256), lds_f, sd, ep); break;
-        case 32: hipLaunchKernelGGL(k_enc_bwd_fill<32>, fg, dim3(256), lds_f, sd, ep); break;
-        case 64: hipLaunchKernelGGL(k_enc_bwd_fill<64>, fg, dim3(256), lds_f, sd, ep); break;
-        default: hipLaunchKernelGGL(k_enc_bwd_fill<128>, fg, dim3(256), lds_f, sd, ep); break;
+        case 16: hipLaunchKernelGGL((k_enc_bwd_fill<16, FD>), fg, dim3(256), lds_f, sd, ep); break;
+        case 32: hipLaunchKernelGGL((k_enc_bwd_fill<32, FD>), fg, dim3(256), lds_f, sd, ep); break;
+        case 64: hipLaunchKernelGGL((k_enc_bwd_fill<64, FD>), fg, dim3(256), lds_f, sd, ep); break;
+        default: hipLaunchKernelGGL((k_enc_bwd_fill<128, FD>), fg, dim3(256), lds_f, sd, ep); break;
     }
     hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, total, parts);
     const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
-    hipLaunchKernelGGL(k_enc_bwd_reduce, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, total, parts);
+    hipLaunchKernelGGL(k_enc_bwd_reduce<FD>, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, total, parts);
+}
+
+static void table_grad_round(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
+    if (m->desc.feat_dim == 3) table_grad_round_fd<3>(m, ep, c0, n, sd);
+    else table_grad_round_fd<2>(m, ep, c0, n, sd);
 }
 
 // Backward from m->dz.  enc_stored: the forward's encoding [B][E], or null to recompute it
@@ -1293,14 +1390,14 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
         const int ds = out ? 16 : hw;
         if (rc) break;
         if (i > 0) {
-            rc = weight_grad(m, i, d, ds, ds, m->acts + (size_t)(i - 1) * B * hw, B, cus, st);
+            rc = weight_grad(m, i, d, ds, ds, m->acts + (size_t)(i - 1) * B * hw, B, cus, precision, st);
         } else if (enc_stored) {
-            rc = weight_grad(m, 0, d, ds, ds, enc_stored, B, cus, st);
+            rc = weight_grad(m, 0, d, ds, ds, enc_stored, B, cus, precision, st);
         } else {
             for (int64_t c0 = 0; c0 < B && !rc; c0 += m->bwd_chunk) {
                 const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
                 if (!(rc = encode_pairs_launch(m, x0 + c0, x1 + c0, n, B, precision, m->enc, st)))
-                    rc = weight_grad(m, 0, d + (size_t)c0 * ds, ds, ds, m->enc, n, cus, st);
+                    rc = weight_grad(m, 0, d + (size_t)c0 * ds, ds, ds, m->enc, n, cus, precision, st);
             }
         }
     }
@@ -1393,11 +1490,11 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
             const float* d = out ? dz_c : delta_c + (size_t)i * n * hw;
             const int ds = out ? 16 : hw;
             if (i > 0) {
-                r = weight_grad(m, i, d, ds, ds, acts_c + (size_t)(i - 1) * n * hw, n, cus, st);
+                r = weight_grad(m, i, d, ds, ds, acts_c + (size_t)(i - 1) * n * hw, n, cus, prec, st);
             } else if (enc_c) {
-                r = weight_grad(m, 0, d, ds, ds, enc_c, n, cus, st);
+                r = weight_grad(m, 0, d, ds, ds, enc_c, n, cus, prec, st);
             } else if (!(r = encode_pairs_launch(m, b->x0 + c0, b->x1 + c0, n, B, prec, m->enc, st))) {
-                r = weight_grad(m, 0, d, ds, ds, m->enc, n, cus, st);
+                r = weight_grad(m, 0, d, ds, ds, m->enc, n, cus, prec, st);
             }
         }
         return r;

@@ -10,7 +10,8 @@ entries and BF16/FP16-rounded weights widened without error).  The GPU's element
              |d enc| <= (6 N_l 2^-33 + 11 u32) max|table of level l| (the two features of one
              sample and level share their weights: their errors are taken as correlated).
   operands   every MFMA operand that is not a stored weight -- the input of each layer in the
-             forward; d heads and each delta in the backward's chain -- is rounded to the MLP
+             forward; d heads and each delta in the backward's chain; both factors of the
+             weight gradients -- is rounded to the MLP
              precision: |d x| <= u |x| + eta, u = 2^-8 (BF16), 2^-11 (FP16), 0 (FP32), eta =
              half the smallest subnormal spacing.  A bias added from a copy of another
              precision than the oracle's: u |b|.
@@ -186,6 +187,8 @@ def backward(orc, desc, tables, prm, fw, x0, x1, dz, Cdz, prec, scale=1.0, W0_gp
             # G_j = sum_b d a^T: (|a| sigma_d + |d| sigma_a)^2 per sample (Cauchy-Schwarz over
             # the correlation of the two factors); samples add
             vG[j] += (sd ** 2).T @ a ** 2 + 2.0 * (sd * ad).T @ (aa * sa) + (ad ** 2).T @ sa ** 2
+            # BF16/FP16: the weight-gradient MFMA takes both factors rounded to that precision
+            vG[j] += (((u * ad + eta) ** 2).T @ a ** 2 + (ad ** 2).T @ (u * aa + eta) ** 2) / 3.0
             vb[j] += (sd ** 2).sum(axis=0)
             io = np.arange(W.shape[0])
             Cop = C.copy()

@@ -56,7 +56,18 @@ def test_model_sizes_match_the_canonical_layout(P):
     assert nm == (832 * 128 + 128) + 3 * (128 * 128 + 128) + (128 * 12 + 12)
 
 
-@pytest.mark.parametrize("kw,code", [(dict(feat_dim=3), 1), (dict(levels=6), 1), (dict(log2_table=30), 1),
+def test_three_feature_entries_size_the_paper_configuration(P):
+    """Two levels of three features (the paper's deformation comparison): 2 T 3 table floats,
+    first layer 2 x 7 x 2 x 3 = 84 wide."""
+    nt, nm = P.nif_model_sizes(_desc(P, levels=2, feat_dim=3, log2_table=19, res=[64, 128], pe_freqs=3,
+                                     hidden_width=64, hidden_layers=3, n_materials=4))
+    assert nt == 2 * 2 ** 19 * 3
+    assert nm == (84 * 64 + 64) + 2 * (64 * 64 + 64) + (64 * 12 + 12)
+
+
+@pytest.mark.parametrize("kw,code", [(dict(feat_dim=4), 1), (dict(feat_dim=3, levels=3, res=[16] * 3), 1),
+                                     (dict(feat_dim=3, concat_encoding=1), 1), (dict(levels=6), 1),
+                                     (dict(levels=2, res=[16, 32]), 1), (dict(log2_table=30), 1),
                                      (dict(hidden_width=48), 2), (dict(hidden_layers=0), 1),
                                      (dict(n_materials=0), 1), (dict(table_dtype=7), 1),
                                      (dict(res=[0] * 8), 1), (dict(pe_freqs=-1), 1), (dict(dist_head=2), 1),

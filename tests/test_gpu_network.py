@@ -30,6 +30,11 @@ MODELS = {
                                       concat_encoding=1),
     "w32_per_sample": dataclasses.replace(S.workload("spheres64").model, hidden_width=32, hidden_layers=2,
                                           pe_freqs=2, log2_table=16, per_sample_tables=1),
+    "paper32": S.workload("spheres32_paper").model,
+    "paper32_f32_per_sample": dataclasses.replace(S.workload("spheres32_paper").model, table_dtype=S.TABLE_F32,
+                                                  log2_table=16, per_sample_tables=1),
+    "fd3_l8_w128": dataclasses.replace(S.workload("spheres32_paper").model, levels=8,
+                                       res=S.level_resolutions(8, 16, 512), hidden_width=128),
 }
 
 
@@ -44,7 +49,8 @@ def _points(n, seed):
     return x0, x1
 
 
-@pytest.mark.parametrize("name", ["torus16", "spheres64", "torus16_per_sample", "w32_per_sample", "torus16_concat"])
+@pytest.mark.parametrize("name", ["torus16", "spheres64", "torus16_per_sample", "w32_per_sample", "torus16_concat",
+                                  "paper32", "paper32_f32_per_sample", "fd3_l8_w128"])
 def test_encoding_matches_oracle(orc, P, name):
     m = MODELS[name]
     say(f"encode {name}")
@@ -114,7 +120,7 @@ def test_fp32_heads_at_the_training_batch_size_sampled(orc, P):
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("name", ["spheres64_p", "spheres64", "w32_concat", "torus16"])
+@pytest.mark.parametrize("name", ["spheres64_p", "spheres64", "w32_concat", "torus16", "paper32"])
 def test_low_precision_heads_error_per_head(orc, P, name, prec):
     """BF16 / FP16 heads against the oracle on the same rounded weights: per-head relative error
     reported, every head within 7 sigma of the first-order rounding-error model."""

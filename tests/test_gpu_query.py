@@ -521,3 +521,44 @@ def test_query_low_precision_end_to_end(orc, P, prec):
                               {k: v[sl] for k, v in got.items()}, prec)
         start += counts[p]
     assert total > 1500
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
+def test_query_paper_configuration(orc, P, prec):
+    """The configuration of the paper's comparison of deformation results (the sphere scene at
+    32^3, two grid levels of three features each, F = 3) under its three poses in one launch:
+    sampled camera rays of every pose against the oracle (BF16 on the same rounded weights)."""
+    import torch
+    w = S.workload("spheres32_paper")
+    m = w.model
+    occ = orc.voxelize(w.scene_kind, S.scene_of(w), w.N)
+    tab, prm, seen = model_params(m, w.seed + 100, scale_tables=1e3)
+    model = P.Model(m)
+    model.set_params(tab, prm)
+    kinds, strengths = S.poses(w)
+    grid = P.Grid(torch.as_tensor(occ).cuda(), w.N, kinds, strengths)
+    os_, ds_ = [], []
+    for p in range(len(kinds)):
+        o, d = S.rays_camera(w.cam_res, w.cam_az_deg[p], sub=97)
+        os_.append(o)
+        ds_.append(d)
+    counts = [x.shape[1] for x in os_]
+    say(f"query spheres32_paper prec={prec}, rays {counts}")
+    got = _np(grid.query(model, dev_f32(np.concatenate(os_, axis=1)), dev_f32(np.concatenate(ds_, axis=1)),
+                         offsets(counts), precision=prec))
+    start, n_ok, n_hit = 0, 0, 0
+    for p in range(len(kinds)):
+        sl = slice(start, start + counts[p])
+        say(f"  pose {p}: kind {kinds[p]} s {strengths[p]}")
+        g = {k: v[sl] for k, v in got.items()}
+        if prec == 0:
+            a, b = _compare(orc, P, m, seen, prm, w.N, occ, int(kinds[p]), float(strengths[p]), os_[p], ds_[p], g)
+        else:
+            a, b = _compare_low(orc, m, seen, prm, w.N, occ, int(kinds[p]), float(strengths[p]), os_[p], ds_[p], g,
+                                prec), 0
+        n_ok += a
+        n_hit += b
+        start += counts[p]
+    assert n_ok > 0.9 * sum(counts)
+    if prec == 0:
+        assert n_hit > 300

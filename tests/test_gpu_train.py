@@ -65,6 +65,9 @@ MODELS = {
     "torus16_concat": dataclasses.replace(S.workload("torus16").model, hidden_width=32, concat_encoding=1),
     "spheres64": S.workload("spheres64").model,
     "blobs128": S.workload("blobs128").model,
+    "paper32": S.workload("spheres32_paper").model,
+    "paper32_f32_per_sample": dataclasses.replace(S.workload("spheres32_paper").model, table_dtype=S.TABLE_F32,
+                                                  log2_table=16, per_sample_tables=1, hidden_width=32),
 }
 
 
@@ -123,7 +126,7 @@ def _train_step(P, model, batch, B, prec=0, lr=(1e-2, 1e-3, 1e-3), fixed=False, 
 
 
 @pytest.mark.parametrize("store", [False, True], ids=["recomputed_encoding", "stored_encoding"])
-@pytest.mark.parametrize("name", ["torus16", "blobs128"])
+@pytest.mark.parametrize("name", ["torus16", "blobs128", "paper32"])
 def test_train_step_matches_oracle(orc, P, name, store):
     m = MODELS[name]
     say(f"train step fp32 {name} store_encoding={int(store)}")
@@ -416,3 +419,108 @@ def test_backward_over_several_chunks_is_additive(P, B):
         nrm = np.linalg.norm(full - acc) / np.linalg.norm(full)
         say(f"  {name}: relative difference {nrm:.2e}")
         assert np.linalg.norm(full) > 0 and nrm <= 1e-5, name
+
+
+def test_autograd_wrappers_compose_to_the_oracle_gradient(orc, P):
+    """NifField (heads with the hand-written backward) composed with NifMultiTaskLoss under
+    torch.autograd: the table and MLP gradients equal the oracle's gradient of the same loss to
+    the whole step's bar (the composition is the step's forward, loss and backward), d s to
+    1e-5; d x0 / d x1 equal the oracle's norm-wise and, element by element, the C-ABI backward
+    fed the same d heads (the wrapper adds only plumbing; the two differ in the order of FP32
+    atomic additions)."""
+    import torch
+    m = MODELS["blobs128"]
+    tab, prm, seen = model_params(m, 51, scale_tables=300.0)
+    B = 1500 + 13
+    batch = _batch(m, B, 52)
+    x0, x1, hit, t, nr, al, mt = batch
+    s = np.array([0.1, -0.3, 0.2, 0.0, 0.4])
+    say(f"autograd composition B={B}")
+    L, gt, gp, gs, gx0, gx1 = orc.loss_grad(m, seen, prm.astype(np.float64), s, x0.T, x1.T, hit, t, nr.T, al.T, mt,
+                                            want_x=True)
+    sig_t, sig_p = _step_model(orc, m, seen, prm, batch, s)
+    model = P.Model(m, max_batch=B)
+    model.set_params(tab, prm)
+    P.nif_model_zero_grads(model.h)
+    X0 = dev_f32(x0).requires_grad_(True)
+    X1 = dev_f32(x1).requires_grad_(True)
+    sv = dev_f32(s).requires_grad_(True)
+    labels = [X0.detach(), X1.detach(), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
+              torch.as_tensor(mt).cuda()]
+    heads = P.NifField.apply(X0, X1, model, P.PREC_FP32)
+    total = P.NifMultiTaskLoss.apply(heads, sv, model, labels)
+    total.backward()
+    g_t, g_p, _ = model.get_grads()
+    # the C-ABI backward of the same d heads, on a second model
+    d_heads = torch.empty_like(heads)
+    d_s = torch.empty(5, device="cuda")
+    P.nif_loss(model.h, heads.detach(), B, P.Batch(*[k.data_ptr() for k in labels]), sv.detach(), False,
+               torch.empty(6, device="cuda"), d_heads, d_s)
+    direct = P.Model(m, max_batch=B)
+    direct.set_params(tab, prm)
+    dx0 = torch.empty((3, B), device="cuda")
+    dx1 = torch.empty((3, B), device="cuda")
+    P.nif_backward(direct.h, X0.detach(), X1.detach(), B, d_heads, dx0, dx1, False, P.PREC_FP32)
+    torch.cuda.synchronize()
+    assert abs(total.item() - L[5]) <= 1e-5 * abs(L[5])
+    _grad_close(g_t.cpu().numpy(), gt, "tables", sigma=sig_t)
+    _grad_close(g_p.cpu().numpy(), gp, "mlp", sigma=sig_p)
+    assert np.abs(sv.grad.cpu().numpy() - gs).max() <= 1e-5 * np.abs(gs).max()
+    for name, got, ref, dref in (("d x0", X0.grad, gx0, dx0), ("d x1", X1.grad, gx1, dx1)):
+        got = got.cpu().numpy().astype(np.float64)
+        nrm = np.linalg.norm(got.T - ref) / np.linalg.norm(ref)
+        say(f"  {name}  norm-wise vs oracle {nrm:.2e}")
+        assert nrm <= 1e-4, name
+        dref = dref.cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, dref, rtol=1e-5, atol=1e-6 * np.abs(dref).max(), err_msg=name)
+    # a batch larger than the reservation is refused (the backward allocates nothing)
+    small = P.Model(m, max_batch=64)
+    small.set_params(tab, prm)
+    h2 = P.NifField.apply(X0, X1, small, P.PREC_FP32)
+    with pytest.raises(P.NifError):
+        h2.sum().backward()
+
+
+@pytest.mark.parametrize("B", [4096 + 7, (1 << 16) + 4099], ids=["one_chunk", "two_chunks"])
+def test_train_step_captured_in_a_graph_replays_like_eager(P, B):
+    """nif_train_step captured in a hipGraph (with its side-stream fork and join) and replayed
+    three times, with eager work between the replays: every replay's losses and gradients
+    equal an eager step's (learning rates 0, so each step sees the same parameters; losses and
+    gradients to 1e-6, the order of their FP32 sums)."""
+    import torch
+    m = MODELS["blobs128"]
+    tab, prm, _ = model_params(m, 61, scale_tables=300.0)
+    batch = _batch(m, B, 62)
+    x0, x1, hit, t, nr, al, mt = batch
+    keep = [dev_f32(x0), dev_f32(x1), torch.as_tensor(hit).cuda(), dev_f32(t), dev_f32(nr), dev_f32(al),
+            torch.as_tensor(mt).cuda()]
+    b = P.Batch(*[k.data_ptr() for k in keep])
+    cfg = P.TrainCfg(0.0, 0.0, 0.0, 0.9, 0.999, 1e-8, P.PREC_BF16, 0.0, 0, 0)
+    model = P.Model(m, max_batch=B)
+    model.set_params(tab, prm)
+    say(f"train step graph capture B={B}")
+    losses = torch.zeros(16, device="cuda")
+    P.nif_train_step(model.h, b, B, cfg, losses)
+    torch.cuda.synchronize()
+    ref_l = losses.cpu().numpy().copy()
+    ref_g = [g.cpu().numpy().astype(np.float64) for g in model.get_grads()]
+    s_cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    cap_losses = torch.zeros(16, device="cuda")
+    with torch.cuda.graph(g, stream=s_cap):
+        P.nif_train_step(model.h, b, B, cfg, cap_losses, stream=s_cap)
+    other = torch.zeros(16, device="cuda")
+    for rep in range(3):
+        cap_losses.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        got_l = cap_losses.cpu().numpy()
+        np.testing.assert_allclose(got_l[:6], ref_l[:6], rtol=1e-6)
+        assert got_l[12] == 0 and got_l[13] == ref_l[13]
+        for name, a, r in zip(("tables", "mlp", "s"), model.get_grads(), ref_g):
+            a = a.cpu().numpy().astype(np.float64)
+            rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300)
+            assert rel <= 1e-6, f"replay {rep}: {name} gradient differs by {rel:.2e}"
+        P.nif_train_step(model.h, b, B, cfg, other)          # eager work between replays
+        torch.cuda.synchronize()
+    del g
