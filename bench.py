@@ -353,7 +353,10 @@ def head_errors(got, ref):
             "distance_rel_p50_p99": q(rel_t), "normal_deg_p50_p99": q(ang), "albedo_l1_p50_p99": q(alb)}
 
 
-def train_leg(steps=5, B=1 << 18):
+TRAIN_VARIANTS = {"bf16": (1, 0), "fp32": (0, 0), "bf16_stored": (1, 1), "fp32_stored": (0, 1)}
+
+
+def train_leg(steps=5, B=1 << 18, variants=tuple(TRAIN_VARIANTS)):
     """Training step on 2^18 ray-voxel segments of the 128^3 blob scene (fwd + loss + bwd + Adam);
     the segments are traced and labelled on the GPU (nif_trace, nif_label)."""
     import torch
@@ -390,8 +393,10 @@ def train_leg(steps=5, B=1 << 18):
     batch = P.Batch(x0.data_ptr(), x1.data_ptr(), hit.data_ptr(), t.data_ptr(), nrm.data_ptr(), alb.data_ptr(),
                     mat.data_ptr())
     res = {}
-    for store in (0, 1):
-        for prec, name in ((1, "bf16"), (0, "fp32")):
+    for vname in variants:
+        prec, store = TRAIN_VARIANTS[vname]
+        name = vname.split("_")[0]
+        if True:
             model = P.Model(m)
             model.set_params(S.init_tables(m, w.seed + 100), S.init_mlp(m, w.seed + 100))
             P.nif_model_reserve(model.h, B)
@@ -509,6 +514,58 @@ def _train_model(P, m, ds, steps, B, fixed, seed, tag, dist_bias=0.0):
     return model, time.perf_counter() - t0, [float(x) for x in losses[:6].cpu()]
 
 
+def _variant_study(w, variants, steps, B, eval_poses):
+    """Train each (name, model, fixed task weights, training set, distance bias) variant on
+    labelled segments of the workload's scene (2^20 random rays through the rest pose only, or
+    through the rest pose and 31 random twist/bend/taper poses) and measure the first-hit
+    query against labelled ground truth on 4 x 256^2 pinhole rays at the rest pose and at
+    eval_poses (unseen)."""
+    import torch
+
+    import nif_synth as S
+    import paper_2604_24666_amd as P
+
+    sp = S.scene_of(w)
+    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
+    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
+    nr = 1 << 20
+    o, d = [torch.as_tensor(a).cuda() for a in S.rays_random(nr, w.seed + 7)]
+    k_dist, s_dist = S.random_poses(31, w.seed + 8, kinds=(S.TWIST, S.BEND, S.TAPER))
+    k_dist = np.concatenate([[S.IDENTITY], k_dist]).astype(np.int32)
+    s_dist = np.concatenate([[0.0], s_dist]).astype(np.float32)
+    data = {}
+    for name, kinds, strengths in (("rest", [S.IDENTITY], [0.0]), ("poses", k_dist, s_dist)):
+        if not any(v[3] == name for v in variants):
+            continue
+        g = P.Grid(occ, w.N, kinds, strengths)
+        off = torch.as_tensor(np.linspace(0, nr, len(kinds) + 1).astype(np.int64)).cuda()
+        data[name] = _segment_dataset(P, g, o, d, off, w.scene_kind, sp, 16)
+        log(f"{w.name}: {data[name]['x0'].shape[1]} training segments ({name}), "
+            f"hit ratio {float(data[name]['hit'].float().mean()):.3f}")
+        del g
+    views = [S.rays_camera(256, az) for az in (0.0, 90.0, 180.0, 270.0)]
+    eo = torch.as_tensor(np.concatenate([v[0] for v in views], 1)).cuda()
+    ed = torch.as_tensor(np.concatenate([v[1] for v in views], 1)).cuda()
+    ne = eo.shape[1]
+    evals = {}
+    for name, (kinds, strengths) in (("rest", ([S.IDENTITY], [0.0])), ("deformed", eval_poses)):
+        g = P.Grid(occ, w.N, kinds, strengths)
+        reps = len(kinds)
+        o_e, d_e = eo.repeat(1, reps).contiguous(), ed.repeat(1, reps).contiguous()
+        off = torch.as_tensor(np.arange(reps + 1, dtype=np.int64) * ne).cuda()
+        evals[name] = (g, o_e, d_e, off, _ground_truth(P, g, o_e, d_e, off, w.scene_kind, sp))
+    res = {}
+    for vname, m, fixed, dname, db in variants:
+        model, train_s, losses = _train_model(P, m, data[dname], steps, B, fixed, w.seed + 200, vname, dist_bias=db)
+        r = {"train_s": train_s, "final_losses": losses}
+        for ename, (g, o_e, d_e, off, gt) in evals.items():
+            r[ename] = _errors(P, model, g, o_e, d_e, off, gt)
+        log(f"{w.name} {vname}: {r}")
+        res[vname] = r
+        del model
+    return res
+
+
 def ablation_leg(steps=2000, B=1 << 16):
     """Table 1 analogue on a synthetic scene: the original LSNIF (trained on the rest pose only),
     the deformation-aware baseline without the proposed training and encoding changes (F = 0,
@@ -518,61 +575,43 @@ def ablation_leg(steps=2000, B=1 << 16):
     unseen deformed poses."""
     import dataclasses
 
-    import torch
-
     import nif_synth as S
-    import paper_2604_24666_amd as P
 
     w = S.workload("spheres64")
-    sp = S.scene_params(w.scene_kind, w.seed)
-    occ = torch.zeros(w.N ** 3, dtype=torch.uint8, device="cuda")
-    P.nif_voxelize(w.scene_kind, sp, w.N, occ)
     base = w.model
     baseline = dataclasses.replace(base, pe_freqs=0, dist_head=S.DIST_SIGMOID)
-    nr = 1 << 20
-    o, d = [torch.as_tensor(a).cuda() for a in S.rays_random(nr, w.seed + 7)]
-    # training data: rest pose only, and a pose distribution (rest + 31 random poses)
-    k_dist, s_dist = S.random_poses(31, w.seed + 8, kinds=(S.TWIST, S.BEND, S.TAPER))
-    k_dist = np.concatenate([[S.IDENTITY], k_dist]).astype(np.int32)
-    s_dist = np.concatenate([[0.0], s_dist]).astype(np.float32)
-    data = {}
-    for name, kinds, strengths in (("rest", [S.IDENTITY], [0.0]), ("poses", k_dist, s_dist)):
-        g = P.Grid(occ, w.N, kinds, strengths)
-        off = torch.as_tensor(np.linspace(0, nr, len(kinds) + 1).astype(np.int64)).cuda()
-        data[name] = _segment_dataset(P, g, o, d, off, w.scene_kind, sp, 16)
-        log(f"ablation: {data[name]['x0'].shape[1]} training segments ({name}), "
-            f"hit ratio {float(data[name]['hit'].float().mean()):.3f}")
-        del g
-    # evaluation: pinhole views of the rest pose, and of four unseen deformed poses
-    views = [S.rays_camera(256, az) for az in (0.0, 90.0, 180.0, 270.0)]
-    eo = torch.as_tensor(np.concatenate([v[0] for v in views], 1)).cuda()
-    ed = torch.as_tensor(np.concatenate([v[1] for v in views], 1)).cuda()
-    ne = eo.shape[1]
-    evals = {}
-    for name, kinds, strengths in (("rest", [S.IDENTITY], [0.0]),
-                                   ("deformed", [S.TWIST, S.BEND, S.TAPER, S.TWIST], [0.85, 0.65, 0.9, 0.35])):
-        g = P.Grid(occ, w.N, kinds, strengths)
-        reps = len(kinds)
-        o_e, d_e = eo.repeat(1, reps).contiguous(), ed.repeat(1, reps).contiguous()
-        off = torch.as_tensor(np.arange(reps + 1, dtype=np.int64) * ne).cuda()
-        evals[name] = (g, o_e, d_e, off, _ground_truth(P, g, o_e, d_e, off, w.scene_kind, sp))
     bias = 0.5 / w.N           # half a voxel: the ReLU distance head is live from the first step
     variants = (("LSNIF", baseline, True, "rest", 0.0), ("Deformed", baseline, True, "poses", 0.0),
                 ("Proposed", base, False, "poses", bias), ("Proposed (distance bias 0)", base, False, "poses", 0.0))
-    res = {}
-    for vname, m, fixed, dname, db in variants:
-        model, train_s, losses = _train_model(P, m, data[dname], steps, B, fixed, w.seed + 200, vname, dist_bias=db)
-        r = {"train_s": train_s, "final_losses": losses}
-        for ename, (g, o_e, d_e, off, gt) in evals.items():
-            r[ename] = _errors(P, model, g, o_e, d_e, off, gt)
-        log(f"ablation {vname}: {r}")
-        res[vname] = r
-        del model
+    res = _variant_study(w, variants, steps, B, ([S.TWIST, S.BEND, S.TAPER, S.TWIST], [0.85, 0.65, 0.9, 0.35]))
     return {"workload": f"spheres64 scene (8 spheres, 64^3), 16-level 2^19 FP16 grid, MLP 64x3; {steps} Adam steps of "
                         f"B = {B} segments (the proposed head's distance bias at half a voxel, and at 0) "
                         f"drawn from 2^20 random rays through the rest pose (LSNIF) or through the "
                         f"rest pose and 31 random twist/bend/taper poses (Deformed, Proposed); evaluated on 4 x 256^2 "
                         f"pinhole rays at the rest pose and at 4 unseen poses against labelled ground truth",
+            **res}
+
+
+def paper_leg(steps=2000, B=1 << 16):
+    """The paper's comparison of deformation results in its own configuration (32^3 voxels, a
+    two-level grid with base resolution 64 and three features per entry, F = 3): the
+    deformation-aware LSNIF baseline without the proposed changes (F = 0, sigmoid-fraction
+    distance, fixed task weights) against the full model, both trained on the same deformed
+    poses and evaluated on the same rays."""
+    import dataclasses
+
+    import nif_synth as S
+
+    w = S.workload("spheres32_paper")
+    base = w.model
+    baseline = dataclasses.replace(base, pe_freqs=0, dist_head=S.DIST_SIGMOID)
+    variants = (("Deformed LSNIF baseline", baseline, True, "poses", 0.0),
+                ("Full model", base, False, "poses", 0.5 / w.N))
+    res = _variant_study(w, variants, steps, B, (list(S.poses(w)[0]), list(S.poses(w)[1])))
+    return {"workload": f"sphere scene at 32^3, 2-level grid (64, 128) with 3 features per entry, 2^19 FP16 entries, "
+                        f"F = 3, MLP 84-64x3-12; {steps} Adam steps of B = {B} segments from 2^20 random rays through "
+                        f"the rest pose and 31 random twist/bend/taper poses; evaluated on 4 x 256^2 pinhole rays at "
+                        f"the rest pose and under twist, bend and taper at full strength against labelled ground truth",
             **res}
 
 
@@ -759,18 +798,20 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
             "rays": n, **res}
 
 
-def run_legs(legs):
+def run_legs(legs, train_variants=tuple(TRAIN_VARIANTS)):
     res = {}
     if "torus" in legs:
         res["torus16"] = torus_leg()
     if "precision" in legs:
         res["precision_compare"] = precision_leg()
     if "train" in legs:
-        res["train"] = train_leg()
+        res["train"] = train_leg(variants=train_variants)
     if "batched" in legs:
         res["batched"] = batched_leg()
     if "ablation" in legs:
         res["ablation"] = ablation_leg()
+    if "paper" in legs:
+        res["paper"] = paper_leg()
     if "render" in legs:
         res["render"] = render_leg()
     return res
@@ -789,8 +830,10 @@ def main():
                     help="profiling runs: skip the headline query and the CPU baseline, print the legs' JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (scale for HBM byte counters)")
+    ap.add_argument("--train-variants", default=",".join(TRAIN_VARIANTS),
+                    help="training-leg variants: " + ",".join(TRAIN_VARIANTS))
     ap.add_argument("--legs", default="torus,precision,train,batched",
-                    help="extra measurements: torus,precision,train,batched,ablation,render (empty for none)")
+                    help="extra measurements: torus,precision,train,batched,ablation,paper,render (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
@@ -812,7 +855,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.legs_only:
-        res = run_legs([x for x in args.legs.split(",") if x])
+        res = run_legs([x for x in args.legs.split(",") if x], tuple(x for x in args.train_variants.split(",") if x))
         print(json.dumps(res), flush=True)
         return
     log("setup ...")
@@ -890,7 +933,7 @@ def main():
     torch.cuda.empty_cache()
     P.nif_set_query_blocks_per_cu(12)           # the legs below use the default launch shape
     P.nif_set_query_rays_per_wave(0)            # unless they tune their own
-    res.update(run_legs(legs))
+    res.update(run_legs(legs, tuple(x for x in args.train_variants.split(",") if x)))
     if cpu is not None:
         res["cpu_baseline"] = cpu
     print(json.dumps(res), flush=True)

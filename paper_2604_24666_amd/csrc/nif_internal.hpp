@@ -69,8 +69,7 @@ struct nif_model {
     int64_t bwd_chunk = 0;              // samples per encoding-backward round
     int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
-    uint16_t* bwd_key = nullptr;        // table-gradient additions: entry within the bucket
-    float* bwd_val = nullptr;           //                            value per feature (Fd each)
+    float* bwd_val = nullptr;           // table-gradient additions: records (Fd values, entry within the bucket)
     uint32_t* ord_u32 = nullptr;        // batch ordering: keys and indices, 2 x 2 x max_batch
     float* ord_f32 = nullptr;           //   the ordered batch (15 max_batch words)
     void* ord_temp = nullptr;           //   radix-sort scratch

@@ -192,7 +192,7 @@ void model_free(nif_model* m) {
     void* ps[] = {m->tables, m->tables_h, m->mlp, m->mlp_pad_f32, m->mlp_pad_bf16, m->mlp_pad_f16, m->s,
                   m->g_tables, m->g_mlp, m->g_s, m->m_tables, m->v_tables, m->m_mlp, m->v_mlp,
                   m->m_s, m->v_s, m->counters, m->dacc, m->tcount, m->zbuf, m->dz, m->acts, m->delta,
-                  m->enc, m->enc_all, m->bwd_cnt, m->bwd_scan, m->bwd_key, m->bwd_val, m->w0l_f32, m->w0l_bf16, m->w0l_f16,
+                  m->enc, m->enc_all, m->bwd_cnt, m->bwd_scan, m->bwd_val, m->w0l_f32, m->w0l_bf16, m->w0l_f16,
                   m->dw_part, m->ord_u32, m->ord_f32, m->ord_temp};
     for (void* p : ps)
         if (p) (void)hipFree(p);

@@ -79,6 +79,7 @@ struct DwArgs {
 };
 
 constexpr int64_t kDwMinK = 512;
+constexpr int kDwKT = 16;                  // samples per LDS-staged tile of k_dw_tile
 
 // Launch shape of one layer's weight gradient: about two blocks per compute unit, each over at
 // least kDwMinK samples.
@@ -101,19 +102,46 @@ static DwArgs dw_shape(int M_pad, int N, int64_t B, int cus) {
 
 static int64_t dw_part_floats(const DwArgs& A) { return A.n_slots * A.M_pad * ((int64_t)A.N + 1); }
 
+// The LDS-staged form (k_dw_tile) serves layers with 64 or 128 output rows and N % 4 == 0.
+static bool dw_tiled(int M_pad, int N) { return (M_pad == 64 || M_pad == 128) && N % 4 == 0; }
+// Column tiles per block of k_dw_tile: 4 waves per block, 64-row halves across them.
+static int dw_tile_ct(int M_pad) { return M_pad == 128 ? 2 : 4; }
+
+// Launch shape of k_dw_tile: about two blocks per compute unit, each over at least kDwTileMinK
+// samples (the partial slots cost a write and a read of M_pad N floats each).
+constexpr int64_t kDwTileMinK = 256;
+static DwArgs dw_tile_shape(int M_pad, int N, int64_t B, int cus) {
+    DwArgs A;
+    memset(&A, 0, sizeof(A));
+    A.M_pad = M_pad; A.N = N; A.B = B;
+    A.n_cb = (N + 63) / 64;
+    A.ks = 1;
+    const int ct = dw_tile_ct(M_pad), n_cg = (A.n_cb + ct - 1) / ct;
+    const int64_t nch = std::max<int64_t>(1, (2LL * cus + n_cg - 1) / n_cg);
+    A.Kc = std::max<int64_t>(kDwTileMinK, (((B + nch - 1) / nch) + kDwKT - 1) / kDwKT * kDwKT);
+    A.n_slots = (B + A.Kc - 1) / A.Kc;
+    return A;
+}
+
 // Partial-slot floats any batch size can need for one layer: dw_shape never uses more K chunks
 // than its first estimate ceil(2 cus / column groups).
 static int64_t dw_part_floats_max(int M_pad, int N, int cus) {
     const int n_cb = (N + 63) / 64, ks = n_cb >= 4 ? 1 : 4 / n_cb, n_cg = (n_cb + 3) / 4;
     const int64_t nch = std::max<int64_t>(1, (2LL * cus + n_cg - 1) / n_cg);
-    return nch * ks * M_pad * ((int64_t)N + 1);
+    int64_t need = nch * ks * M_pad * ((int64_t)N + 1);
+    if (dw_tiled(M_pad, N)) {             // k_dw_tile: slots <= ceil(2 cus / column groups) + 1
+        const int ct = dw_tile_ct(M_pad), n_cgt = (n_cb + ct - 1) / ct;
+        const int64_t slots = (2LL * cus + n_cgt - 1) / n_cgt + 1;
+        need = std::max(need, slots * M_pad * ((int64_t)N + 1));
+    }
+    return need;
 }
 
 int model_reserve(nif_model* m, int64_t B) {
     if (B <= m->max_batch) return NIF_OK;
     for (float** p : {&m->zbuf, &m->dz, &m->acts, &m->delta, &m->enc, &m->enc_all})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
-    for (void** p : {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val})
+    for (void** p : {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_val})
         if (*p) { (void)hipFree(*p); *p = nullptr; }
     m->max_batch = 0;
     {
@@ -125,11 +153,11 @@ int model_reserve(nif_model* m, int64_t B) {
         const int64_t n_blk = ((chunk + 15) / 16 + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock;
         const int64_t n_add = chunk * 2 * m->S * L * 8;
         const int64_t n_cnt = n_buckets * n_blk;
-        const size_t sz[4] = {sizeof(int32_t) * (size_t)n_cnt,
+        const size_t sz[3] = {sizeof(int32_t) * (size_t)n_cnt,
                               sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 3 + n_buckets),
-                              sizeof(uint16_t) * (size_t)n_add, sizeof(float) * (size_t)m->desc.feat_dim * (size_t)n_add};
-        void** ptr[4] = {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_key, (void**)&m->bwd_val};
-        for (int i = 0; i < 4; ++i)
+                              sizeof(float) * (size_t)(m->desc.feat_dim + 1) * (size_t)n_add};
+        void** ptr[3] = {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_val};
+        for (int i = 0; i < 3; ++i)
             if (hipMalloc(ptr[i], sz[i]) != hipSuccess) {
                 (void)hipGetLastError();
                 return fail(NIF_E_OOM, "encoding-backward buffer allocation failed");
@@ -557,6 +585,148 @@ __global__ void __launch_bounds__(256) k_dw_part(DwArgs A) {
     }
 }
 
+// Weight gradient dW = D^T H of a layer with 64 RW output rows, staged through LDS.  Block
+// (x, y) covers K chunk x and CT 64-column tiles starting at column 64 CT y, with RW x CT waves:
+// wave (rw, ct) owns rows [64 rw, + 64) and columns [64 (CT y + ct), + 64) as 4 x 4 MFMA tiles
+// (tile (a, c): rows 16a + 4q + r, columns 16c + j of the wave's).  The block's threads load
+// each 16-sample tile of D [16][64 RW] and H [16][64 CT] with coalesced float4 loads into
+// registers while the waves multiply the previous tile out of LDS (double buffer, one barrier
+// per tile), so a tile's loads are in flight behind a whole tile of MFMAs and each operand
+// row is fetched once per block.  LDS rows are padded by 4 floats, so the column reads of the
+// four lane quarters (4 rows apart) fall in distinct banks.  Partials (and the bias sums, by
+// the waves of column tile 0) go to slot x; k_dw_sum adds the slots.  Needs N % 4 == 0.
+template <int RW, int CT, int PREC>
+__global__ void __launch_bounds__(64 * RW * CT) __attribute__((amdgpu_waves_per_eu(3))) k_dw_tile(DwArgs A) {
+    constexpr int NT = 64 * RW * CT;
+    constexpr int M = 64 * RW, LDD = M + 4;
+    constexpr int NC = 64 * CT, LDH = NC + 4;
+    constexpr int F4D = kDwKT * M / 4, F4H = kDwKT * NC / 4;
+    constexpr int NLD = (F4D + F4H + NT - 1) / NT;
+    __shared__ float sD[2][kDwKT * LDD];
+    __shared__ float sH[2][kDwKT * LDH];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
+    const int rw = w / CT, ct = w % CT;
+    const int64_t kc0 = (int64_t)blockIdx.x * A.Kc, kc1 = std::min<int64_t>(A.B, kc0 + A.Kc);
+    const int col0 = (int)blockIdx.y * NC;
+    const int cb = (int)blockIdx.y * CT + ct;
+    const bool live = cb < A.n_cb;
+    const int n_tiles = (int)((kc1 - kc0 + kDwKT - 1) / kDwKT);
+    float4 reg[NLD];
+    auto load = [&](int t) {
+        const int64_t kt = kc0 + (int64_t)t * kDwKT;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int idx = tid + i * NT;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (idx < F4D) {
+                const int r = idx / (M / 4), c4 = idx % (M / 4);
+                const int64_t k = kt + r;
+                if (k < kc1) v = *reinterpret_cast<const float4*>(A.d + k * A.dstride + 4 * c4);
+            } else if (idx < F4D + F4H) {
+                const int h = idx - F4D, r = h / (NC / 4), c4 = h % (NC / 4);
+                const int64_t k = kt + r;
+                const int col = col0 + 4 * c4;
+                if (k < kc1 && col < A.N) v = *reinterpret_cast<const float4*>(A.h + k * A.hstride + col);
+            }
+            reg[i] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int idx = tid + i * NT;
+            if (idx < F4D) {
+                const int r = idx / (M / 4), c4 = idx % (M / 4);
+                *reinterpret_cast<float4*>(&sD[buf][r * LDD + 4 * c4]) = reg[i];
+            } else if (idx < F4D + F4H) {
+                const int h = idx - F4D, r = h / (NC / 4), c4 = h % (NC / 4);
+                *reinterpret_cast<float4*>(&sH[buf][r * LDH + 4 * c4]) = reg[i];
+            }
+        }
+    };
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bs[4] = {0.f, 0.f, 0.f, 0.f};
+    const int dc = 64 * rw + j;                // this lane's row within the block's D tile
+    const int hc = 64 * ct + j;                // this lane's column within the block's H tile
+    if (n_tiles > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int t = 0; t < n_tiles; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < n_tiles) load(t + 1);
+        if (live) {
+            const float* D = sD[cur];
+            const float* H = sH[cur];
+            if constexpr (PREC == P_FP32) {
+#pragma unroll
+                for (int st4 = 0; st4 < kDwKT / 4; ++st4) {
+                    const int k = 4 * st4 + q;
+                    float bv[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) bv[c] = H[k * LDH + hc + 16 * c];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const float av = D[k * LDD + dc + 16 * a];
+                        bs[a] += av;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[a][c] = mfma32(av, bv[c], acc[a][c]);
+                    }
+                }
+            } else {
+                static_assert(kDwKT == 16, "one 16x16x16 MFMA step per tile");
+                shortx4 bp[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float* hp = H + 4 * q * LDH + hc + 16 * c;
+                    bp[c] = pack4<PREC>(hp[0], hp[LDH], hp[2 * LDH], hp[3 * LDH]);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const float* dp = D + 4 * q * LDD + dc + 16 * a;
+                    const float d0 = dp[0], d1 = dp[LDD], d2 = dp[2 * LDD], d3 = dp[3 * LDD];
+                    bs[a] += (d0 + d1) + (d2 + d3);
+                    const shortx4 ap = pack4<PREC>(d0, d1, d2, d3);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[a][c] = mfma16<PREC>(ap, bp[c], acc[a][c]);
+                }
+            }
+        }
+        if (t + 1 < n_tiles) store(cur ^ 1);
+        __syncthreads();
+    }
+    if (!live) return;
+    const int64_t slot = blockIdx.x;
+    float* P = A.part + slot * A.M_pad * A.N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 64 * rw + 16 * a + 4 * q + r;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int col = 64 * cb + 16 * c + j;
+                if (col < A.N) P[(int64_t)row * A.N + col] = acc[a][c][r];
+            }
+        }
+    if (cb == 0) {             // bias: sum of D over the chunk, row 64 rw + 16a + j (lanes of one j sum their k)
+        float* pb = A.part + A.n_slots * A.M_pad * A.N + slot * A.M_pad;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            float v = bs[a];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (q == 0) pb[64 * rw + 16 * a + j] = v;
+        }
+    }
+}
+
 // gW[m][n] += sum over slots of part[slot][m][n] (m < M_real), gb[m] likewise.  Block: 64
 // consecutive outputs x kDwSumGroups groups of slots (the groups' sums meet in LDS), so each
 // thread's chain of dependent loads is n_slots / kDwSumGroups long.
@@ -642,12 +812,17 @@ struct EncBwdParams {
     int32_t n_buckets;   // L * NBL
     int32_t n_blk;       // blocks of the chunk grid
     int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
-    uint16_t* key;       // additions: entry within the bucket
-    float* val;          // additions: Fd values each
+    float* val;          // additions: records of Fd values and the entry within the bucket (as bits)
     int64_t cap;         // capacity of key / val
     uint32_t* vmax;      // bits of the largest |value| of the chunk's additions (+inf if not finite)
 };
 
+
+// A table-gradient addition with two features: both values and the entry within the bucket
+// (its bits), written with one 12-byte store.
+struct AddRec3 {
+    float v0, v1, key;
+};
 
 // Sample position, d position / d x and the in-range mask of PE combination c (point-major).
 __device__ __forceinline__ void pe_combo_grad(const float xs[6], int c, int S, double smp[3], float dsdx[3],
@@ -838,12 +1013,12 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
                                 fin = fin && isfinite(v[f]);
                                 a = fmaxf(a, fabsf(v[f]));
                             }
-                            P.key[slot] = (uint16_t)(idx[cc] & kmask);
+                            // one record store: (values, entry within the bucket)
+                            const float kb = __uint_as_float(idx[cc] & kmask);
                             if constexpr (FD == 2) {
-                                reinterpret_cast<float2*>(P.val)[slot] = make_float2(v[0], v[1]);
+                                *reinterpret_cast<AddRec3*>(P.val + (size_t)slot * 3) = AddRec3{v[0], v[1], kb};
                             } else {
-#pragma unroll
-                                for (int f = 0; f < FD; ++f) P.val[(size_t)slot * FD + f] = v[f];
+                                *reinterpret_cast<float4*>(P.val + (size_t)slot * 4) = make_float4(v[0], v[1], v[2], kb);
                             }
                             vmx = fin ? fmaxf(vmx, a) : INFINITY;
                         }
@@ -1029,17 +1204,11 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     const int64_t g0 = start >> 4, g1 = (end + 15) >> 4;      // aligned groups of 16
     for (int64_t g = g0 + threadIdx.x; g < g1; g += 256) {
         const int64_t base = g << 4;
-        uint32_t kw[8];
-        {
-            const uint4 k0 = *reinterpret_cast<const uint4*>(P.key + base);
-            const uint4 k1 = *reinterpret_cast<const uint4*>(P.key + base + 8);
-            kw[0] = k0.x; kw[1] = k0.y; kw[2] = k0.z; kw[3] = k0.w;
-            kw[4] = k1.x; kw[5] = k1.y; kw[6] = k1.z; kw[7] = k1.w;
-        }
-        float vv[16 * FD];
+        constexpr int RS = FD + 1;                            // floats per record
+        float vv[16 * RS];
 #pragma unroll
-        for (int r = 0; r < 4 * FD; ++r) {
-            const float4 t = *reinterpret_cast<const float4*>(P.val + base * FD + 4 * r);
+        for (int r = 0; r < 4 * RS; ++r) {
+            const float4 t = *reinterpret_cast<const float4*>(P.val + base * RS + 4 * r);
             vv[4 * r] = t.x; vv[4 * r + 1] = t.y; vv[4 * r + 2] = t.z; vv[4 * r + 3] = t.w;
         }
         uint32_t cur = 0xffffffffu;
@@ -1057,15 +1226,15 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t k = base + r;
-            const uint32_t key = (k >= start && k < end) ? ((kw[r >> 1] >> (16 * (r & 1))) & 0xffffu) : 0xffffffffu;
+            const uint32_t key = (k >= start && k < end) ? __float_as_uint(vv[RS * r + FD]) : 0xffffffffu;
             if (key != cur) {
                 flush();
                 cur = key;
 #pragma unroll
-                for (int f = 0; f < FD; ++f) rs[f] = vv[FD * r + f];
+                for (int f = 0; f < FD; ++f) rs[f] = vv[RS * r + f];
             } else {
 #pragma unroll
-                for (int f = 0; f < FD; ++f) rs[f] += vv[FD * r + f];
+                for (int f = 0; f < FD; ++f) rs[f] += vv[RS * r + f];
             }
         }
         flush();
@@ -1267,9 +1436,35 @@ static void launch_dw_part(const DwArgs& A, dim3 grid, hipStream_t st) {
 
 // Weight gradient of one layer; with BF16/FP16 MLP arithmetic its operands are rounded to that
 // precision as in the forward and the MLP backward (FP32 accumulation either way).
+template <int PREC>
+static void launch_dw_tile(const DwArgs& A, dim3 grid, hipStream_t st) {
+    if (A.M_pad == 128) hipLaunchKernelGGL((k_dw_tile<2, 2, PREC>), grid, dim3(256), 0, st, A);
+    else hipLaunchKernelGGL((k_dw_tile<1, 4, PREC>), grid, dim3(256), 0, st, A);
+}
+
 static int weight_grad(nif_model* m, int layer, const float* d, int dstride, int M_pad, const float* h, int64_t B,
                        int cus, int32_t precision, hipStream_t st) {
-    DwArgs A = dw_shape(M_pad, m->dims[layer], B, cus);
+    const int N = m->dims[layer];
+    if (dw_tiled(M_pad, N) && dstride % 4 == 0) {
+        DwArgs A = dw_tile_shape(M_pad, N, B, cus);
+        A.d = d;
+        A.dstride = dstride;
+        A.M_real = m->dims[layer + 1];
+        A.h = h;
+        A.hstride = N;
+        A.part = m->dw_part;
+        if (dw_part_floats(A) > m->dw_part_n) return fail(NIF_E_STATE, "weight-gradient scratch too small");
+        const int ct = dw_tile_ct(M_pad);
+        const dim3 grid((unsigned)A.n_slots, (unsigned)((A.n_cb + ct - 1) / ct));
+        if (precision == NIF_PREC_BF16) launch_dw_tile<P_BF16>(A, grid, st);
+        else if (precision == NIF_PREC_FP16) launch_dw_tile<P_FP16>(A, grid, st);
+        else launch_dw_tile<P_FP32>(A, grid, st);
+        const int64_t n_out = (int64_t)A.M_real * A.N + A.M_real;
+        hipLaunchKernelGGL(k_dw_sum, dim3((unsigned)((n_out + 63) / 64)), dim3(64 * kDwSumGroups), 0, st, A,
+                           m->g_mlp + m->w_off[layer], A.N, m->g_mlp + m->b_off[layer]);
+        return NIF_OK;
+    }
+    DwArgs A = dw_shape(M_pad, N, B, cus);
     A.d = d;
     A.dstride = dstride;
     A.M_real = m->dims[layer + 1];
@@ -1305,7 +1500,7 @@ static EncBwdParams table_grad_params(nif_model* m, const float* x0, const float
     ep.NBL = 1 << (log2T - ep.SB);
     const int n_sets = m->desc.per_sample_tables ? m->S : 1;
     ep.n_buckets = m->desc.levels * n_sets * ep.NBL;
-    ep.cnt = m->bwd_cnt; ep.key = m->bwd_key; ep.val = m->bwd_val;
+    ep.cnt = m->bwd_cnt; ep.val = m->bwd_val;
     ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
     ep.vmax = nullptr;
     return ep;
