@@ -37,12 +37,17 @@ def _pe(x, F):
     return np.stack(out, axis=1)                       # [n][S][3]
 
 
-def test_dense_levels_reproduce_linear_fields_through_every_pe_sample(orc):
+@pytest.mark.parametrize("fd", [2, 3], ids=["8_levels_2_features", "2_levels_3_features"])
+def test_dense_levels_reproduce_linear_fields_through_every_pe_sample(orc, fd):
     """Trilinear interpolation has linear precision: with table entries linear in the vertex
     coordinates the encoding equals that linear function at pos = sample * N_l, for every
     sample of gamma, every dense level and every feature (pins Eq. (1)'s samples, the
-    [0,1] mapping, the level resolutions and the output order)."""
-    m = _small_model(res=[3, 5, 7, 9, 11, 13, 15, 17], log2_table=14)
+    [0,1] mapping, the level resolutions and the output order (point, sample, level, feature),
+    with two features per entry and with the paper's comparison configuration's three)."""
+    if fd == 2:
+        m = _small_model(res=[3, 5, 7, 9, 11, 13, 15, 17], log2_table=14)
+    else:
+        m = _small_model(levels=2, feat_dim=3, res=[5, 9], log2_table=14, pe_freqs=3)
     rng = np.random.default_rng(0)
     coef = rng.normal(size=(m.levels, m.feat_dim, 3))
     const = rng.normal(size=(m.levels, m.feat_dim))
@@ -134,14 +139,15 @@ def test_points_are_clamped_to_the_unit_cube(orc):
     assert np.array_equal(orc.encode(m, tab, x), orc.encode(m, tab, np.clip(x, 0, 1)))
 
 
-def test_partition_of_unity_on_all_levels(orc):
-    m = S.workload("spheres64").model
+@pytest.mark.parametrize("name", ["spheres64", "spheres32_paper"])
+def test_partition_of_unity_on_all_levels(orc, name):
+    m = S.workload(name).model
+    const = np.array([0.25, -3.0, 7.5])[:m.feat_dim]
     tab = np.empty((m.levels, m.table_size, m.feat_dim))
-    tab[:, :, 0] = 0.25
-    tab[:, :, 1] = -3.0
+    tab[:, :, :] = const
     x = np.random.default_rng(3).uniform(0, 1, size=(16, 3))
-    enc = orc.encode(m, tab, x).reshape(16, -1, 2)
-    assert np.abs(enc[..., 0] - 0.25).max() < 1e-14 and np.abs(enc[..., 1] + 3).max() < 1e-14
+    enc = orc.encode(m, tab, x).reshape(16, -1, m.feat_dim)
+    assert np.abs(enc - const).max() < 1e-13
 
 
 def test_hashed_level_reads_the_instant_ngp_hash_entry_at_a_vertex(orc):
@@ -167,12 +173,15 @@ def test_hashed_level_reads_the_instant_ngp_hash_entry_at_a_vertex(orc):
         assert exact.sum() >= 1
 
 
-@pytest.mark.parametrize("per_sample", [0, 1])
-def test_encoding_adjoint_is_the_transpose_of_the_encoding(orc, per_sample):
+@pytest.mark.parametrize("per_sample,fd", [(0, 2), (1, 2), (0, 3), (1, 3)])
+def test_encoding_adjoint_is_the_transpose_of_the_encoding(orc, per_sample, fd):
     """psi is linear in the tables, psi(x; t) = J(x) t, so <v, psi(x; t)> = <J^T v, t> for any
     tables t and any v: the adjoint scatter agrees with the encoding itself, on dense and
     hashed levels; and J^T |v| >= |J^T v| (trilinear weights are nonnegative)."""
-    m = _small_model(log2_table=12, per_sample_tables=per_sample)
+    if fd == 2:
+        m = _small_model(log2_table=12, per_sample_tables=per_sample)
+    else:
+        m = _small_model(levels=2, feat_dim=3, res=[12, 24], log2_table=12, pe_freqs=3, per_sample_tables=per_sample)
     rng = np.random.default_rng(3)
     x = rng.uniform(-0.05, 1.05, (200, 3))
     W = m.n_samples * m.levels * m.feat_dim
@@ -383,11 +392,15 @@ def test_uncertainty_weights_are_stationary_at_log_loss(orc):
                                                                    (4, S.DIST_LOG_RELU, False, 0),
                                                                    (4, S.DIST_SIGMOID, True, 0),
                                                                    (4, S.DIST_LOG_RELU, False, 1),
-                                                                   (4, S.DIST_LOG_RELU, False, 2)])
+                                                                   (4, S.DIST_LOG_RELU, False, 2),
+                                                                   (4, S.DIST_LOG_RELU, False, 3)])
 def test_gradient_matches_central_finite_differences(orc, n_materials, dist_head, fixed, per_sample):
-    """per_sample 2: the concatenated [gamma, phi] encoding (one table set)."""
+    """per_sample 2: the concatenated [gamma, phi] encoding (one table set); 3: two levels of
+    three features with F = 3 (the paper's comparison configuration, small tables)."""
     m = _small_model(n_materials=n_materials, dist_head=dist_head, per_sample_tables=int(per_sample == 1),
                      concat_encoding=int(per_sample == 2))
+    if per_sample == 3:
+        m = dataclasses.replace(m, levels=2, feat_dim=3, res=[16, 40], pe_freqs=3)
     tab, prm, x0, x1, hit, t, nr, al, mt = _batch(m, 20, 62 + n_materials)
     s = np.array([0.1, -0.2, 0.3, 0.0, 0.5])
     L, gt, gp, gs, gx0, gx1 = orc.loss_grad(m, tab, prm, s, x0, x1, hit, t, nr, al, mt, want_x=True,
