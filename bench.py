@@ -42,9 +42,9 @@ KQUERY_SOURCES = ["paper_2604_24666_amd/csrc/nif_query.hip", "paper_2604_24666_a
                   "paper_2604_24666_amd/csrc/nif_internal.hpp", "paper_2604_24666_amd/build.py",
                   "nif_synth/__init__.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "b286b7fce0494ffa057e3eef33670a4f50461d815f806bc014d2e0e13db76b4a",
-    "fetch_kib": 1.04882e8, "write_kib": 1.94201e6,         # per k_query<64, FP32, 64> launch, default workload
-    "fetch_scale": 1048576 / 524302, "write_scale": 1048576 / 1048576,   # 1 GiB copy reads 524,302 / writes 1,048,576 KiB
+    "sources_sha256": "40cb194647c7519b32051652efb9c2c060bff0b0d3af2cca434245ab46fae5c6",
+    "fetch_kib": 1.04827e8, "write_kib": 1.93983e6,         # per k_query<64, FP32, 64> launch, default workload
+    "fetch_scale": 1048576 / 524303, "write_scale": 1048576 / 1048577,   # 1 GiB copy reads 524,303 / writes 1,048,577 KiB
 }
 
 
