@@ -813,6 +813,7 @@ struct EncBwdParams {
     int32_t n_blk;       // blocks of the chunk grid
     int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
     float* val;          // additions: records of Fd values and the entry within the bucket (as bits)
+    int32_t w_lds;       // fill: the block's first-layer weight rows staged in LDS
     int64_t cap;         // capacity of key / val
     uint32_t* vmax;      // bits of the largest |value| of the chunk's additions (+inf if not finite)
 };
@@ -875,6 +876,10 @@ __device__ __forceinline__ bool tile_sample(const EncBwdParams& P, int64_t tile,
     }
     return valid;
 }
+
+// Largest dynamic LDS of a fill block that stages its first-layer rows (else they are read from
+// memory for every tile).
+constexpr size_t kFillLdsMax = 60 * 1024;
 
 // Levels per block row of the count and fill passes: two with two features per entry (the
 // four (level, feature) rows of a PE combination), one with three.
@@ -946,6 +951,20 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     const uint32_t kmask = (1u << P.SB) - 1u;
     const int nloc = LG * P.NBL * n_table_sets(P);
     for (int i = tid; i < nloc; i += 256) s_cur[i] = P.cnt[group_bucket_global<LG>(P, lp, i) * P.n_blk + blockIdx.x];
+    // The W0 rows this block multiplies (combination c, (level, feature) r of its group: row
+    // 4c + r, zero where r >= LG FD), staged once in LDS with rows padded by 4 floats, so the
+    // MFMA's A operand is read from LDS rather than fetched again for every tile.
+    constexpr int LDW = HW + 4;
+    float* s_w = reinterpret_cast<float*>(s_cur + ((nloc + 3) & ~3));
+    if (P.w_lds) {
+        for (int i = tid; i < 4 * n_comb * (HW / 4); i += 256) {
+            const int r = i / (HW / 4), c4 = i % (HW / 4);
+            const int ca = r >> 2, fr = r & 3;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (fr < LG * FD) v = *reinterpret_cast<const float4*>(P.W0t + ((size_t)(ca * L + lp) * FD + fr) * HW + 4 * c4);
+            *reinterpret_cast<float4*>(s_w + r * LDW + 4 * c4) = v;
+        }
+    }
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
     const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
@@ -977,7 +996,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
             {
                 const int l0 = lp;
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                const float* wrow = P.W0t + (size_t)(a_live ? (ca * L + l0) * FD + (j & 3) : 0) * HW + q * KQ;
+                const float* wrow = P.w_lds ? s_w + (size_t)(a_live ? 4 * ca + (j & 3) : 0) * LDW + q * KQ
+                                            : P.W0t + (size_t)(a_live ? (ca * L + l0) * FD + (j & 3) : 0) * HW + q * KQ;
 #pragma unroll
                 for (int t = 0; t < KQ; t += 4) {
                     float4 av = *reinterpret_cast<const float4*>(wrow + t);
@@ -1530,11 +1550,17 @@ static void table_grad_round_fd(nif_model* m, EncBwdParams ep, int64_t c0, int64
     hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, total);
     hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
+    // the fill's staged first-layer rows: 4 per PE combination, hw + 4 floats each (up to 60 KiB)
+    const int nloc = LG * ep.NBL * n_sets;
+    const size_t w_bytes = sizeof(float) * 4 * (size_t)(2 * m->S) * (size_t)(hw + 4);
+    const size_t cur_bytes = sizeof(int32_t) * (size_t)((nloc + 3) & ~3);
+    ep.w_lds = cur_bytes + w_bytes <= kFillLdsMax ? 1 : 0;
+    const size_t lds_fill = ep.w_lds ? cur_bytes + w_bytes : lds_f;
     switch (hw) {
-        case 16: hipLaunchKernelGGL((k_enc_bwd_fill<16, FD>), fg, dim3(256), lds_f, sd, ep); break;
-        case 32: hipLaunchKernelGGL((k_enc_bwd_fill<32, FD>), fg, dim3(256), lds_f, sd, ep); break;
-        case 64: hipLaunchKernelGGL((k_enc_bwd_fill<64, FD>), fg, dim3(256), lds_f, sd, ep); break;
-        default: hipLaunchKernelGGL((k_enc_bwd_fill<128, FD>), fg, dim3(256), lds_f, sd, ep); break;
+        case 16: hipLaunchKernelGGL((k_enc_bwd_fill<16, FD>), fg, dim3(256), lds_fill, sd, ep); break;
+        case 32: hipLaunchKernelGGL((k_enc_bwd_fill<32, FD>), fg, dim3(256), lds_fill, sd, ep); break;
+        case 64: hipLaunchKernelGGL((k_enc_bwd_fill<64, FD>), fg, dim3(256), lds_fill, sd, ep); break;
+        default: hipLaunchKernelGGL((k_enc_bwd_fill<128, FD>), fg, dim3(256), lds_fill, sd, ep); break;
     }
     hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, total, parts);
     const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
