@@ -159,11 +159,7 @@ int nif_model_get_grads(const nif_model* m, float* gt, float* gm, float* gs, nif
 
 int nif_model_zero_grads(nif_model* m, nif_stream stream) {
     REQUIRE(m, "model is null");
-    hipStream_t st = S(stream);
-    int rc;
-    if ((rc = nif::check_hip(hipMemsetAsync(m->g_tables, 0, sizeof(float) * m->n_table, st), "zero grads"))) return rc;
-    if ((rc = nif::check_hip(hipMemsetAsync(m->g_mlp, 0, sizeof(float) * m->n_mlp, st), "zero grads"))) return rc;
-    return nif::check_hip(hipMemsetAsync(m->g_s, 0, sizeof(float) * 8, st), "zero grads");
+    return nif::zero_grads_launch(m, S(stream));
 }
 
 int nif_model_reserve(nif_model* m, int64_t max_batch) {

@@ -1634,6 +1634,14 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     return check_hip(hipGetLastError(), "backward launch");
 }
 
+// Zero the gradient accumulators with kernels (no memset nodes when the caller captures a graph).
+int zero_grads_launch(nif_model* m, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_table)), dim3(256), 0, st, m->g_tables, m->n_table);
+    hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(m->n_mlp)), dim3(256), 0, st, m->g_mlp, m->n_mlp);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, st, m->g_s, (int64_t)8);
+    return check_hip(hipGetLastError(), "zero grads");
+}
+
 int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh, int32_t, float* dx0,
                     float* dx1, int32_t precision, hipStream_t st) {
     if (B == 0) return NIF_OK;

@@ -11,7 +11,8 @@ and the gradients, whose d heads the step forms from its own heads: the loss's s
 derivative over the heads' error interval is added).  Every element must lie within its
 bound; the norm-wise error and the worst |error| / bound are reported.
 
-Model: the training workload's network (MLP 832-128x4-12, 16-level 2^19 FP16 grid), tables
+Models: the training workload's network (MLP 832-128x4-12, 16-level 2^19 FP16 grid) and the
+paper's comparison configuration (two levels of three features, F = 3, MLP 84-64x3-12); tables
 U(+-0.03), the distance head's bias at half a voxel so that its ReLU is live."""
 import numpy as np
 import pytest
@@ -22,7 +23,7 @@ from _helpers import dev_f32, model_params, quantized_mlp, say
 
 pytestmark = pytest.mark.gpu
 
-MODEL = S.workload("blobs128").model
+MODELS = {"blobs128": S.workload("blobs128").model, "paper32": S.workload("spheres32_paper").model}
 PRECS = [(1, "bf16"), (2, "fp16"), (0, "fp32")]
 HEADS = {"hit": [0], "dist": [1], "normal": [2, 3, 4], "albedo": [5, 6, 7], "material": [8, 9, 10, 11]}
 
@@ -33,8 +34,8 @@ def P():
     return P
 
 
-def _setup(seed, prec):
-    m = MODEL
+def _setup(seed, prec, name="blobs128"):
+    m = MODELS[name]
     tab, prm, seen = model_params(m, seed, scale_tables=300.0)
     prm[m.n_mlp_params - m.n_heads + 1] = 0.004
     return m, tab, prm, seen, quantized_mlp(prm, prec)
@@ -58,9 +59,10 @@ def _batch(m, B, seed):
     return x0, x1, hit, t, nr, al, mt
 
 
+@pytest.mark.parametrize("name", list(MODELS))
 @pytest.mark.parametrize("prec,pname", PRECS)
-def test_heads_within_the_derived_bound(orc, P, prec, pname):
-    m, tab, prm, seen, q = _setup(61, prec)
+def test_heads_within_the_derived_bound(orc, P, prec, pname, name):
+    m, tab, prm, seen, q = _setup(61, prec, name)
     B = 3000 + 17
     x0, x1, *_ = _batch(m, B, 62)
     say(f"heads {pname}: B={B}")
@@ -78,10 +80,11 @@ def test_heads_within_the_derived_bound(orc, P, prec, pname):
     BD.check(got, ref, fw["sz"], "heads", say)
 
 
+@pytest.mark.parametrize("name", list(MODELS))
 @pytest.mark.parametrize("prec,pname", PRECS)
-def test_backward_within_the_derived_bound(orc, P, prec, pname):
+def test_backward_within_the_derived_bound(orc, P, prec, pname, name):
     import torch
-    m, tab, prm, seen, q = _setup(71, prec)
+    m, tab, prm, seen, q = _setup(71, prec, name)
     B = 2048 + 37
     x0, x1, hit, t, nr, al, mt = _batch(m, B, 72)
     s = np.array([0.2, -0.1, 0.3, 0.1, -0.2])
@@ -108,10 +111,11 @@ def test_backward_within_the_derived_bound(orc, P, prec, pname):
              max_frac=BD.TABLE_FLIP_FRAC)
 
 
+@pytest.mark.parametrize("name", list(MODELS))
 @pytest.mark.parametrize("prec,pname", PRECS)
-def test_train_step_within_the_derived_bound(orc, P, prec, pname):
+def test_train_step_within_the_derived_bound(orc, P, prec, pname, name):
     import torch
-    m, tab, prm, seen, q = _setup(81, prec)
+    m, tab, prm, seen, q = _setup(81, prec, name)
     B = 2048 + 11
     x0, x1, hit, t, nr, al, mt = _batch(m, B, 82)
     s0 = np.zeros(5)

@@ -524,3 +524,44 @@ def test_train_step_captured_in_a_graph_replays_like_eager(P, B):
         P.nif_train_step(model.h, b, B, cfg, other)          # eager work between replays
         torch.cuda.synchronize()
     del g
+
+
+def test_backward_captured_in_a_graph_replays_like_eager(P):
+    """nif_backward (accumulators zeroed by kernels, side-stream fork and join) captured in a
+    hipGraph and replayed three times with eager work between: gradients and d x0 / d x1 of
+    every replay equal an eager call's (FP32 atomic order: 1e-6 norm-wise)."""
+    import torch
+    m = MODELS["blobs128"]
+    tab, prm, _ = model_params(m, 91, scale_tables=300.0)
+    B = (1 << 16) + 333
+    rng = np.random.default_rng(92)
+    x0 = dev_f32(rng.uniform(0.02, 0.98, (3, B)))
+    x1 = dev_f32(rng.uniform(0.02, 0.98, (3, B)))
+    dh = dev_f32(rng.normal(size=(B, m.n_heads)) * 1e-3)
+    model = P.Model(m, max_batch=B)
+    model.set_params(tab, prm)
+    say(f"backward graph capture B={B}")
+    dx0 = torch.empty((3, B), device="cuda")
+    dx1 = torch.empty((3, B), device="cuda")
+    P.nif_backward(model.h, x0, x1, B, dh, dx0, dx1, False, P.PREC_FP32)
+    torch.cuda.synchronize()
+    ref = [g.cpu().numpy().astype(np.float64) for g in model.get_grads()] + [dx0.cpu().numpy(), dx1.cpu().numpy()]
+    s_cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    cx0 = torch.empty((3, B), device="cuda")
+    cx1 = torch.empty((3, B), device="cuda")
+    with torch.cuda.graph(g, stream=s_cap):
+        P.nif_backward(model.h, x0, x1, B, dh, cx0, cx1, False, P.PREC_FP32, stream=s_cap)
+    ox0 = torch.empty((3, B), device="cuda")
+    ox1 = torch.empty((3, B), device="cuda")
+    for rep in range(3):
+        cx0.fill_(7.0)
+        g.replay()
+        torch.cuda.synchronize()
+        got = [a.cpu().numpy().astype(np.float64) for a in model.get_grads()] + [cx0.cpu().numpy(), cx1.cpu().numpy()]
+        for name, a, r in zip(("tables", "mlp", "s", "d x0", "d x1"), got, ref):
+            rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300)
+            assert rel <= 1e-6, f"replay {rep}: {name} differs by {rel:.2e}"
+        P.nif_backward(model.h, x1, x0, B, dh, ox0, ox1, True, P.PREC_FP32)     # eager work between replays
+        torch.cuda.synchronize()
+    del g
