@@ -798,8 +798,32 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
             "rays": n, **res}
 
 
+def ceilings_leg():
+    """Device ceilings measured on this GPU (nif_microbench), read beside the published peaks:
+    streaming HBM reads; random 4- and 8-byte gathers from a 32 MiB table (the FP16 hash tables'
+    size: resident in the Infinity Cache, not in one XCD's 4 MB L2) and from a 1 MiB one (L2
+    resident); the FP32 16x16x4 and BF16 16x16x16 MFMA forms the kernels use."""
+    import paper_2604_24666_amd as P
+    out = {}
+    for name, kind, nbytes, nops, unit in (
+            ("hbm_read", P.MB_HBM_READ, 4 << 30, 1, "GB/s"),
+            ("gather4_32MiB", P.MB_GATHER4, 32 << 20, 1 << 30, "GB/s"),
+            ("gather8_32MiB", P.MB_GATHER8, 32 << 20, 1 << 30, "GB/s"),
+            ("gather4_1MiB", P.MB_GATHER4, 1 << 20, 1 << 30, "GB/s"),
+            ("mfma_f32_16x16x4", P.MB_MFMA_F32, 0, 1 << 26, "TFLOP/s"),
+            ("mfma_bf16_16x16x16", P.MB_MFMA_BF16, 0, 1 << 26, "TFLOP/s")):
+        rate, ms = P.nif_microbench(kind, nbytes, nops, 5)
+        out[name] = {"value": rate / (1e9 if unit == "GB/s" else 1e12), "unit": unit, "ms": ms}
+        if kind in (P.MB_GATHER4, P.MB_GATHER8):
+            out[name]["gathers_per_s"] = rate / (4 if kind == P.MB_GATHER4 else 8)
+        log(f"ceiling {name}: {out[name]['value']:.1f} {unit} ({ms:.3f} ms per launch)")
+    return out
+
+
 def run_legs(legs, train_variants=tuple(TRAIN_VARIANTS)):
     res = {}
+    if "ceilings" in legs:
+        res["ceilings"] = ceilings_leg()
     if "torus" in legs:
         res["torus16"] = torus_leg()
     if "precision" in legs:
@@ -832,8 +856,8 @@ def main():
                     help="only run a plain 1 GiB device copy 3 times (scale for HBM byte counters)")
     ap.add_argument("--train-variants", default=",".join(TRAIN_VARIANTS),
                     help="training-leg variants: " + ",".join(TRAIN_VARIANTS))
-    ap.add_argument("--legs", default="torus,precision,train,batched",
-                    help="extra measurements: torus,precision,train,batched,ablation,paper,render (empty for none)")
+    ap.add_argument("--legs", default="ceilings,torus,precision,train,batched",
+                    help="extra measurements: ceilings,torus,precision,train,batched,ablation,paper,render (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",

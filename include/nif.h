@@ -262,6 +262,18 @@ int nif_set_query_blocks_per_cu(int32_t blocks_per_cu);
  * the GPU), or 0 = chosen from the launch size (16 below 8192 rays per compute unit).
  * Process-wide; results do not depend on it. */
 int nif_set_query_rays_per_wave(int32_t rays_per_wave);
+/* Measurement support (not part of the method): device ceilings that the rooflines are read
+ * against, each timed with device events over `reps` launches after one warm-up.
+ *   NIF_MB_HBM_READ    streaming float4 reads of an n_bytes buffer: result[0] = bytes/s
+ *   NIF_MB_GATHER4     n_ops random 4-byte gathers (one half2 table entry) at hashed indices of
+ *                      an n_bytes table, eight in flight per lane: result[0] = gathered bytes/s
+ *   NIF_MB_GATHER8     the same with 8-byte gathers (an aligned entry pair)
+ *   NIF_MB_MFMA_F32    n_ops v_mfma_f32_16x16x4_f32 (four independent chains per wave): FLOP/s
+ *   NIF_MB_MFMA_BF16   n_ops v_mfma_f32_16x16x16_bf16: FLOP/s
+ * result[1] = milliseconds per launch.  Allocates and frees its buffers; synchronises the
+ * stream.  n_bytes: a multiple of 16 in [4096, 2^33] (memory kinds); n_ops in [1, 2^40]. */
+enum { NIF_MB_HBM_READ = 0, NIF_MB_GATHER4 = 1, NIF_MB_GATHER8 = 2, NIF_MB_MFMA_F32 = 3, NIF_MB_MFMA_BF16 = 4 };
+int nif_microbench(int32_t kind, int64_t n_bytes, int64_t n_ops, int32_t reps, double* result, nif_stream stream);
 /* Autotuner of the fused query's launch shape: runs nif_query on the caller's rays (flags 0,
  * no stats) once to warm up and `reps` times timed with device events, for every pair of
  * workgroups per CU in {4, 6, 8, 10, 12, 14, 16, 20, 24} and rays per wave in {16, 64}; keeps

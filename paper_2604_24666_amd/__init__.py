@@ -21,7 +21,7 @@ __all__ = ["NifError", "lib", "ModelDesc", "Pose", "Rays", "Hits", "Segments", "
            "nif_model_create", "nif_model_destroy", "nif_model_sizes", "nif_model_set_params",
            "nif_model_get_params", "nif_model_get_grads", "nif_model_zero_grads", "nif_model_reserve",
            "nif_model_reserve_encoding",
-           "nif_voxelize", "nif_label", "nif_label_noalloc", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz",
+           "nif_voxelize", "nif_label", "nif_label_noalloc", "nif_build_grid", "nif_grid_destroy", "nif_grid_info", "nif_grid_bounds", "nif_grid_update", "nif_trace", "nif_query", "nif_set_query_blocks_per_cu", "nif_wall_clock_khz", "nif_microbench",
            "nif_encode", "nif_forward", "nif_backward", "nif_train_step", "nif_loss",
            "Model", "Grid", "NifField", "NifMultiTaskLoss", "label"]
 
@@ -110,6 +110,7 @@ def lib():
             "nif_set_query_blocks_per_cu": ([I32], C.c_int), "nif_set_query_rays_per_wave": ([I32], C.c_int),
             "nif_autotune_query": ([P, P, P, I64, P, I32, I32, P, P, P], C.c_int),
             "nif_wall_clock_khz": ([C.POINTER(C.c_int32)], C.c_int),
+            "nif_microbench": ([I32, I64, I64, I32, P, P], C.c_int),
             "nif_encode": ([P, P, I64, P, P], C.c_int),
             "nif_forward": ([P, P, P, I64, P, I32, P], C.c_int),
             "nif_backward": ([P, P, P, I64, P, P, P, I32, I32, P], C.c_int),
@@ -276,6 +277,16 @@ def nif_query(model, grid, rays: Rays, n: int, hits: Hits, flags: int = 0, preci
               stream=None):
     _check(lib().nif_query(model, grid, C.byref(rays), n, C.byref(hits), flags, precision, _ptr(stats),
                            _stream(stream)))
+
+
+MB_HBM_READ, MB_GATHER4, MB_GATHER8, MB_MFMA_F32, MB_MFMA_BF16 = 0, 1, 2, 3, 4
+
+
+def nif_microbench(kind: int, n_bytes: int, n_ops: int, reps: int = 5, stream=None):
+    """(rate, ms per launch) of one device-ceiling microbenchmark (bytes/s or FLOP/s)."""
+    r = (C.c_double * 2)()
+    _check(lib().nif_microbench(int(kind), int(n_bytes), int(n_ops), int(reps), r, _stream(stream)))
+    return r[0], r[1]
 
 
 def nif_wall_clock_khz() -> int:

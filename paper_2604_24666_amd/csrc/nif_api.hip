@@ -321,6 +321,17 @@ int nif_set_query_blocks_per_cu(int32_t v) {
     return nif::set_query_blocks_per_cu(v);
 }
 
+int nif_microbench(int32_t kind, int64_t n_bytes, int64_t n_ops, int32_t reps, double* result, nif_stream stream) {
+    REQUIRE(kind >= NIF_MB_HBM_READ && kind <= NIF_MB_MFMA_BF16, "kind must be one of NIF_MB_*");
+    REQUIRE(result, "result is null");
+    REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+    REQUIRE(n_ops >= 1 && n_ops <= ((int64_t)1 << 40), "n_ops must be in [1, 2^40]");
+    if (kind <= NIF_MB_GATHER8)
+        REQUIRE(n_bytes >= 4096 && n_bytes % 16 == 0 && n_bytes <= ((int64_t)1 << 33),
+                "n_bytes must be a multiple of 16 in [4096, 2^33]");
+    return nif::microbench(kind, n_bytes, n_ops, reps, result, S(stream));
+}
+
 int nif_autotune_query(const nif_model* m, const nif_grid* g, const nif_rays* rays, int64_t n, const nif_hits* out,
                        int32_t precision, int32_t reps, int32_t* best, float* best_ms, nif_stream stream) {
     REQUIRE(g && m, "model and grid must not be null");

@@ -136,6 +136,7 @@ void model_free(nif_model* m);
 int model_sync_working(nif_model* m, hipStream_t st);
 int model_sync_mlp(nif_model* m, hipStream_t st);
 int zero_grads_launch(nif_model* m, hipStream_t st);
+int microbench(int32_t kind, int64_t n_bytes, int64_t n_ops, int32_t reps, double* result, hipStream_t st);
 int backward_launch(nif_model* m, const float* x0, const float* x1, int64_t B, const float* dh,
                     int32_t dh_stride, float* dx0, float* dx1, int32_t precision, hipStream_t st);
 int train_step_launch(nif_model* m, const nif_batch* b, int64_t B, const nif_train_cfg* cfg,
