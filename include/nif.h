@@ -126,7 +126,7 @@ int nif_model_get_grads(const nif_model* model, float* g_tables_dev, float* g_ml
                         nif_stream stream);
 int nif_model_zero_grads(nif_model* model, nif_stream stream);
 /* Allocates the training scratch for batches of up to max_batch samples (activations,
-   deltas, a [min(max_batch, 2^16)][E] encoding scratch for the backward's recomputation,
+   deltas, a [min(max_batch, 2^17)][E] encoding scratch for the backward's recomputation,
    table-gradient additions, weight-gradient partials and the spatially ordered copy of a
    batch); nif_backward and nif_train_step fail with NIF_E_STATE above it.  A later call
    with a larger max_batch frees and re-allocates everything, the stored encoding included. */
@@ -298,7 +298,7 @@ int nif_forward(const nif_model* model, const float* x0_dev, const float* x1_dev
  * dL/dx0, dL/dx1 (SoA, nullable).  Hand-written: MLP backward, hash-grid scatter-add with
  * the trilinear weights (additions grouped by table slice and summed in 64-bit fixed
  * point), PE chain rule.  Nothing is kept from nif_forward: the hidden activations are
- * recomputed, and the encoding is recomputed per chunk of 2^16 samples. */
+ * recomputed, and the encoding is recomputed per chunk of 2^17 samples. */
 int nif_backward(nif_model* model, const float* x0_dev, const float* x1_dev, int64_t B,
                  const float* d_heads_dev, float* d_x0_dev, float* d_x1_dev, int32_t accumulate,
                  int32_t precision, nif_stream stream);
@@ -329,8 +329,8 @@ typedef struct {
     int32_t fixed_task_weights; /* 1 = ablation without uncertainty weighting: total = sum of
                                    the five task losses, s neither used nor updated */
     int32_t store_encoding;     /* 0: the forward keeps no encoding; the backward recomputes it
-                                   (gathers again) per chunk of 2^16 samples for the first
-                                   layer's weight gradient, in a [2^16][E] FP32 scratch.
+                                   (gathers again) per chunk of 2^17 samples for the first
+                                   layer's weight gradient, in a [2^17][E] FP32 scratch.
                                    1: the forward stores the [B][E] FP32 encoding for the
                                    backward (one gather pass less per step; max_batch E 4 bytes
                                    more device memory, from nif_model_reserve_encoding; without

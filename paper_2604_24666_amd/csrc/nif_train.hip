@@ -32,7 +32,7 @@ enum { TC_NPOS = 0, TC_STEP = 1, TC_GOOD = 2, TC_NONFINITE = 3, TC_SKIP = 4 };
 enum { DA_SUM = 0, DA_SCALE = 5, DA_SCALE_USED = 6, DA_C1 = 7, DA_C2 = 8 };
 constexpr float kDistEps = 1e-4f;
 constexpr int kGrowIntervalDefault = 1000;  // clean steps before the loss scale doubles
-constexpr int64_t kEncBwdChunk = 1 << 16;  // samples per count/fill/reduce round
+constexpr int64_t kEncBwdChunk = 1 << 17;  // samples per count/fill/reduce round
 constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
 
 // Concatenated encoding: d x of the appended gamma values, d enc_v = (W0^T delta_0)_v times

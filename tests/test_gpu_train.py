@@ -236,14 +236,14 @@ def test_training_reduces_the_loss(orc, P, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_stored_and_recomputed_encoding_give_the_same_step(P, prec):
     """The two encoding policies of the training step at a batch of several recomputation
-    chunks (2^16 + 4321 samples, spatially ordered): same losses and task-weight gradients;
+    chunks (2^17 + 4321 samples, spatially ordered): same losses and task-weight gradients;
     table gradients equal up to FP32 rounding (that path never reads the encoding, but its
     register-merged runs and multi-part slices are summed in an order set by atomics); MLP
     gradients equal up to the summation order of the first layer's chunks."""
     import torch
     m = MODELS["blobs128"]
     tab, prm, _ = model_params(m, 21, scale_tables=300.0)
-    B = (1 << 16) + 4321
+    B = (1 << 17) + 4321
     batch = _batch(m, B, 22)
     out = []
     for store in (False, True):
@@ -389,10 +389,10 @@ def test_train_step_rejects_oversized_batches(P):
         _train_step(P, model, _batch(m, 65, 1), 65)
 
 
-@pytest.mark.parametrize("B", [(1 << 16) + 4321, 1 << 18])
+@pytest.mark.parametrize("B", [(1 << 17) + 4321, 1 << 18])
 def test_backward_over_several_chunks_is_additive(P, B):
-    """Batches larger than one table-gradient round (2^16 samples), up to the training batch of
-    the benchmark (2^18, four rounds): the gradient of the whole batch equals the gradient of its
+    """Batches larger than one table-gradient round (2^17 samples), up to the training batch of
+    the benchmark (2^18, two rounds): the gradient of the whole batch equals the gradient of its
     two halves accumulated (the sum is linear in the samples), within FP32 summation-order
     error."""
     import torch
@@ -481,7 +481,7 @@ def test_autograd_wrappers_compose_to_the_oracle_gradient(orc, P):
         h2.sum().backward()
 
 
-@pytest.mark.parametrize("B", [4096 + 7, (1 << 16) + 4099], ids=["one_chunk", "two_chunks"])
+@pytest.mark.parametrize("B", [4096 + 7, (1 << 17) + 4099], ids=["one_chunk", "two_chunks"])
 def test_train_step_captured_in_a_graph_replays_like_eager(P, B):
     """nif_train_step captured in a hipGraph (with its side-stream fork and join) and replayed
     three times, with eager work between the replays: every replay's losses and gradients
