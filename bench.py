@@ -743,11 +743,12 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
     stats = torch.zeros(5 + 2 * n_p, dtype=torch.int64, device="cuda")
     khz = P.nif_wall_clock_khz()
     res = {}
-    for prec, name in ((1, "bf16"), (0, "fp32")):
-        shape = tuned_query_shape("blobs128_b", model.h, grid.h, rays, n, hits, prec)
+    def measure(prec, dealing):
+        """Median launch time and per-pose completion latencies of the graph-replayed launch."""
         torch.cuda.synchronize()
         s_cap = torch.cuda.Stream()
-        call = lambda: P.nif_query(model.h, grid.h, rays, n, hits, P.Q_POSE_TIMES, prec, stats, stream=s_cap)
+        call = lambda: P.nif_query(model.h, grid.h, rays, n, hits, P.Q_POSE_TIMES | dealing, prec, stats,
+                                   stream=s_cap)
         with torch.cuda.stream(s_cap):
             call()
         torch.cuda.synchronize()
@@ -771,10 +772,15 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
             launch_ms.append(a.elapsed_time(b))
             assert np.array_equal(st[5 + n_p:5 + 2 * n_p], counts), "rays finished per pose"
             lat.append((st[5:5 + n_p] - st[4]).astype(np.float64) / khz)     # ticks -> ms
+        del g
         lat = np.concatenate(lat)
-        ms = float(np.median(launch_ms))
         evals_per_launch = (int(stats.cpu().numpy()[1]) - evals) / replays
-        achieved = evals_per_launch * GATHER_BYTES_PER_EVAL / (float(np.mean(launch_ms)) * 1e-3) / 1e9
+        return float(np.median(launch_ms)), float(np.mean(launch_ms)), lat, evals_per_launch
+
+    for prec, name in ((1, "bf16"), (0, "fp32")):
+        shape = tuned_query_shape("blobs128_b", model.h, grid.h, rays, n, hits, prec)
+        ms, ms_mean, lat, evals_per_launch = measure(prec, 0)
+        achieved = evals_per_launch * GATHER_BYTES_PER_EVAL / (ms_mean * 1e-3) / 1e9
         res[name] = {"rays_per_s": n / (ms * 1e-3), "ms_per_launch_median": ms,
                      "pose_latency_ms_p50": float(np.quantile(lat, 0.5)),
                      "pose_latency_ms_p99": float(np.quantile(lat, 0.99)),
@@ -788,7 +794,14 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
                      "launch_shape": {"blocks_per_cu": shape[0], "rays_per_wave": shape[1]}}
         log(f"batched leg {name}: {ms:.2f} ms per launch, pose latency p50 {res[name]['pose_latency_ms_p50']:.2f} "
             f"p99 {res[name]['pose_latency_ms_p99']:.2f} ms")
-        del g
+        ms, _, lat, _ = measure(prec, P.Q_POSE_ORDER)
+        res[name]["pose_ordered"] = {"rays_per_s": n / (ms * 1e-3), "ms_per_launch_median": ms,
+                                     "pose_latency_ms_p50": float(np.quantile(lat, 0.5)),
+                                     "pose_latency_ms_p99": float(np.quantile(lat, 0.99)),
+                                     "note": "NIF_Q_POSE_ORDER: each XCD's ray range walks the poses in order"}
+        log(f"batched leg {name} pose-ordered: {ms:.2f} ms per launch, pose latency p50 "
+            f"{res[name]['pose_ordered']['pose_latency_ms_p50']:.2f} p99 "
+            f"{res[name]['pose_ordered']['pose_latency_ms_p99']:.2f} ms")
     return {"workload": f"blobs128_b: 16 poses (twist/bend/taper, s ~ U(0,1]), {n} rays in uneven counts "
                         f"[{int(counts.min())}, {int(counts.max())}], half pinhole (random azimuth), half secondary "
                         f"(origin uniform in the pose's occupied deformed box, direction uniform on S^2); one "
@@ -930,6 +943,18 @@ def main():
     log(f"query kernel {q_ms.mean():.3f} ms (min {q_ms.min():.3f}), grid rebuild {b_ms.mean():.3f} ms, "
         f"step {ms_step:.3f} ms, network evaluations/launch {evals_per_launch:.0f}")
     hit_rate = float(out["hit"].float().mean().item())
+    # traversal alone: the voxel proxy (NIF_Q_NO_NETWORK) walks every ray to its first occupied
+    # voxel, a lower bound of the traversal inside the query (which walks on past empty-hit segments)
+    pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    P.nif_query(model.h, grid.h, rays, n, hits, P.Q_NO_NETWORK, args.precision, None)
+    pe0.record(stream)
+    for _ in range(3):
+        P.nif_query(model.h, grid.h, rays, n, hits, P.Q_NO_NETWORK, args.precision, None)
+    pe1.record(stream)
+    torch.cuda.synchronize()
+    proxy_ms = pe0.elapsed_time(pe1) / 3
+    query()                                    # restore the outputs of the full query
+    torch.cuda.synchronize()
     res = {
         "metric": "ray queries/sec (first-hit neural intersection, FP32 MLP; train samples/s reported separately)",
         "value": n / (ms_step * 1e-3),
@@ -943,6 +968,10 @@ def main():
         "launch_shape": {"blocks_per_cu": shape[0], "rays_per_wave": shape[1], "chosen_by": "nif_autotune_query"},
         "query_kernel_ms": float(q_ms.mean()), "grid_rebuild_ms": float(b_ms.mean()),
         "network_evals_per_step": float(evals_per_launch), "hit_rate": hit_rate,
+        "time_shares": {"grid_rebuild": float(b_ms.mean()) / ms_step,
+                        "traversal_to_first_occupied_voxel": proxy_ms / float(q_ms.mean()),
+                        "note": "grid re-pose per step and the voxel-proxy launch (traversal only, to each ray's "
+                                "first occupied voxel) against the fused query; the paper reports 2-3 % for its BVH"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": kquery_traffic_bytes(),
                      "kernel": "k_query (fused traversal + encoding + MLP)",

@@ -241,9 +241,12 @@ typedef struct {
     float *dnx, *dny, *dnz;     /* the normal carried to deformed space: (dD/dx)^-T n at the
                                    rest hit point, normalized (for shading the posed surface) */
 } nif_hits;
-enum { NIF_Q_FIRST_HIT = 0, NIF_Q_NO_NETWORK = 8, NIF_Q_POSE_TIMES = 16 };
+enum { NIF_Q_FIRST_HIT = 0, NIF_Q_NO_NETWORK = 8, NIF_Q_POSE_TIMES = 16, NIF_Q_POSE_ORDER = 32 };
 /* flags: NIF_Q_FIRST_HIT, or NIF_Q_NO_NETWORK (the voxel proxy: first occupied voxel is
- * the hit, D = t_in, no network); NIF_Q_POSE_TIMES adds per-pose completion times.
+ * the hit, D = t_in, no network); NIF_Q_POSE_TIMES adds per-pose completion times;
+ * NIF_Q_POSE_ORDER (first-hit query) deals the rays pose by pose: each of the 8 per-XCD ray
+ * ranges walks its eighth of pose 0, then of pose 1, and so on, so that poses complete in
+ * order rather than all near the end of the launch (per-ray results are the same).
  * precision: NIF_PREC_*.  stats_dev: nullable int64[4] {rays done, network evaluations,
  * degenerate voxel tests, reserved}, accumulated; with NIF_Q_POSE_TIMES it must hold
  * 5 + 2 n_poses entries: [4] the kernel's start and [5 + p] the completion of pose p, in

@@ -31,7 +31,7 @@ LIB_PATH = os.path.join(_HERE, "libnif.so")
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 DIST_LOG_RELU, DIST_SIGMOID = 0, 1
 TABLE_F32, TABLE_F16 = 0, 1
-Q_FIRST_HIT, Q_NO_NETWORK, Q_POSE_TIMES = 0, 8, 16
+Q_FIRST_HIT, Q_NO_NETWORK, Q_POSE_TIMES, Q_POSE_ORDER = 0, 8, 16, 32
 
 
 class NifError(RuntimeError):
@@ -265,8 +265,10 @@ def nif_grid_update(h, kinds, strengths, stream=None):
 def make_rays(o, d, pose_offsets, tmax=None) -> Rays:
     """o, d: float32 [3][n] device tensors; pose_offsets: int64 [P+1] device tensor;
     tmax: optional float32 [n] device tensor (occlusion bound of each ray)."""
-    return Rays(o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), d[0].data_ptr(), d[1].data_ptr(),
-                d[2].data_ptr(), pose_offsets.data_ptr(), _ptr(tmax))
+    r = Rays(o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr(), d[0].data_ptr(), d[1].data_ptr(),
+             d[2].data_ptr(), pose_offsets.data_ptr(), _ptr(tmax))
+    r._keep = (o, d, pose_offsets, tmax)        # the struct holds raw pointers: keep the tensors alive
+    return r
 
 
 def nif_trace(grid, rays: Rays, n: int, max_seg: int, seg: Segments, stream=None):
@@ -483,7 +485,9 @@ def alloc_hits(n, dev):
 
 def hits_struct(out) -> Hits:
     names = [f[0] for f in Hits._fields_]
-    return Hits(*[out[k].data_ptr() if out.get(k) is not None else None for k in names])
+    h = Hits(*[out[k].data_ptr() if out.get(k) is not None else None for k in names])
+    h._keep = out                                # the struct holds raw pointers: keep the tensors alive
+    return h
 
 
 class NifMultiTaskLoss(torch.autograd.Function):

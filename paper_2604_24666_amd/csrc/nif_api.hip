@@ -297,7 +297,7 @@ int nif_query(const nif_model* m, const nif_grid* g, const nif_rays* rays, int64
     int rc = validate_rays(rays, n);
     if (rc) return rc;
     REQUIRE(out, "out is null");
-    REQUIRE((flags & ~(uint32_t)(NIF_Q_NO_NETWORK | NIF_Q_POSE_TIMES)) == 0, "unknown query flags");
+    REQUIRE((flags & ~(uint32_t)(NIF_Q_NO_NETWORK | NIF_Q_POSE_TIMES | NIF_Q_POSE_ORDER)) == 0, "unknown query flags");
     REQUIRE(precision >= 0 && precision <= 2, "precision must be NIF_PREC_FP32, _BF16 or _FP16");
     if (!(flags & NIF_Q_NO_NETWORK)) {
         REQUIRE(m, "model is null");

@@ -263,11 +263,11 @@ __global__ void k_bin_sort(const PoseDev* __restrict__ poses, const int32_t* __r
 // ------------------------------------------------------------------ host orchestration
 
 void grid_free(nif_grid* g) {
-    void* ps[] = {g->poses, g->verts, g->bin_start, g->bin_cells, g->list, g->counts, g->scratch};
+    void* ps[] = {g->poses, g->verts, g->bin_start, g->bin_cells, g->list, g->counts, g->scratch, g->order_pre};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     g->poses = nullptr; g->verts = nullptr; g->bin_start = nullptr; g->bin_cells = nullptr;
-    g->list = nullptr; g->counts = nullptr; g->scratch = nullptr;
+    g->list = nullptr; g->counts = nullptr; g->scratch = nullptr; g->order_pre = nullptr;
 }
 
 // scratch layout: bbox [6 P] | totals [P] | overflow [1] | n_occ [1]
@@ -336,6 +336,7 @@ int grid_build(nif_grid* g, const uint8_t* occ, int32_t N, const nif_pose* poses
     NIF_TRY(hipMalloc(&g->poses, sizeof(PoseDev) * n_poses), "hipMalloc poses");
     NIF_TRY(hipMalloc(&g->verts, sizeof(float4) * nv * n_poses), "hipMalloc vertices");
     NIF_TRY(hipMalloc(&g->scratch, sizeof(int32_t) * (7 * n_poses + 8)), "hipMalloc grid scratch");
+    NIF_TRY(hipMalloc(&g->order_pre, sizeof(int64_t) * 8 * (n_poses + 1)), "hipMalloc dealing table");
     NIF_TRY(hipMalloc(&g->list, sizeof(int32_t) * (ncell + 1)), "hipMalloc occupied list");
     // occupied voxels, compacted once
     NIF_TRY(hipMemsetAsync(sc_nocc(g), 0, sizeof(int32_t), st), "memset");

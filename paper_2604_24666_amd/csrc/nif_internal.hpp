@@ -19,6 +19,7 @@ struct nif_grid {
     int32_t* list = nullptr;                // device, occupied voxel ids (shared by all poses)
     int32_t* counts = nullptr;              // device, per-bin counters (build scratch)
     int32_t* scratch = nullptr;             // device, boxes / totals / flags
+    int64_t* order_pre = nullptr;           // device [8][n_poses + 1]: pose-ordered dealing (query)
     int64_t bin_total = 0, max_bins = 0, ref_capacity = 0;
     int64_t n_occupied = 0;
     std::vector<int64_t> refs_per_pose;

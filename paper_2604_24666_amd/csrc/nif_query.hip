@@ -33,6 +33,7 @@ struct RayArgs {
     const float* tmax;          // nullable: occlusion bound per ray
     int32_t n_poses;
     int64_t n;
+    const int64_t* order_pre;   // nullable: pose-ordered dealing, [8][n_poses + 1] (k_order_prefix)
 };
 
 __device__ __forceinline__ Ray load_ray(const RayArgs& R, int64_t r) {
@@ -263,12 +264,26 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
     // Rays are dealt in 8 contiguous ranges, one per XCD: workgroups are dispatched to the
     // XCDs round-robin, so workgroup b starts on range b mod 8 and the waves sharing an L2
     // walk neighbouring rays (coherent rays touch the same table lines).  A wave whose range
-    // runs dry moves on to the next one, so the load still balances across the chip.
+    // runs dry moves on to the next one, so the load still balances across the chip.  With
+    // pose-ordered dealing, range k is the concatenation over the poses of the k-th eighth of
+    // each pose's rays (positions counted in R.order_pre), so every XCD finishes pose p
+    // before it starts pose p + 1.
     const int home = (int)(blockIdx.x & 7);
     const int64_t span = (R.n + 7) / 8;
+    const int64_t* opre = R.order_pre;
+    auto range_of = [&](int id, int64_t& l, int64_t& h) {
+        if (opre) {
+            l = 0;
+            h = opre[(int64_t)id * (R.n_poses + 1) + R.n_poses];
+        } else {
+            l = std::min<int64_t>((int64_t)id * span, R.n);
+            h = std::min<int64_t>(l + span, R.n);
+        }
+    };
     int cur = 0;                                   // ranges tried (wave-uniform); 8 = none left
     int rid = home;
-    int64_t lo = std::min<int64_t>((int64_t)rid * span, R.n), hi = std::min<int64_t>(lo + span, R.n);
+    int64_t lo, hi;
+    range_of(rid, lo, hi);
     int bad = 0;
     int64_t n_done = 0, n_eval = 0;
     if (pose_times && lane == 0) atomicMin((unsigned long long*)&stats[4], (unsigned long long)wall_clock64());
@@ -329,8 +344,20 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
                     if (r >= hi) {
                         r = -1;
                     } else {
+                        if (opre) {                  // position r of range rid -> (pose, ray)
+                            const int64_t* pre = opre + (int64_t)rid * (R.n_poses + 1);
+                            int a = 0, b = R.n_poses - 1;
+                            while (a < b) {          // last pose p with pre[p] <= r
+                                const int mid = (a + b + 1) >> 1;
+                                if (pre[mid] <= r) a = mid; else b = mid - 1;
+                            }
+                            pose = a;
+                            const int64_t cnt = R.off[a + 1] - R.off[a];
+                            r = R.off[a] + cnt * rid / 8 + (r - pre[a]);
+                        } else {
+                            pose = find_pose(R.off, R.n_poses, r);
+                        }
                         ray = load_ray(R, r);
-                        pose = find_pose(R.off, R.n_poses, r);
                         P = G.poses[pose];
                         trav_init(P, ray, tv);
                         nq = 0;
@@ -340,8 +367,7 @@ __global__ void __launch_bounds__(64, NIF_QUERY_MIN_WAVES) k_query(NetParams np,
                 if (lo + (int64_t)base + popc64(m) >= hi) {       // this range is used up: next one
                     ++cur;
                     rid = (home + cur) & 7;
-                    lo = std::min<int64_t>((int64_t)rid * span, R.n);
-                    hi = std::min<int64_t>(lo + span, R.n);
+                    range_of(rid, lo, hi);
                 }
             }
             const bool search = r >= 0 && !has;
@@ -562,10 +588,25 @@ static GridArgs grid_args(const nif_grid* g) {
     return G;
 }
 
+// Pose-ordered dealing: pre[k][p] = rays of poses 0 .. p-1 in range k, whose share of pose q
+// is [off[q] + c_q k / 8, off[q] + c_q (k + 1) / 8), c_q the pose's ray count.
+__global__ void k_order_prefix(const int64_t* __restrict__ off, int n_poses, int64_t* __restrict__ pre) {
+    const int k = threadIdx.x;
+    if (k >= 8) return;
+    int64_t acc = 0;
+    for (int p = 0; p < n_poses; ++p) {
+        pre[(int64_t)k * (n_poses + 1) + p] = acc;
+        const int64_t c = off[p + 1] - off[p];
+        acc += c * (k + 1) / 8 - c * k / 8;
+    }
+    pre[(int64_t)k * (n_poses + 1) + n_poses] = acc;
+}
+
 static RayArgs ray_args(const nif_grid* g, const nif_rays* r, int64_t n) {
     RayArgs R;
     R.ox = r->ox; R.oy = r->oy; R.oz = r->oz; R.dx = r->dx; R.dy = r->dy; R.dz = r->dz;
     R.off = r->pose_offsets; R.tmax = r->tmax; R.n_poses = g->n_poses; R.n = n;
+    R.order_pre = nullptr;
     return R;
 }
 
@@ -623,13 +664,17 @@ int query_launch(const nif_model* m, const nif_grid* g, const nif_rays* r, int64
                  uint32_t flags, int32_t precision, int64_t* stats, hipStream_t st) {
     if (n == 0) return NIF_OK;
     const GridArgs G = grid_args(g);
-    const RayArgs R = ray_args(g, r, n);
+    RayArgs R = ray_args(g, r, n);
     if (flags & NIF_Q_NO_NETWORK) {
         const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)device_cus() * 16);
         hipLaunchKernelGGL(k_proxy, dim3((unsigned)blocks), dim3(256), 0, st, G, R, *out, stats);
         return check_hip(hipGetLastError(), "k_proxy launch");
     }
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, m->counters, 8);
+    if (flags & NIF_Q_POSE_ORDER) {
+        hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(64), 0, st, R.off, R.n_poses, g->order_pre);
+        R.order_pre = g->order_pre;
+    }
     const int pt = (flags & NIF_Q_POSE_TIMES) && stats ? 1 : 0;
     if (pt) hipLaunchKernelGGL(k_reset_pose_times, dim3(1), dim3(256), 0, st, stats, g->n_poses);
     int rc;
