@@ -127,8 +127,8 @@ int nif_model_get_grads(const nif_model* model, float* g_tables_dev, float* g_ml
 int nif_model_zero_grads(nif_model* model, nif_stream stream);
 /* Allocates the training scratch for batches of up to max_batch samples (activations,
    deltas, a [min(max_batch, 2^17)][E] encoding scratch for the backward's recomputation,
-   table-gradient additions, weight-gradient partials and the spatially ordered copy of a
-   batch); nif_backward and nif_train_step fail with NIF_E_STATE above it.  A later call
+   the table-gradient additions of a round of min(max_batch, 2^18) samples, weight-gradient
+   partials and the spatially ordered copy of a batch); nif_backward and nif_train_step fail with NIF_E_STATE above it.  A later call
    with a larger max_batch frees and re-allocates everything, the stored encoding included. */
 int nif_model_reserve(nif_model* model, int64_t max_batch);
 /* Allocates the [max_batch][E] FP32 stored encoding that nif_train_step uses when

@@ -67,7 +67,8 @@ struct nif_model {
     float* enc = nullptr;               // [bwd_chunk][E] encoding recomputed for the first layer's dW
     float* enc_all = nullptr;           // [max_batch][E] stored encoding (store_encoding steps only;
                                         //   allocated by nif_model_reserve_encoding)
-    int64_t bwd_chunk = 0;              // samples per encoding-backward round
+    int64_t bwd_chunk = 0;              // samples per training chunk (forward, MLP backward, one fill launch)
+    int64_t bwd_round = 0;              // samples per table-gradient round (count, scan, reduce): whole chunks
     int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
     float* bwd_val = nullptr;           // table-gradient additions: records (Fd values, entry within the bucket)

@@ -32,7 +32,8 @@ enum { TC_NPOS = 0, TC_STEP = 1, TC_GOOD = 2, TC_NONFINITE = 3, TC_SKIP = 4 };
 enum { DA_SUM = 0, DA_SCALE = 5, DA_SCALE_USED = 6, DA_C1 = 7, DA_C2 = 8 };
 constexpr float kDistEps = 1e-4f;
 constexpr int kGrowIntervalDefault = 1000;  // clean steps before the loss scale doubles
-constexpr int64_t kEncBwdChunk = 1 << 17;  // samples per count/fill/reduce round
+constexpr int64_t kEncBwdChunk = 1 << 17;  // samples per training chunk (and per fill launch)
+constexpr int kEncBwdRoundChunks = 2;      // chunks per table-gradient round (count, scan, reduce)
 constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
 
 // Concatenated encoding: d x of the appended gamma values, d enc_v = (W0^T delta_0)_v times
@@ -150,8 +151,12 @@ int model_reserve(nif_model* m, int64_t B) {
         const int SB = log2T <= 12 ? log2T : std::max(12, log2T - 8);
         const int64_t n_buckets = (int64_t)L * (m->desc.per_sample_tables ? m->S : 1) * (1 << (log2T - SB));
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(B, kEncBwdChunk));
-        const int64_t n_blk = ((chunk + 15) / 16 + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock;
-        const int64_t n_add = chunk * 2 * m->S * L * 8;
+        // a round's additions are indexed by int32 offsets
+        const int64_t per = 2 * (int64_t)m->S * L * 8;
+        int64_t round = std::min<int64_t>(std::max<int64_t>(B, 1), chunk * kEncBwdRoundChunks);
+        while (round > chunk && round * per > INT32_MAX) round -= chunk;
+        const int64_t n_blk = ((round + 15) / 16 + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock;
+        const int64_t n_add = round * per;
         const int64_t n_cnt = n_buckets * n_blk;
         const size_t sz[3] = {sizeof(int32_t) * (size_t)n_cnt,
                               sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 3 + n_buckets),
@@ -163,6 +168,7 @@ int model_reserve(nif_model* m, int64_t B) {
                 return fail(NIF_E_OOM, "encoding-backward buffer allocation failed");
             }
         m->bwd_chunk = chunk;
+        m->bwd_round = round;
     }
     const int64_t hw = m->desc.hidden_width, nh = m->desc.hidden_layers;
     const struct { float** p; int64_t n; } a[] = {{&m->zbuf, B * m->H}, {&m->dz, B * 16}, {&m->acts, B * hw * nh},
@@ -805,17 +811,18 @@ struct EncBwdParams {
     float* dx0;          // nullable SoA [3][B]
     float* dx1;
     int64_t B;           // stride of the SoA point arrays
-    int64_t c0;          // first sample of this chunk
-    int64_t n;           // samples in this chunk
+    int64_t c0;          // first sample of this round
+    int64_t n;           // samples in this round
     int32_t SB;          // log2 entries per bucket
     int32_t NBL;         // buckets per level
     int32_t n_buckets;   // L * NBL
-    int32_t n_blk;       // blocks of the chunk grid
+    int32_t n_blk;       // blocks of the round's grid
+    int32_t blk0;        // fill: the launch's first block within the round
     int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
     float* val;          // additions: records of Fd values and the entry within the bucket (as bits)
     int32_t w_lds;       // fill: the block's first-layer weight rows staged in LDS
     int64_t cap;         // capacity of key / val
-    uint32_t* vmax;      // bits of the largest |value| of the chunk's additions (+inf if not finite)
+    uint32_t* vmax;      // bits of the largest |value| of the round's additions (+inf if not finite)
 };
 
 
@@ -950,7 +957,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     const int lp = (int)blockIdx.y * LG;       // first level of this block's group
     const uint32_t kmask = (1u << P.SB) - 1u;
     const int nloc = LG * P.NBL * n_table_sets(P);
-    for (int i = tid; i < nloc; i += 256) s_cur[i] = P.cnt[group_bucket_global<LG>(P, lp, i) * P.n_blk + blockIdx.x];
+    const int bx = (int)blockIdx.x + P.blk0;   // block within the round
+    for (int i = tid; i < nloc; i += 256) s_cur[i] = P.cnt[group_bucket_global<LG>(P, lp, i) * P.n_blk + bx];
     // The W0 rows this block multiplies (combination c, (level, feature) r of its group: row
     // 4c + r, zero where r >= LG FD), staged once in LDS with rows padded by 4 floats, so the
     // MFMA's A operand is read from LDS rather than fetched again for every tile.
@@ -967,8 +975,8 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
     }
     __syncthreads();
     const int64_t n_tiles = (P.n + 15) / 16;
-    const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(blockIdx.x + 1) * kBwdTilesPerBlock);
-    for (int64_t tile = (int64_t)blockIdx.x * kBwdTilesPerBlock + w; tile < t_end; tile += 4) {
+    const int64_t t_end = std::min<int64_t>(n_tiles, (int64_t)(bx + 1) * kBwdTilesPerBlock);
+    for (int64_t tile = (int64_t)bx * kBwdTilesPerBlock + w; tile < t_end; tile += 4) {
         int64_t seg;
         float xs[6];
         const bool valid = tile_sample(P, tile, j, seg, xs);
@@ -1186,9 +1194,10 @@ template <int FD> constexpr int kLog2Window = FD == 2 ? 12 : 11;
 // bucket cut into one part is added to the table gradient directly; parts of a bucket cut into
 // several add their nonzero window entries with atomics.
 // The window is summed in 64-bit fixed point with integer LDS atomics (several times the rate
-// of floating-point LDS atomics): with |value| < 2^e over the chunk and at most N additions,
+// of floating-point LDS atomics): with |value| < 2^e over the round and at most N additions,
 // the scale 2^s, s = 62 - e - ceil(log2 N), keeps every partial sum below 2^62 while the unit
-// is 2^-34 of the largest addition; the sum is exact in that unit and independent of order.
+// is 2^-31 to 2^-32 of the largest addition (2^18 samples per round); the sum is exact in
+// that unit and independent of order.
 template <int FD>
 __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const int32_t* __restrict__ total,
                                                         const int32_t* __restrict__ parts) {
@@ -1521,37 +1530,66 @@ static EncBwdParams table_grad_params(nif_model* m, const float* x0, const float
     const int n_sets = m->desc.per_sample_tables ? m->S : 1;
     ep.n_buckets = m->desc.levels * n_sets * ep.NBL;
     ep.cnt = m->bwd_cnt; ep.val = m->bwd_val;
-    ep.cap = m->bwd_chunk * 2 * m->S * m->desc.levels * 8;
+    ep.cap = m->bwd_round * 2 * m->S * m->desc.levels * 8;
     ep.vmax = nullptr;
     return ep;
 }
 
-// One round of the table gradient: samples [c0, c0 + n), n <= bwd_chunk: count / scan / fill /
-// parts / reduce on stream sd (the round's scratch is shared, so rounds run in stream order).
+// A round of the table gradient over samples [c0, c0 + n), n <= bwd_round, on stream sd: the
+// count and scan (positions only) when it begins, one fill launch per chunk once the chunk's
+// first-layer deltas exist, then the parts and the reduction.  Rounds share their scratch, so
+// they run in stream order.
+struct TgRound {
+    EncBwdParams ep;
+    int32_t* total;
+    int32_t* parts;
+};
+
 template <int FD>
-static void table_grad_round_fd(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
-    constexpr int LG = kLevelGroup<FD>, LW = kLog2Window<FD>;
-    const int hw = m->desc.hidden_width;
-    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
-    const unsigned n_win = ep.SB > LW ? 1u << (ep.SB - LW) : 1u;
+static TgRound tg_begin_fd(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
+    constexpr int LG = kLevelGroup<FD>;
     ep.c0 = c0;
     ep.n = n;
+    ep.blk0 = 0;
     const int64_t n_tiles = (ep.n + 15) / 16;
     ep.n_blk = (int32_t)((n_tiles + kBwdTilesPerBlock - 1) / kBwdTilesPerBlock);
     const int64_t n_cnt = (int64_t)ep.n_buckets * ep.n_blk;
     const int n_chunks = (int)((n_cnt + 4095) / 4096);
     int32_t* sums = m->bwd_scan;
-    int32_t* total = m->bwd_scan + n_chunks;
-    int32_t* parts = total + 1;
-    ep.vmax = reinterpret_cast<uint32_t*>(parts + ep.n_buckets + 1);
+    TgRound R;
+    R.total = m->bwd_scan + n_chunks;
+    R.parts = R.total + 1;
+    ep.vmax = reinterpret_cast<uint32_t*>(R.parts + ep.n_buckets + 1);
+    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
     const dim3 fg((unsigned)ep.n_blk, (unsigned)(m->desc.levels / LG));
     const size_t lds_f = sizeof(int32_t) * LG * (size_t)ep.NBL * n_sets;
     hipLaunchKernelGGL(k_enc_bwd_count<FD>, fg, dim3(256), lds_f, sd, ep);
     hipLaunchKernelGGL(k_scan_sums, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, total);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, sd, sums, n_chunks, R.total);
     hipLaunchKernelGGL(k_scan_apply, dim3(n_chunks), dim3(256), 0, sd, ep.cnt, n_cnt, sums);
+    R.ep = ep;
+    return R;
+}
+
+// Fill of the round's samples [c0, c0 + n) (whole blocks of the round: c0 - round start is a
+// multiple of 16 kBwdTilesPerBlock, or n reaches the round's end); delta rows of sample seg at
+// delta + (seg - drow0) HW.
+template <int FD>
+static void tg_fill_fd(nif_model* m, const TgRound& R, const float* delta, int64_t drow0, int64_t c0, int64_t n,
+                       hipStream_t sd) {
+    constexpr int LG = kLevelGroup<FD>;
+    EncBwdParams ep = R.ep;
+    ep.delta0 = delta;
+    ep.drow0 = drow0;
+    const int64_t per_blk = 16 * kBwdTilesPerBlock;
+    ep.blk0 = (int32_t)((c0 - ep.c0) / per_blk);
+    const int64_t blk1 = std::min<int64_t>(ep.n_blk, (c0 + n - ep.c0 + per_blk - 1) / per_blk);
+    const int hw = m->desc.hidden_width;
+    const int n_sets = m->desc.per_sample_tables ? m->S : 1;
+    const dim3 fg((unsigned)(blk1 - ep.blk0), (unsigned)(m->desc.levels / LG));
     // the fill's staged first-layer rows: 4 per PE combination, hw + 4 floats each (up to 60 KiB)
     const int nloc = LG * ep.NBL * n_sets;
+    const size_t lds_f = sizeof(int32_t) * (size_t)nloc;
     const size_t w_bytes = sizeof(float) * 4 * (size_t)(2 * m->S) * (size_t)(hw + 4);
     const size_t cur_bytes = sizeof(int32_t) * (size_t)((nloc + 3) & ~3);
     ep.w_lds = cur_bytes + w_bytes <= kFillLdsMax ? 1 : 0;
@@ -1562,14 +1600,29 @@ static void table_grad_round_fd(nif_model* m, EncBwdParams ep, int64_t c0, int64
         case 64: hipLaunchKernelGGL((k_enc_bwd_fill<64, FD>), fg, dim3(256), lds_fill, sd, ep); break;
         default: hipLaunchKernelGGL((k_enc_bwd_fill<128, FD>), fg, dim3(256), lds_fill, sd, ep); break;
     }
-    hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, total, parts);
-    const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
-    hipLaunchKernelGGL(k_enc_bwd_reduce<FD>, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, total, parts);
 }
 
-static void table_grad_round(nif_model* m, EncBwdParams ep, int64_t c0, int64_t n, hipStream_t sd) {
-    if (m->desc.feat_dim == 3) table_grad_round_fd<3>(m, ep, c0, n, sd);
-    else table_grad_round_fd<2>(m, ep, c0, n, sd);
+template <int FD>
+static void tg_end_fd(nif_model* m, const TgRound& R, hipStream_t sd) {
+    constexpr int LW = kLog2Window<FD>;
+    const EncBwdParams& ep = R.ep;
+    const unsigned n_win = ep.SB > LW ? 1u << (ep.SB - LW) : 1u;
+    hipLaunchKernelGGL(k_enc_bwd_parts, dim3(1), dim3(1024), 0, sd, ep, R.total, R.parts);
+    const int64_t max_parts = ep.n_buckets + (ep.n * 2 * m->S * m->desc.levels * 8) / kReducePart + 1;
+    hipLaunchKernelGGL(k_enc_bwd_reduce<FD>, dim3((unsigned)max_parts, n_win), dim3(256), 0, sd, ep, R.total, R.parts);
+}
+
+static TgRound tg_begin(nif_model* m, const EncBwdParams& ep, int64_t c0, int64_t n, hipStream_t sd) {
+    return m->desc.feat_dim == 3 ? tg_begin_fd<3>(m, ep, c0, n, sd) : tg_begin_fd<2>(m, ep, c0, n, sd);
+}
+static void tg_fill(nif_model* m, const TgRound& R, const float* delta, int64_t drow0, int64_t c0, int64_t n,
+                    hipStream_t sd) {
+    if (m->desc.feat_dim == 3) tg_fill_fd<3>(m, R, delta, drow0, c0, n, sd);
+    else tg_fill_fd<2>(m, R, delta, drow0, c0, n, sd);
+}
+static void tg_end(nif_model* m, const TgRound& R, hipStream_t sd) {
+    if (m->desc.feat_dim == 3) tg_end_fd<3>(m, R, sd);
+    else tg_end_fd<2>(m, R, sd);
 }
 
 // Backward from m->dz.  enc_stored: the forward's encoding [B][E], or null to recompute it
@@ -1597,9 +1650,14 @@ static int backward_core(nif_model* m, const float* x0, const float* x1, int64_t
     hipStream_t sd = m->side;
     if ((rc = check_hip(hipEventRecord(m->ev_fork, st), "backward fork"))) return rc;
     if ((rc = check_hip(hipStreamWaitEvent(sd, m->ev_fork, 0), "backward fork"))) return rc;
-    // encoding backward (layer 0): count / scan / fill / reduce per chunk of samples
+    // encoding backward (layer 0): count / scan / fill / reduce per round of samples
     const EncBwdParams ep = table_grad_params(m, x0, x1, B, dx0, dx1);
-    for (int64_t c0 = 0; c0 < B; c0 += m->bwd_chunk) table_grad_round(m, ep, c0, std::min<int64_t>(m->bwd_chunk, B - c0), sd);
+    for (int64_t c0 = 0; c0 < B; c0 += m->bwd_round) {
+        const int64_t n = std::min<int64_t>(m->bwd_round, B - c0);
+        const TgRound R = tg_begin(m, ep, c0, n, sd);
+        tg_fill(m, R, m->delta, 0, c0, n, sd);
+        tg_end(m, R, sd);
+    }
     if ((rc = check_hip(hipEventRecord(m->ev_join, sd), "backward join"))) return rc;
     // weight gradients of every layer (layer 0 from the stored or the recomputed encoding)
     int dev = 0, cus = 256;
@@ -1729,8 +1787,15 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
         return r;
     };
     // The weight gradients of chunk c are issued after chunk c + 1's MLP backward, so the next
-    // table-gradient round (the longer branch) can start as early as possible.
+    // fill (the longer branch) can start as early as possible.  A table-gradient round (up to
+    // bwd_round samples, whole chunks) counts and scans its additions as soon as it begins (the
+    // positions are known), fills once per chunk after that chunk's MLP backward, and reduces
+    // after its last chunk.
     int64_t prev_c0 = -1, prev_n = 0;
+    int64_t round_end = 0;
+    TgRound R;
+    memset(&R, 0, sizeof(R));
+    bool round_open = false;
     for (int64_t c0 = 0; c0 < B && !rc; c0 += m->bwd_chunk) {
         const int64_t n = std::min<int64_t>(m->bwd_chunk, B - c0);
         float* acts_c = m->acts + (size_t)c0 * nh * hw;      // [hidden layers][n][hw]
@@ -1738,6 +1803,16 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
         float* z_c = m->zbuf + (size_t)c0 * H;
         float* dz_c = m->dz + (size_t)c0 * 16;
         float* enc_c = cfg->store_encoding ? m->enc_all + (size_t)c0 * m->E : nullptr;
+        if (c0 >= round_end) {                  // a round begins with this chunk
+            if (round_open) tg_end(m, R, sd);
+            const int64_t rn = std::min<int64_t>(m->bwd_round, B - c0);
+            if ((rc = check_hip(hipEventRecord(m->ev_fork, st), "train fork"))) break;
+            if ((rc = check_hip(hipStreamWaitEvent(sd, m->ev_fork, 0), "train fork"))) break;
+            forked = true;
+            R = tg_begin(m, ep, c0, rn, sd);
+            round_open = true;
+            round_end = c0 + rn;
+        }
         if ((rc = forward_rows_launch(m, b->x0 + c0, b->x1 + c0, n, B, z_c, prec, acts_c, enc_c, st))) break;
         hipLaunchKernelGGL(k_loss, dim3(grid_for(n)), dim3(256), 0, st, z_c, H, n, B, B, b->hit + c0, b->t + c0,
                            b->n + c0, b->a + c0, b->m + c0, m->s, m->tcount, m->dacc, dz_c, 16, b->x0 + c0, b->x1 + c0,
@@ -1748,14 +1823,12 @@ int train_step_launch(nif_model* m, const nif_batch* b_in, int64_t B, const nif_
         if (rc) break;
         if ((rc = check_hip(hipEventRecord(m->ev_fork, st), "train fork"))) break;
         if ((rc = check_hip(hipStreamWaitEvent(sd, m->ev_fork, 0), "train fork"))) break;
-        forked = true;
-        ep.delta0 = delta_c;                    // layer 0 of the chunk's block
-        ep.drow0 = c0;
-        table_grad_round(m, ep, c0, n, sd);
+        tg_fill(m, R, delta_c, c0, c0, n, sd);     // layer 0 of the chunk's block
         if (prev_c0 >= 0 && (rc = chunk_weight_grads(prev_c0, prev_n))) break;
         prev_c0 = c0;
         prev_n = n;
     }
+    if (!rc && round_open) tg_end(m, R, sd);
     if (!rc && prev_c0 >= 0) rc = chunk_weight_grads(prev_c0, prev_n);
     if (forked) {                               // join before the gradients are read
         const int rj = check_hip(hipEventRecord(m->ev_join, sd), "train join");

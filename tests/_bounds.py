@@ -262,10 +262,10 @@ def _table_error(orc, desc, tables, x0, x1, denc, vdenc, det_denc):
     var += U32 ** 2 / 3.0 * (g ** 2 + gabs ** 2)
     # the sums run in 64-bit fixed point: each addition is rounded to the unit 2^(e + nb - 62),
     # the largest addition below 2^e (one more for the GPU's own rounding of it), nb bits of
-    # the chunk's addition count
+    # the round's addition count (rounds of up to 2^18 samples)
     if vmax > 0.0:
         e = np.frexp(vmax)[1] + 1
-        total = min(n, 1 << 16) * 2 * S * Lv * 8
+        total = min(n, 1 << 18) * 2 * S * Lv * 8
         nb = int(np.ceil(np.log2(total + 1)))
         unit = 2.0 ** (e + nb - 62)
         var += cnt * unit ** 2 / 12.0

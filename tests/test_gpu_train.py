@@ -267,10 +267,10 @@ def test_stored_and_recomputed_encoding_give_the_same_step(P, prec):
 
 @pytest.mark.parametrize("store", [False, True], ids=["recomputed_encoding", "stored_encoding"])
 def test_pipelined_step_at_full_batch_matches_the_separate_calls(P, store):
-    """At the benchmark's training batch (2^18 samples: spatially ordered, four pipelined
-    chunks, the table gradient on the side stream) the step's losses and gradients equal those
-    of nif_forward -> nif_loss -> nif_backward on the same batch (calls held to the oracle by
-    the tests above), within FP32 summation-order error."""
+    """At the benchmark's training batch (2^18 samples: spatially ordered, two pipelined
+    chunks of one table-gradient round on the side stream) the step's losses and gradients
+    equal those of nif_forward -> nif_loss -> nif_backward on the same batch (calls held to the
+    oracle by the tests above), within FP32 summation-order error."""
     import torch
     m = MODELS["blobs128"]
     tab, prm, _ = model_params(m, 41, scale_tables=300.0)
@@ -389,10 +389,10 @@ def test_train_step_rejects_oversized_batches(P):
         _train_step(P, model, _batch(m, 65, 1), 65)
 
 
-@pytest.mark.parametrize("B", [(1 << 17) + 4321, 1 << 18])
+@pytest.mark.parametrize("B", [(1 << 17) + 4321, (1 << 18) + 4321])
 def test_backward_over_several_chunks_is_additive(P, B):
-    """Batches larger than one table-gradient round (2^17 samples), up to the training batch of
-    the benchmark (2^18, two rounds): the gradient of the whole batch equals the gradient of its
+    """Batches of more than one chunk (2^17 samples) in one table-gradient round, and of more
+    than one round (2^18 samples): the gradient of the whole batch equals the gradient of its
     two halves accumulated (the sum is linear in the samples), within FP32 summation-order
     error."""
     import torch
@@ -481,7 +481,8 @@ def test_autograd_wrappers_compose_to_the_oracle_gradient(orc, P):
         h2.sum().backward()
 
 
-@pytest.mark.parametrize("B", [4096 + 7, (1 << 17) + 4099], ids=["one_chunk", "two_chunks"])
+@pytest.mark.parametrize("B", [4096 + 7, (1 << 17) + 4099, (1 << 18) + (1 << 17) + 4099],
+                         ids=["one_chunk", "two_chunks", "two_rounds"])
 def test_train_step_captured_in_a_graph_replays_like_eager(P, B):
     """nif_train_step captured in a hipGraph (with its side-stream fork and join) and replayed
     three times, with eager work between the replays: every replay's losses and gradients
