@@ -422,7 +422,7 @@ def train_leg(steps=5, B=1 << 18, variants=tuple(TRAIN_VARIANTS)):
                         "rays through 8 random twist/bend poses, labelled on the GPU from the analytic scene, "
                         "MLP 832-128x4-12, 16-level 2^19 FP16 grid, Adam", "hit_ratio": hit_ratio,
             "label_ms": label_ms,
-            "encoding_policy": "bf16 / fp32: the backward recomputes the encoding (chunks of 2^16 samples); "
+            "encoding_policy": "bf16 / fp32: the backward recomputes the encoding (chunks of 2^17 samples); "
                                "stored_encoding: the forward keeps the [B][832] FP32 encoding for the backward",
             **res}
 
