@@ -71,7 +71,7 @@ struct nif_model {
     int64_t bwd_round = 0;              // samples per table-gradient round (count, scan, reduce): whole chunks
     int32_t* bwd_cnt = nullptr;         // [buckets][blocks] addition counts / offsets
     int32_t* bwd_scan = nullptr;        // scan partial sums + total
-    float* bwd_val = nullptr;           // table-gradient additions: records (Fd values, entry within the bucket)
+    float* bwd_val = nullptr;           // table-gradient records, 16 bytes each (corner-pair records with two features)
     uint32_t* ord_u32 = nullptr;        // batch ordering: keys and indices, 2 x 2 x max_batch
     float* ord_f32 = nullptr;           //   the ordered batch (15 max_batch words)
     void* ord_temp = nullptr;           //   radix-sort scratch

@@ -35,6 +35,7 @@ constexpr int kGrowIntervalDefault = 1000;  // clean steps before the loss scale
 constexpr int64_t kEncBwdChunk = 1 << 17;  // samples per training chunk (and per fill launch)
 constexpr int kEncBwdRoundChunks = 2;      // chunks per table-gradient round (count, scan, reduce)
 constexpr int kBwdTilesPerBlock = 8;       // 16-sample tiles per encoding-backward block (4 waves)
+constexpr int kRecFloats = 4;              // floats per table-gradient record (16 bytes)
 
 // Concatenated encoding: d x of the appended gamma values, d enc_v = (W0^T delta_0)_v times
 // d gamma_v / d x_a of the clamped coordinate (zero outside the cube), added to dx0 / dx1.
@@ -160,7 +161,8 @@ int model_reserve(nif_model* m, int64_t B) {
         const int64_t n_cnt = n_buckets * n_blk;
         const size_t sz[3] = {sizeof(int32_t) * (size_t)n_cnt,
                               sizeof(int32_t) * (size_t)((n_cnt + 4095) / 4096 + 3 + n_buckets),
-                              sizeof(float) * (size_t)(m->desc.feat_dim + 1) * (size_t)n_add};
+                              // the reduction reads whole aligned groups of 16 records
+                              sizeof(float) * kRecFloats * (size_t)(n_add + 16)};
         void** ptr[3] = {(void**)&m->bwd_cnt, (void**)&m->bwd_scan, (void**)&m->bwd_val};
         for (int i = 0; i < 3; ++i)
             if (hipMalloc(ptr[i], sz[i]) != hipSuccess) {
@@ -826,11 +828,13 @@ struct EncBwdParams {
 };
 
 
-// A table-gradient addition with two features: both values and the entry within the bucket
-// (its bits), written with one 12-byte store.
-struct AddRec3 {
-    float v0, v1, key;
-};
+// Table-gradient records, 16 bytes each.  Three features: one addition (v0, v1, v2, entry
+// within the bucket as bits).  Two features: the additions of an x-neighbour corner pair, whose
+// trilinear weights share the y and z factors A: (a0, a1) = A d enc, w = the x weight of the
+// upper corner, and both entries k0 | k1 << 16; the lower corner receives (1 - w) a, the upper
+// w a.  A pair whose corners fall into different buckets is written as two records with k0 = k1,
+// w = 0 and a pre-multiplied by the corner's x factor.
+__device__ __forceinline__ uint32_t pair_key(uint32_t k0, uint32_t k1) { return k0 | (k1 << 16); }
 
 // Sample position, d position / d x and the in-range mask of PE combination c (point-major).
 __device__ __forceinline__ void pe_combo_grad(const float xs[6], int c, int S, double smp[3], float dsdx[3],
@@ -934,9 +938,19 @@ __global__ void __launch_bounds__(256) k_enc_bwd_count(EncBwdParams P) {
                 uint32_t idx[8];
                 float wt[3];
                 level_corners(P.enc, lp + k, smp, idx, wt);
-                if (live)
+                if (!live) continue;
+                int32_t* h = s_h + (sb + k) * P.NBL;
+                if constexpr (FD == 2) {
 #pragma unroll
-                    for (int cc = 0; cc < 8; ++cc) atomicAdd(&s_h[(sb + k) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
+                    for (int pr = 0; pr < 4; ++pr) {
+                        const int b0 = (int)(idx[2 * pr] >> P.SB), b1 = (int)(idx[2 * pr + 1] >> P.SB);
+                        atomicAdd(&h[b0], 1);
+                        if (b1 != b0) atomicAdd(&h[b1], 1);
+                    }
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 8; ++cc) atomicAdd(&h[(int)(idx[cc] >> P.SB)], 1);
+                }
             }
         }
     }
@@ -1027,30 +1041,56 @@ __global__ void __launch_bounds__(256) k_enc_bwd_fill(EncBwdParams P) {
 #pragma unroll
                     for (int f = 0; f < FD; ++f) gf[f] = acc[FD * k + f];
                     float dl[3] = {0.f, 0.f, 0.f};
+                    int32_t* cur = s_cur + (combo_set(P, c) * LG + l - lp) * P.NBL;
+                    float amax = 0.f;
+                    bool fin = true;
+                    if constexpr (FD == 2) {
 #pragma unroll
-                    for (int cc = 0; cc < 8; ++cc) {
-                        const float cw = corner_weight(wt, cc);
-                        const int32_t slot = atomicAdd(&s_cur[(combo_set(P, c) * LG + l - lp) * P.NBL + (int)(idx[cc] >> P.SB)], 1);
-                        if (slot < P.cap) {      // always true: the count pass saw the same additions
+                        for (int pr = 0; pr < 4; ++pr) {
+                            const int cl = 2 * pr;                 // lower-x corner; cl + 1 the upper
+                            const float A = (((cl >> 1) & 1) ? wt[1] : 1.f - wt[1]) * (((cl >> 2) & 1) ? wt[2] : 1.f - wt[2]);
+                            const float a0 = A * gf[0], a1 = A * gf[1];
+                            const uint32_t k0 = idx[cl] & kmask, k1 = idx[cl + 1] & kmask;
+                            const int b0 = (int)(idx[cl] >> P.SB), b1 = (int)(idx[cl + 1] >> P.SB);
+                            fin = fin && isfinite(a0) && isfinite(a1);
+                            amax = fmaxf(amax, fmaxf(fabsf(a0), fabsf(a1)));
+                            if (b0 == b1) {
+                                const int32_t slot = atomicAdd(&cur[b0], 1);
+                                if (slot < P.cap)      // always true: the count pass saw the same records
+                                    *reinterpret_cast<float4*>(P.val + (size_t)slot * kRecFloats) =
+                                        make_float4(a0, a1, wt[0], __uint_as_float(pair_key(k0, k1)));
+                            } else {
+                                const float w0 = 1.f - wt[0];
+                                const int32_t s0 = atomicAdd(&cur[b0], 1), s1 = atomicAdd(&cur[b1], 1);
+                                if (s0 < P.cap)
+                                    *reinterpret_cast<float4*>(P.val + (size_t)s0 * kRecFloats) =
+                                        make_float4(w0 * a0, w0 * a1, 0.f, __uint_as_float(pair_key(k0, k0)));
+                                if (s1 < P.cap)
+                                    *reinterpret_cast<float4*>(P.val + (size_t)s1 * kRecFloats) =
+                                        make_float4(wt[0] * a0, wt[0] * a1, 0.f, __uint_as_float(pair_key(k1, k1)));
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int cc = 0; cc < 8; ++cc) {
+                            const float cw = corner_weight(wt, cc);
+                            const int32_t slot = atomicAdd(&cur[(int)(idx[cc] >> P.SB)], 1);
                             float v[FD];
-                            bool fin = true;
-                            float a = 0.f;
 #pragma unroll
                             for (int f = 0; f < FD; ++f) {
                                 v[f] = cw * gf[f];
                                 fin = fin && isfinite(v[f]);
-                                a = fmaxf(a, fabsf(v[f]));
+                                amax = fmaxf(amax, fabsf(v[f]));
                             }
-                            // one record store: (values, entry within the bucket)
-                            const float kb = __uint_as_float(idx[cc] & kmask);
-                            if constexpr (FD == 2) {
-                                *reinterpret_cast<AddRec3*>(P.val + (size_t)slot * 3) = AddRec3{v[0], v[1], kb};
-                            } else {
-                                *reinterpret_cast<float4*>(P.val + (size_t)slot * 4) = make_float4(v[0], v[1], v[2], kb);
-                            }
-                            vmx = fin ? fmaxf(vmx, a) : INFINITY;
+                            if (slot < P.cap)
+                                *reinterpret_cast<float4*>(P.val + (size_t)slot * kRecFloats) =
+                                    make_float4(v[0], v[1], v[2], __uint_as_float(idx[cc] & kmask));
                         }
-                        if (P.dx0) {
+                    }
+                    vmx = fin ? fmaxf(vmx, amax) : INFINITY;
+                    if (P.dx0) {
+#pragma unroll
+                        for (int cc = 0; cc < 8; ++cc) {
                             const size_t te = ((size_t)combo_set(P, c) * (size_t)P.enc.set_stride +
                                                ((size_t)l << P.enc.log2T) + idx[cc]) * FD;
                             float gd = 0.f;
@@ -1231,39 +1271,60 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     // same entry, so equal consecutive keys are summed in registers before the LDS atomic and
     // the lanes of a wave work 16 additions apart.
     const int64_t g0 = start >> 4, g1 = (end + 15) >> 4;      // aligned groups of 16
+    auto add_fixed = [&](uint32_t e, const float* r) {       // e: entry within the bucket
+        if ((int)(e >> LW) != w) return;
+        const int k = (int)(e & (WN - 1));
+#pragma unroll
+        for (int f = 0; f < FD; ++f)
+            if (r[f] != 0.f) atomicAdd(&s_acc[FD * k + f], (unsigned long long)llrint(ldexp((double)r[f], sc)));
+    };
     for (int64_t g = g0 + threadIdx.x; g < g1; g += 256) {
         const int64_t base = g << 4;
-        constexpr int RS = FD + 1;                            // floats per record
-        float vv[16 * RS];
+        float vv[16 * kRecFloats];
 #pragma unroll
-        for (int r = 0; r < 4 * RS; ++r) {
-            const float4 t = *reinterpret_cast<const float4*>(P.val + base * RS + 4 * r);
+        for (int r = 0; r < 16; ++r) {
+            const float4 t = *reinterpret_cast<const float4*>(P.val + (base + r) * kRecFloats);
             vv[4 * r] = t.x; vv[4 * r + 1] = t.y; vv[4 * r + 2] = t.z; vv[4 * r + 3] = t.w;
         }
-        uint32_t cur = 0xffffffffu;
-        float rs[FD];
+        bool have = false;
+        uint32_t cur = 0;
+        float r0[FD], r1[FD];
 #pragma unroll
-        for (int f = 0; f < FD; ++f) rs[f] = 0.f;
+        for (int f = 0; f < FD; ++f) r0[f] = r1[f] = 0.f;
         auto flush = [&]() {
-            if ((int)(cur >> LW) == w) {
-                const int e = (int)(cur & (WN - 1));
-#pragma unroll
-                for (int f = 0; f < FD; ++f)
-                    atomicAdd(&s_acc[FD * e + f], (unsigned long long)llrint(ldexp((double)rs[f], sc)));
+            if (!have) return;
+            if constexpr (FD == 2) {
+                add_fixed(cur & 0xffffu, r0);
+                add_fixed(cur >> 16, r1);
+            } else {
+                add_fixed(cur, r0);
             }
         };
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t k = base + r;
-            const uint32_t key = (k >= start && k < end) ? __float_as_uint(vv[RS * r + FD]) : 0xffffffffu;
-            if (key != cur) {
-                flush();
-                cur = key;
+            if (k < start || k >= end) continue;
+            const float* rec = vv + kRecFloats * r;
+            const uint32_t key = __float_as_uint(rec[3]);
+            float c0[FD], c1[FD];
+            if constexpr (FD == 2) {
+                const float wx = rec[2];
+                const float wl = 1.f - wx;
 #pragma unroll
-                for (int f = 0; f < FD; ++f) rs[f] = vv[RS * r + f];
+                for (int f = 0; f < FD; ++f) { c0[f] = wl * rec[f]; c1[f] = wx * rec[f]; }
             } else {
 #pragma unroll
-                for (int f = 0; f < FD; ++f) rs[f] += vv[RS * r + f];
+                for (int f = 0; f < FD; ++f) { c0[f] = rec[f]; c1[f] = 0.f; }
+            }
+            if (!have || key != cur) {
+                flush();
+                have = true;
+                cur = key;
+#pragma unroll
+                for (int f = 0; f < FD; ++f) { r0[f] = c0[f]; r1[f] = c1[f]; }
+            } else {
+#pragma unroll
+                for (int f = 0; f < FD; ++f) { r0[f] += c0[f]; r1[f] += c1[f]; }
             }
         }
         flush();
