@@ -568,8 +568,9 @@ def test_query_paper_configuration(orc, P, prec):
 def test_query_pose_ordered_dealing_gives_the_same_results(orc, P, prec):
     """NIF_Q_POSE_ORDER changes only which wave takes which ray: over poses of uneven counts
     (one empty, one with fewer rays than the 8 per-XCD ranges) every per-ray output equals the
-    default dealing's bit for bit, every ray is done once, and the first pose completes no later
-    than the last."""
+    default dealing's bit for bit and every ray of every pose is done once.  (Completion order
+    is a scheduling effect, not checked here: a launch this small has all its rays in flight at
+    once; bench.py's batched leg measures the per-pose latencies.)"""
     import torch
     w = S.workload("torus16")
     m = w.model
@@ -599,5 +600,3 @@ def test_query_pose_ordered_dealing_gives_the_same_results(orc, P, prec):
     P_ = len(counts)
     for st in sts:
         assert st[0] == n and list(st[5 + P_:5 + 2 * P_]) == counts
-    st = sts[1]
-    assert st[5] <= st[5 + P_ - 1], "pose 0 completes before the last pose"
