@@ -821,10 +821,10 @@ struct EncBwdParams {
     int32_t n_blk;       // blocks of the round's grid
     int32_t blk0;        // fill: the launch's first block within the round
     int32_t* cnt;        // [n_buckets][n_blk] counts, then exclusive offsets
-    float* val;          // additions: records of Fd values and the entry within the bucket (as bits)
+    float* val;          // table-gradient records, kRecFloats floats each (see below)
     int32_t w_lds;       // fill: the block's first-layer weight rows staged in LDS
-    int64_t cap;         // capacity of key / val
-    uint32_t* vmax;      // bits of the largest |value| of the round's additions (+inf if not finite)
+    int64_t cap;         // capacity of val, in records
+    uint32_t* vmax;      // bits of a bound on the round's |additions| (+inf if one is not finite)
 };
 
 
