@@ -42,8 +42,8 @@ KQUERY_SOURCES = ["paper_2604_24666_amd/csrc/nif_query.hip", "paper_2604_24666_a
                   "paper_2604_24666_amd/csrc/nif_internal.hpp", "paper_2604_24666_amd/build.py",
                   "nif_synth/__init__.py"]
 KQUERY_TRAFFIC = {
-    "sources_sha256": "6ee12398fa8abbe2496511de1dee88df6e635ebee5dd0e18768089634be52798",
-    "fetch_kib": 1.04867e8, "write_kib": 1.93796e6,         # per k_query<64, FP32, 64> launch, default workload
+    "sources_sha256": "7bb9c2a0530250ba2433426a0daaf766a3013fcd580931cd0dedcc63e86ea54a",
+    "fetch_kib": 1.04862e8, "write_kib": 1.93924e6,         # per k_query<64, FP32, 64> launch, default workload
     "fetch_scale": 1048576 / 524303, "write_scale": 1048576 / 1048577,   # 1 GiB copy reads 524,303 / writes 1,048,577 KiB
 }
 
