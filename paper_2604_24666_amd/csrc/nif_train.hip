@@ -1266,10 +1266,11 @@ __global__ void __launch_bounds__(256) k_enc_bwd_reduce(EncBwdParams P, const in
     const int64_t b_end = b + 1 < P.n_buckets ? (int64_t)P.cnt[(int64_t)(b + 1) * P.n_blk] : (int64_t)*total;
     const int64_t start = b_start + (int64_t)part * kReducePart;
     const int64_t end = std::min<int64_t>(b_end, start + kReducePart);
-    // Thread t takes 16 consecutive additions per step (vector loads, coalesced across the
-    // wave): additions next to each other come from neighbouring samples and often hit the
-    // same entry, so equal consecutive keys are summed in registers before the LDS atomic and
-    // the lanes of a wave work 16 additions apart.
+    // Thread t takes 16 consecutive records per step (16-byte loads, coalesced across the
+    // wave): records next to each other come from neighbouring samples and often hit the same
+    // entries, so runs of equal keys are summed in registers before the LDS atomics, and the
+    // lanes of a wave work 16 records apart.  Every record adds at most |a| < 2^e in all (its
+    // two parts split a by weights summing to 1), so N counts records in the scale above.
     const int64_t g0 = start >> 4, g1 = (end + 15) >> 4;      // aligned groups of 16
     auto add_fixed = [&](uint32_t e, const float* r) {       // e: entry within the bucket
         if ((int)(e >> LW) != w) return;
