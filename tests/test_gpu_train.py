@@ -68,6 +68,10 @@ MODELS = {
     "paper32": S.workload("spheres32_paper").model,
     "paper32_f32_per_sample": dataclasses.replace(S.workload("spheres32_paper").model, table_dtype=S.TABLE_F32,
                                                   log2_table=16, per_sample_tables=1, hidden_width=32),
+    # 2^21-entry tables: 8192-entry buckets reduced in two LDS windows each, so the two entries
+    # of a corner-pair record can fall into different windows
+    "wide_table": dataclasses.replace(S.workload("torus16").model, levels=4, log2_table=21,
+                                      res=[16, 64, 256, 1024], pe_freqs=2, hidden_width=32, hidden_layers=2),
 }
 
 
