@@ -72,6 +72,10 @@ MODELS = {
     # of a corner-pair record can fall into different windows
     "wide_table": dataclasses.replace(S.workload("torus16").model, levels=4, log2_table=21,
                                       res=[16, 64, 256, 1024], pe_freqs=2, hidden_width=32, hidden_layers=2),
+    # 12 bands at width 128: the fill's first-layer rows (105 KiB) exceed its LDS budget, so it
+    # reads them from memory
+    "wide_pe": dataclasses.replace(S.workload("torus16").model, levels=4, res=[16, 32, 64, 128], pe_freqs=12,
+                                   hidden_width=128, hidden_layers=1),
 }
 
 
