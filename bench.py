@@ -802,6 +802,19 @@ def batched_leg(replays=50, warmup=5, train_steps=1000):
         log(f"batched leg {name} pose-ordered: {ms:.2f} ms per launch, pose latency p50 "
             f"{res[name]['pose_ordered']['pose_latency_ms_p50']:.2f} p99 "
             f"{res[name]['pose_ordered']['pose_latency_ms_p99']:.2f} ms")
+    # traversal alone: the voxel proxy walks every ray to its first occupied voxel, against the
+    # BF16 launch (a lower bound of the query's traversal, which walks on past empty segments)
+    P.nif_query(model.h, grid.h, rays, n, hits, P.Q_NO_NETWORK, 1, None)
+    pa, pb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pa.record()
+    for _ in range(3):
+        P.nif_query(model.h, grid.h, rays, n, hits, P.Q_NO_NETWORK, 1, None)
+    pb.record()
+    torch.cuda.synchronize()
+    proxy_ms = pa.elapsed_time(pb) / 3
+    res["time_shares"] = {"traversal_to_first_occupied_voxel": proxy_ms / res["bf16"]["ms_per_launch_median"],
+                          "proxy_ms": proxy_ms}
+    log(f"batched leg voxel proxy: {proxy_ms:.2f} ms")
     return {"workload": f"blobs128_b: 16 poses (twist/bend/taper, s ~ U(0,1]), {n} rays in uneven counts "
                         f"[{int(counts.min())}, {int(counts.max())}], half pinhole (random azimuth), half secondary "
                         f"(origin uniform in the pose's occupied deformed box, direction uniform on S^2); one "
